@@ -1,0 +1,212 @@
+/*
+ * kktfwi.h - C ABI of the MI355X (gfx950) full-space Gauss-Newton KKT solver for
+ * 2-D frequency-domain acoustic full-waveform inversion with PML
+ * (Malovichko, Orazbayev, Khokhlov, "Iterative PDE-constrained optimization for
+ * seismic full-waveform inversion", arXiv 2204.06489).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Pointers are DEVICE pointers owned by the caller unless marked [host].  The
+ *   library never keeps a caller pointer after the call returns; gamma and the
+ *   acquisition arrays are copied.
+ * - Complex numbers are interleaved (re, im): c128 = two doubles, c64 = two floats.
+ * - Wavefields are [K][nz][nx] row-major (x fastest).  Node (i, j) is at
+ *   x = i*h, z = j*h; the listed nx x nz nodes include the PML strips and the
+ *   field is zero outside them (U = 0 on the boundary, Section 2).
+ * - The control is the squared slowness on the core (non-PML) nodes,
+ *   [nz - 2 npml][nx - 2 npml] row-major; Ng = (nx - 2 npml)(nz - 2 npml).
+ * - Packed KKT vectors xi = (du, ds, lambda) are
+ *   [ du_0 .. du_{K-1} | ds | lambda_0 .. lambda_{K-1} ], length 2*K*nx*nz + Ng,
+ *   c128 (the stacking of eq. partitioned_system_matrix, Section 5).
+ * - All device work is ordered on the problem's HIP stream.  Calls that return
+ *   statistics (helmholtz_solve, newton_step, helmholtz_adjoint_gradient, the
+ *   factorisation) synchronise that stream before returning; kkt_apply and
+ *   precond_apply are asynchronous.
+ * - Errors are returned as kf_status; no exception crosses the ABI.  Argument
+ *   validation happens before any HIP call; the message of the last failure on
+ *   the calling thread is kf_last_error().  On KF_ENOCONV the outputs hold the
+ *   last iterate and the statistics are filled; after any other error the
+ *   outputs are unspecified.
+ * - One problem is used by one host thread at a time.
+ */
+#ifndef KKTFWI_H
+#define KKTFWI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kf_problem kf_problem;
+
+typedef enum {
+  KF_OK = 0,
+  KF_EINVAL = 1,      /* invalid argument (null pointer, eps <= 0, node off the grid, ...) */
+  KF_ESHAPE = 2,      /* inconsistent sizes */
+  KF_ENOMEM = 3,      /* device allocation failed */
+  KF_EHIP = 4,        /* a HIP runtime call failed */
+  KF_ENOCONV = 5,     /* iteration limit reached before the tolerance */
+  KF_EBREAKDOWN = 6,  /* Krylov breakdown (zero or non-finite Arnoldi norm) */
+  KF_ENAN = 7,        /* non-finite residual */
+  KF_ESTATE = 8       /* call needs state that is not set (e.g. no background field) */
+} kf_status;
+
+/* Arithmetic of Helmholtz block solves. */
+typedef enum {
+  KF_C128 = 0,   /* complex128 buffers, FP64 factors: direct solve to rounding */
+  KF_C64 = 1,    /* complex64 buffers and factors (FP32 arithmetic and accumulation) */
+  KF_MIXED = 2   /* complex128 buffers; complex64 factors inside FP64 iterative
+                    refinement until the relative residual meets rtol */
+} kf_prec;
+
+/* Preconditioner of the KKT system (Section 5). */
+typedef enum {
+  KF_PC_EXACT = 0,   /* eq. precond: A and A^* solved exactly (FP64 factors) */
+  KF_PC_INEXACT = 1  /* eq. precond_approx: A replaced by A~ = the complex64
+                        factorisation of A (one sweep per block solve) */
+} kf_pc;
+
+/* Problem description (Sections 2-4).  Arrays marked [host] are copied. */
+typedef struct {
+  int32_t nx, nz;          /* grid nodes including the PML strips (>= 3 each) */
+  double h;                /* grid spacing, metres (> 0) */
+  int32_t npml;            /* PML width in cells on all four sides (0 <= 2 npml < min(nx, nz)) */
+  double pml_r0;           /* design reflection of the quadratic PML profile, 0 < r0 < 1 */
+  double pml_cref;         /* reference speed of the PML profile, m/s (> 0) */
+  double omega;            /* circular frequency 2 pi f, rad/s (> 0) */
+  int32_t K;               /* number of sources (>= 1) */
+  const int32_t *src_ix;   /* [host][K] source node columns; f_k = e_src / h^2 (unit point source) */
+  const int32_t *src_iz;   /* [host][K] source node rows */
+  int32_t nrec;            /* receivers per source (>= 1); the same nodes for every source */
+  const int32_t *rec_ix;   /* [host][nrec] receiver node columns (Dirac receivers on nodes) */
+  const int32_t *rec_iz;   /* [host][nrec] receiver node rows */
+  const double *w;         /* [host][K][nrec] real receiver weights W_k, or NULL for W = I */
+  double eps;              /* L = eps * I on the control (> 0; the preconditioner needs L^-1) */
+  int32_t reg_on_update;   /* 0: b_s = -eps s_n (eq. KKT); 1: b_s = 0, i.e. the -L s_n := 0
+                              variant of the multi-frequency experiment (Section 6) */
+} kf_desc;
+
+typedef struct {
+  double rtol;             /* relative residual target of one Newton-step KKT solve */
+  int32_t restart;         /* FGMRES restart length m (1..200) */
+  int32_t maxit;           /* total outer iteration limit */
+  int32_t pc;              /* kf_pc */
+  int32_t fwd_prec;        /* kf_prec of the background forward solve u_n = A^-1 f (C128 or MIXED) */
+  double fwd_rtol;         /* tolerance of that solve when fwd_prec = KF_MIXED */
+  int32_t misfit_after;    /* 1: also solve A(gamma_{n+1}) u = f and report the new misfit */
+} kf_newton_opts;
+
+typedef struct {
+  int32_t outer_iters;     /* FGMRES iterations taken */
+  int32_t restarts;        /* completed restart cycles */
+  double rel_res;          /* true ||b - M xi|| / ||b|| at exit (recomputed with kkt_apply) */
+  double rel_res_hist[512];/* FGMRES residual estimate per iteration (first 512) */
+  double misfit_before;    /* ||d - Q u_n|| / ||d|| */
+  double misfit_after;     /* ||d - Q u_{n+1}|| / ||d|| (if requested, else -1) */
+  double phi_before;       /* 1/2 sum_k ||W_k (d_k - Q u_k)||^2 */
+  double ds_imag_ratio;    /* ||Im ds|| / ||ds|| */
+  double t_factor_ms;      /* time in the block factorisation(s) */
+  double t_forward_ms;     /* background forward solve */
+  double t_precond_ms;     /* preconditioner applications */
+  double t_matvec_ms;      /* kkt_apply calls */
+  double t_orth_ms;        /* orthogonalisation, Givens, updates */
+  double t_total_ms;       /* whole call */
+  int32_t fwd_refine_iters;/* refinement sweeps of the forward solve (KF_MIXED) */
+} kf_newton_stats;
+
+typedef struct {
+  int32_t iters;           /* sweeps (1 for a direct solve; refinement steps for KF_MIXED) */
+  double rel_res_max;      /* max over sources of ||rhs_k - A x_k|| / ||rhs_k|| (computed
+                              when rtol > 0 or the precision is KF_MIXED, else -1) */
+} kf_solve_stats;
+
+/* Library version string. */
+const char *kf_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char *kf_last_error(void);
+
+/* Create a problem: validates and copies the description and gamma ([nz][nx] FP64, host
+ * or device: `gamma_on_device` says which), allocates device state and builds the PML
+ * coefficients (Section 2).  `hip_stream` is a hipStream_t (NULL = default stream). */
+kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t gamma_on_device,
+                    void *hip_stream, kf_problem **out);
+kf_status kf_destroy(kf_problem *p);
+/* Replace gamma (device pointer, [nz][nx]); invalidates the factorisation and u_n. */
+kf_status kf_set_gamma(kf_problem *p, const double *gamma);
+/* Read gamma back into a device buffer [nz][nx]. */
+kf_status kf_get_gamma(kf_problem *p, double *gamma_out);
+/* Set the background fields u_n (c128 [K][nz][nx], device) used by P = omega^2 diag(u_n)
+ * in kkt_apply and precond_apply (eq. P). */
+kf_status kf_set_background(kf_problem *p, const void *u_n);
+/* Copy u_n out (c128 [K][nz][nx], device). */
+kf_status kf_get_background(kf_problem *p, void *u_n_out);
+/* Change the stream used by subsequent calls. */
+kf_status kf_set_stream(kf_problem *p, void *hip_stream);
+/* Build the block factorisation of A(gamma, omega) now (it is otherwise built on the first
+ * solve that needs it).  `which`: bit 0 = FP64 factors, bit 1 = complex64 copy. */
+kf_status kf_factor(kf_problem *p, int32_t which, double *t_ms /*[host], may be NULL*/);
+
+/* y = A x or y = A^H x for all K sources (the 5-point PML Helmholtz operator of Section 2,
+ * eq. Au=f).  x, y: [K][nz][nx] c128 (prec KF_C128) or c64 (KF_C64). Asynchronous. */
+kf_status kf_stencil_apply(kf_problem *p, int32_t adjoint, int32_t prec, const void *x, void *y);
+
+/* Solve A x_k = rhs_k (adjoint = 0) or A^H x_k = rhs_k (adjoint = 1) for all K sources:
+ * the K independent block solves of the stacked forward problem (Section 2, eq. helmholtz).
+ * prec: kf_prec.  rhs and x may alias.  rtol is the refinement target for KF_MIXED
+ * (ignored otherwise, except that rtol > 0 makes the call report the residual).
+ * maxit bounds the refinement sweeps.  Returns KF_ENOCONV if KF_MIXED misses rtol. */
+kf_status helmholtz_solve(kf_problem *p, int32_t adjoint, int32_t prec, const void *rhs, void *x,
+                          double rtol, int32_t maxit, kf_solve_stats *st /*[host], may be NULL*/);
+
+/* y = M xi with the KKT matrix of eq. KKT,
+ *   M = [[F, 0, A^*], [0, L, -P^*], [A, -P, 0]],  F_k = Q^T W_k^2 Q,  P_k = omega^2 diag(u_k) E,
+ * applied matrix-free (needs kf_set_background or a previous newton_step).  xi, y: packed
+ * c128 (no aliasing).  Asynchronous. */
+kf_status kkt_apply(kf_problem *p, const void *xi, void *y);
+
+/* z = P^-1 y for the block-triangular preconditioner of eq. precond (pc = KF_PC_EXACT) or
+ * eq. precond_approx (KF_PC_INEXACT):
+ *   z_lam = A^-* y_u;  z_s = (y_s + P^* z_lam) / eps;  z_u = A^-1 (y_lam + P z_s).
+ * y, z packed c128 (no aliasing).  Asynchronous. */
+kf_status precond_apply(kf_problem *p, int32_t pc, const void *y, void *z);
+
+/* One full-space Gauss-Newton step (Sections 3-5):
+ *   u_n = A(gamma_n)^-1 f;  r_k = d_k - Q u_k;  b = [Q^T W^2 r ; -eps s_n or 0 ; 0];
+ *   solve M xi = b by right-preconditioned flexible GMRES to ||b - M xi|| <= rtol ||b||;
+ *   gamma_{n+1} = gamma_n + Re(ds) on the core (PML values unchanged).
+ * d_obs: [K][nrec] c128 device.  xi_out: packed c128 device or NULL.  gamma_next: device
+ * [nz][nx] receiving gamma_{n+1}, or NULL.  update_in_place = 1 also makes gamma_{n+1} the
+ * problem's gamma (for the next step); with 0 the problem keeps gamma_n, so kkt_apply and
+ * precond_apply still describe the system that was solved.  u_n stays available as the
+ * background (kf_get_background).  Returns KF_ENOCONV (outputs and stats filled) if
+ * maxit is reached first. */
+kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newton_opts *opts /*[host]*/,
+                      void *xi_out, double *gamma_next, int32_t update_in_place,
+                      kf_newton_stats *st /*[host], may be NULL*/);
+
+/* Reduced gradient through the forward solve (Section 3, gradient; Section 4, eq. tmp2):
+ * for u = A(gamma)^-1 f and grad_u = dl/dRe(u) + i dl/dIm(u) (both [K][nz][nx], c128 or
+ * c64 per prec), computes mu = A^-H grad_u and
+ *   grad_gamma[j][i] = omega^2 sum_k Re(conj(mu_k) X_i Z_j u_k)     ([nz][nx], FP64),
+ * which on the core equals omega^2 sum_k Re(conj(mu_k) u_k).  Synchronous. */
+kf_status helmholtz_adjoint_gradient(kf_problem *p, int32_t prec, const void *u, const void *grad_u,
+                                     double *grad_gamma);
+
+/* Build the point sources f_k = e_src / h^2 of the problem into f ([K][nz][nx], c128). */
+kf_status kf_sources(kf_problem *p, void *f);
+
+/* Sizes of the problem: out[0..5] = nx, nz, K, nrec, Ng, packed length (as int64). */
+kf_status kf_sizes(kf_problem *p, int64_t *out /*[host][6]*/);
+
+/* Per-kernel timing with HIP events recorded around every launch of the named kernel
+ * family on the problem's stream: enable (1) / disable (0) and reset the counters. */
+kf_status kf_profile_enable(kf_problem *p, int32_t on);
+/* Read accumulated (launch count, total milliseconds) of a kernel family:
+ * "kkt_apply", "stencil", "blu_factor", "blu_sweep", "precond_stage", "orth", "reduce". */
+kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KKTFWI_H */

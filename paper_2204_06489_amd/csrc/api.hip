@@ -1,0 +1,753 @@
+// C ABI of libkktfwi: validation, device state, Helmholtz block solves, the KKT
+// operator and preconditioner, flexible GMRES and the Gauss-Newton step.
+#include "common.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+static kf_status fail(kf_status st, const std::string &msg) {
+  set_error(msg);
+  return st;
+}
+#define CHECK_ST(expr)                  \
+  do {                                  \
+    kf_status s_ = (expr);              \
+    if (s_ != KF_OK) return s_;         \
+  } while (0)
+
+extern "C" const char *kf_version(void) { return "kktfwi 0.1 (gfx950)"; }
+extern "C" const char *kf_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// profiling: HIP events around launches of a kernel family, from a pool
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(kf_problem *p) {
+  if (p->ev_free.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = p->ev_free.back();
+  p->ev_free.pop_back();
+  return e;
+}
+ProfScope::ProfScope(kf_problem *p_, int id_) : p(p_), id(id_) {
+  if (!p->prof) return;
+  a = take_event(p);
+  b = take_event(p);
+  if (a) hipEventRecord(a, p->stream);
+}
+ProfScope::~ProfScope() {
+  if (!p->prof || !a || !b) return;
+  hipEventRecord(b, p->stream);
+  p->pending[id].push_back({a, b});
+}
+static void prof_collect(kf_problem *p) {
+  bool any = false;
+  for (int i = 0; i < PROF_N; ++i) any |= !p->pending[i].empty();
+  if (!any) return;
+  hipStreamSynchronize(p->stream);
+  for (int i = 0; i < PROF_N; ++i) {
+    for (auto &pr : p->pending[i]) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, pr.first, pr.second);
+      p->counters[i].launches += 1;
+      p->counters[i].ms += ms;
+      p->ev_free.push_back(pr.first);
+      p->ev_free.push_back(pr.second);
+    }
+    p->pending[i].clear();
+  }
+}
+
+// phase timer for the Newton-step breakdown (events, summed at the end)
+struct PhaseTimer {
+  kf_problem *p;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> recs;
+  int cur = -1;
+  hipEvent_t cur_a = nullptr;
+  explicit PhaseTimer(kf_problem *p_) : p(p_) {}
+  void start(int phase) {
+    cur = phase;
+    cur_a = take_event(p);
+    if (cur_a) hipEventRecord(cur_a, p->stream);
+  }
+  void stop() {
+    hipEvent_t b = take_event(p);
+    if (b && cur_a) {
+      hipEventRecord(b, p->stream);
+      recs.push_back({cur, {cur_a, b}});
+    }
+    cur_a = nullptr;
+  }
+  void sum(double *out, int n) {
+    hipStreamSynchronize(p->stream);
+    for (auto &r : recs) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, r.second.first, r.second.second);
+      if (r.first < n) out[r.first] += ms;
+      p->ev_free.push_back(r.second.first);
+      p->ev_free.push_back(r.second.second);
+    }
+    recs.clear();
+  }
+};
+enum { PH_PRECOND = 0, PH_MATVEC, PH_ORTH, PH_N };
+
+// ---------------------------------------------------------------------------
+// allocation helpers
+// ---------------------------------------------------------------------------
+template <typename T> static kf_status dalloc(T **ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(KF_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes failed: " +
+                               hipGetErrorString(e));
+  }
+  return KF_OK;
+}
+template <typename T> static void dfree(T *&ptr) {
+  if (ptr) hipFree((void *)ptr);
+  ptr = nullptr;
+}
+
+static void free_all(kf_problem *p) {
+  dfree(p->gamma); dfree(p->xn); dfree(p->ixh); dfree(p->zn); dfree(p->izh);
+  dfree(p->d_src); dfree(p->d_rnode); dfree(p->d_wsq); dfree(p->d_rec); dfree(p->d_w);
+  dfree(p->d_rptr); dfree(p->d_rlist); dfree(p->d_r); dfree(p->d_wr);
+  dfree(p->u_n); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->xmid); dfree(p->xmid32);
+  dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
+  dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
+  if (p->host_pinned) hipHostFree(p->host_pinned);
+  p->host_pinned = nullptr;
+  for (int i = 0; i < PROF_N; ++i) {
+    for (auto &pr : p->pending[i]) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+    p->pending[i].clear();
+  }
+  for (auto e : p->ev_free) hipEventDestroy(e);
+  p->ev_free.clear();
+}
+
+// ---------------------------------------------------------------------------
+// validation (no HIP calls)
+// ---------------------------------------------------------------------------
+static const int MAX_NZ = 1024;  // column block size held by the factorisation kernels
+
+static kf_status validate_desc(const kf_desc *d) {
+  if (!d) return fail(KF_EINVAL, "desc is NULL");
+  if (d->nx < 3 || d->nz < 3) return fail(KF_ESHAPE, "nx and nz must be >= 3");
+  if (d->nz > MAX_NZ) return fail(KF_ESHAPE, "nz must be <= 1024 (column block of the factorisation)");
+  if ((int64_t)d->nx * d->nz > (int64_t)1 << 31) return fail(KF_ESHAPE, "grid too large");
+  if (!(d->h > 0.0) || !std::isfinite(d->h)) return fail(KF_EINVAL, "h must be > 0");
+  if (d->npml < 0 || 2 * d->npml >= d->nx || 2 * d->npml >= d->nz)
+    return fail(KF_EINVAL, "npml must satisfy 0 <= 2*npml < min(nx, nz)");
+  if (d->npml > 0 && !(d->pml_r0 > 0.0 && d->pml_r0 < 1.0)) return fail(KF_EINVAL, "pml_r0 must be in (0, 1)");
+  if (d->npml > 0 && !(d->pml_cref > 0.0 && std::isfinite(d->pml_cref))) return fail(KF_EINVAL, "pml_cref must be > 0");
+  if (!(d->omega > 0.0) || !std::isfinite(d->omega)) return fail(KF_EINVAL, "omega must be > 0");
+  if (d->K < 1) return fail(KF_EINVAL, "K must be >= 1");
+  if (!d->src_ix || !d->src_iz) return fail(KF_EINVAL, "source index arrays are NULL");
+  if (d->nrec < 1) return fail(KF_EINVAL, "nrec must be >= 1");
+  if (!d->rec_ix || !d->rec_iz) return fail(KF_EINVAL, "receiver index arrays are NULL");
+  if (!(d->eps > 0.0) || !std::isfinite(d->eps))
+    return fail(KF_EINVAL, "eps must be > 0 (the preconditioner applies L^-1 = I/eps)");
+  for (int k = 0; k < d->K; ++k)
+    if (d->src_ix[k] < 0 || d->src_ix[k] >= d->nx || d->src_iz[k] < 0 || d->src_iz[k] >= d->nz)
+      return fail(KF_EINVAL, "source " + std::to_string(k) + " is off the grid");
+  for (int r = 0; r < d->nrec; ++r)
+    if (d->rec_ix[r] < 0 || d->rec_ix[r] >= d->nx || d->rec_iz[r] < 0 || d->rec_iz[r] >= d->nz)
+      return fail(KF_EINVAL, "receiver " + std::to_string(r) + " is off the grid");
+  if (d->w)
+    for (int64_t q = 0; q < (int64_t)d->K * d->nrec; ++q)
+      if (!std::isfinite(d->w[q])) return fail(KF_EINVAL, "weights must be finite");
+  return KF_OK;
+}
+
+static kf_status check_p(kf_problem *p) {
+  if (!p) return fail(KF_EINVAL, "problem is NULL");
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy / state
+// ---------------------------------------------------------------------------
+extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t gamma_on_device, void *hip_stream,
+                               kf_problem **out) {
+  if (!out) return fail(KF_EINVAL, "out is NULL");
+  *out = nullptr;
+  CHECK_ST(validate_desc(desc));
+  if (!gamma) return fail(KF_EINVAL, "gamma is NULL");
+  if (!gamma_on_device) {
+    for (int64_t q = 0; q < (int64_t)desc->nx * desc->nz; ++q)
+      if (!std::isfinite(gamma[q])) return fail(KF_EINVAL, "gamma must be finite");
+  }
+  kf_problem *p = new kf_problem();
+  p->d = *desc;
+  p->nx = desc->nx; p->nz = desc->nz; p->npml = desc->npml; p->K = desc->K; p->nrec = desc->nrec;
+  p->nxc = p->nx - 2 * p->npml; p->nzc = p->nz - 2 * p->npml;
+  p->Nu = (int64_t)p->nx * p->nz; p->Ng = (int64_t)p->nxc * p->nzc; p->Nxi = 2 * p->K * p->Nu + p->Ng;
+  p->h = desc->h; p->omega = desc->omega; p->eps = desc->eps;
+  p->stream = (hipStream_t)hip_stream;
+  p->mid = p->nx / 2;
+  p->src_ix.assign(desc->src_ix, desc->src_ix + p->K);
+  p->src_iz.assign(desc->src_iz, desc->src_iz + p->K);
+  p->rec_ix.assign(desc->rec_ix, desc->rec_ix + p->nrec);
+  p->rec_iz.assign(desc->rec_iz, desc->rec_iz + p->nrec);
+  p->w.assign((size_t)p->K * p->nrec, 1.0);
+  if (desc->w) std::copy(desc->w, desc->w + (size_t)p->K * p->nrec, p->w.begin());
+  p->d.src_ix = p->src_ix.data(); p->d.src_iz = p->src_iz.data();
+  p->d.rec_ix = p->rec_ix.data(); p->d.rec_iz = p->rec_iz.data(); p->d.w = p->w.data();
+
+  // receivers: natural node of each, unique nodes, CSR lists and summed W^2 per node
+  std::vector<int32_t> rec(p->nrec), src(p->K);
+  for (int r = 0; r < p->nrec; ++r) rec[r] = p->rec_iz[r] * p->nx + p->rec_ix[r];
+  for (int k = 0; k < p->K; ++k) src[k] = p->src_iz[k] * p->nx + p->src_ix[k];
+  std::map<int32_t, std::vector<int32_t>> bynode;
+  for (int r = 0; r < p->nrec; ++r) bynode[rec[r]].push_back(r);
+  std::vector<int32_t> rnode, rptr(1, 0), rlist;
+  for (auto &kv : bynode) {
+    rnode.push_back(kv.first);
+    for (int r : kv.second) rlist.push_back(r);
+    rptr.push_back((int32_t)rlist.size());
+  }
+  p->nru = (int)rnode.size();
+  std::vector<double> wsq((size_t)p->K * p->nru, 0.0);
+  for (int k = 0; k < p->K; ++k)
+    for (int u = 0; u < p->nru; ++u)
+      for (int e = rptr[u]; e < rptr[u + 1]; ++e) {
+        double ww = p->w[(size_t)k * p->nrec + rlist[e]];
+        wsq[(size_t)k * p->nru + u] += ww * ww;
+      }
+
+  const size_t Nu = p->Nu, K = p->K, m = p->nz;
+  kf_status st = KF_OK;
+#define ALLOC(ptr, n) if (st == KF_OK) st = dalloc(&(ptr), (n))
+  ALLOC(p->gamma, Nu);
+  ALLOC(p->xn, (size_t)p->nx); ALLOC(p->ixh, (size_t)p->nx + 1);
+  ALLOC(p->zn, (size_t)p->nz); ALLOC(p->izh, (size_t)p->nz + 1);
+  ALLOC(p->d_src, K); ALLOC(p->d_rnode, (size_t)p->nru); ALLOC(p->d_wsq, K * p->nru);
+  ALLOC(p->d_rec, (size_t)p->nrec); ALLOC(p->d_w, K * p->nrec);
+  ALLOC(p->d_rptr, (size_t)p->nru + 1); ALLOC(p->d_rlist, (size_t)p->nrec);
+  ALLOC(p->d_r, K * p->nrec); ALLOC(p->d_wr, K * p->nrec);
+  ALLOC(p->u_n, K * Nu);
+  ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m);
+  ALLOC(p->fac_work, 2 * m * m);
+  ALLOC(p->xmid, K * m); ALLOC(p->xmid32, K * m);
+  ALLOC(p->vec_a, K * Nu); ALLOC(p->vec_b, K * Nu); ALLOC(p->vec_c, K * Nu); ALLOC(p->vec_d, K * Nu);
+  ALLOC(p->red, (size_t)1024 * 2 * 256 + K * 64);
+  ALLOC(p->red_out, std::max<size_t>(K, 1024));
+#undef ALLOC
+  if (st == KF_OK && hipHostMalloc((void **)&p->host_pinned, sizeof(double) * std::max<size_t>(K, 1024)) != hipSuccess) {
+    p->host_pinned = nullptr;
+    st = fail(KF_ENOMEM, "hipHostMalloc failed");
+  }
+  if (st != KF_OK) { free_all(p); delete p; return st; }
+
+  auto h2d = [&](void *dst, const void *srcp, size_t bytes) -> kf_status {
+    HIP_TRY(hipMemcpyAsync(dst, srcp, bytes, hipMemcpyHostToDevice, p->stream));
+    return KF_OK;
+  };
+  st = h2d(p->d_src, src.data(), sizeof(int32_t) * K);
+  if (st == KF_OK) st = h2d(p->d_rec, rec.data(), sizeof(int32_t) * p->nrec);
+  if (st == KF_OK) st = h2d(p->d_rnode, rnode.data(), sizeof(int32_t) * p->nru);
+  if (st == KF_OK) st = h2d(p->d_rptr, rptr.data(), sizeof(int32_t) * (p->nru + 1));
+  if (st == KF_OK) st = h2d(p->d_rlist, rlist.data(), sizeof(int32_t) * p->nrec);
+  if (st == KF_OK) st = h2d(p->d_wsq, wsq.data(), sizeof(double) * K * p->nru);
+  if (st == KF_OK) st = h2d(p->d_w, p->w.data(), sizeof(double) * K * p->nrec);
+  if (st == KF_OK) {
+    hipError_t e = hipMemcpyAsync(p->gamma, gamma, sizeof(double) * Nu,
+                                  gamma_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) st = fail(KF_EHIP, std::string("copy of gamma failed: ") + hipGetErrorString(e));
+  }
+  if (st == KF_OK) st = launch_pml(p, p->d);
+  if (st == KF_OK && hipStreamSynchronize(p->stream) != hipSuccess) st = fail(KF_EHIP, "stream synchronize failed");
+  if (st != KF_OK) { free_all(p); delete p; return st; }
+  *out = p;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_destroy(kf_problem *p) {
+  if (!p) return KF_OK;
+  hipStreamSynchronize(p->stream);
+  free_all(p);
+  delete p;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_set_stream(kf_problem *p, void *s) {
+  CHECK_ST(check_p(p));
+  p->stream = (hipStream_t)s;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_set_gamma(kf_problem *p, const double *gamma) {
+  CHECK_ST(check_p(p));
+  if (!gamma) return fail(KF_EINVAL, "gamma is NULL");
+  HIP_TRY(hipMemcpyAsync(p->gamma, gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+  p->have_T64 = p->have_T32 = false;
+  p->have_un = false;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_get_gamma(kf_problem *p, double *out) {
+  CHECK_ST(check_p(p));
+  if (!out) return fail(KF_EINVAL, "output is NULL");
+  HIP_TRY(hipMemcpyAsync(out, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+  return KF_OK;
+}
+
+extern "C" kf_status kf_set_background(kf_problem *p, const void *u) {
+  CHECK_ST(check_p(p));
+  if (!u) return fail(KF_EINVAL, "u_n is NULL");
+  HIP_TRY(hipMemcpyAsync(p->u_n, u, sizeof(double2) * p->K * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+  p->have_un = true;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_get_background(kf_problem *p, void *out) {
+  CHECK_ST(check_p(p));
+  if (!out) return fail(KF_EINVAL, "output is NULL");
+  if (!p->have_un) return fail(KF_ESTATE, "no background field");
+  HIP_TRY(hipMemcpyAsync(out, p->u_n, sizeof(double2) * p->K * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+  return KF_OK;
+}
+
+extern "C" kf_status kf_factor(kf_problem *p, int32_t which, double *t_ms) {
+  CHECK_ST(check_p(p));
+  if (which < 1 || which > 3) return fail(KF_EINVAL, "which must be 1, 2 or 3");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  auto t0 = std::chrono::steady_clock::now();
+  CHECK_ST(blu_factor(p, which));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (t_ms) *t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return KF_OK;
+}
+
+extern "C" kf_status kf_sizes(kf_problem *p, int64_t *out) {
+  CHECK_ST(check_p(p));
+  if (!out) return fail(KF_EINVAL, "output is NULL");
+  out[0] = p->nx; out[1] = p->nz; out[2] = p->K; out[3] = p->nrec; out[4] = p->Ng; out[5] = p->Nxi;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_sources(kf_problem *p, void *f) {
+  CHECK_ST(check_p(p));
+  if (!f) return fail(KF_EINVAL, "f is NULL");
+  return launch_sources(p, (double2 *)f);
+}
+
+extern "C" kf_status kf_stencil_apply(kf_problem *p, int32_t adjoint, int32_t prec, const void *x, void *y) {
+  CHECK_ST(check_p(p));
+  if (!x || !y) return fail(KF_EINVAL, "x or y is NULL");
+  if (x == y) return fail(KF_EINVAL, "x and y must not alias");
+  if (prec == KF_C128) return launch_stencil<double>(p, adjoint, (const double2 *)x, (double2 *)y);
+  if (prec == KF_C64) return launch_stencil<float>(p, adjoint, (const float2 *)x, (float2 *)y);
+  return fail(KF_EINVAL, "prec must be KF_C128 or KF_C64");
+}
+
+// ---------------------------------------------------------------------------
+// Helmholtz block solves
+// ---------------------------------------------------------------------------
+// max_k ||rhs_k - op(A) x_k|| / ||rhs_k|| in FP64 (x, rhs c128); uses vec_a, vec_b
+static kf_status residual_max(kf_problem *p, int adjoint, const double2 *rhs, const double2 *x, double *relmax,
+                              std::vector<double> *rn_cache) {
+  const int64_t n = (int64_t)p->K * p->Nu;
+  std::vector<double> rn(p->K), bn(p->K);
+  if (rn_cache && !rn_cache->empty()) bn = *rn_cache;
+  else {
+    CHECK_ST(per_source_norms(p, rhs, p->Nu, p->K, bn.data()));
+    if (rn_cache) *rn_cache = bn;
+  }
+  CHECK_ST(launch_stencil<double>(p, adjoint, x, p->vec_a));
+  HIP_TRY(hipMemcpyAsync(p->vec_b, rhs, sizeof(double2) * n, hipMemcpyDeviceToDevice, p->stream));
+  CHECK_ST(launch_axpy_field(p, n, make_double2(-1.0, 0.0), p->vec_a, p->vec_b));
+  CHECK_ST(per_source_norms(p, p->vec_b, p->Nu, p->K, rn.data()));
+  double mx = 0.0;
+  for (int k = 0; k < p->K; ++k) {
+    double r = bn[k] > 0.0 ? rn[k] / bn[k] : rn[k];
+    if (!std::isfinite(r)) return fail(KF_ENAN, "non-finite residual in block solve");
+    mx = std::max(mx, r);
+  }
+  *relmax = mx;
+  return KF_OK;
+}
+
+// complex64 sweeps inside FP64 iterative refinement (x, rhs c128; rhs may alias x)
+static kf_status solve_mixed(kf_problem *p, int adjoint, const double2 *rhs, double2 *x, double rtol, int maxit,
+                             int *iters, double *relmax) {
+  const int64_t n = (int64_t)p->K * p->Nu;
+  if (rhs == x) {
+    HIP_TRY(hipMemcpyAsync(p->vec_c, rhs, sizeof(double2) * n, hipMemcpyDeviceToDevice, p->stream));
+    rhs = p->vec_c;
+  }
+  CHECK_ST(blu_solve_mixed_io(p, adjoint, rhs, x));
+  int it = 1;
+  std::vector<double> bn;
+  double rm = 0.0;
+  for (;;) {
+    CHECK_ST(residual_max(p, adjoint, rhs, x, &rm, &bn));   // residual left in vec_b
+    if (rm <= rtol || it >= maxit) break;
+    CHECK_ST(blu_solve_mixed_io(p, adjoint, p->vec_b, p->vec_a));
+    CHECK_ST(launch_axpy_field(p, n, make_double2(1.0, 0.0), p->vec_a, x));
+    ++it;
+  }
+  *iters = it;
+  *relmax = rm;
+  if (rm > rtol) return fail(KF_ENOCONV, "mixed-precision refinement did not reach rtol");
+  return KF_OK;
+}
+
+extern "C" kf_status helmholtz_solve(kf_problem *p, int32_t adjoint, int32_t prec, const void *rhs, void *x,
+                                     double rtol, int32_t maxit, kf_solve_stats *st) {
+  CHECK_ST(check_p(p));
+  if (!rhs || !x) return fail(KF_EINVAL, "rhs or x is NULL");
+  if (prec != KF_C128 && prec != KF_C64 && prec != KF_MIXED) return fail(KF_EINVAL, "invalid precision");
+  if (prec == KF_MIXED && !(rtol > 0.0)) return fail(KF_EINVAL, "KF_MIXED needs rtol > 0");
+  if (maxit < 1) maxit = 1;
+  const int64_t n = (int64_t)p->K * p->Nu;
+  int iters = 1;
+  double rm = -1.0;
+  kf_status res = KF_OK;
+  if (prec == KF_C128) {
+    CHECK_ST(blu_solve<double>(p, adjoint, (const double2 *)rhs, (double2 *)x));
+    if (rtol > 0.0) {
+      if (rhs == x) return fail(KF_EINVAL, "residual report needs rhs and x distinct");
+      CHECK_ST(residual_max(p, adjoint, (const double2 *)rhs, (const double2 *)x, &rm, nullptr));
+    }
+  } else if (prec == KF_C64) {
+    CHECK_ST(blu_solve<float>(p, adjoint, (const float2 *)rhs, (float2 *)x));
+    if (rtol > 0.0) {
+      if (rhs == x) return fail(KF_EINVAL, "residual report needs rhs and x distinct");
+      CHECK_ST(launch_copy_c64_to_c128(p, n, (const float2 *)rhs, p->vec_c));
+      CHECK_ST(launch_copy_c64_to_c128(p, n, (const float2 *)x, p->vec_d));
+      CHECK_ST(residual_max(p, adjoint, p->vec_c, p->vec_d, &rm, nullptr));
+    }
+  } else {
+    res = solve_mixed(p, adjoint, (const double2 *)rhs, (double2 *)x, rtol, maxit, &iters, &rm);
+    if (res != KF_OK && res != KF_ENOCONV) return res;
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (st) { st->iters = iters; st->rel_res_max = rm; }
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// KKT operator and preconditioner (eq. KKT, eq. precond, eq. precond_approx)
+// ---------------------------------------------------------------------------
+extern "C" kf_status kkt_apply(kf_problem *p, const void *xi, void *y) {
+  CHECK_ST(check_p(p));
+  if (!xi || !y) return fail(KF_EINVAL, "xi or y is NULL");
+  if (xi == y) return fail(KF_EINVAL, "xi and y must not alias");
+  if (!p->have_un) return fail(KF_ESTATE, "no background field (kf_set_background or newton_step first)");
+  return launch_kkt_apply(p, (const double2 *)xi, (double2 *)y);
+}
+
+static kf_status precond_impl(kf_problem *p, int pc, const double2 *y, double2 *z) {
+  const size_t Ku = (size_t)p->K * p->Nu;
+  const double2 *yu = y;
+  double2 *zu = z, *zl = z + Ku + p->Ng;
+  // stage 1: z_lam = A^-* y_u
+  if (pc == KF_PC_EXACT) CHECK_ST(blu_solve<double>(p, 1, yu, zl));
+  else CHECK_ST(blu_solve_mixed_io(p, 1, yu, zl));
+  // stage 2: z_s = (y_s + P^* z_lam) / eps, and z_u := y_lam + P z_s
+  CHECK_ST(launch_precond_stage2(p, y, z));
+  // stage 3: z_u = A^-1 (y_lam + P z_s)
+  if (pc == KF_PC_EXACT) CHECK_ST(blu_solve<double>(p, 0, zu, zu));
+  else CHECK_ST(blu_solve_mixed_io(p, 0, zu, zu));
+  return KF_OK;
+}
+
+extern "C" kf_status precond_apply(kf_problem *p, int32_t pc, const void *y, void *z) {
+  CHECK_ST(check_p(p));
+  if (!y || !z) return fail(KF_EINVAL, "y or z is NULL");
+  if (y == z) return fail(KF_EINVAL, "y and z must not alias");
+  if (pc != KF_PC_EXACT && pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
+  if (!p->have_un) return fail(KF_ESTATE, "no background field (kf_set_background or newton_step first)");
+  return precond_impl(p, pc, (const double2 *)y, (double2 *)z);
+}
+
+// ---------------------------------------------------------------------------
+// flexible GMRES (right preconditioned, CGS2, Givens on the device)
+// ---------------------------------------------------------------------------
+static kf_status ensure_krylov(kf_problem *p, int m) {
+  if (p->krylov_m >= m) return KF_OK;
+  dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
+  p->krylov_m = 0;
+  const size_t N = p->Nxi;
+  CHECK_ST(dalloc(&p->V, (size_t)(m + 1) * N));
+  CHECK_ST(dalloc(&p->Z, (size_t)m * N));
+  CHECK_ST(dalloc(&p->xi_w, N));
+  CHECK_ST(dalloc(&p->xi_b, N));
+  CHECK_ST(dalloc(&p->xi_x, N));
+  CHECK_ST(dalloc(&p->hess, (size_t)(m + 1) * m + 6 * (size_t)(m + 1) + 16));
+  p->krylov_m = m;
+  return KF_OK;
+}
+
+struct FgmresOut {
+  int iters = 0, restarts = 0;
+  double rel_res = 1.0;
+  std::vector<double> hist;
+  double ph[PH_N] = {0, 0, 0};
+};
+
+static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, double tol, int m, int maxit,
+                        FgmresOut &o) {
+  const int64_t N = p->Nxi;
+  double2 *H = p->hess;
+  double2 *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *h1 = g + (m + 1), *h2 = h1 + (m + 1),
+          *y = h2 + (m + 1);
+  double *scal = (double *)(y + m + 8);  // [0] norm, [1] beta, [2] resid estimate, [3] ||b||
+  PhaseTimer pt(p);
+  CHECK_ST(norm_c128(p, b, N, scal + 3));
+  HIP_TRY(hipMemcpyAsync(p->host_pinned, scal + 3, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const double bnorm = p->host_pinned[0];
+  HIP_TRY(hipMemsetAsync(x, 0, sizeof(double2) * N, p->stream));
+  o.hist.assign(1, 1.0);
+  if (!std::isfinite(bnorm)) return fail(KF_ENAN, "non-finite right-hand side");
+  if (bnorm == 0.0) { o.rel_res = 0.0; return KF_OK; }
+  int total = 0;
+  kf_status status = KF_OK;
+  for (;;) {
+    double2 *V0 = p->V;
+    if (total == 0) {
+      HIP_TRY(hipMemcpyAsync(V0, b, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+    } else {
+      pt.start(PH_MATVEC);
+      CHECK_ST(launch_kkt_apply(p, x, p->xi_w));
+      pt.stop();
+      HIP_TRY(hipMemcpyAsync(V0, b, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+      CHECK_ST(launch_axpy_field(p, N, make_double2(-1.0, 0.0), p->xi_w, V0));
+    }
+    CHECK_ST(norm_c128(p, V0, N, scal + 1));
+    HIP_TRY(hipMemcpyAsync(p->host_pinned, scal + 1, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    const double beta = p->host_pinned[0];
+    if (!std::isfinite(beta)) { status = fail(KF_ENAN, "non-finite residual in FGMRES"); break; }
+    o.rel_res = beta / bnorm;
+    if (o.rel_res <= tol) break;
+    if (total >= maxit) { status = fail(KF_ENOCONV, "FGMRES reached maxit"); break; }
+    CHECK_ST(scale_inv(p, N, scal + 1, V0, V0));
+    CHECK_ST(set_g0(p, m, scal + 1, g));
+    int nj = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double2 *Vj = p->V + (size_t)j * N, *Vn = p->V + (size_t)(j + 1) * N, *Zj = p->Z + (size_t)j * N;
+      pt.start(PH_PRECOND);
+      CHECK_ST(precond_impl(p, pc, Vj, Zj));
+      pt.stop();
+      pt.start(PH_MATVEC);
+      CHECK_ST(launch_kkt_apply(p, Zj, Vn));
+      pt.stop();
+      pt.start(PH_ORTH);
+      CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
+      CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h1, -1.0, Vn, N));
+      CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h2));
+      CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h2, -1.0, Vn, N));
+      CHECK_ST(norm_c128(p, Vn, N, scal + 0));
+      CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
+      CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
+      pt.stop();
+      HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      const double hn = p->host_pinned[0], est = p->host_pinned[2] / bnorm;
+      ++total;
+      nj = j + 1;
+      o.hist.push_back(est);
+      if (!std::isfinite(est) || !std::isfinite(hn)) { status = fail(KF_ENAN, "non-finite value in Arnoldi"); break; }
+      if (hn == 0.0) { breakdown = true; break; }   // exact solution in the current space
+      if (est <= tol || total >= maxit) break;
+    }
+    if (status != KF_OK) break;
+    pt.start(PH_ORTH);
+    CHECK_ST(hess_backsolve(p, nj, m, H, g, y));
+    CHECK_ST(multiaxpy_c128(p, p->Z, nj, y, 1.0, x, N));
+    pt.stop();
+    o.restarts += 1;
+    (void)breakdown;
+  }
+  o.iters = total;
+  pt.sum(o.ph, PH_N);
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// one Gauss-Newton step in the full space (Sections 3-5)
+// ---------------------------------------------------------------------------
+static double host_norm(kf_problem *p, const double2 *x, int64_t n, kf_status *st) {
+  *st = norm_c128(p, x, n, p->red_out);
+  if (*st != KF_OK) return NAN;
+  if (hipMemcpyAsync(p->host_pinned, p->red_out, sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
+    *st = fail(KF_EHIP, "readback failed");
+    return NAN;
+  }
+  return p->host_pinned[0];
+}
+
+static kf_status forward_solve(kf_problem *p, int prec, double rtol, double2 *u, int *iters) {
+  CHECK_ST(launch_sources(p, p->vec_c));
+  *iters = 1;
+  if (prec == KF_MIXED) {
+    double rm;
+    kf_status st = solve_mixed(p, 0, p->vec_c, u, rtol, 20, iters, &rm);
+    return st;
+  }
+  return blu_solve<double>(p, 0, p->vec_c, u);
+}
+
+extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newton_opts *o, void *xi_out,
+                                 double *gamma_next, int32_t update_in_place, kf_newton_stats *st) {
+  CHECK_ST(check_p(p));
+  if (!d_obs || !o) return fail(KF_EINVAL, "d_obs or opts is NULL");
+  if (!(o->rtol > 0.0) || o->restart < 1 || o->restart > 200 || o->maxit < 1)
+    return fail(KF_EINVAL, "need rtol > 0, 1 <= restart <= 200, maxit >= 1");
+  if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
+  if (o->fwd_prec != KF_C128 && o->fwd_prec != KF_MIXED) return fail(KF_EINVAL, "fwd_prec must be C128 or MIXED");
+  if (o->fwd_prec == KF_MIXED && !(o->fwd_rtol > 0.0)) return fail(KF_EINVAL, "fwd_rtol must be > 0");
+  kf_newton_stats S;
+  std::memset(&S, 0, sizeof(S));
+  S.misfit_after = -1.0;
+  auto T0 = std::chrono::steady_clock::now();
+  auto ms_since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+  };
+  CHECK_ST(ensure_krylov(p, o->restart));
+  const int64_t N = p->Nxi;
+  const size_t Ku = (size_t)p->K * p->Nu;
+  // factorisation of A(gamma_n)
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  auto t = std::chrono::steady_clock::now();
+  int which = 1 | ((o->pc == KF_PC_INEXACT || o->fwd_prec == KF_MIXED) ? 2 : 0);
+  CHECK_ST(blu_factor(p, which));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_factor_ms = ms_since(t);
+  // background field u_n = A^-1 f
+  t = std::chrono::steady_clock::now();
+  int fit = 0;
+  CHECK_ST(forward_solve(p, o->fwd_prec, o->fwd_rtol, p->u_n, &fit));
+  p->have_un = true;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_forward_ms = ms_since(t);
+  S.fwd_refine_iters = fit;
+  // data residual and right-hand side b (eq. KKT)
+  kf_status e = KF_OK;
+  CHECK_ST(launch_residual(p, (const double2 *)d_obs, p->u_n, p->d_r, p->d_wr));
+  const int64_t nd = (int64_t)p->K * p->nrec;
+  double rn = host_norm(p, p->d_r, nd, &e); CHECK_ST(e);
+  double dn = host_norm(p, (const double2 *)d_obs, nd, &e); CHECK_ST(e);
+  double wn = host_norm(p, p->d_wr, nd, &e); CHECK_ST(e);
+  S.misfit_before = dn > 0 ? rn / dn : rn;
+  S.phi_before = 0.5 * wn * wn;
+  CHECK_ST(launch_rhs(p, p->d_r, p->d_rptr, p->d_rlist, p->xi_b, p->d.reg_on_update));
+  // KKT solve
+  FgmresOut fo;
+  kf_status fst = fgmres(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->restart, o->maxit, fo);
+  if (fst != KF_OK && fst != KF_ENOCONV) return fst;
+  S.outer_iters = fo.iters;
+  S.restarts = fo.restarts;
+  S.rel_res = fo.rel_res;
+  for (size_t q = 1; q < fo.hist.size() && q <= 512; ++q) S.rel_res_hist[q - 1] = fo.hist[q];
+  S.t_precond_ms = fo.ph[PH_PRECOND];
+  S.t_matvec_ms = fo.ph[PH_MATVEC];
+  S.t_orth_ms = fo.ph[PH_ORTH];
+  // ||Im ds|| / ||ds||
+  const double2 *ds = p->xi_x + Ku;
+  double dsn = host_norm(p, ds, p->Ng, &e); CHECK_ST(e);
+  CHECK_ST(imag_part(p, p->Ng, ds, p->vec_a));
+  double dsi = host_norm(p, p->vec_a, p->Ng, &e); CHECK_ST(e);
+  S.ds_imag_ratio = dsn > 0 ? dsi / dsn : 0.0;
+  if (xi_out) HIP_TRY(hipMemcpyAsync(xi_out, p->xi_x, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+  // gamma_{n+1} = gamma_n + Re(ds) on the core
+  if (update_in_place || o->misfit_after) {
+    if (!update_in_place) HIP_TRY(hipMemcpyAsync(p->vec_d, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+    CHECK_ST(launch_update_gamma(p, ds, p->gamma));
+    p->have_T64 = p->have_T32 = false;
+    if (gamma_next) HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+    if (o->misfit_after) {
+      CHECK_ST(blu_factor(p, o->fwd_prec == KF_MIXED ? 3 : 1));
+      int it2;
+      double2 *u1 = p->V;  // Krylov space is free after the solve: m+1 >= 2 packed vectors > K*Nu
+      CHECK_ST(forward_solve(p, o->fwd_prec, o->fwd_rtol, u1, &it2));
+      CHECK_ST(launch_residual(p, (const double2 *)d_obs, u1, p->d_r, p->d_wr));
+      double rn1 = host_norm(p, p->d_r, nd, &e); CHECK_ST(e);
+      S.misfit_after = dn > 0 ? rn1 / dn : rn1;
+    }
+    if (!update_in_place) {
+      // restore gamma_n (kept in vec_d, which no step above overwrote)
+      HIP_TRY(hipMemcpyAsync(p->gamma, p->vec_d, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+      p->have_T64 = p->have_T32 = false;
+    }
+  } else if (gamma_next) {
+    HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+    CHECK_ST(launch_update_gamma(p, ds, gamma_next));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_total_ms = ms_since(T0);
+  if (st) *st = S;
+  prof_collect(p);
+  return fst;
+}
+
+// ---------------------------------------------------------------------------
+// reduced gradient through the forward solve (autograd backward)
+// ---------------------------------------------------------------------------
+extern "C" kf_status helmholtz_adjoint_gradient(kf_problem *p, int32_t prec, const void *u, const void *grad_u,
+                                                double *grad_gamma) {
+  CHECK_ST(check_p(p));
+  if (!u || !grad_u || !grad_gamma) return fail(KF_EINVAL, "null pointer argument");
+  if (prec == KF_C128) {
+    CHECK_ST(blu_solve<double>(p, 1, (const double2 *)grad_u, p->vec_a));
+    CHECK_ST(launch_grad_gamma(p, u, p->vec_a, 0, grad_gamma));
+  } else if (prec == KF_C64) {
+    float2 *mu = (float2 *)p->vec_a;
+    CHECK_ST(blu_solve<float>(p, 1, (const float2 *)grad_u, mu));
+    CHECK_ST(launch_grad_gamma(p, u, mu, 1, grad_gamma));
+  } else if (prec == KF_MIXED) {
+    int it;
+    double rm;
+    CHECK_ST(solve_mixed(p, 1, (const double2 *)grad_u, p->vec_d, 1e-12, 10, &it, &rm));
+    CHECK_ST(launch_grad_gamma(p, u, p->vec_d, 0, grad_gamma));
+  } else {
+    return fail(KF_EINVAL, "invalid precision");
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling API
+// ---------------------------------------------------------------------------
+static const char *prof_names[PROF_N] = {"kkt_apply", "stencil", "blu_factor", "blu_sweep", "precond_stage",
+                                         "orth", "reduce"};
+
+extern "C" kf_status kf_profile_enable(kf_problem *p, int32_t on) {
+  CHECK_ST(check_p(p));
+  prof_collect(p);
+  p->prof = on != 0;
+  for (int i = 0; i < PROF_N; ++i) p->counters[i] = ProfCounter();
+  return KF_OK;
+}
+
+extern "C" kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms) {
+  CHECK_ST(check_p(p));
+  if (!name || !launches || !total_ms) return fail(KF_EINVAL, "null pointer argument");
+  prof_collect(p);
+  for (int i = 0; i < PROF_N; ++i)
+    if (std::strcmp(name, prof_names[i]) == 0) {
+      *launches = p->counters[i].launches;
+      *total_ms = p->counters[i].ms;
+      return KF_OK;
+    }
+  return fail(KF_EINVAL, std::string("unknown kernel family ") + name);
+}

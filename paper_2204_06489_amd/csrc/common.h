@@ -1,0 +1,197 @@
+// Internal declarations shared by the HIP translation units of libkktfwi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kktfwi.h"
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on interleaved (re, im) pairs
+// ---------------------------------------------------------------------------
+template <typename R> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename R> using cplx = typename cvec<R>::type;
+
+template <typename R> __host__ __device__ inline cplx<R> mk(R re, R im) { cplx<R> c; c.x = re; c.y = im; return c; }
+template <typename C> __host__ __device__ inline C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+template <typename C> __host__ __device__ inline C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename C> __host__ __device__ inline C cmul(C a, C b) { C c; c.x = a.x * b.x - a.y * b.y; c.y = a.x * b.y + a.y * b.x; return c; }
+// conj(a) * b
+template <typename C> __host__ __device__ inline C cmulc(C a, C b) { C c; c.x = a.x * b.x + a.y * b.y; c.y = a.x * b.y - a.y * b.x; return c; }
+template <typename C> __host__ __device__ inline C cconj(C a) { a.y = -a.y; return a; }
+template <typename C, typename R> __host__ __device__ inline C cscale(C a, R s) { a.x *= s; a.y *= s; return a; }
+// acc += a * b
+template <typename C> __host__ __device__ inline void cfma(C &acc, C a, C b) {
+  acc.x += a.x * b.x - a.y * b.y;
+  acc.y += a.x * b.y + a.y * b.x;
+}
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm keeps the scaling safe for the large PML stretch factors
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    double r = b.x / b.y, d = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+template <typename C> __host__ __device__ inline double cabs2(C a) { return (double)a.x * a.x + (double)a.y * a.y; }
+
+template <typename To, typename From> __device__ inline cplx<To> ccast(From a) { return mk<To>((To)a.x, (To)a.y); }
+
+// ---------------------------------------------------------------------------
+// PML and stencil coefficients of one grid (device arrays, c128)
+//   xn[i]   = X(x_i)                 i = 0..nx-1
+//   ixh[i]  = 1 / X(x_{i-1/2})       i = 0..nx   (faces of node i are ixh[i], ixh[i+1])
+//   zn, izh likewise along z
+// ---------------------------------------------------------------------------
+struct Grid {
+  int nx, nz, npml;
+  double h, omega;
+  const double *gamma;      // [nz][nx]
+  const double2 *xn, *ixh, *zn, *izh;
+};
+
+// The five stencil weights of node (i, j) of A (Section 2, 5-point PML scheme):
+//   (A u)_ij = cc u_ij + cxm u_{i-1,j} + cxp u_{i+1,j} + czm u_{i,j-1} + czp u_{i,j+1}
+struct Stencil5 { double2 cc, cxm, cxp, czm, czp; };
+
+__device__ inline Stencil5 stencil_at(const Grid &g, int i, int j) {
+  const double ih2 = 1.0 / (g.h * g.h);
+  const double2 X = g.xn[i], Z = g.zn[j];
+  Stencil5 s;
+  s.cxm = cscale(cmul(Z, g.ixh[i]), -ih2);
+  s.cxp = cscale(cmul(Z, g.ixh[i + 1]), -ih2);
+  s.czm = cscale(cmul(X, g.izh[j]), -ih2);
+  s.czp = cscale(cmul(X, g.izh[j + 1]), -ih2);
+  const double w2g = g.omega * g.omega * g.gamma[(size_t)j * g.nx + i];
+  double2 m = cscale(cmul(X, Z), w2g);
+  s.cc = csub(make_double2(0.0, 0.0), cadd(cadd(s.cxm, s.cxp), cadd(s.czm, s.czp)));
+  s.cc = csub(s.cc, m);
+  return s;
+}
+
+// coupling weight between column i-1 and column i at row j (the block-tridiagonal
+// off-diagonal C_i of A; A is complex symmetric so it is the same in both directions)
+__device__ inline double2 coupling_x(const Grid &g, int i, int j) {
+  return cscale(cmul(g.zn[j], g.ixh[i]), -1.0 / (g.h * g.h));
+}
+
+// ---------------------------------------------------------------------------
+// problem state
+// ---------------------------------------------------------------------------
+struct ProfCounter { int64_t launches = 0; double ms = 0.0; };
+
+struct kf_problem {
+  kf_desc d;                      // copy; its host arrays point into the vectors below
+  std::vector<int32_t> src_ix, src_iz, rec_ix, rec_iz;
+  std::vector<double> w;          // [K][nrec]
+  int nx, nz, npml, K, nrec, nxc, nzc;
+  int64_t Nu, Ng, Nxi;
+  double h, omega, eps;
+  hipStream_t stream = nullptr;
+
+  // device state
+  double *gamma = nullptr;                     // [nz][nx]
+  double2 *xn = nullptr, *ixh = nullptr, *zn = nullptr, *izh = nullptr;
+  int32_t *d_src = nullptr;                    // [K] natural node index of source k
+  int32_t *d_rnode = nullptr;                  // [nru] unique receiver nodes
+  int nru = 0;
+  double *d_wsq = nullptr;                     // [K][nru] sum of w^2 of receivers at a node
+  int32_t *d_rec = nullptr;                    // [nrec] natural node of receiver r
+  int32_t *d_rptr = nullptr, *d_rlist = nullptr; // receivers of each unique node (CSR)
+  double2 *d_r = nullptr, *d_wr = nullptr;     // [K][nrec] data residual and weighted residual
+  double *d_w = nullptr;                       // [K][nrec]
+  double2 *u_n = nullptr;                      // [K][nz][nx]
+  bool have_un = false;
+
+  // block factorisation (column sweep, both ends)
+  int mid = 0;                                 // meeting column
+  double2 *T64 = nullptr;                      // [nx][nz][nz], T_i stored transposed
+  float2 *T32 = nullptr;                       // complex64 copy
+  bool have_T64 = false, have_T32 = false;
+  double2 *fac_work = nullptr;                 // factorisation scratch
+  double2 *xmid = nullptr;                     // [K][nz] middle-column solve buffer (c128)
+  float2 *xmid32 = nullptr;
+
+  // scratch
+  double2 *vec_a = nullptr, *vec_b = nullptr, *vec_c = nullptr, *vec_d = nullptr;  // [K][nz][nx] each
+  double *red = nullptr;                       // reduction partials
+  double *red_out = nullptr;                   // small reduction results
+  double *host_pinned = nullptr;               // pinned readback buffer
+
+  // Krylov bases (allocated on first use)
+  int krylov_m = 0;
+  double2 *V = nullptr, *Z = nullptr;          // (m+1) and m packed vectors
+  double2 *xi_w = nullptr, *xi_b = nullptr, *xi_x = nullptr;
+  double2 *hess = nullptr;                     // (m+1) x m Hessenberg + rotations etc.
+
+  Grid grid() const { return Grid{nx, nz, npml, h, omega, gamma, xn, ixh, zn, izh}; }
+
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free;             // event pool
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[8];
+  ProfCounter counters[8];
+};
+
+enum ProfId { PROF_KKT = 0, PROF_STENCIL, PROF_FACTOR, PROF_SWEEP, PROF_PRECOND, PROF_ORTH, PROF_REDUCE, PROF_N };
+
+// error plumbing
+void set_error(const std::string &msg);
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      set_error(std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_));    \
+      return KF_EHIP;                                                                    \
+    }                                                                                    \
+  } while (0)
+
+// profiling helpers (no-ops unless enabled)
+struct ProfScope {
+  kf_problem *p; int id; hipEvent_t a{}, b{};
+  ProfScope(kf_problem *p_, int id_);
+  ~ProfScope();
+};
+
+// ---------------------------------------------------------------------------
+// launchers (all enqueue on p->stream)
+// ---------------------------------------------------------------------------
+kf_status launch_pml(kf_problem *p, const kf_desc &d);
+template <typename R> kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *y);
+kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y);
+kf_status launch_precond_stage2(kf_problem *p, const double2 *y, double2 *z);
+kf_status launch_sources(kf_problem *p, double2 *f);
+kf_status launch_residual(kf_problem *p, const double2 *d_obs, const double2 *u, double2 *r, double2 *wr);
+kf_status launch_rhs(kf_problem *p, const double2 *r, const int32_t *rptr, const int32_t *rlist, double2 *b,
+                     int reg_on_update);
+kf_status launch_update_gamma(kf_problem *p, const double2 *ds, double *target);
+kf_status launch_grad_gamma(kf_problem *p, const void *u, const void *mu, int c64, double *grad);
+kf_status launch_axpy_field(kf_problem *p, int64_t n, double2 a, const double2 *x, double2 *y);
+kf_status launch_copy_c128_to_c64(kf_problem *p, int64_t n, const double2 *x, float2 *y);
+kf_status launch_copy_c64_to_c128(kf_problem *p, int64_t n, const float2 *x, double2 *y);
+
+// block factorisation and sweeps
+kf_status blu_factor(kf_problem *p, int which);
+template <typename R> kf_status blu_solve(kf_problem *p, int adjoint, const cplx<R> *rhs, cplx<R> *x);
+kf_status blu_solve_mixed_io(kf_problem *p, int adjoint, const double2 *rhs, double2 *x);  // c64 factors, c128 I/O
+
+// reductions (deterministic, fixed order)
+kf_status per_source_norms(kf_problem *p, const double2 *x, int64_t n_per, int K, double *out_host);
+kf_status dot_c128(kf_problem *p, const double2 *a, const double2 *b, int64_t n, double2 *out_dev);
+kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev);
+kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev);
+kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w, int64_t n);
+// FGMRES small dense algebra on the device (single-thread kernels)
+kf_status arnoldi_finish(kf_problem *p, int j, int m, const double2 *h1, const double2 *h2, const double *nrm,
+                         double2 *H, double2 *cs, double2 *sn, double2 *g, double *resid);
+kf_status scale_inv(kf_problem *p, int64_t n, const double *nrm, const double2 *x, double2 *y);
+kf_status hess_backsolve(kf_problem *p, int nj, int m, const double2 *H, const double2 *g, double2 *y);
+kf_status set_g0(kf_problem *p, int m, const double *beta, double2 *g);
+kf_status imag_part(kf_problem *p, int64_t n, const double2 *x, double2 *y);

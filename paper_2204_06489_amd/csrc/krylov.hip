@@ -1,0 +1,302 @@
+// Krylov building blocks: deterministic wave64 reductions (fixed-order two-stage,
+// no atomics), multi-dot / multi-axpy for classical Gram-Schmidt, and the small
+// dense Hessenberg algebra of flexible GMRES kept on the device.
+#include "common.h"
+
+namespace {
+
+constexpr int RB = 256;      // reduction block size (4 wavefronts)
+constexpr int RG = 1024;     // reduction grid size (fixed => fixed summation order)
+constexpr int MDOT = 8;      // vectors per multi-dot pass
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum of NV doubles per thread; result valid in thread 0
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *lds /*[NV][RB/64]*/) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) lds[q * (RB / 64) + wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < RB / 64; ++w) s += lds[q * (RB / 64) + w];
+      v[q] = s;
+    }
+  }
+}
+
+// partial[blockIdx][0..1] = sum conj(a) b over the block's grid-stride share
+__global__ __launch_bounds__(RB) void k_dot_partial(const double2 *__restrict__ a, const double2 *__restrict__ b,
+                                                    int64_t n, double *partial) {
+  __shared__ double lds[2 * RB / 64];
+  double v[2] = {0.0, 0.0};
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
+    double2 x = a[t], y = b[t];
+    v[0] += x.x * y.x + x.y * y.y;
+    v[1] += x.x * y.y - x.y * y.x;
+  }
+  block_sum<2>(v, lds);
+  if (threadIdx.x == 0) { partial[2 * blockIdx.x] = v[0]; partial[2 * blockIdx.x + 1] = v[1]; }
+}
+
+__global__ __launch_bounds__(RB) void k_norm2_partial(const double2 *__restrict__ a, int64_t n, double *partial) {
+  __shared__ double lds[RB / 64];
+  double v[1] = {0.0};
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
+    double2 x = a[t];
+    v[0] += x.x * x.x + x.y * x.y;
+  }
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// sum the RG partials of nq quantities in fixed order; out[q] = sum (or sqrt for norms)
+__global__ __launch_bounds__(RB) void k_finish(const double *__restrict__ partial, int nq, int stride, int take_sqrt,
+                                               double *out) {
+  __shared__ double lds[RB / 64];
+  for (int q = 0; q < nq; ++q) {
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < RG; b += RB) v[0] += partial[(size_t)b * stride + q];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[q] = take_sqrt ? sqrt(v[0]) : v[0];
+    __syncthreads();
+  }
+}
+
+// h[q] = V_q^H w for q in [q0, q0 + NQ): partial sums per block
+template <int NQ>
+__global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restrict__ V, int q0, int nv,
+                                                         const double2 *__restrict__ w, int64_t n, double *partial,
+                                                         int stride) {
+  __shared__ double lds[2 * NQ * RB / 64];
+  double v[2 * NQ];
+#pragma unroll
+  for (int q = 0; q < 2 * NQ; ++q) v[q] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
+    double2 y = w[t];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q0 + q < nv) {
+        double2 x = V[(size_t)(q0 + q) * n + t];
+        v[2 * q] += x.x * y.x + x.y * y.y;
+        v[2 * q + 1] += x.x * y.y - x.y * y.x;
+      }
+    }
+  }
+  block_sum<2 * NQ>(v, lds);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 2 * NQ; ++q)
+      if (q0 + q / 2 < nv) partial[(size_t)blockIdx.x * stride + 2 * q0 + q] = v[q];
+}
+
+// w += sign * sum_q V_q h_q
+__global__ __launch_bounds__(RB) void k_multiaxpy(const double2 *__restrict__ V, int nv, const double2 *__restrict__ h,
+                                                  double sign, double2 *w, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)gridDim.x * RB) {
+    double2 acc = w[t];
+    for (int q = 0; q < nv; ++q) {
+      double2 hq = h[q];
+      hq.x *= sign; hq.y *= sign;
+      cfma(acc, V[(size_t)q * n + t], hq);
+    }
+    w[t] = acc;
+  }
+}
+
+// per-source ||x_k||^2 partials: grid (RG/8, K)
+__global__ __launch_bounds__(RB) void k_src_norm_partial(const double2 *__restrict__ x, int64_t n_per, double *partial) {
+  __shared__ double lds[RB / 64];
+  const int k = blockIdx.y;
+  const int nb = gridDim.x;
+  double v[1] = {0.0};
+  const double2 *xk = x + (size_t)k * n_per;
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n_per; t += (int64_t)nb * RB) {
+    double2 a = xk[t];
+    v[0] += a.x * a.x + a.y * a.y;
+  }
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) partial[(size_t)k * nb + blockIdx.x] = v[0];
+}
+__global__ void k_src_norm_finish(const double *__restrict__ partial, int nb, int K, double *out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(size_t)k * nb + b];
+  out[k] = sqrt(s);
+}
+
+}  // namespace
+
+#define LAUNCH_CHECK()                                                              \
+  do {                                                                              \
+    hipError_t e_ = hipGetLastError();                                              \
+    if (e_ != hipSuccess) {                                                         \
+      set_error(std::string("kernel launch failed: ") + hipGetErrorString(e_));     \
+      return KF_EHIP;                                                               \
+    }                                                                               \
+  } while (0)
+
+// p->red must hold RG * 2 * (max vectors) doubles
+kf_status dot_c128(kf_problem *p, const double2 *a, const double2 *b, int64_t n, double2 *out_dev) {
+  ProfScope ps(p, PROF_REDUCE);
+  hipLaunchKernelGGL(k_dot_partial, dim3(RG), dim3(RB), 0, p->stream, a, b, n, p->red);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2, 2, 0, (double *)out_dev);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev) {
+  ProfScope ps(p, PROF_REDUCE);
+  hipLaunchKernelGGL(k_norm2_partial, dim3(RG), dim3(RB), 0, p->stream, a, n, p->red);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 1, 1, 1, out_dev);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev) {
+  ProfScope ps(p, PROF_ORTH);
+  int stride = 2 * nv;
+  for (int q0 = 0; q0 < nv; q0 += MDOT) {
+    hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, p->red, stride);
+    LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w,
+                         int64_t n) {
+  ProfScope ps(p, PROF_ORTH);
+  int64_t b = (n + RB - 1) / RB;
+  unsigned grid = (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+  hipLaunchKernelGGL(k_multiaxpy, dim3(grid), dim3(RB), 0, p->stream, V, nv, h_dev, sign, w, n);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status per_source_norms(kf_problem *p, const double2 *x, int64_t n_per, int K, double *out_host) {
+  ProfScope ps(p, PROF_REDUCE);
+  const int nb = 64;
+  hipLaunchKernelGGL(k_src_norm_partial, dim3(nb, K), dim3(RB), 0, p->stream, x, n_per, p->red);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_src_norm_finish, dim3((K + 63) / 64), dim3(64), 0, p->stream, p->red, nb, K, p->red_out);
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(out_host, p->red_out, sizeof(double) * K, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return KF_OK;
+}
+
+namespace {
+
+// Column j of the Hessenberg matrix from the two Gram-Schmidt passes, previous
+// Givens rotations applied, a new rotation annihilating H[j+1][j], and the
+// least-squares right-hand side g updated; resid = |g[j+1]| is the GMRES
+// residual norm estimate.  H is (m+1) x m column-major.
+__global__ void k_arnoldi_finish(int j, int m, const double2 *h1, const double2 *h2, const double *nrm, double2 *H,
+                                 double2 *cs, double2 *sn, double2 *g, double *resid) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2 *col = H + (size_t)j * (m + 1);
+  for (int i = 0; i <= j; ++i) col[i] = cadd(h1[i], h2 ? h2[i] : make_double2(0.0, 0.0));
+  col[j + 1] = make_double2(nrm[0], 0.0);
+  for (int i = 0; i < j; ++i) {
+    double2 a = col[i], b = col[i + 1];
+    double c = cs[i].x;
+    double2 s = sn[i];
+    col[i] = cadd(cscale(a, c), cmul(s, b));
+    col[i + 1] = csub(cscale(b, c), cmulc(s, a));
+  }
+  double2 a = col[j], b = col[j + 1];
+  double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
+  double r = sqrt(na * na + nb * nb);
+  double c;
+  double2 s;
+  if (r == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
+  else if (na == 0.0) { c = 0.0; s = make_double2(1.0, 0.0); }
+  else {
+    c = na / r;
+    double2 ph = cscale(a, 1.0 / na);          // a / |a|
+    s = cscale(cmul(ph, cconj(b)), 1.0 / r);   // (a/|a|) conj(b) / r
+  }
+  cs[j] = make_double2(c, 0.0);
+  sn[j] = s;
+  col[j] = cadd(cscale(a, c), cmul(s, b));
+  col[j + 1] = make_double2(0.0, 0.0);
+  double2 gj = g[j];
+  g[j] = cscale(gj, c);
+  g[j + 1] = csub(make_double2(0.0, 0.0), cmulc(s, gj));
+  resid[0] = sqrt(cabs2(g[j + 1]));
+}
+
+__global__ void k_backsolve(int nj, int m, const double2 *H, const double2 *g, double2 *y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = nj - 1; i >= 0; --i) {
+    double2 acc = g[i];
+    for (int l = i + 1; l < nj; ++l) acc = csub(acc, cmul(H[(size_t)l * (m + 1) + i], y[l]));
+    y[i] = cdiv(acc, H[(size_t)i * (m + 1) + i]);
+  }
+}
+
+__global__ void k_set_g0(int m, const double *beta, double2 *g) {
+  int t = threadIdx.x;
+  for (int i = t; i <= m; i += blockDim.x) g[i] = make_double2(i == 0 ? beta[0] : 0.0, 0.0);
+}
+
+__global__ void k_scale_inv(int64_t n, const double *nrm, const double2 *x, double2 *y) {
+  double s = nrm[0] > 0.0 ? 1.0 / nrm[0] : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    y[t] = cscale(x[t], s);
+}
+
+__global__ void k_imag(int64_t n, const double2 *x, double2 *y) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    y[t] = make_double2(0.0, x[t].y);
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+kf_status arnoldi_finish(kf_problem *p, int j, int m, const double2 *h1, const double2 *h2, const double *nrm,
+                         double2 *H, double2 *cs, double2 *sn, double2 *g, double *resid) {
+  ProfScope ps(p, PROF_ORTH);
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, p->stream, j, m, h1, h2, nrm, H, cs, sn, g, resid);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status hess_backsolve(kf_problem *p, int nj, int m, const double2 *H, const double2 *g, double2 *y) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, p->stream, nj, m, H, g, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status set_g0(kf_problem *p, int m, const double *beta, double2 *g) {
+  hipLaunchKernelGGL(k_set_g0, dim3(1), dim3(256), 0, p->stream, m, beta, g);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status scale_inv(kf_problem *p, int64_t n, const double *nrm, const double2 *x, double2 *y) {
+  ProfScope ps(p, PROF_ORTH);
+  hipLaunchKernelGGL(k_scale_inv, dim3(grid_for(n)), dim3(256), 0, p->stream, n, nrm, x, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status imag_part(kf_problem *p, int64_t n, const double2 *x, double2 *y) {
+  hipLaunchKernelGGL(k_imag, dim3(grid_for(n)), dim3(256), 0, p->stream, n, x, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}

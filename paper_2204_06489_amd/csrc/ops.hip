@@ -1,0 +1,383 @@
+// Field kernels of the full-space Gauss-Newton step on gfx950 (wave64).
+//
+// Layout: fields [K][nz][nx] (x fastest), control [nzc][nxc] on the core nodes,
+// packed KKT vectors [du (K*Nu) | ds (Ng) | lambda (K*Nu)].
+// All kernels are memory-bound stencil / elementwise sweeps; none is a dense
+// contraction, so none uses MFMA.
+#include "common.h"
+
+#include <cmath>
+
+namespace {
+
+constexpr int BX = 64;   // one wavefront across x
+constexpr int BY = 4;    // four wavefronts down z
+
+// ---------------------------------------------------------------------------
+// PML stretch factors (Section 2; quadratic profile with design reflection r0)
+// ---------------------------------------------------------------------------
+__global__ void k_stretch(int n, double h, int npml, double omega, double r0, double cref,
+                          double2 *fn, double2 *ifh) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > n) return;
+  double width = npml * h;
+  auto sigma = [&](double x) {
+    if (npml == 0) return 0.0;
+    double smax = 3.0 * cref / (2.0 * width) * log(1.0 / r0);
+    double d = fmax(fmax(npml * h - x, x - (n - 1 - npml) * h), 0.0);
+    return smax * (d / width) * (d / width);
+  };
+  if (t < n) fn[t] = make_double2(1.0, sigma(t * h) / omega);
+  // face t sits at (t - 1/2) h
+  double2 f = make_double2(1.0, sigma((t - 0.5) * h) / omega);
+  ifh[t] = cdiv(make_double2(1.0, 0.0), f);
+}
+
+// ---------------------------------------------------------------------------
+// y_k = A x_k  (or A^H x_k = conj-coefficient stencil, A being complex symmetric)
+// ---------------------------------------------------------------------------
+template <typename R, bool ADJ>
+__global__ __launch_bounds__(BX *BY) void k_stencil(Grid g, int K, const cplx<R> *__restrict__ x,
+                                                     cplx<R> *__restrict__ y) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || j >= g.nz) return;
+  Stencil5 s = stencil_at(g, i, j);
+  if (ADJ) { s.cc = cconj(s.cc); s.cxm = cconj(s.cxm); s.cxp = cconj(s.cxp); s.czm = cconj(s.czm); s.czp = cconj(s.czp); }
+  const cplx<R> cc = ccast<R>(s.cc), cxm = ccast<R>(s.cxm), cxp = ccast<R>(s.cxp),
+                czm = ccast<R>(s.czm), czp = ccast<R>(s.czp);
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t p = (size_t)j * g.nx + i;
+  const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
+  for (int k = blockIdx.z; k < K; k += gridDim.z) {
+    const cplx<R> *xk = x + k * Nu;
+    cplx<R> acc = cmul(cc, xk[p]);
+    if (hxm) cfma(acc, cxm, xk[p - 1]);
+    if (hxp) cfma(acc, cxp, xk[p + 1]);
+    if (hzm) cfma(acc, czm, xk[p - g.nx]);
+    if (hzp) cfma(acc, czp, xk[p + g.nx]);
+    y[k * Nu + p] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused KKT matvec (eq. KKT):  for every node and every source k
+//   y_u,k   = A^H lambda_k                      (F_k du_k is added by k_kkt_F)
+//   y_lam,k = A du_k - omega^2 u_k (E ds)
+//   y_s     = eps ds - omega^2 sum_k E^T (conj(u_k) lambda_k)
+// One thread owns one node and loops over all sources, so the sum over k is a
+// register accumulator (no atomics, fixed order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BX *BY) void k_kkt_apply(Grid g, int K, int nxc, double eps,
+                                                       const double2 *__restrict__ xi,
+                                                       const double2 *__restrict__ un,
+                                                       double2 *__restrict__ y) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || j >= g.nz) return;
+  const Stencil5 s = stencil_at(g, i, j);
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const int nzc = g.nz - 2 * g.npml;
+  const size_t Ng = (size_t)nxc * nzc;
+  const size_t p = (size_t)j * g.nx + i;
+  const bool core = i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
+  const size_t c = core ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
+  const double2 *du = xi;
+  const double2 *dsv = xi + (size_t)K * Nu;
+  const double2 *lam = dsv + Ng;
+  double2 *yu = y;
+  double2 *ys = y + (size_t)K * Nu;
+  double2 *yl = ys + Ng;
+  const double w2 = g.omega * g.omega;
+  const double2 ds = core ? dsv[c] : make_double2(0.0, 0.0);
+  const double2 w2ds = cscale(ds, w2);
+  const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < K; ++k) {
+    const size_t o = (size_t)k * Nu + p;
+    const double2 l0 = lam[o], d0 = du[o], u = un[o];
+    double2 ah = cmulc(s.cc, l0);     // conj(coefficient) * lambda
+    double2 a = cmul(s.cc, d0);
+    if (hxm) { ah = cadd(ah, cmulc(s.cxm, lam[o - 1])); cfma(a, s.cxm, du[o - 1]); }
+    if (hxp) { ah = cadd(ah, cmulc(s.cxp, lam[o + 1])); cfma(a, s.cxp, du[o + 1]); }
+    if (hzm) { ah = cadd(ah, cmulc(s.czm, lam[o - g.nx])); cfma(a, s.czm, du[o - g.nx]); }
+    if (hzp) { ah = cadd(ah, cmulc(s.czp, lam[o + g.nx])); cfma(a, s.czp, du[o + g.nx]); }
+    yu[o] = ah;
+    yl[o] = csub(a, cmul(u, w2ds));
+    acc = cadd(acc, cmulc(u, l0));
+  }
+  if (core) ys[c] = csub(cscale(ds, eps), cscale(acc, w2));
+}
+
+// y_u,k(node) += (sum of W_k^2 over the receivers at that node) du_k(node)
+__global__ void k_kkt_F(int K, int nru, const int32_t *__restrict__ rnode, const double *__restrict__ wsq,
+                        size_t Nu, const double2 *__restrict__ du, double2 *__restrict__ yu) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * nru) return;
+  int k = t / nru, u = t % nru;
+  size_t o = (size_t)k * Nu + rnode[u];
+  double2 v = yu[o];
+  cfma(v, make_double2(wsq[t], 0.0), du[o]);
+  yu[o] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner stage 2 (eq. precond, middle row) fused with the right-hand side
+// of stage 3:
+//   z_s   = (y_s + omega^2 sum_k E^T (conj(u_k) z_lam,k)) / eps
+//   rhs_k = y_lam,k + omega^2 u_k (E z_s)            -> written into z_u,k
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BX *BY) void k_precond_stage2(Grid g, int K, int nxc, double eps,
+                                                            const double2 *__restrict__ y,
+                                                            const double2 *__restrict__ un,
+                                                            double2 *__restrict__ z) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || j >= g.nz) return;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const int nzc = g.nz - 2 * g.npml;
+  const size_t Ng = (size_t)nxc * nzc;
+  const size_t p = (size_t)j * g.nx + i;
+  const bool core = i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
+  const size_t c = core ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
+  const double2 *ys = y + (size_t)K * Nu;
+  const double2 *yl = ys + Ng;
+  double2 *zu = z;
+  double2 *zs = z + (size_t)K * Nu;
+  const double2 *zl = zs + Ng;
+  const double w2 = g.omega * g.omega;
+  double2 s = make_double2(0.0, 0.0);
+  if (core) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = 0; k < K; ++k) {
+      size_t o = (size_t)k * Nu + p;
+      acc = cadd(acc, cmulc(un[o], zl[o]));
+    }
+    s = cscale(cadd(ys[c], cscale(acc, w2)), 1.0 / eps);
+    zs[c] = s;
+  }
+  const double2 w2s = cscale(s, w2);
+  for (int k = 0; k < K; ++k) {
+    size_t o = (size_t)k * Nu + p;
+    zu[o] = cadd(yl[o], cmul(un[o], w2s));
+  }
+}
+
+// f_k = e_src_k / h^2
+__global__ void k_sources(int K, size_t Nu, const int32_t *__restrict__ src, double val, double2 *f) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)K * Nu) return;
+  int k = (int)(t / Nu);
+  size_t p = t % Nu;
+  f[t] = make_double2(p == (size_t)src[k] ? val : 0.0, 0.0);
+}
+
+// r_k = d_k - Q u_k,  wr = W r  (per receiver)
+__global__ void k_residual(int K, int nrec, size_t Nu, const int32_t *__restrict__ rec,
+                           const double *__restrict__ w, const double2 *__restrict__ d,
+                           const double2 *__restrict__ u, double2 *r, double2 *wr) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * nrec) return;
+  int k = t / nrec, q = t % nrec;
+  double2 v = csub(d[t], u[(size_t)k * Nu + rec[q]]);
+  r[t] = v;
+  wr[t] = cscale(v, w[t]);
+}
+
+// b_u,k(node) = sum over receivers at the node of W_k^2 r_k   (Q^T W^T W r, eq. KKT)
+__global__ void k_rhs_u(int K, int nru, int nrec, size_t Nu, const int32_t *__restrict__ rnode,
+                        const int32_t *__restrict__ rptr, const int32_t *__restrict__ rlist,
+                        const double *__restrict__ w, const double2 *__restrict__ r, double2 *bu) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * nru) return;
+  int k = t / nru, u = t % nru;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int e = rptr[u]; e < rptr[u + 1]; ++e) {
+    int q = rlist[e];
+    double ww = w[k * nrec + q];
+    acc = cadd(acc, cscale(r[k * nrec + q], ww * ww));
+  }
+  bu[(size_t)k * Nu + rnode[u]] = acc;
+}
+
+// b_s = -eps s_n on the control nodes
+__global__ void k_rhs_s(int nx, int npml, int nxc, int nzc, double eps, const double *__restrict__ gamma,
+                        double2 *bs) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nxc * nzc) return;
+  int ic = t % nxc, jc = t / nxc;
+  bs[t] = make_double2(-eps * gamma[(size_t)(jc + npml) * nx + ic + npml], 0.0);
+}
+
+// gamma_core += Re(ds)   (s_{n+1} = s_n + ds, Section 3)
+__global__ void k_update_gamma(int nx, int npml, int nxc, int nzc, const double2 *__restrict__ ds,
+                               double *gamma) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nxc * nzc) return;
+  int ic = t % nxc, jc = t / nxc;
+  gamma[(size_t)(jc + npml) * nx + ic + npml] += ds[t].x;
+}
+
+// grad[j][i] = omega^2 sum_k Re(conj(mu_k) X_i Z_j u_k)
+template <typename C>
+__global__ __launch_bounds__(BX *BY) void k_grad_gamma(Grid g, int K, const C *__restrict__ u,
+                                                        const C *__restrict__ mu, double *grad) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || j >= g.nz) return;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t p = (size_t)j * g.nx + i;
+  const double2 xz = cmul(g.xn[i], g.zn[j]);
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    C a = u[k * Nu + p], m = mu[k * Nu + p];
+    double2 ud = make_double2((double)a.x, (double)a.y);
+    double2 md = make_double2((double)m.x, (double)m.y);
+    acc += cmulc(md, cmul(xz, ud)).x;
+  }
+  grad[p] = g.omega * g.omega * acc;
+}
+
+__global__ void k_axpy(int64_t n, double2 a, const double2 *__restrict__ x, double2 *y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t < n; t += (int64_t)gridDim.x * blockDim.x) y[t] = cadd(y[t], cmul(a, x[t]));
+}
+__global__ void k_c128_to_c64(int64_t n, const double2 *__restrict__ x, float2 *y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t < n; t += (int64_t)gridDim.x * blockDim.x) y[t] = make_float2((float)x[t].x, (float)x[t].y);
+}
+__global__ void k_c64_to_c128(int64_t n, const float2 *__restrict__ x, double2 *y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t < n; t += (int64_t)gridDim.x * blockDim.x) y[t] = make_double2(x[t].x, x[t].y);
+}
+
+inline dim3 field_grid(const kf_problem *p, int zdim = 1) {
+  return dim3((p->nx + BX - 1) / BX, (p->nz + BY - 1) / BY, zdim);
+}
+inline unsigned blocks_for(int64_t n, int bs = 256) {
+  int64_t b = (n + bs - 1) / bs;
+  return (unsigned)(b < 1 ? 1 : (b > 65535 * 16 ? 65535 * 16 : b));
+}
+
+}  // namespace
+
+#define LAUNCH_CHECK()                                                              \
+  do {                                                                              \
+    hipError_t e_ = hipGetLastError();                                              \
+    if (e_ != hipSuccess) {                                                         \
+      set_error(std::string("kernel launch failed: ") + hipGetErrorString(e_));     \
+      return KF_EHIP;                                                               \
+    }                                                                               \
+  } while (0)
+
+kf_status launch_pml(kf_problem *p, const kf_desc &d) {
+  hipLaunchKernelGGL(k_stretch, dim3((p->nx + 256) / 256), dim3(256), 0, p->stream, p->nx, p->h, p->npml,
+                     p->omega, d.pml_r0, d.pml_cref, p->xn, p->ixh);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_stretch, dim3((p->nz + 256) / 256), dim3(256), 0, p->stream, p->nz, p->h, p->npml,
+                     p->omega, d.pml_r0, d.pml_cref, p->zn, p->izh);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+template <typename R>
+kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *y) {
+  ProfScope ps(p, PROF_STENCIL);
+  int zdim = p->K < 64 ? p->K : 64;
+  if (adjoint)
+    hipLaunchKernelGGL((k_stencil<R, true>), field_grid(p, zdim), dim3(BX, BY), 0, p->stream, p->grid(), p->K, x, y);
+  else
+    hipLaunchKernelGGL((k_stencil<R, false>), field_grid(p, zdim), dim3(BX, BY), 0, p->stream, p->grid(), p->K, x, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+template kf_status launch_stencil<double>(kf_problem *, int, const double2 *, double2 *);
+template kf_status launch_stencil<float>(kf_problem *, int, const float2 *, float2 *);
+
+kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
+  ProfScope ps(p, PROF_KKT);
+  hipLaunchKernelGGL(k_kkt_apply, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K, p->nxc, p->eps,
+                     xi, p->u_n, y);
+  LAUNCH_CHECK();
+  int n = p->K * p->nru;
+  hipLaunchKernelGGL(k_kkt_F, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->d_rnode, p->d_wsq,
+                     (size_t)p->Nu, xi, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_precond_stage2(kf_problem *p, const double2 *y, double2 *z) {
+  ProfScope ps(p, PROF_PRECOND);
+  hipLaunchKernelGGL(k_precond_stage2, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K, p->nxc,
+                     p->eps, y, p->u_n, z);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_sources(kf_problem *p, double2 *f) {
+  int64_t n = (int64_t)p->K * p->Nu;
+  hipLaunchKernelGGL(k_sources, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p->stream, p->K, (size_t)p->Nu,
+                     p->d_src, 1.0 / (p->h * p->h), f);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+// residual buffers live in p->red_out-adjacent scratch owned by the caller (api.hip)
+kf_status launch_residual(kf_problem *p, const double2 *d_obs, const double2 *u, double2 *r, double2 *wr) {
+  int n = p->K * p->nrec;
+  hipLaunchKernelGGL(k_residual, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nrec, (size_t)p->Nu,
+                     p->d_rec, p->d_w, d_obs, u, r, wr);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_rhs(kf_problem *p, const double2 *r, const int32_t *rptr, const int32_t *rlist, double2 *b,
+                     int reg_on_update) {
+  HIP_TRY(hipMemsetAsync(b, 0, sizeof(double2) * p->Nxi, p->stream));
+  int n = p->K * p->nru;
+  hipLaunchKernelGGL(k_rhs_u, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->nrec,
+                     (size_t)p->Nu, p->d_rnode, rptr, rlist, p->d_w, r, b);
+  LAUNCH_CHECK();
+  if (!reg_on_update) {
+    int ng = (int)p->Ng;
+    hipLaunchKernelGGL(k_rhs_s, dim3((ng + 255) / 256), dim3(256), 0, p->stream, p->nx, p->npml, p->nxc, p->nzc,
+                       p->eps, p->gamma, b + (size_t)p->K * p->Nu);
+    LAUNCH_CHECK();
+  }
+  return KF_OK;
+}
+
+kf_status launch_update_gamma(kf_problem *p, const double2 *ds, double *target) {
+  int ng = (int)p->Ng;
+  hipLaunchKernelGGL(k_update_gamma, dim3((ng + 255) / 256), dim3(256), 0, p->stream, p->nx, p->npml, p->nxc,
+                     p->nzc, ds, target);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_grad_gamma(kf_problem *p, const void *u, const void *mu, int c64, double *grad) {
+  if (c64)
+    hipLaunchKernelGGL(k_grad_gamma<float2>, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K,
+                       (const float2 *)u, (const float2 *)mu, grad);
+  else
+    hipLaunchKernelGGL(k_grad_gamma<double2>, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K,
+                       (const double2 *)u, (const double2 *)mu, grad);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_axpy_field(kf_problem *p, int64_t n, double2 a, const double2 *x, double2 *y) {
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(256), 0, p->stream, n, a, x, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status launch_copy_c128_to_c64(kf_problem *p, int64_t n, const double2 *x, float2 *y) {
+  hipLaunchKernelGGL(k_c128_to_c64, dim3(blocks_for(n)), dim3(256), 0, p->stream, n, x, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status launch_copy_c64_to_c128(kf_problem *p, int64_t n, const float2 *x, double2 *y) {
+  hipLaunchKernelGGL(k_c64_to_c128, dim3(blocks_for(n)), dim3(256), 0, p->stream, n, x, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
