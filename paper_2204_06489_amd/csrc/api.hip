@@ -141,12 +141,12 @@ static void free_all(kf_problem *p) {
 // ---------------------------------------------------------------------------
 // validation (no HIP calls)
 // ---------------------------------------------------------------------------
-static const int MAX_NZ = 1024;  // column block size held by the factorisation kernels
+static const int MAX_NZ = 512;   // column block size held by the factorisation kernels
 
 static kf_status validate_desc(const kf_desc *d) {
   if (!d) return fail(KF_EINVAL, "desc is NULL");
   if (d->nx < 3 || d->nz < 3) return fail(KF_ESHAPE, "nx and nz must be >= 3");
-  if (d->nz > MAX_NZ) return fail(KF_ESHAPE, "nz must be <= 1024 (column block of the factorisation)");
+  if (d->nz > MAX_NZ) return fail(KF_ESHAPE, "nz must be <= 512 (column block of the factorisation)");
   if ((int64_t)d->nx * d->nz > (int64_t)1 << 31) return fail(KF_ESHAPE, "grid too large");
   if (!(d->h > 0.0) || !std::isfinite(d->h)) return fail(KF_EINVAL, "h must be > 0");
   if (d->npml < 0 || 2 * d->npml >= d->nx || 2 * d->npml >= d->nz)
@@ -240,7 +240,7 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   ALLOC(p->d_r, K * p->nrec); ALLOC(p->d_wr, K * p->nrec);
   ALLOC(p->u_n, K * Nu);
   ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m);
-  ALLOC(p->fac_work, 2 * m * m);
+  ALLOC(p->fac_work, 2 * (m * m + 16 * m));
   ALLOC(p->xmid, K * m); ALLOC(p->xmid32, K * m);
   ALLOC(p->vec_a, K * Nu); ALLOC(p->vec_b, K * Nu); ALLOC(p->vec_c, K * Nu); ALLOC(p->vec_d, K * Nu);
   ALLOC(p->red, (size_t)1024 * 2 * 256 + K * 64);

@@ -21,87 +21,206 @@
 
 namespace {
 
-constexpr int FAC_THREADS = 1024;
-
 // In-place Gauss-Jordan inversion of the row-major m x m matrix S (global memory),
-// then writes the inverse transposed into Tt.  Called by a whole workgroup.
-__device__ void gj_invert_store(double2 *S, int m, double2 *Tt, double2 *prow, double2 *fcol, int *piv,
-                                double *red_v, int *red_i) {
+// blocked by NB-column panels, then the inverse written transposed into Tt.  Called
+// by a whole workgroup.
+//
+// For each panel the classical in-place Gauss-Jordan steps (partial pivoting over
+// all rows, pivot row scaled, pivot column eliminated from every other row, the
+// eliminated column replaced by the accumulated transform) run on the m x NB panel
+// in LDS.  Their combined effect on every other column x is
+//     x  <-  (P x with the panel's pivot rows zeroed) + Pan (P x)[pivot rows],
+// P the panel's row interchanges and Pan the finished panel, which is one rank-NB
+// update of the matrix (register tiles of TR x TC entries per thread).  After the
+// last panel the row interchanges are undone as column interchanges.
+constexpr int TR = 4, TC = 4;   // update tile per thread
+constexpr int NB_MAX = 16;
+
+// orders the LDS accesses of the lanes of one wavefront (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NB, int RMAX>
+__device__ __forceinline__ void gj_invert_store(double2 *S, int m, double2 *Tt, double2 *pan /*[m][NB]*/,
+                                                double2 *x1 /*[NB][m]*/, double2 *rowbuf /*[2][NB]*/, int *piv,
+                                                int *perm /*[m]*/, double2 *tmp /*[NB][m] global*/) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = 0; k < m; ++k) {
-    // pivot search: max |S[j][k]| over j >= k (ties -> smallest j)
-    double best = -1.0; int bi = k;
-    for (int j = k + tid; j < m; j += nt) {
-      double a = cabs2(S[(size_t)j * m + k]);
-      if (a > best) { best = a; bi = j; }
-    }
-    red_v[tid] = best; red_i[tid] = bi;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int K0 = 0; K0 < m; K0 += NB) {
+    const int nb = min(NB, m - K0);
+    for (int r = tid; r < m; r += nt) perm[r] = r;
     __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        double a = red_v[tid + s]; int ai = red_i[tid + s];
-        if (a > red_v[tid] || (a == red_v[tid] && ai < red_i[tid])) { red_v[tid] = a; red_i[tid] = ai; }
+    // Gauss-Jordan on the panel by wavefront 0, the panel held in registers: lane l
+    // owns rows l, l + 64, ...  A pivot step is a shuffle reduction for the pivot, a
+    // two-row exchange through LDS and register arithmetic; no workgroup barrier.
+    if (wave == 0) {
+      double2 v[RMAX][NB];
+#pragma unroll
+      for (int t = 0; t < RMAX; ++t) {
+        const int r = lane + 64 * t;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v[t][c] = (r < m && c < nb) ? S[(size_t)r * m + K0 + c] : make_double2(0.0, 0.0);
       }
-      __syncthreads();
-    }
-    const int pr = red_i[0];
-    if (tid == 0) piv[k] = pr;
-    if (pr != k) {
-      for (int l = tid; l < m; l += nt) {
-        double2 a = S[(size_t)k * m + l];
-        S[(size_t)k * m + l] = S[(size_t)pr * m + l];
-        S[(size_t)pr * m + l] = a;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (q < nb) {
+          const int k = K0 + q;
+          double best = -1.0;
+          int bi = m;
+#pragma unroll
+          for (int t = 0; t < RMAX; ++t) {
+            const int r = lane + 64 * t;
+            if (r >= k && r < m) {
+              double a = cabs2(v[t][q]);
+              if (a > best) { best = a; bi = r; }
+            }
+          }
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            double ob = __shfl_xor(best, o, 64);
+            int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+          }
+          const int pr = bi;
+          // rows k and pr to LDS (pr first)
+#pragma unroll
+          for (int t = 0; t < RMAX; ++t) {
+            const int r = lane + 64 * t;
+            if (r == pr)
+#pragma unroll
+              for (int c = 0; c < NB; ++c) rowbuf[c] = v[t][c];
+            if (r == k)
+#pragma unroll
+              for (int c = 0; c < NB; ++c) rowbuf[NB + c] = v[t][c];
+          }
+          if (lane == 0) {
+            piv[k] = pr;
+            int a = perm[k]; perm[k] = perm[pr]; perm[pr] = a;
+          }
+          wave_sync();
+          double2 prow[NB];
+#pragma unroll
+          for (int c = 0; c < NB; ++c) prow[c] = rowbuf[c];
+          // the new row k is the old row pr, scaled; the pivot entry becomes 1 / pivot
+          const double2 d = cdiv(make_double2(1.0, 0.0), prow[q]);
+#pragma unroll
+          for (int c = 0; c < NB; ++c) prow[c] = (c == q) ? d : cmul(prow[c], d);
+#pragma unroll
+          for (int t = 0; t < RMAX; ++t) {
+            const int r = lane + 64 * t;
+            if (r == k) {
+#pragma unroll
+              for (int c = 0; c < NB; ++c) v[t][c] = prow[c];
+            } else {
+              if (r == pr)   // the old row k moves to pr, then is eliminated like every other row
+#pragma unroll
+                for (int c = 0; c < NB; ++c) v[t][c] = rowbuf[NB + c];
+              const double2 f = v[t][q];
+#pragma unroll
+              for (int c = 0; c < NB; ++c)
+                v[t][c] = csub(c == q ? make_double2(0.0, 0.0) : v[t][c], cmul(f, prow[c]));
+            }
+          }
+          wave_sync();   // rowbuf is rewritten by the next pivot step
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RMAX; ++t) {
+        const int r = lane + 64 * t;
+        if (r < m)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) pan[r * NB + c] = v[t][c];
       }
     }
     __syncthreads();
-    const double2 d = cdiv(make_double2(1.0, 0.0), S[(size_t)k * m + k]);
-    for (int l = tid; l < m; l += nt) {
-      double2 v = (l == k) ? d : cmul(S[(size_t)k * m + l], d);
-      prow[l] = v;
-      fcol[l] = (l == k) ? make_double2(0.0, 0.0) : S[(size_t)l * m + k];
+    // The panel's row interchanges on the other columns, as one permutation: the new
+    // pivot-block rows go to x1, the old pivot-block rows are staged in tmp, and every
+    // row outside the block that took part in an interchange receives the old
+    // pivot-block row the interchanges moved there (perm[r] is its origin).
+    for (int e = tid; e < nb * m; e += nt) {
+      const int q = e / m, c = e % m;
+      x1[e] = S[(size_t)perm[K0 + q] * m + c];
+      tmp[e] = S[(size_t)(K0 + q) * m + c];
     }
     __syncthreads();
-    for (int l = tid; l < m; l += nt) S[(size_t)k * m + l] = prow[l];
-    for (size_t e = tid; e < (size_t)m * m; e += nt) {
-      int j = (int)(e / m), l = (int)(e % m);
-      if (j == k) continue;
-      double2 a = (l == k) ? make_double2(0.0, 0.0) : S[e];
-      S[e] = csub(a, cmul(fcol[j], prow[l]));
+    for (int e = tid; e < nb * m; e += nt) {
+      const int q = e / m, c = e % m;
+      const int r = piv[K0 + q];
+      if (r >= K0 + nb && perm[r] != r && !(c >= K0 && c < K0 + nb)) S[(size_t)r * m + c] = tmp[(size_t)(perm[r] - K0) * m + c];
+    }
+    __syncthreads();
+    // rank-nb update of every column outside the panel (register tiles TR x TC)
+    const int ntr = (m + TR - 1) / TR, ntc = (m + TC - 1) / TC;
+    for (int t = tid; t < ntr * ntc; t += nt) {
+      const int r0 = (t / ntc) * TR, c0 = (t % ntc) * TC;
+      double2 acc[TR][TC];
+#pragma unroll
+      for (int a = 0; a < TR; ++a)
+#pragma unroll
+        for (int b = 0; b < TC; ++b) {
+          int r = r0 + a, c = c0 + b;
+          bool in = r < m && c < m && !(r >= K0 && r < K0 + nb) && !(c >= K0 && c < K0 + nb);
+          acc[a][b] = in ? S[(size_t)r * m + c] : make_double2(0.0, 0.0);
+        }
+      for (int q = 0; q < nb; ++q) {
+        double2 pr[TR], xc[TC];
+#pragma unroll
+        for (int a = 0; a < TR; ++a) pr[a] = (r0 + a < m) ? pan[(r0 + a) * NB + q] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int b = 0; b < TC; ++b) xc[b] = (c0 + b < m) ? x1[q * m + c0 + b] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < TR; ++a)
+#pragma unroll
+          for (int b = 0; b < TC; ++b) cfma(acc[a][b], pr[a], xc[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < TR; ++a)
+#pragma unroll
+        for (int b = 0; b < TC; ++b) {
+          int r = r0 + a, c = c0 + b;
+          if (r < m && c < m && !(c >= K0 && c < K0 + nb)) S[(size_t)r * m + c] = acc[a][b];
+        }
+    }
+    for (int e = tid; e < m * nb; e += nt) {
+      int r = e / nb, q = e % nb;
+      S[(size_t)r * m + K0 + q] = pan[r * NB + q];
     }
     __syncthreads();
   }
   // undo the row interchanges as column interchanges, in reverse order
   if (tid == 0) {
-    for (int c = 0; c < m; ++c) red_i[c] = c;
+    for (int c = 0; c < m; ++c) perm[c] = c;
     for (int k = m - 1; k >= 0; --k) {
-      int a = red_i[k]; red_i[k] = red_i[piv[k]]; red_i[piv[k]] = a;
+      int a = perm[k]; perm[k] = perm[piv[k]]; perm[piv[k]] = a;
     }
   }
   __syncthreads();
   // Tt[c][j] = Sinv[j][c] = S[j][colsrc[c]]
   for (size_t e = tid; e < (size_t)m * m; e += nt) {
     int c = (int)(e / m), j = (int)(e % m);
-    Tt[e] = S[(size_t)j * m + red_i[c]];
+    Tt[e] = S[(size_t)j * m + perm[c]];
   }
   __syncthreads();
 }
 
 // S = D_i - C_a Tprev C_a (- C_b Tnext C_b), row-major.  ca/cb: column index whose
-// coupling weights scale the correction, or -1 for none.
-__device__ void build_schur(const Grid &g, int m, int i, const double2 *Tprev, int ca, const double2 *Tnext, int cb,
-                            double2 *S) {
+// coupling weights scale the correction, or -1 for none.  cw: LDS scratch [2][m].
+__device__ __forceinline__ void build_schur(const Grid &g, int m, int i, const double2 *Tprev, int ca, const double2 *Tnext, int cb,
+                            double2 *S, double2 *cw) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = tid; j < m; j += nt) {
+    cw[j] = ca >= 0 ? coupling_x(g, ca, j) : make_double2(0.0, 0.0);
+    cw[m + j] = cb >= 0 ? coupling_x(g, cb, j) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
   for (size_t e = tid; e < (size_t)m * m; e += nt) {
     int j = (int)(e / m), l = (int)(e % m);
     double2 v = make_double2(0.0, 0.0);
-    if (ca >= 0) {  // Tprev[j][l] = Tt_prev[l][j]
-      double2 t = Tprev[(size_t)l * m + j];
-      v = csub(v, cmul(cmul(coupling_x(g, ca, j), t), coupling_x(g, ca, l)));
-    }
-    if (cb >= 0) {
-      double2 t = Tnext[(size_t)l * m + j];
-      v = csub(v, cmul(cmul(coupling_x(g, cb, j), t), coupling_x(g, cb, l)));
-    }
+    if (ca >= 0) v = csub(v, cmul(cmul(cw[j], Tprev[(size_t)l * m + j]), cw[l]));   // Tprev[j][l] = Tt[l][j]
+    if (cb >= 0) v = csub(v, cmul(cmul(cw[m + j], Tnext[(size_t)l * m + j]), cw[m + l]));
     S[e] = v;
   }
   __syncthreads();
@@ -116,35 +235,39 @@ __device__ void build_schur(const Grid &g, int m, int i, const double2 *Tprev, i
 }
 
 // blockIdx.x = 0: left sweep over columns 0..mid-1; 1: right sweep over nx-1..mid+1.
-// mode 1: the middle column (one block).
-__global__ __launch_bounds__(FAC_THREADS) void k_blu_factor(Grid g, int mid, int mode, double2 *T, double2 *work) {
+// mode 1: the middle column (one block).  work: per block an m x m matrix and an
+// NB x m staging area.
+template <int NB, int RMAX, int NT>
+__global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, int mode, double2 *T, double2 *work) {
   extern __shared__ unsigned char smem[];
   const int m = g.nz;
-  double2 *prow = (double2 *)smem;
-  double2 *fcol = prow + m;
-  int *piv = (int *)(fcol + m);
-  double *red_v = (double *)(piv + ((m + 1) & ~1));
-  int *red_i = (int *)(red_v + FAC_THREADS);
+  double2 *pan = (double2 *)smem;          // [m][NB]
+  double2 *x1 = pan + (size_t)m * NB;      // [NB][m]
+  double2 *cw = x1 + (size_t)m * NB;       // [2][m]
+  double2 *prow = cw + 2 * (size_t)m;      // [2][NB] row exchange buffer
+  int *piv = (int *)(prow + 2 * NB);       // [m]
+  int *perm = piv + m;                     // [m]
   const size_t mm = (size_t)m * m;
-  double2 *S = work + (size_t)blockIdx.x * mm;
+  double2 *S = work + (size_t)blockIdx.x * (mm + (size_t)NB_MAX * m);
+  double2 *tmp = S + mm;
   if (mode == 0) {
     if (blockIdx.x == 0) {
       for (int i = 0; i < mid; ++i) {
-        build_schur(g, m, i, i > 0 ? T + (size_t)(i - 1) * mm : nullptr, i > 0 ? i : -1, nullptr, -1, S);
-        gj_invert_store(S, m, T + (size_t)i * mm, prow, fcol, piv, red_v, red_i);
+        build_schur(g, m, i, i > 0 ? T + (size_t)(i - 1) * mm : nullptr, i > 0 ? i : -1, nullptr, -1, S, cw);
+        gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, pan, x1, prow, piv, perm, tmp);
       }
     } else {
       for (int i = g.nx - 1; i > mid; --i) {
         bool has = i + 1 < g.nx;
-        build_schur(g, m, i, has ? T + (size_t)(i + 1) * mm : nullptr, has ? i + 1 : -1, nullptr, -1, S);
-        gj_invert_store(S, m, T + (size_t)i * mm, prow, fcol, piv, red_v, red_i);
+        build_schur(g, m, i, has ? T + (size_t)(i + 1) * mm : nullptr, has ? i + 1 : -1, nullptr, -1, S, cw);
+        gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, pan, x1, prow, piv, perm, tmp);
       }
     }
   } else {
     bool hl = mid > 0, hr = mid + 1 < g.nx;
     build_schur(g, m, mid, hl ? T + (size_t)(mid - 1) * mm : nullptr, hl ? mid : -1,
-                hr ? T + (size_t)(mid + 1) * mm : nullptr, hr ? mid + 1 : -1, S);
-    gj_invert_store(S, m, T + (size_t)mid * mm, prow, fcol, piv, red_v, red_i);
+                hr ? T + (size_t)(mid + 1) * mm : nullptr, hr ? mid + 1 : -1, S, cw);
+    gj_invert_store<NB, RMAX>(S, m, T + (size_t)mid * mm, pan, x1, prow, piv, perm, tmp);
   }
 }
 
@@ -157,8 +280,42 @@ template <typename IO> __device__ inline IO from_r(float2 a);
 template <> __device__ inline double2 from_r<double2>(float2 a) { return make_double2(a.x, a.y); }
 template <> __device__ inline float2 from_r<float2>(float2 a) { return a; }
 
+// y[s][j] = sum_l T_i[j][l] w[s][l] for the rows j = threadIdx.x < m.  The l-range is
+// split over the blockDim.y wave groups (more loads in flight per column step); the
+// partial sums meet in LDS and the complete result is valid in threads with
+// threadIdx.y == 0.  Tt is T_i stored transposed, so lanes read consecutive rows.
+template <typename R, int NS>
+__device__ inline void col_matvec(const cplx<R> *__restrict__ Tt, int m, const cplx<R> *w, cplx<R> *part,
+                                  cplx<R> (&acc)[NS]) {
+  using C = cplx<R>;
+  const int j = threadIdx.x, gy = threadIdx.y, G = blockDim.y;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
+  if (j < m) {
+    const int chunk = (m + G - 1) / G;
+    const int l0 = gy * chunk, l1 = min(m, l0 + chunk);
+#pragma unroll 8
+    for (int l = l0; l < l1; ++l) {
+      C t = Tt[(size_t)l * m + j];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) cfma(acc[s], t, w[s * m + l]);
+    }
+  }
+  if (G > 1) {
+    if (gy > 0 && j < m)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) part[((gy - 1) * NS + s) * m + j] = acc[s];
+    __syncthreads();
+    if (gy == 0 && j < m)
+      for (int q = 1; q < G; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = cadd(acc[s], part[((q - 1) * NS + s) * m + j]);
+  }
+}
+
 // Forward sweeps: side 0 computes y_i for i = 0..mid-1, side 1 for i = nx-1..mid+1.
 // T: factors of type cplx<R> ([nx][m][m], transposed); b, x: IO type [K][nz][nx].
+// Block (roundup64(m), G): thread (j, 0) owns row j of every column vector.
 template <typename R, typename IO, bool ADJ, int NS>
 __global__ void k_blu_fwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x) {
   using C = cplx<R>;
@@ -166,46 +323,49 @@ __global__ void k_blu_fwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
   const int m = g.nz;
   C *v = (C *)smem;          // [NS][m] previous y
   C *w = v + NS * m;         // [NS][m] right-hand side of this column
-  const int tid = threadIdx.x, nt = blockDim.x;
+  C *part = w + NS * m;      // [G-1][NS][m] partial sums
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = blockIdx.x * NS;
   const int side = blockIdx.y;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
-  int cnt = side == 0 ? mid : g.nx - 1 - mid;
+  const int cnt = side == 0 ? mid : g.nx - 1 - mid;
+  auto col_of = [&](int step) { return side == 0 ? step : g.nx - 1 - step; };
+  IO bnext[NS];
+  if (owner && cnt > 0)
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (k0 + s < K) bnext[s] = b[(k0 + s) * Nu + (size_t)j * g.nx + col_of(0)];
   for (int step = 0; step < cnt; ++step) {
-    const int i = side == 0 ? step : g.nx - 1 - step;
+    const int i = col_of(step);
     const int cc = side == 0 ? i : i + 1;  // coupling column to the previous block
-    for (int j = tid; j < m; j += nt) {
+    if (owner) {
       C cj = step > 0 ? to_r<R>(coupling_x(g, cc, j)) : mk<R>(0, 0);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        int k = k0 + s;
         C r = mk<R>(0, 0);
-        if (k < K) {
-          r = to_r<R>(b[k * Nu + (size_t)j * g.nx + i]);
+        if (k0 + s < K) {
+          r = to_r<R>(bnext[s]);
           if (ADJ) r = cconj(r);
           if (step > 0) r = csub(r, cmul(cj, v[s * m + j]));
         }
         w[s * m + j] = r;
       }
+      // prefetch the next column's right-hand side while the matvec runs
+      if (step + 1 < cnt)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (k0 + s < K) bnext[s] = b[(k0 + s) * Nu + (size_t)j * g.nx + col_of(step + 1)];
     }
     __syncthreads();
-    const C *Ti = T + (size_t)i * mm;
-    for (int j = tid; j < m; j += nt) {
-      C acc[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
-#pragma unroll 4
-      for (int l = 0; l < m; ++l) {
-        C t = Ti[(size_t)l * m + j];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) cfma(acc[s], t, w[s * m + l]);
-      }
+    C acc[NS];
+    col_matvec<R, NS>(T + (size_t)i * mm, m, w, part, acc);
+    if (owner) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         v[s * m + j] = acc[s];
-        int k = k0 + s;
-        if (k < K) x[k * Nu + (size_t)j * g.nx + i] = from_r<IO>(acc[s]);
+        if (k0 + s < K) x[(k0 + s) * Nu + (size_t)j * g.nx + i] = from_r<IO>(acc[s]);
       }
     }
     __syncthreads();
@@ -220,11 +380,13 @@ __global__ void k_blu_mid(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
   extern __shared__ unsigned char smem[];
   const int m = g.nz;
   C *w = (C *)smem;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  C *part = w + 2 * NS * m;
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = blockIdx.x * NS;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
-  for (int j = tid; j < m; j += nt) {
+  if (owner) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       int k = k0 + s;
@@ -240,17 +402,9 @@ __global__ void k_blu_mid(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
     }
   }
   __syncthreads();
-  const C *Ti = T + (size_t)mid * mm;
-  for (int j = tid; j < m; j += nt) {
-    C acc[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
-#pragma unroll 4
-    for (int l = 0; l < m; ++l) {
-      C t = Ti[(size_t)l * m + j];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) cfma(acc[s], t, w[s * m + l]);
-    }
+  C acc[NS];
+  col_matvec<R, NS>(T + (size_t)mid * mm, m, w, part, acc);
+  if (owner) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       int k = k0 + s;
@@ -269,47 +423,41 @@ __global__ void k_blu_bwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
   using C = cplx<R>;
   extern __shared__ unsigned char smem[];
   const int m = g.nz;
-  C *w = (C *)smem;  // [NS][m] coupled previous x
-  const int tid = threadIdx.x, nt = blockDim.x;
+  C *w = (C *)smem;          // [NS][m] coupled previous x
+  C *part = w + 2 * NS * m;
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = blockIdx.x * NS;
   const int side = blockIdx.y;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
-  C xr[NS][4];  // rows owned by this thread (m <= 4 * blockDim.x)
-  // start from x_mid
-  for (int j = tid, q = 0; j < m; j += nt, ++q)
+  C xr[NS];
+  if (owner)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) xr[s][q] = (k0 + s < K) ? xmid[(size_t)(k0 + s) * m + j] : mk<R>(0, 0);
-  int cnt = side == 0 ? mid : g.nx - 1 - mid;
+    for (int s = 0; s < NS; ++s) xr[s] = (k0 + s < K) ? xmid[(size_t)(k0 + s) * m + j] : mk<R>(0, 0);
+  const int cnt = side == 0 ? mid : g.nx - 1 - mid;
   for (int step = 0; step < cnt; ++step) {
     const int i = side == 0 ? mid - 1 - step : mid + 1 + step;
     const int cc = side == 0 ? i + 1 : i;
-    for (int j = tid, q = 0; j < m; j += nt, ++q) {
+    IO yv[NS];
+    if (owner) {
       C cj = to_r<R>(coupling_x(g, cc, j));
 #pragma unroll
-      for (int s = 0; s < NS; ++s) w[s * m + j] = cmul(cj, xr[s][q]);
+      for (int s = 0; s < NS; ++s) {
+        w[s * m + j] = cmul(cj, xr[s]);
+        if (k0 + s < K) yv[s] = x[(k0 + s) * Nu + (size_t)j * g.nx + i];   // y_i, used after the matvec
+      }
     }
     __syncthreads();
-    const C *Ti = T + (size_t)i * mm;
-    for (int j = tid, q = 0; j < m; j += nt, ++q) {
-      C acc[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
-#pragma unroll 4
-      for (int l = 0; l < m; ++l) {
-        C t = Ti[(size_t)l * m + j];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) cfma(acc[s], t, w[s * m + l]);
-      }
+    C acc[NS];
+    col_matvec<R, NS>(T + (size_t)i * mm, m, w, part, acc);
+    if (owner) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        int k = k0 + s;
-        if (k < K) {
-          size_t o = k * Nu + (size_t)j * g.nx + i;
-          C y = to_r<R>(x[o]);
-          C xi = csub(y, acc[s]);
-          xr[s][q] = xi;
-          x[o] = from_r<IO>(ADJ ? cconj(xi) : xi);
+        if (k0 + s < K) {
+          C xi = csub(to_r<R>(yv[s]), acc[s]);
+          xr[s] = xi;
+          x[(k0 + s) * Nu + (size_t)j * g.nx + i] = from_r<IO>(ADJ ? cconj(xi) : xi);
         }
       }
     }
@@ -317,9 +465,12 @@ __global__ void k_blu_bwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
   }
 }
 
-inline int sweep_threads(int m) {
-  int t = ((m + 63) / 64) * 64;
-  return t > 512 ? 512 : (t < 64 ? 64 : t);
+// block shape of the sweeps: x covers the rows, y splits each dot product
+inline dim3 sweep_block(int m) {
+  int rj = ((m + 63) / 64) * 64;
+  int gy = 1024 / rj;
+  gy = gy > 4 ? 4 : (gy < 1 ? 1 : gy);
+  return dim3(rj, gy);
 }
 
 }  // namespace
@@ -340,11 +491,23 @@ kf_status blu_factor(kf_problem *p, int which) {
     if (!p->have_T64) {
       ProfScope ps(p, PROF_FACTOR);
       Grid g = p->grid();
-      size_t smem = 2 * m * sizeof(double2) + ((m + 1) & ~1) * sizeof(int) + FAC_THREADS * (sizeof(double) + sizeof(int));
-      hipLaunchKernelGGL(k_blu_factor, dim3(2), dim3(FAC_THREADS), smem, p->stream, g, p->mid, 0, p->T64, p->fac_work);
-      LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_blu_factor, dim3(1), dim3(FAC_THREADS), smem, p->stream, g, p->mid, 1, p->T64, p->fac_work);
-      LAUNCH_CHECK();
+      auto launch = [&](auto kern, int nb, int nthreads) -> kf_status {
+        size_t smem = (2 * (size_t)m * nb + 2 * (size_t)m + 2 * nb) * sizeof(double2) + 2 * (size_t)m * sizeof(int);
+        HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        hipLaunchKernelGGL(kern, dim3(2), dim3(nthreads), smem, p->stream, g, p->mid, 0, p->T64, p->fac_work);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), smem, p->stream, g, p->mid, 1, p->T64, p->fac_work);
+        LAUNCH_CHECK();
+        return KF_OK;
+      };
+      // panel width and rows per lane of the register-resident panel, by column height
+      // (the register-resident panel needs the larger VGPR budget of 256-thread groups
+      //  once a lane owns five or more rows)
+      kf_status st = m <= 128 ? launch(k_blu_factor<8, 2, 512>, 8, 512)
+                   : m <= 192 ? launch(k_blu_factor<8, 3, 512>, 8, 512)
+                   : m <= 320 ? launch(k_blu_factor<8, 5, 256>, 8, 256)
+                              : launch(k_blu_factor<8, 8, 256>, 8, 256);
+      if (st != KF_OK) return st;
       p->have_T64 = true;
     }
   }
@@ -370,13 +533,13 @@ kf_status sweep(kf_problem *p, const cplx<R> *T, const IO *rhs, IO *x, cplx<R> *
   const int m = p->nz;
   Grid g = p->grid();
   int groups = (p->K + NS - 1) / NS;
-  int nt = sweep_threads(m);
-  size_t smem = 2 * NS * m * sizeof(cplx<R>);
-  hipLaunchKernelGGL((k_blu_fwd<R, IO, ADJ, NS>), dim3(groups, 2), dim3(nt), smem, p->stream, g, p->K, p->mid, T, rhs, x);
+  dim3 blk = sweep_block(m);
+  size_t smem = (2 + (blk.y - 1)) * NS * m * sizeof(cplx<R>);
+  hipLaunchKernelGGL((k_blu_fwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_blu_mid<R, IO, ADJ, NS>), dim3(groups), dim3(nt), smem, p->stream, g, p->K, p->mid, T, rhs, x, xmid);
+  hipLaunchKernelGGL((k_blu_mid<R, IO, ADJ, NS>), dim3(groups), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x, xmid);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_blu_bwd<R, IO, ADJ, NS>), dim3(groups, 2), dim3(nt), smem, p->stream, g, p->K, p->mid, T, x, xmid);
+  hipLaunchKernelGGL((k_blu_bwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, x, xmid);
   LAUNCH_CHECK();
   return KF_OK;
 }
