@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark: full-space Gauss-Newton step time on one MI355X (and KKT-matvec GB/s).
+
+One step = one whole Newton step of the method on the GPU (Sections 3-5): block
+factorisation of A(gamma_n), background solve u_n = A^-1 f, data residual and
+KKT right-hand side, flexible GMRES with the block-triangular preconditioner to
+||b - M xi|| <= 1e-6 ||b||, and the update gamma_{n+1} = gamma_n + Re(ds), which
+the next step continues from.
+
+Workload (default): the 401 x 141 grid (h = 10 m, 20-cell PML) of the seeded
+faulted-lens earth, 40 sources and 401 receivers on the first core row, 5 Hz,
+inexact preconditioner (complex64 block sweeps), FGMRES(30), b_s = 0.  Inputs
+are synthetic; the observed data are a forward solve of the true model.
+
+Prints one JSON line.  Also reported:
+  roofline      the kernel with the most GPU time in the timed steps, timed live
+                with HIP events on the library's stream;
+  kkt_apply     the fused KKT matvec at this size and at 801 x 281 x 80 sources
+                (1.45 GB per call, larger than the 256 MB Infinity Cache);
+  cpu_baseline  the FP64 oracle (banded LU, the paper's own CPU algorithm) timed on
+                a bounded sample of the same workload on the host.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1")
+    ap.add_argument("--freq-index", type=int, default=1)
+    ap.add_argument("--pc", default="inexact", choices=["exact", "inexact"])
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-kkt", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_work(name, p):
+    """Algorithmic work of one launch of a kernel family: (amount, unit, dtype)."""
+    nx, nz, K, Nu, Ng = p.nx, p.nz, p.K, p.Nu, p.Ng
+    m = nz
+    if name == "kkt_apply":
+        # read du, lambda, u_n, write y_u, y_lambda per node-source; gamma per node;
+        # ds read + y_s write per control node (receiver term is a separate kernel)
+        return Nu * (80 * K + 8) + 32 * Ng, "bytes", "f64"
+    if name == "blu_factor":
+        # nx-1 dense complex Gauss-Jordan inversions of m x m (m^3 complex MACs each)
+        return 8.0 * m ** 3 * (nx - 1), "flops", "f64"
+    if name.startswith("blu_fwd") or name.startswith("blu_bwd"):
+        # a dense m x m complex matvec per column and source, all columns but the middle
+        return 8.0 * m * m * (nx - 1) * K, "flops", ("f32" if name.endswith("c64") else "f64")
+    raise KeyError(name)
+
+
+def roofline_for(name, p, launches, total_ms):
+    amount, unit, dt = kernel_work(name, p)
+    avg_s = total_ms / launches * 1e-3
+    if unit == "bytes":
+        achieved = amount / avg_s / 1e9
+        peak = HBM_PEAK_GBS
+        out = {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s"}
+    else:
+        achieved = amount / avg_s / 1e12
+        peak = FP32_PEAK_TFLOPS if dt == "f32" else FP64_PEAK_TFLOPS
+        out = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    out.update({"frac": achieved / peak, "traffic": None, "kernel": name, "launches": launches,
+                "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount, "work_unit": unit})
+    return out
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None once the
+    kernel sources differ from the build the counters were taken on."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    tab = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2204_06489_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    k = tab.get("kernels", {}).get(name)
+    if k is None or h.hexdigest()[:16] != tab.get("source_sha"):
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+def observed_data(inp, torch, KKTProblem):
+    pt = KKTProblem.from_inputs(inp, gamma=inp["gamma_true"])
+    u, _ = pt.helmholtz_solve(pt.sources())
+    riz = torch.as_tensor(inp["rec_iz"]).long().cuda()
+    rix = torch.as_tensor(inp["rec_ix"]).long().cuda()
+    d = u[:, riz, rix].contiguous()
+    del u
+    pt.close()
+    return d
+
+
+def hbm_kkt(torch, KKTProblem, args):
+    """kkt_apply at 801 x 281, 80 sources (working set far above the Infinity Cache)."""
+    from synthetic.configs import make_problem_inputs
+    inp = make_problem_inputs("c2", 0)
+    p = KKTProblem.from_inputs(inp, eps=inp["eps"] or 1.0)
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    u = torch.randn(p.field_shape, dtype=torch.complex128, device="cuda", generator=g)
+    p.set_background(u)
+    xi = torch.randn(p.Nxi, dtype=torch.complex128, device="cuda", generator=g)
+    y = p.empty_xi()
+    for _ in range(3):
+        p.kkt_apply(xi, out=y)
+    torch.cuda.synchronize()
+    p.profile_enable(True)
+    for _ in range(20):
+        p.kkt_apply(xi, out=y)
+    n, ms = p.profile_read("kkt_apply")
+    p.profile_enable(False)
+    r = roofline_for("kkt_apply", p, n, ms)
+    p.close()
+    return {"grid": "801x281", "K": 80, "GB_per_call": r["work_per_launch"] / 1e9,
+            "avg_launch_us": r["avg_launch_us"], "GB_s": r["achieved"], "frac_of_hbm_peak": r["frac"]}
+
+
+def cpu_baseline(inp, gpu_iters, args):
+    """The oracle (numpy/scipy, banded LU) on a bounded sample of the same step."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.kkt import Problem, gmres_right
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        p = Problem.from_inputs(inp, gamma=inp["gamma0"], eps=inp["eps"], reg_on_update=True)
+        t_factor = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        u_n = p.forward()
+        t_fwd = time.perf_counter() - t0
+        rng = np.random.default_rng(0)
+        d = p.sample(u_n) * (1.0 + 0.1 * rng.standard_normal((p.K, p.nrec)))
+        b = p.rhs(p.residual(d, u_n))
+        n_it = 2
+        t0 = time.perf_counter()
+        gmres_right(lambda v: p.kkt_apply(u_n, v), lambda v: p.precond_apply(u_n, v), b, tol=1e-30,
+                    restart=args.restart, maxit=n_it)
+        t_it = (time.perf_counter() - t0) / n_it
+    est = t_factor + t_fwd + gpu_iters * t_it
+    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"full-size banded-LU factorisation ({t_factor:.1f} s), background solve ({t_fwd:.1f} s) "
+                       f"and {n_it} right-preconditioned GMRES iterations with the exact banded-LU "
+                       f"preconditioner ({t_it:.1f} s each), scaled to the GPU step's {gpu_iters:.1f} outer "
+                       f"iterations; one BLAS thread")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU source sharding is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from synthetic.configs import make_problem_inputs
+    from paper_2204_06489_amd.solver import KKTProblem
+
+    torch.cuda.set_device(0)
+    if args.copy_calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": a.numel() * 8, "launches": 3}))
+        return
+    inp = make_problem_inputs(args.config, args.freq_index)
+    if inp["eps"] is None:
+        raise SystemExit("no eps for this workload in synthetic/eps_table.json")
+    log(args, f"workload {args.config} f={inp['freq']} Hz grid {inp['nx']}x{inp['nz']} K={inp['K']}")
+    d = observed_data(inp, torch, KKTProblem)
+    p = KKTProblem.from_inputs(inp, reg_on_update=True)
+    opts = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec="c128",
+                update_in_place=True, want_xi=False)
+    for w in range(args.warmup):
+        _, _, st = p.newton_step(d, **opts)
+        log(args, f"warmup {w}: iters={st['outer_iters']} rel={st['rel_res']:.2e} {st['t_total_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    families = ["kkt_apply", "blu_factor", "blu_fwd_c64", "blu_bwd_c64", "blu_fwd_c128", "blu_bwd_c128"]
+    p.profile_enable(True)
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        _, _, st = p.newton_step(d, **opts)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {f: p.profile_read(f) for f in families}
+    p.profile_enable(False)
+    for k, st in enumerate(stats):
+        log(args, f"step {k}: iters={st['outer_iters']} rel={st['rel_res']:.2e} total={st['t_total_ms']:.1f} ms "
+                  f"factor={st['t_factor_ms']:.1f} fwd={st['t_forward_ms']:.1f} pc={st['t_precond_ms']:.1f} "
+                  f"mv={st['t_matvec_ms']:.1f} orth={st['t_orth_ms']:.1f} misfit={st['misfit_before']:.4f}")
+    ms_per_step = elapsed / args.steps * 1e3
+    dominant = max((f for f in families if prof[f][0] > 0), key=lambda f: prof[f][1])
+    roof = roofline_for(dominant, p, *prof[dominant])
+    roof["traffic"] = measured_traffic(dominant)
+    kkt_here = roofline_for("kkt_apply", p, *prof["kkt_apply"]) if prof["kkt_apply"][0] else None
+    per_kernel = {f: {"launches": n, "total_ms": ms, "avg_us": (ms / n * 1e3 if n else None)}
+                  for f, (n, ms) in prof.items()}
+    mean = lambda key: float(np.mean([s[key] for s in stats]))
+    result = {
+        "metric": "Newton-step time to KKT rel. res 1e-6",
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 outer (FP64) + c64 block sweeps" if args.pc == "inexact" else "c128",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.config}: {inp['nx']}x{inp['nz']} grid, h={inp['h']:g} m, "
+                                f"{inp['npml']}-cell PML, faulted-lens model, {inp['K']} sources, "
+                                f"{len(inp['rec_ix'])} receivers, {inp['freq']:g} Hz, "
+                                f"{'inexact' if args.pc == 'inexact' else 'exact'} block-triangular "
+                                f"preconditioner, FGMRES({args.restart}) to {args.rtol:g}, b_s = 0"),
+                   "global_batch": inp["K"], "parallelism": "single GPU"},
+        "roofline": roof,
+        "breakdown_ms": {"factor": mean("t_factor_ms"), "forward": mean("t_forward_ms"),
+                         "precond": mean("t_precond_ms"), "matvec": mean("t_matvec_ms"),
+                         "orth": mean("t_orth_ms"), "outer_iters": mean("outer_iters"),
+                         "rel_res": max(s["rel_res"] for s in stats),
+                         "misfit_first": stats[0]["misfit_before"], "misfit_last": stats[-1]["misfit_before"]},
+        "per_kernel": per_kernel,
+        "kkt_apply": {"this_workload": kkt_here and {"GB_s": kkt_here["achieved"], "frac": kkt_here["frac"],
+                                                      "note": "183 MB per call: Infinity-Cache resident"}},
+    }
+    if not args.no_hbm_kkt:
+        p.close()
+        result["kkt_apply"]["hbm"] = hbm_kkt(torch, KKTProblem, args)
+    if not args.no_cpu_baseline:
+        log(args, "timing the oracle on the host ...")
+        result["cpu_baseline"] = cpu_baseline(inp, result["breakdown_ms"]["outer_iters"], args)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -203,7 +203,11 @@ kf_status kf_sizes(kf_problem *p, int64_t *out /*[host][6]*/);
  * family on the problem's stream: enable (1) / disable (0) and reset the counters. */
 kf_status kf_profile_enable(kf_problem *p, int32_t on);
 /* Read accumulated (launch count, total milliseconds) of a kernel family:
- * "kkt_apply", "stencil", "blu_factor", "blu_sweep", "precond_stage", "orth", "reduce". */
+ * "kkt_apply" (the fused kernel, without the receiver term), "stencil", "blu_factor" (the
+ * two-sided sweep of the factorisation, without the middle column), "blu_sweep" (a whole
+ * block solve), "blu_fwd_c128",
+ * "blu_fwd_c64", "blu_bwd_c128", "blu_bwd_c64" (the forward-sweep and back-substitution
+ * kernels alone), "precond_stage", "orth", "reduce".  Unknown names give KF_EINVAL. */
 kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
 
 #ifdef __cplusplus

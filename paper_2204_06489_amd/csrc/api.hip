@@ -728,8 +728,9 @@ extern "C" kf_status helmholtz_adjoint_gradient(kf_problem *p, int32_t prec, con
 // ---------------------------------------------------------------------------
 // profiling API
 // ---------------------------------------------------------------------------
-static const char *prof_names[PROF_N] = {"kkt_apply", "stencil", "blu_factor", "blu_sweep", "precond_stage",
-                                         "orth", "reduce"};
+static const char *prof_names[PROF_N] = {"kkt_apply", "stencil",     "blu_factor",  "blu_sweep",
+                                         "precond_stage", "orth",  "reduce",      "blu_fwd_c128",
+                                         "blu_fwd_c64",   "blu_bwd_c128", "blu_bwd_c64"};
 
 extern "C" kf_status kf_profile_enable(kf_problem *p, int32_t on) {
   CHECK_ST(check_p(p));

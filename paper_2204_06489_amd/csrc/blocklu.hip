@@ -237,8 +237,9 @@ __device__ __forceinline__ void build_schur(const Grid &g, int m, int i, const d
 // blockIdx.x = 0: left sweep over columns 0..mid-1; 1: right sweep over nx-1..mid+1.
 // mode 1: the middle column (one block).  work: per block an m x m matrix and an
 // NB x m staging area.
-template <int NB, int RMAX, int NT>
-__global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, int mode, double2 *T, double2 *work) {
+template <int NB, int RMAX, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, double2 *T, double2 *work) {
+  const int mode = MODE;
   extern __shared__ unsigned char smem[];
   const int m = g.nz;
   double2 *pan = (double2 *)smem;          // [m][NB]
@@ -489,24 +490,27 @@ kf_status blu_factor(kf_problem *p, int which) {
   const size_t mm = (size_t)m * m;
   if (which & 1) {
     if (!p->have_T64) {
-      ProfScope ps(p, PROF_FACTOR);
       Grid g = p->grid();
-      auto launch = [&](auto kern, int nb, int nthreads) -> kf_status {
+      auto launch = [&](auto sides, auto middle, int nb, int nthreads) -> kf_status {
         size_t smem = (2 * (size_t)m * nb + 2 * (size_t)m + 2 * nb) * sizeof(double2) + 2 * (size_t)m * sizeof(int);
-        HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        hipLaunchKernelGGL(kern, dim3(2), dim3(nthreads), smem, p->stream, g, p->mid, 0, p->T64, p->fac_work);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), smem, p->stream, g, p->mid, 1, p->T64, p->fac_work);
+        HIP_TRY(hipFuncSetAttribute((const void *)sides, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        HIP_TRY(hipFuncSetAttribute((const void *)middle, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        {
+          ProfScope ps(p, PROF_FACTOR);
+          hipLaunchKernelGGL(sides, dim3(2), dim3(nthreads), smem, p->stream, g, p->mid, p->T64, p->fac_work);
+          LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(middle, dim3(1), dim3(nthreads), smem, p->stream, g, p->mid, p->T64, p->fac_work);
         LAUNCH_CHECK();
         return KF_OK;
       };
       // panel width and rows per lane of the register-resident panel, by column height
       // (the register-resident panel needs the larger VGPR budget of 256-thread groups
       //  once a lane owns five or more rows)
-      kf_status st = m <= 128 ? launch(k_blu_factor<8, 2, 512>, 8, 512)
-                   : m <= 192 ? launch(k_blu_factor<8, 3, 512>, 8, 512)
-                   : m <= 320 ? launch(k_blu_factor<8, 5, 256>, 8, 256)
-                              : launch(k_blu_factor<8, 8, 256>, 8, 256);
+      kf_status st = m <= 128 ? launch(k_blu_factor<8, 2, 512, 0>, k_blu_factor<8, 2, 512, 1>, 8, 512)
+                   : m <= 192 ? launch(k_blu_factor<8, 3, 512, 0>, k_blu_factor<8, 3, 512, 1>, 8, 512)
+                   : m <= 320 ? launch(k_blu_factor<8, 5, 256, 0>, k_blu_factor<8, 5, 256, 1>, 8, 256)
+                              : launch(k_blu_factor<8, 8, 256, 0>, k_blu_factor<8, 8, 256, 1>, 8, 256);
       if (st != KF_OK) return st;
       p->have_T64 = true;
     }
@@ -535,12 +539,19 @@ kf_status sweep(kf_problem *p, const cplx<R> *T, const IO *rhs, IO *x, cplx<R> *
   int groups = (p->K + NS - 1) / NS;
   dim3 blk = sweep_block(m);
   size_t smem = (2 + (blk.y - 1)) * NS * m * sizeof(cplx<R>);
-  hipLaunchKernelGGL((k_blu_fwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x);
-  LAUNCH_CHECK();
+  const bool fp32 = sizeof(R) == sizeof(float);
+  {
+    ProfScope pf(p, fp32 ? PROF_FWD32 : PROF_FWD64);
+    hipLaunchKernelGGL((k_blu_fwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x);
+    LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL((k_blu_mid<R, IO, ADJ, NS>), dim3(groups), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x, xmid);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_blu_bwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, x, xmid);
-  LAUNCH_CHECK();
+  {
+    ProfScope pb(p, fp32 ? PROF_BWD32 : PROF_BWD64);
+    hipLaunchKernelGGL((k_blu_bwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, x, xmid);
+    LAUNCH_CHECK();
+  }
   return KF_OK;
 }
 }  // namespace

@@ -136,11 +136,12 @@ struct kf_problem {
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_free;             // event pool
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[8];
-  ProfCounter counters[8];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[16];
+  ProfCounter counters[16];
 };
 
-enum ProfId { PROF_KKT = 0, PROF_STENCIL, PROF_FACTOR, PROF_SWEEP, PROF_PRECOND, PROF_ORTH, PROF_REDUCE, PROF_N };
+enum ProfId { PROF_KKT = 0, PROF_STENCIL, PROF_FACTOR, PROF_SWEEP, PROF_PRECOND, PROF_ORTH, PROF_REDUCE,
+              PROF_FWD64, PROF_FWD32, PROF_BWD64, PROF_BWD32, PROF_N };
 
 // error plumbing
 void set_error(const std::string &msg);

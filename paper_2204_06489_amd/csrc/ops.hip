@@ -295,10 +295,12 @@ template kf_status launch_stencil<double>(kf_problem *, int, const double2 *, do
 template kf_status launch_stencil<float>(kf_problem *, int, const float2 *, float2 *);
 
 kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
-  ProfScope ps(p, PROF_KKT);
-  hipLaunchKernelGGL(k_kkt_apply, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K, p->nxc, p->eps,
-                     xi, p->u_n, y);
-  LAUNCH_CHECK();
+  {
+    ProfScope ps(p, PROF_KKT);
+    hipLaunchKernelGGL(k_kkt_apply, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K, p->nxc, p->eps,
+                       xi, p->u_n, y);
+    LAUNCH_CHECK();
+  }
   int n = p->K * p->nru;
   hipLaunchKernelGGL(k_kkt_F, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->d_rnode, p->d_wsq,
                      (size_t)p->Nu, xi, y);
