@@ -26,6 +26,7 @@ class HelmholtzSolve(torch.autograd.Function):
             f = f.to(torch.complex64)
         u, _ = problem.helmholtz_solve(f, adjoint=False, prec=prec)
         ctx.problem, ctx.prec = problem, prec
+        ctx.token = problem.gamma_token
         ctx.save_for_backward(gamma, u)
         return u
 
@@ -33,8 +34,9 @@ class HelmholtzSolve(torch.autograd.Function):
     def backward(ctx, grad_u):
         gamma, u = ctx.saved_tensors
         problem, prec = ctx.problem, ctx.prec
-        # the factors may belong to another gamma if the problem was reused in between
-        problem.set_gamma(gamma.detach())
+        # the factors belong to another gamma if the problem was reused in between
+        if problem.gamma_token != ctx.token:
+            problem.set_gamma(gamma.detach())
         dt = torch.complex64 if prec == "c64" else torch.complex128
         g = problem.adjoint_gradient(u.contiguous(), grad_u.to(dt).contiguous(), prec=prec)
         return g.to(gamma.dtype), None, None

@@ -131,6 +131,7 @@ class KKTProblem:
         g = gamma.to(device=self.device, dtype=torch.float64).contiguous()
         check(lib().kf_set_gamma(self._h, _ptr(g, numel=self.Nu, name="gamma")))
         torch.cuda.current_stream().synchronize()
+        self.gamma_token = getattr(self, "gamma_token", 0) + 1
 
     def get_gamma(self):
         out = torch.empty((self.nz, self.nx), dtype=torch.float64, device=self.device)
@@ -196,6 +197,8 @@ class KKTProblem:
         s = check(lib().newton_step(self._h, _ptr(d_obs, torch.complex128, self.K * self.nrec, "d_obs"),
                                     C.byref(o), _ptr(xi) if xi is not None else None, _ptr(g1),
                                     int(bool(update_in_place)), C.byref(st)), allow=(KF_ENOCONV,))
+        if update_in_place:
+            self.gamma_token = getattr(self, "gamma_token", 0) + 1
         stats = {f: getattr(st, f) for f, _ in KfNewtonStats._fields_ if f != "rel_res_hist"}
         stats["rel_res_hist"] = list(st.rel_res_hist[:max(0, st.outer_iters)])
         stats["converged"] = s != KF_ENOCONV

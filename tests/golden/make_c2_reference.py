@@ -1,0 +1,62 @@
+"""Write the FP64 oracle's Newton step on the 801 x 281, 80-source, 5 Hz workload.
+
+Calls only the oracle (banded-LU forward solves, assembled KKT matrix, right-
+preconditioned GMRES with the exact banded-LU preconditioner of eq. precond) and
+stores what the mixed-precision GPU step is compared with: ds, gamma_{n+1}, the
+misfit before and after the step, and the KKT relative residual reached.
+
+Usage: python -m tests.golden.make_c2_reference [out.npz]   (about an hour of CPU)
+"""
+
+import os
+import sys
+import time
+
+import numpy as np
+
+from oracle.kkt import Problem, gmres_right
+from synthetic.configs import make_problem_inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def main(out):
+    t0 = time.time()
+    inp = make_problem_inputs("c2", 0)
+    pt = Problem.from_inputs(inp, gamma=inp["gamma_true"], eps=inp["eps"])
+    d = pt.sample(pt.forward())
+    del pt
+    print(f"data ({time.time() - t0:.0f}s)", flush=True)
+    p = Problem.from_inputs(inp, eps=inp["eps"], reg_on_update=True)
+    u_n = p.forward()
+    r = p.residual(d, u_n)
+    b = p.rhs(r)
+    M = p.assemble_M(u_n)
+    print(f"setup ({time.time() - t0:.0f}s)", flush=True)
+    it = [0]
+
+    def apply_M(v):
+        return M @ v
+
+    def apply_P(v):
+        it[0] += 1
+        if it[0] % 5 == 0:
+            print(f"  precond {it[0]} ({time.time() - t0:.0f}s)", flush=True)
+        return p.precond_apply(u_n, v)
+
+    xi, hist, _ = gmres_right(apply_M, apply_P, b, tol=1e-10, restart=15, maxit=400)
+    rel = np.linalg.norm(b - M @ xi) / np.linalg.norm(b)
+    ds = p.unpack(xi)[1]
+    g1 = p.update(ds)
+    q = Problem.from_inputs(inp, gamma=g1, eps=inp["eps"])
+    u1 = q.forward()
+    mis0 = np.linalg.norm(r) / np.linalg.norm(d)
+    mis1 = np.linalg.norm(d - q.sample(u1)) / np.linalg.norm(d)
+    np.savez_compressed(out, ds=ds, gamma_next=g1, misfit_before=mis0, misfit_after=mis1, rel_res=rel,
+                        iterations=len(hist) - 1, d=d)
+    print(f"done: {len(hist) - 1} iterations rel_res={rel:.2e} misfit {mis0:.4e} -> {mis1:.4e} "
+          f"({time.time() - t0:.0f}s)", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "c2_newton_oracle.npz"))
