@@ -125,7 +125,7 @@ static void free_all(kf_problem *p) {
   dfree(p->gamma); dfree(p->xn); dfree(p->ixh); dfree(p->zn); dfree(p->izh);
   dfree(p->d_src); dfree(p->d_rnode); dfree(p->d_wsq); dfree(p->d_rec); dfree(p->d_w);
   dfree(p->d_rptr); dfree(p->d_rlist); dfree(p->d_r); dfree(p->d_wr);
-  dfree(p->u_n); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->xmid); dfree(p->xmid32);
+  dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->xmid); dfree(p->xmid32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
   if (p->host_pinned) hipHostFree(p->host_pinned);
@@ -239,6 +239,8 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   ALLOC(p->d_rptr, (size_t)p->nru + 1); ALLOC(p->d_rlist, (size_t)p->nrec);
   ALLOC(p->d_r, K * p->nrec); ALLOC(p->d_wr, K * p->nrec);
   ALLOC(p->u_n, K * Nu);
+  p->kkt_groups_max = (int)std::min<size_t>(K, 64);
+  ALLOC(p->ys_part, (size_t)p->kkt_groups_max * p->Ng);
   ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m);
   ALLOC(p->fac_work, 2 * (m * m + 16 * m));
   ALLOC(p->xmid, K * m); ALLOC(p->xmid32, K * m);

@@ -108,6 +108,8 @@ struct kf_problem {
   double2 *d_r = nullptr, *d_wr = nullptr;     // [K][nrec] data residual and weighted residual
   double *d_w = nullptr;                       // [K][nrec]
   double2 *u_n = nullptr;                      // [K][nz][nx]
+  double2 *ys_part = nullptr;                  // [groups][Ng] per-source-group parts of sum_k P_k^* lambda_k
+  int kkt_groups_max = 0;
   bool have_un = false;
 
   // block factorisation (column sweep, both ends)

@@ -60,53 +60,79 @@ __global__ __launch_bounds__(BX *BY) void k_stencil(Grid g, int K, const cplx<R>
   }
 }
 
-// ---------------------------------------------------------------------------
-// Fused KKT matvec (eq. KKT):  for every node and every source k
-//   y_u,k   = A^H lambda_k                      (F_k du_k is added by k_kkt_F)
-//   y_lam,k = A du_k - omega^2 u_k (E ds)
-//   y_s     = eps ds - omega^2 sum_k E^T (conj(u_k) lambda_k)
-// One thread owns one node and loops over all sources, so the sum over k is a
-// register accumulator (no atomics, fixed order).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BX *BY) void k_kkt_apply(Grid g, int K, int nxc, double eps,
+// Fused KKT matvec on 64 x (TY * RPT) tiles: thread (x, y) owns the RPT nodes
+// (i, j0 + y + TY r) and loops over the sources of its group (blockIdx.z).  The rows
+// of a tile share the vertical neighbours of their du / lambda rows through L1, so only
+// the two rows beyond the tile are fetched again by the neighbouring tile.  Each group
+// writes its part of the sum over k of P_k^* lambda_k into ys_part ([group][Ng]);
+// k_kkt_ys_finish adds the groups in fixed order.
+template <int TY, int RPT>
+__global__ __launch_bounds__(64 * TY) void k_kkt_tile(Grid g, int K, int kpg, int nxc,
                                                        const double2 *__restrict__ xi,
                                                        const double2 *__restrict__ un,
-                                                       double2 *__restrict__ y) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  if (i >= g.nx || j >= g.nz) return;
-  const Stencil5 s = stencil_at(g, i, j);
+                                                       double2 *__restrict__ y, double2 *__restrict__ ys_part) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= g.nx) return;
   const size_t Nu = (size_t)g.nx * g.nz;
   const int nzc = g.nz - 2 * g.npml;
   const size_t Ng = (size_t)nxc * nzc;
-  const size_t p = (size_t)j * g.nx + i;
-  const bool core = i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
-  const size_t c = core ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
   const double2 *du = xi;
   const double2 *dsv = xi + (size_t)K * Nu;
   const double2 *lam = dsv + Ng;
   double2 *yu = y;
-  double2 *ys = y + (size_t)K * Nu;
-  double2 *yl = ys + Ng;
+  double2 *yl = y + (size_t)K * Nu + Ng;
   const double w2 = g.omega * g.omega;
-  const double2 ds = core ? dsv[c] : make_double2(0.0, 0.0);
-  const double2 w2ds = cscale(ds, w2);
-  const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int k = 0; k < K; ++k) {
-    const size_t o = (size_t)k * Nu + p;
-    const double2 l0 = lam[o], d0 = du[o], u = un[o];
-    double2 ah = cmulc(s.cc, l0);     // conj(coefficient) * lambda
-    double2 a = cmul(s.cc, d0);
-    if (hxm) { ah = cadd(ah, cmulc(s.cxm, lam[o - 1])); cfma(a, s.cxm, du[o - 1]); }
-    if (hxp) { ah = cadd(ah, cmulc(s.cxp, lam[o + 1])); cfma(a, s.cxp, du[o + 1]); }
-    if (hzm) { ah = cadd(ah, cmulc(s.czm, lam[o - g.nx])); cfma(a, s.czm, du[o - g.nx]); }
-    if (hzp) { ah = cadd(ah, cmulc(s.czp, lam[o + g.nx])); cfma(a, s.czp, du[o + g.nx]); }
-    yu[o] = ah;
-    yl[o] = csub(a, cmul(u, w2ds));
-    acc = cadd(acc, cmulc(u, l0));
+  const bool hxm = i > 0, hxp = i + 1 < g.nx;
+  Stencil5 st[RPT];
+  size_t pp[RPT], cc[RPT];
+  bool in[RPT], core[RPT], hzm[RPT], hzp[RPT];
+  double2 w2ds[RPT], acc[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int j = blockIdx.y * TY * RPT + threadIdx.y + TY * r;
+    in[r] = j < g.nz;
+    const int jj = in[r] ? j : 0;
+    st[r] = stencil_at(g, i, jj);
+    pp[r] = (size_t)jj * g.nx + i;
+    core[r] = in[r] && i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
+    cc[r] = core[r] ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
+    w2ds[r] = cscale(core[r] ? dsv[cc[r]] : make_double2(0.0, 0.0), w2);
+    hzm[r] = jj > 0;
+    hzp[r] = jj + 1 < g.nz;
+    acc[r] = make_double2(0.0, 0.0);
   }
-  if (core) ys[c] = csub(cscale(ds, eps), cscale(acc, w2));
+  const int k0 = blockIdx.z * kpg, k1 = min(K, k0 + kpg);
+  for (int k = k0; k < k1; ++k) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (!in[r]) continue;
+      const Stencil5 &s = st[r];
+      const size_t o = (size_t)k * Nu + pp[r];
+      const double2 l0 = lam[o], d0 = du[o], u = un[o];
+      double2 ah = cmulc(s.cc, l0);     // conj(weight) * lambda: A^H lambda
+      double2 a = cmul(s.cc, d0);
+      if (hxm) { ah = cadd(ah, cmulc(s.cxm, lam[o - 1])); cfma(a, s.cxm, du[o - 1]); }
+      if (hxp) { ah = cadd(ah, cmulc(s.cxp, lam[o + 1])); cfma(a, s.cxp, du[o + 1]); }
+      if (hzm[r]) { ah = cadd(ah, cmulc(s.czm, lam[o - g.nx])); cfma(a, s.czm, du[o - g.nx]); }
+      if (hzp[r]) { ah = cadd(ah, cmulc(s.czp, lam[o + g.nx])); cfma(a, s.czp, du[o + g.nx]); }
+      yu[o] = ah;
+      yl[o] = csub(a, cmul(u, w2ds[r]));
+      acc[r] = cadd(acc[r], cmulc(u, l0));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (core[r]) ys_part[(size_t)blockIdx.z * Ng + cc[r]] = acc[r];
+}
+
+// y_s = eps ds - omega^2 sum over source groups (fixed order)
+__global__ void k_kkt_ys_finish(size_t Ng, int groups, double eps, double w2, const double2 *__restrict__ ds,
+                                const double2 *__restrict__ part, double2 *__restrict__ ys) {
+  size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Ng) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = 0; q < groups; ++q) acc = cadd(acc, part[(size_t)q * Ng + c]);
+  ys[c] = csub(cscale(ds[c], eps), cscale(acc, w2));
 }
 
 // y_u,k(node) += (sum of W_k^2 over the receivers at that node) du_k(node)
@@ -295,12 +321,27 @@ template kf_status launch_stencil<double>(kf_problem *, int, const double2 *, do
 template kf_status launch_stencil<float>(kf_problem *, int, const float2 *, float2 *);
 
 kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
+  constexpr int TY = 16, RPT = 1;
+  const int tx = (p->nx + 63) / 64, tz = (p->nz + TY * RPT - 1) / (TY * RPT);
+  // source groups: at least ~2 blocks of 16 waves per CU
+  int groups = (512 + tx * tz - 1) / (tx * tz);
+  groups = groups < 1 ? 1 : (groups > p->K ? p->K : groups);
+  const int kpg = (p->K + groups - 1) / groups;
+  groups = (p->K + kpg - 1) / kpg;
+  if (groups > p->kkt_groups_max) {
+    set_error("kkt_apply: source-group scratch too small");
+    return KF_EINVAL;
+  }
   {
     ProfScope ps(p, PROF_KKT);
-    hipLaunchKernelGGL(k_kkt_apply, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K, p->nxc, p->eps,
-                       xi, p->u_n, y);
+    hipLaunchKernelGGL((k_kkt_tile<TY, RPT>), dim3(tx, tz, groups), dim3(64, TY), 0, p->stream, p->grid(), p->K, kpg,
+                       p->nxc, xi, p->u_n, y, p->ys_part);
     LAUNCH_CHECK();
   }
+  hipLaunchKernelGGL(k_kkt_ys_finish, dim3((unsigned)((p->Ng + 255) / 256)), dim3(256), 0, p->stream, (size_t)p->Ng,
+                     groups, p->eps, p->omega * p->omega, xi + (size_t)p->K * p->Nu, p->ys_part,
+                     y + (size_t)p->K * p->Nu);
+  LAUNCH_CHECK();
   int n = p->K * p->nru;
   hipLaunchKernelGGL(k_kkt_F, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->d_rnode, p->d_wsq,
                      (size_t)p->Nu, xi, y);
