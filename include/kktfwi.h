@@ -210,6 +210,35 @@ kf_status kf_profile_enable(kf_problem *p, int32_t on);
  * kernels alone), "precond_stage", "orth", "reduce".  Unknown names give KF_EINVAL. */
 kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
 
+/* ---- batches: several problems (e.g. frequencies on uneven grids) advanced together ----
+ * The frequency sweep of Section 6 treats each frequency as its own Newton step; a batch
+ * runs such independent problems together: every factorisation and every batched block
+ * solve is one persistent work-list launch over all problems, and the preconditioner +
+ * KKT matvec of each FGMRES column can be replayed from a captured hipGraph.  A batch
+ * holds up to 8 problems (not owned: destroy the batch before its problems) and orders
+ * all their work on its own stream (the problems' streams are set to it while the batch
+ * exists; kf_batch_destroy gives each problem back the stream it had before).  With
+ * hip_stream = NULL the batch creates a non-blocking stream of its own (the legacy NULL
+ * stream cannot be captured); work the caller queued elsewhere must be complete (or
+ * ordered by the caller) before a batched call. */
+typedef struct kf_batch kf_batch;
+kf_status kf_batch_create(kf_problem *const *problems /*[host][n]*/, int32_t n, void *hip_stream, kf_batch **out);
+kf_status kf_batch_destroy(kf_batch *b);
+/* Factorise every problem that needs it (which: bit 0 FP64 factors, bit 1 complex64 copy). */
+kf_status kf_batch_factor(kf_batch *b, int32_t which, double *t_ms /*[host], may be NULL*/);
+/* A x = rhs or A^H x = rhs for every source of every problem (prec KF_C128 or KF_C64);
+ * rhs[q], x[q] are device fields of problem q ([host] arrays of n pointers). */
+kf_status helmholtz_solve_batched(kf_batch *b, int32_t adjoint, int32_t prec, const void *const *rhs,
+                                  void *const *x);
+/* newton_step (above) for every problem together; per-problem arrays are [host][n] of
+ * device pointers (xi_out, gamma_next entries may be NULL) and st is [host][n].  The
+ * problems' FGMRES iterations advance in lockstep, each with its own scalars and its own
+ * stopping test.  use_graph = 1 replays each Krylov column's preconditioner and matvec
+ * for all problems from a captured hipGraph.  opts->fwd_prec must be KF_C128. */
+kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, const kf_newton_opts *opts,
+                              void *const *xi_out, double *const *gamma_next, int32_t update_in_place,
+                              int32_t use_graph, kf_newton_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

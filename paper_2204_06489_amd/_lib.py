@@ -71,6 +71,12 @@ _SIGNATURES = {
     "helmholtz_adjoint_gradient": (C.c_int, [P, C.c_int32, P, P, P]),
     "kf_sources": (C.c_int, [P, P]),
     "kf_sizes": (C.c_int, [P, C.POINTER(C.c_int64)]),
+    "kf_batch_create": (C.c_int, [C.POINTER(P), C.c_int32, P, C.POINTER(P)]),
+    "kf_batch_destroy": (C.c_int, [P]),
+    "kf_batch_factor": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double)]),
+    "helmholtz_solve_batched": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(P), C.POINTER(P)]),
+    "newton_step_batched": (C.c_int, [P, C.POINTER(P), C.POINTER(KfNewtonOpts), C.POINTER(P), C.POINTER(P),
+                                      C.c_int32, C.c_int32, C.POINTER(KfNewtonStats)]),
     "kf_profile_enable": (C.c_int, [P, C.c_int32]),
     "kf_profile_read": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }

@@ -754,3 +754,321 @@ extern "C" kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *l
     }
   return fail(KF_EINVAL, std::string("unknown kernel family ") + name);
 }
+
+// ---------------------------------------------------------------------------
+// batches: several problems (frequencies, uneven grids) advanced together
+// ---------------------------------------------------------------------------
+struct kf_batch {
+  std::vector<kf_problem *> p;
+  std::vector<hipStream_t> prev_stream;  // each problem's stream before it joined the batch
+  hipStream_t stream = nullptr;
+  bool own_stream = false;                // created here (a NULL stream cannot be captured)
+  unsigned int *counter = nullptr;      // work-list counter of the persistent kernels
+  std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;  // (Krylov column, problem mask)
+  int graph_pc = -1;
+};
+
+static void batch_drop_graphs(kf_batch *b) {
+  for (auto &kv : b->graphs) hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+extern "C" kf_status kf_batch_create(kf_problem *const *problems, int32_t n, void *hip_stream, kf_batch **out) {
+  if (!out) return fail(KF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!problems || n < 1 || n > KF_BATCH_MAX) return fail(KF_EINVAL, "batch needs 1..8 problems");
+  for (int q = 0; q < n; ++q)
+    if (!problems[q]) return fail(KF_EINVAL, "NULL problem in batch");
+  kf_batch *b = new kf_batch();
+  b->p.assign(problems, problems + n);
+  b->stream = (hipStream_t)hip_stream;
+  if (!b->stream) {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return fail(KF_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    b->own_stream = true;
+  }
+  for (kf_problem *p : b->p) {          // the batch orders all work on one stream
+    b->prev_stream.push_back(p->stream);
+    p->stream = b->stream;
+  }
+  if (dalloc(&b->counter, 1) != KF_OK) { delete b; return KF_ENOMEM; }
+  *out = b;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_batch_destroy(kf_batch *b) {
+  if (!b) return KF_OK;
+  hipStreamSynchronize(b->stream);
+  batch_drop_graphs(b);
+  dfree(b->counter);
+  for (size_t q = 0; q < b->p.size(); ++q) b->p[q]->stream = b->prev_stream[q];
+  if (b->own_stream) hipStreamDestroy(b->stream);
+  delete b;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_batch_factor(kf_batch *b, int32_t which, double *t_ms) {
+  if (!b) return fail(KF_EINVAL, "batch is NULL");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  auto t0 = std::chrono::steady_clock::now();
+  CHECK_ST(blu_factor_batch(b->p, which, b->stream, b->counter));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (t_ms) *t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return KF_OK;
+}
+
+extern "C" kf_status helmholtz_solve_batched(kf_batch *b, int32_t adjoint, int32_t prec, const void *const *rhs,
+                                             void *const *x) {
+  if (!b || !rhs || !x) return fail(KF_EINVAL, "null argument");
+  for (size_t q = 0; q < b->p.size(); ++q)
+    if (!rhs[q] || !x[q]) return fail(KF_EINVAL, "null field pointer");
+  if (prec == KF_C128) {
+    CHECK_ST(blu_factor_batch(b->p, 1, b->stream, b->counter));
+    CHECK_ST((blu_solve_batch<double, double2>(b->p, adjoint, (const double2 *const *)rhs, (double2 *const *)x,
+                                                b->stream, b->counter)));
+  } else if (prec == KF_C64) {
+    CHECK_ST(blu_factor_batch(b->p, 3, b->stream, b->counter));
+    CHECK_ST((blu_solve_batch<float, float2>(b->p, adjoint, (const float2 *const *)rhs, (float2 *const *)x,
+                                              b->stream, b->counter)));
+  } else {
+    return fail(KF_EINVAL, "batched solve supports KF_C128 and KF_C64");
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return KF_OK;
+}
+
+// the preconditioner (eq. precond / precond_approx) and KKT matvec of Krylov column j
+// for the problems in `sel`: z_j = P^-1 v_j, v_{j+1} = M z_j.  Both block solves of the
+// preconditioner are single persistent launches over all selected problems.
+static kf_status batch_column(kf_batch *b, const std::vector<kf_problem *> &sel, int pc, int j) {
+  const size_t n = sel.size();
+  std::vector<const double2 *> yu(n);
+  std::vector<double2 *> zl(n), zu(n);
+  for (size_t q = 0; q < n; ++q) {
+    kf_problem *p = sel[q];
+    const size_t N = p->Nxi, Ku = (size_t)p->K * p->Nu;
+    yu[q] = p->V + (size_t)j * N;
+    zu[q] = p->Z + (size_t)j * N;
+    zl[q] = zu[q] + Ku + p->Ng;
+  }
+  if (pc == KF_PC_EXACT) CHECK_ST((blu_solve_batch<double, double2>(sel, 1, yu.data(), zl.data(), b->stream, b->counter)));
+  else CHECK_ST((blu_solve_batch<float, double2>(sel, 1, yu.data(), zl.data(), b->stream, b->counter)));
+  for (size_t q = 0; q < n; ++q) CHECK_ST(launch_precond_stage2(sel[q], sel[q]->V + (size_t)j * sel[q]->Nxi, zu[q]));
+  std::vector<const double2 *> zin(zu.begin(), zu.end());
+  if (pc == KF_PC_EXACT) CHECK_ST((blu_solve_batch<double, double2>(sel, 0, zin.data(), zu.data(), b->stream, b->counter)));
+  else CHECK_ST((blu_solve_batch<float, double2>(sel, 0, zin.data(), zu.data(), b->stream, b->counter)));
+  for (size_t q = 0; q < n; ++q) CHECK_ST(launch_kkt_apply(sel[q], zu[q], sel[q]->V + (size_t)(j + 1) * sel[q]->Nxi));
+  return KF_OK;
+}
+
+// replay (capturing on first use) the graph of column j for the problem mask
+static kf_status batch_column_graph(kf_batch *b, const std::vector<kf_problem *> &sel, unsigned mask, int pc, int j) {
+  if (b->graph_pc != pc) { batch_drop_graphs(b); b->graph_pc = pc; }
+  auto key = std::make_pair(j, mask);
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    std::vector<bool> prof(sel.size());
+    for (size_t q = 0; q < sel.size(); ++q) { prof[q] = sel[q]->prof; sel[q]->prof = false; }
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    kf_status st = batch_column(b, sel, pc, j);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    for (size_t q = 0; q < sel.size(); ++q) sel[q]->prof = prof[q];
+    if (st != KF_OK) { if (graph) hipGraphDestroy(graph); return st; }
+    if (e != hipSuccess) return fail(KF_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(KF_EHIP, std::string("graph instantiate failed: ") + hipGetErrorString(e));
+    it = b->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, b->stream));
+  return KF_OK;
+}
+
+// One full-space Gauss-Newton step for every problem of the batch: the factorisations,
+// background solves and every preconditioner application run as persistent launches
+// over all problems; the FGMRES iterations of the problems advance in lockstep, the
+// preconditioner + KKT matvec of each Krylov column replayed from a captured hipGraph
+// (use_graph != 0).  Each problem keeps its own Krylov scalars and stops at its own
+// tolerance.  Arrays d_obs, xi_out, gamma_next and st have one entry per problem.
+extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, const kf_newton_opts *o,
+                                         void *const *xi_out, double *const *gamma_next, int32_t update_in_place,
+                                         int32_t use_graph, kf_newton_stats *st) {
+  if (!b || !d_obs || !o) return fail(KF_EINVAL, "null argument");
+  const int n = (int)b->p.size();
+  for (int q = 0; q < n; ++q) if (!d_obs[q]) return fail(KF_EINVAL, "null d_obs entry");
+  if (!(o->rtol > 0.0) || o->restart < 1 || o->restart > 200 || o->maxit < 1)
+    return fail(KF_EINVAL, "need rtol > 0, 1 <= restart <= 200, maxit >= 1");
+  if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
+  if (o->fwd_prec != KF_C128) return fail(KF_EINVAL, "batched steps use a complex128 background solve");
+  const int m = o->restart;
+  auto T0 = std::chrono::steady_clock::now();
+  auto ms_since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+  };
+  std::vector<kf_newton_stats> S(n);
+  for (auto &s : S) { std::memset(&s, 0, sizeof(s)); s.misfit_after = -1.0; }
+  for (kf_problem *p : b->p) CHECK_ST(ensure_krylov(p, m));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  auto t = std::chrono::steady_clock::now();
+  CHECK_ST(blu_factor_batch(b->p, o->pc == KF_PC_INEXACT ? 3 : 1, b->stream, b->counter));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  const double t_fac = ms_since(t);
+  t = std::chrono::steady_clock::now();
+  {
+    std::vector<const double2 *> f(n);
+    std::vector<double2 *> u(n);
+    for (int q = 0; q < n; ++q) {
+      CHECK_ST(launch_sources(b->p[q], b->p[q]->vec_c));
+      f[q] = b->p[q]->vec_c;
+      u[q] = b->p[q]->u_n;
+    }
+    CHECK_ST((blu_solve_batch<double, double2>(b->p, 0, f.data(), u.data(), b->stream, b->counter)));
+    for (kf_problem *p : b->p) p->have_un = true;
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  const double t_fwd = ms_since(t);
+  // residuals and right-hand sides
+  std::vector<double> bnorm(n), dn(n);
+  kf_status e = KF_OK;
+  for (int q = 0; q < n; ++q) {
+    kf_problem *p = b->p[q];
+    CHECK_ST(launch_residual(p, (const double2 *)d_obs[q], p->u_n, p->d_r, p->d_wr));
+    const int64_t nd = (int64_t)p->K * p->nrec;
+    double rn = host_norm(p, p->d_r, nd, &e); CHECK_ST(e);
+    dn[q] = host_norm(p, (const double2 *)d_obs[q], nd, &e); CHECK_ST(e);
+    double wn = host_norm(p, p->d_wr, nd, &e); CHECK_ST(e);
+    S[q].misfit_before = dn[q] > 0 ? rn / dn[q] : rn;
+    S[q].phi_before = 0.5 * wn * wn;
+    CHECK_ST(launch_rhs(p, p->d_r, p->d_rptr, p->d_rlist, p->xi_b, p->d.reg_on_update));
+    bnorm[q] = host_norm(p, p->xi_b, p->Nxi, &e); CHECK_ST(e);
+    HIP_TRY(hipMemsetAsync(p->xi_x, 0, sizeof(double2) * p->Nxi, b->stream));
+    S[q].t_factor_ms = t_fac;
+    S[q].t_forward_ms = t_fwd;
+  }
+  // lockstep flexible GMRES
+  std::vector<bool> done(n, false);
+  std::vector<int> total(n, 0);
+  std::vector<std::vector<double>> hist(n);
+  kf_status status = KF_OK;
+  for (int q = 0; q < n; ++q) if (bnorm[q] == 0.0) { done[q] = true; S[q].rel_res = 0.0; }
+  double t_cols = 0.0, t_orth = 0.0;
+  for (;;) {
+    // true residual at the start of each cycle
+    std::vector<int> act;
+    for (int q = 0; q < n; ++q) {
+      if (done[q]) continue;
+      kf_problem *p = b->p[q];
+      const int64_t N = p->Nxi;
+      double2 *H = p->hess;
+      double2 *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *h1 = g + (m + 1), *h2 = h1 + (m + 1),
+              *y = h2 + (m + 1);
+      double *scal = (double *)(y + m + 8);
+      (void)cs; (void)sn; (void)h1; (void)h2;
+      HIP_TRY(hipMemcpyAsync(p->V, p->xi_b, sizeof(double2) * N, hipMemcpyDeviceToDevice, b->stream));
+      if (total[q] > 0) {
+        CHECK_ST(launch_kkt_apply(p, p->xi_x, p->xi_w));
+        CHECK_ST(launch_axpy_field(p, N, make_double2(-1.0, 0.0), p->xi_w, p->V));
+      }
+      CHECK_ST(norm_c128(p, p->V, N, scal + 1));
+      HIP_TRY(hipMemcpyAsync(p->host_pinned, scal + 1, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      const double beta = p->host_pinned[0];
+      if (!std::isfinite(beta)) { status = fail(KF_ENAN, "non-finite residual in batched FGMRES"); done[q] = true; continue; }
+      S[q].rel_res = beta / bnorm[q];
+      if (S[q].rel_res <= o->rtol) { done[q] = true; continue; }
+      if (total[q] >= o->maxit) { status = fail(KF_ENOCONV, "batched FGMRES reached maxit"); done[q] = true; continue; }
+      CHECK_ST(scale_inv(p, N, scal + 1, p->V, p->V));
+      CHECK_ST(set_g0(p, m, scal + 1, g));
+      act.push_back(q);
+    }
+    if (act.empty()) break;
+    std::vector<int> nj(n, 0);
+    std::vector<bool> live(n, false);
+    for (int q : act) live[q] = true;
+    for (int j = 0; j < m; ++j) {
+      std::vector<kf_problem *> sel;
+      unsigned mask = 0;
+      for (int q : act) { sel.push_back(b->p[q]); mask |= 1u << q; }
+      auto tc = std::chrono::steady_clock::now();
+      if (use_graph) CHECK_ST(batch_column_graph(b, sel, mask, o->pc, j));
+      else CHECK_ST(batch_column(b, sel, o->pc, j));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      t_cols += ms_since(tc);
+      tc = std::chrono::steady_clock::now();
+      for (int q : act) {
+        kf_problem *p = b->p[q];
+        if (!live[q]) continue;
+        const int64_t N = p->Nxi;
+        double2 *H = p->hess;
+        double2 *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *h1 = g + (m + 1), *h2 = h1 + (m + 1),
+                *y = h2 + (m + 1);
+        double *scal = (double *)(y + m + 8);
+        double2 *Vn = p->V + (size_t)(j + 1) * N;
+        CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
+        CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h1, -1.0, Vn, N));
+        CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h2));
+        CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h2, -1.0, Vn, N));
+        CHECK_ST(norm_c128(p, Vn, N, scal + 0));
+        CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
+        CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
+        HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        const double hn = p->host_pinned[0], est = p->host_pinned[2] / bnorm[q];
+        total[q] += 1;
+        nj[q] = j + 1;
+        hist[q].push_back(est);
+        if (!std::isfinite(est) || !std::isfinite(hn)) { status = fail(KF_ENAN, "non-finite value in Arnoldi"); live[q] = false; }
+        else if (hn == 0.0 || est <= o->rtol || total[q] >= o->maxit) live[q] = false;
+      }
+      t_orth += ms_since(tc);
+      bool any = false;
+      for (int q : act) any = any || live[q];
+      if (!any) break;
+    }
+    for (int q : act) {
+      kf_problem *p = b->p[q];
+      double2 *H = p->hess;
+      double2 *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *h1 = g + (m + 1), *h2 = h1 + (m + 1),
+              *y = h2 + (m + 1);
+      (void)cs; (void)sn; (void)h1; (void)h2;
+      CHECK_ST(hess_backsolve(p, nj[q], m, H, g, y));
+      CHECK_ST(multiaxpy_c128(p, p->Z, nj[q], y, 1.0, p->xi_x, p->Nxi));
+      S[q].restarts += 1;
+    }
+  }
+  // updates and statistics
+  for (int q = 0; q < n; ++q) {
+    kf_problem *p = b->p[q];
+    const size_t Ku = (size_t)p->K * p->Nu;
+    const double2 *ds = p->xi_x + Ku;
+    S[q].outer_iters = total[q];
+    for (size_t r = 0; r < hist[q].size() && r < 512; ++r) S[q].rel_res_hist[r] = hist[q][r];
+    double dsn = host_norm(p, ds, p->Ng, &e); CHECK_ST(e);
+    CHECK_ST(imag_part(p, p->Ng, ds, p->vec_a));
+    double dsi = host_norm(p, p->vec_a, p->Ng, &e); CHECK_ST(e);
+    S[q].ds_imag_ratio = dsn > 0 ? dsi / dsn : 0.0;
+    if (xi_out && xi_out[q])
+      HIP_TRY(hipMemcpyAsync(xi_out[q], p->xi_x, sizeof(double2) * p->Nxi, hipMemcpyDeviceToDevice, b->stream));
+    if (gamma_next && gamma_next[q]) {
+      HIP_TRY(hipMemcpyAsync(gamma_next[q], p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, b->stream));
+      CHECK_ST(launch_update_gamma(p, ds, gamma_next[q]));
+    }
+    if (update_in_place) {
+      CHECK_ST(launch_update_gamma(p, ds, p->gamma));
+      p->have_T64 = p->have_T32 = false;
+    }
+    S[q].t_precond_ms = t_cols;    // columns (preconditioner + matvec) of all problems together
+    S[q].t_orth_ms = t_orth;
+  }
+  if (update_in_place) batch_drop_graphs(b);   // the captured solves refer to factors about to change
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int q = 0; q < n; ++q) {
+    S[q].t_total_ms = ms_since(T0);
+    if (st) st[q] = S[q];
+  }
+  return status;
+}

@@ -237,10 +237,9 @@ __device__ __forceinline__ void build_schur(const Grid &g, int m, int i, const d
 // blockIdx.x = 0: left sweep over columns 0..mid-1; 1: right sweep over nx-1..mid+1.
 // mode 1: the middle column (one block).  work: per block an m x m matrix and an
 // NB x m staging area.
-template <int NB, int RMAX, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, double2 *T, double2 *work) {
-  const int mode = MODE;
-  extern __shared__ unsigned char smem[];
+template <int NB, int RMAX>
+__device__ __forceinline__ void blu_factor_body(const Grid &g, int mid, int mode, int side, double2 *T, double2 *work,
+                                                unsigned char *smem) {
   const int m = g.nz;
   double2 *pan = (double2 *)smem;          // [m][NB]
   double2 *x1 = pan + (size_t)m * NB;      // [NB][m]
@@ -249,10 +248,10 @@ __global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, double2 *T, 
   int *piv = (int *)(prow + 2 * NB);       // [m]
   int *perm = piv + m;                     // [m]
   const size_t mm = (size_t)m * m;
-  double2 *S = work + (size_t)blockIdx.x * (mm + (size_t)NB_MAX * m);
+  double2 *S = work + (size_t)side * (mm + (size_t)NB_MAX * m);
   double2 *tmp = S + mm;
   if (mode == 0) {
-    if (blockIdx.x == 0) {
+    if (side == 0) {
       for (int i = 0; i < mid; ++i) {
         build_schur(g, m, i, i > 0 ? T + (size_t)(i - 1) * mm : nullptr, i > 0 ? i : -1, nullptr, -1, S, cw);
         gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, pan, x1, prow, piv, perm, tmp);
@@ -270,6 +269,12 @@ __global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, double2 *T, 
                 hr ? T + (size_t)(mid + 1) * mm : nullptr, hr ? mid + 1 : -1, S, cw);
     gj_invert_store<NB, RMAX>(S, m, T + (size_t)mid * mm, pan, x1, prow, piv, perm, tmp);
   }
+}
+
+template <int NB, int RMAX, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, double2 *T, double2 *work) {
+  extern __shared__ unsigned char smem[];
+  blu_factor_body<NB, RMAX>(g, mid, MODE, blockIdx.x, T, work, smem);
 }
 
 template <typename R> __device__ inline cplx<R> to_r(double2 a) { return mk<R>((R)a.x, (R)a.y); }
@@ -318,17 +323,16 @@ __device__ inline void col_matvec(const cplx<R> *__restrict__ Tt, int m, const c
 // T: factors of type cplx<R> ([nx][m][m], transposed); b, x: IO type [K][nz][nx].
 // Block (roundup64(m), G): thread (j, 0) owns row j of every column vector.
 template <typename R, typename IO, bool ADJ, int NS>
-__global__ void k_blu_fwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x) {
+__device__ __forceinline__ void blu_fwd_body(const Grid &g, int K, int mid, const cplx<R> *__restrict__ T,
+                                             const IO *b, IO *x, int group, int side, unsigned char *smem) {
   using C = cplx<R>;
-  extern __shared__ unsigned char smem[];
   const int m = g.nz;
   C *v = (C *)smem;          // [NS][m] previous y
   C *w = v + NS * m;         // [NS][m] right-hand side of this column
   C *part = w + NS * m;      // [G-1][NS][m] partial sums
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
-  const int k0 = blockIdx.x * NS;
-  const int side = blockIdx.y;
+  const int k0 = group * NS;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
   const int cnt = side == 0 ? mid : g.nx - 1 - mid;
@@ -375,16 +379,15 @@ __global__ void k_blu_fwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
 
 // Middle column: x_mid = T_mid (b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}).
 template <typename R, typename IO, bool ADJ, int NS>
-__global__ void k_blu_mid(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x,
-                          cplx<R> *xmid) {
+__device__ __forceinline__ void blu_mid_body(const Grid &g, int K, int mid, const cplx<R> *__restrict__ T,
+                                             const IO *b, IO *x, cplx<R> *xmid, int group, unsigned char *smem) {
   using C = cplx<R>;
-  extern __shared__ unsigned char smem[];
   const int m = g.nz;
   C *w = (C *)smem;
   C *part = w + 2 * NS * m;
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
-  const int k0 = blockIdx.x * NS;
+  const int k0 = group * NS;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
   if (owner) {
@@ -420,16 +423,15 @@ __global__ void k_blu_mid(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
 // Back-substitution outward from the middle: side 0: x_i = y_i - T_i C_{i+1} x_{i+1}
 // (i = mid-1..0); side 1: x_i = y_i - T_i C_i x_{i-1} (i = mid+1..nx-1).
 template <typename R, typename IO, bool ADJ, int NS>
-__global__ void k_blu_bwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, IO *x, const cplx<R> *xmid) {
+__device__ __forceinline__ void blu_bwd_body(const Grid &g, int K, int mid, const cplx<R> *__restrict__ T, IO *x,
+                                             const cplx<R> *xmid, int group, int side, unsigned char *smem) {
   using C = cplx<R>;
-  extern __shared__ unsigned char smem[];
   const int m = g.nz;
   C *w = (C *)smem;          // [NS][m] coupled previous x
   C *part = w + 2 * NS * m;
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
-  const int k0 = blockIdx.x * NS;
-  const int side = blockIdx.y;
+  const int k0 = group * NS;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
   C xr[NS];
@@ -465,6 +467,82 @@ __global__ void k_blu_bwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T,
     __syncthreads();
   }
 }
+
+template <typename R, typename IO, bool ADJ, int NS>
+__global__ void k_blu_fwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x) {
+  extern __shared__ unsigned char smem[];
+  blu_fwd_body<R, IO, ADJ, NS>(g, K, mid, T, b, x, blockIdx.x, blockIdx.y, smem);
+}
+template <typename R, typename IO, bool ADJ, int NS>
+__global__ void k_blu_mid(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x, cplx<R> *xmid) {
+  extern __shared__ unsigned char smem[];
+  blu_mid_body<R, IO, ADJ, NS>(g, K, mid, T, b, x, xmid, blockIdx.x, smem);
+}
+template <typename R, typename IO, bool ADJ, int NS>
+__global__ void k_blu_bwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, IO *x, const cplx<R> *xmid) {
+  extern __shared__ unsigned char smem[];
+  blu_bwd_body<R, IO, ADJ, NS>(g, K, mid, T, x, xmid, blockIdx.x, blockIdx.y, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work-list kernels for a batch of problems (several frequencies on
+// uneven grids).  A fixed grid of workgroups drains one list of items covering every
+// problem: a workgroup takes the next item index from a device counter, decodes
+// (problem, source group, side) and runs the same body as the single-problem kernel.
+// The loop ends for the whole workgroup at once when the list is exhausted, so every
+// wave reaches the exit.  The counter is cleared by a kernel launched just before.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int next_item(unsigned int *counter, int *slot) {
+  if (threadIdx.x == 0 && threadIdx.y == 0) *slot = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int item = *slot;
+  __syncthreads();
+  return item;
+}
+
+__device__ __forceinline__ int find_problem(const int *first, int nprob, int item) {
+  int q = 0;
+  while (q + 1 < nprob && first[q + 1] <= item) ++q;
+  return q;
+}
+
+template <typename R, typename IO, bool ADJ, int NS, int PHASE>
+__global__ void k_blu_sweep_batch(SweepBatch bt, unsigned int *counter) {
+  extern __shared__ unsigned char smem[];
+  __shared__ int slot;
+  for (;;) {
+    const int item = next_item(counter, &slot);
+    if (item >= bt.total) break;
+    const int q = find_problem(bt.first, bt.n, item);
+    const SweepProblem &pp = bt.p[q];
+    const int local = item - bt.first[q];
+    const cplx<R> *T = (const cplx<R> *)pp.T;
+    if (PHASE == 0)
+      blu_fwd_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.mid, T, (const IO *)pp.b, (IO *)pp.x, local >> 1, local & 1, smem);
+    else if (PHASE == 1)
+      blu_mid_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.mid, T, (const IO *)pp.b, (IO *)pp.x, (cplx<R> *)pp.xmid, local, smem);
+    else
+      blu_bwd_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.mid, T, (IO *)pp.x, (const cplx<R> *)pp.xmid, local >> 1, local & 1,
+                                   smem);
+    __syncthreads();
+  }
+}
+
+template <int NB, int RMAX, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_blu_factor_batch(FactorBatch bt, unsigned int *counter) {
+  extern __shared__ unsigned char smem[];
+  __shared__ int slot;
+  for (;;) {
+    const int item = next_item(counter, &slot);
+    if (item >= bt.total) break;
+    const int q = find_problem(bt.first, bt.n, item);
+    const FactorProblem &pp = bt.p[q];
+    blu_factor_body<NB, RMAX>(pp.g, pp.mid, MODE, item - bt.first[q], pp.T, pp.work, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_u32(unsigned int *c) { *c = 0u; }
 
 // block shape of the sweeps: x covers the rows, y splits each dot product
 inline dim3 sweep_block(int m) {
@@ -576,3 +654,111 @@ kf_status blu_solve_mixed_io(kf_problem *p, int adjoint, const double2 *rhs, dou
   return adjoint ? sweep<float, double2, true>(p, p->T32, rhs, x, p->xmid32)
                  : sweep<float, double2, false>(p, p->T32, rhs, x, p->xmid32);
 }
+
+// ---------------------------------------------------------------------------
+// batch launchers: every problem of the batch in one persistent launch per phase
+// ---------------------------------------------------------------------------
+namespace {
+template <int NB, int RMAX, int NT>
+kf_status factor_batch_launch(const std::vector<kf_problem *> &ps, hipStream_t s, unsigned int *counter, int m_max) {
+  FactorBatch bt{};
+  bt.n = (int)ps.size();
+  size_t smem = (2 * (size_t)m_max * NB + 2 * (size_t)m_max + 2 * NB) * sizeof(double2) + 2 * (size_t)m_max * sizeof(int);
+  HIP_TRY(hipFuncSetAttribute((const void *)k_blu_factor_batch<NB, RMAX, NT, 0>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  HIP_TRY(hipFuncSetAttribute((const void *)k_blu_factor_batch<NB, RMAX, NT, 1>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  for (int mode = 0; mode < 2; ++mode) {
+    int tot = 0;
+    for (int q = 0; q < bt.n; ++q) {
+      kf_problem *p = ps[q];
+      bt.first[q] = tot;
+      bt.p[q] = FactorProblem{p->grid(), p->mid, p->T64, p->fac_work};
+      tot += mode == 0 ? 2 : 1;
+    }
+    bt.first[bt.n] = tot;
+    bt.total = tot;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+    LAUNCH_CHECK();
+    if (mode == 0) hipLaunchKernelGGL((k_blu_factor_batch<NB, RMAX, NT, 0>), dim3(tot), dim3(NT), smem, s, bt, counter);
+    else hipLaunchKernelGGL((k_blu_factor_batch<NB, RMAX, NT, 1>), dim3(tot), dim3(NT), smem, s, bt, counter);
+    LAUNCH_CHECK();
+  }
+  return KF_OK;
+}
+}  // namespace
+
+kf_status blu_factor_batch(const std::vector<kf_problem *> &all, int which, hipStream_t s, unsigned int *counter) {
+  std::vector<kf_problem *> ps;
+  int m_max = 0;
+  for (kf_problem *p : all)
+    if ((which & 3) && !p->have_T64) { ps.push_back(p); m_max = std::max(m_max, p->nz); }
+  if (!ps.empty()) {
+    if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
+    kf_status st = m_max <= 128 ? factor_batch_launch<8, 2, 512>(ps, s, counter, m_max)
+                 : m_max <= 192 ? factor_batch_launch<8, 3, 512>(ps, s, counter, m_max)
+                 : m_max <= 320 ? factor_batch_launch<8, 5, 256>(ps, s, counter, m_max)
+                                : factor_batch_launch<8, 8, 256>(ps, s, counter, m_max);
+    if (st != KF_OK) return st;
+    for (kf_problem *p : ps) p->have_T64 = true;
+  }
+  if (which & 2)
+    for (kf_problem *p : all)
+      if (!p->have_T32) {
+        const size_t mm = (size_t)p->nz * p->nz;
+        kf_status st = launch_copy_c128_to_c64(p, (int64_t)p->nx * mm, p->T64, p->T32);
+        if (st != KF_OK) return st;
+        p->have_T32 = true;
+      }
+  return KF_OK;
+}
+
+// rhs[q], x[q]: IO-typed fields of problem q; R = double uses the FP64 factors, float
+// the complex64 ones.
+template <typename R, typename IO>
+kf_status blu_solve_batch(const std::vector<kf_problem *> &ps, int adjoint, const IO *const *rhs, IO *const *x,
+                          hipStream_t s, unsigned int *counter) {
+  constexpr int NS = 1;
+  const bool fp32 = sizeof(R) == sizeof(float);
+  SweepBatch bt{};
+  bt.n = (int)ps.size();
+  if (bt.n > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
+  int m_max = 0;
+  for (int q = 0; q < bt.n; ++q) {
+    kf_problem *p = ps[q];
+    if (!(fp32 ? p->have_T32 : p->have_T64)) { set_error("batch solve before factorisation"); return KF_ESTATE; }
+    m_max = std::max(m_max, p->nz);
+    bt.p[q] = SweepProblem{p->grid(), p->K, p->mid, fp32 ? (const void *)p->T32 : (const void *)p->T64,
+                           rhs[q], x[q], fp32 ? (void *)p->xmid32 : (void *)p->xmid};
+  }
+  dim3 blk = sweep_block(m_max);
+  size_t smem = (2 + (blk.y - 1)) * NS * m_max * sizeof(cplx<R>);
+  for (int phase = 0; phase < 3; ++phase) {
+    int tot = 0;
+    for (int q = 0; q < bt.n; ++q) {
+      bt.first[q] = tot;
+      const int groups = (ps[q]->K + NS - 1) / NS;
+      tot += phase == 1 ? groups : 2 * groups;
+    }
+    bt.first[bt.n] = tot;
+    bt.total = tot;
+    const unsigned grid = (unsigned)std::min(tot, 1024);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+    LAUNCH_CHECK();
+#define SWEEP_PHASE(PH)                                                                                     \
+  if (adjoint) hipLaunchKernelGGL((k_blu_sweep_batch<R, IO, true, NS, PH>), dim3(grid), blk, smem, s, bt, counter); \
+  else hipLaunchKernelGGL((k_blu_sweep_batch<R, IO, false, NS, PH>), dim3(grid), blk, smem, s, bt, counter);
+    if (phase == 0) { SWEEP_PHASE(0) }
+    else if (phase == 1) { SWEEP_PHASE(1) }
+    else { SWEEP_PHASE(2) }
+#undef SWEEP_PHASE
+    LAUNCH_CHECK();
+  }
+  return KF_OK;
+}
+template kf_status blu_solve_batch<double, double2>(const std::vector<kf_problem *> &, int, const double2 *const *,
+                                                    double2 *const *, hipStream_t, unsigned int *);
+template kf_status blu_solve_batch<float, double2>(const std::vector<kf_problem *> &, int, const double2 *const *,
+                                                   double2 *const *, hipStream_t, unsigned int *);
+template kf_status blu_solve_batch<float, float2>(const std::vector<kf_problem *> &, int, const float2 *const *,
+                                                  float2 *const *, hipStream_t, unsigned int *);

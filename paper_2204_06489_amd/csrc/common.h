@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -81,6 +82,34 @@ __device__ inline Stencil5 stencil_at(const Grid &g, int i, int j) {
 __device__ inline double2 coupling_x(const Grid &g, int i, int j) {
   return cscale(cmul(g.zn[j], g.ixh[i]), -1.0 / (g.h * g.h));
 }
+
+// ---------------------------------------------------------------------------
+// batch descriptors, passed by value to the persistent work-list kernels
+// ---------------------------------------------------------------------------
+constexpr int KF_BATCH_MAX = 8;
+struct SweepProblem {
+  Grid g;
+  int K, mid;
+  const void *T;       // factors (c128 or c64)
+  const void *b;       // right-hand sides (IO type)
+  void *x;             // solutions (IO type)
+  void *xmid;          // middle-column buffer (compute type)
+};
+struct SweepBatch {
+  int n, total;
+  int first[KF_BATCH_MAX + 1];   // first item of each problem (prefix sums)
+  SweepProblem p[KF_BATCH_MAX];
+};
+struct FactorProblem {
+  Grid g;
+  int mid;
+  double2 *T, *work;
+};
+struct FactorBatch {
+  int n, total;
+  int first[KF_BATCH_MAX + 1];
+  FactorProblem p[KF_BATCH_MAX];
+};
 
 // ---------------------------------------------------------------------------
 // problem state
@@ -184,6 +213,12 @@ kf_status launch_copy_c64_to_c128(kf_problem *p, int64_t n, const float2 *x, dou
 kf_status blu_factor(kf_problem *p, int which);
 template <typename R> kf_status blu_solve(kf_problem *p, int adjoint, const cplx<R> *rhs, cplx<R> *x);
 kf_status blu_solve_mixed_io(kf_problem *p, int adjoint, const double2 *rhs, double2 *x);  // c64 factors, c128 I/O
+
+// batches: persistent work-list kernels over several problems (one launch per phase)
+kf_status blu_factor_batch(const std::vector<kf_problem *> &ps, int which, hipStream_t s, unsigned int *counter);
+template <typename R, typename IO>
+kf_status blu_solve_batch(const std::vector<kf_problem *> &ps, int adjoint, const IO *const *rhs, IO *const *x,
+                          hipStream_t s, unsigned int *counter);
 
 // reductions (deterministic, fixed order)
 kf_status per_source_norms(kf_problem *p, const double2 *x, int64_t n_per, int K, double *out_host);

@@ -220,3 +220,78 @@ class KKTProblem:
         n, ms = C.c_int64(), C.c_double()
         check(lib().kf_profile_read(self._h, name.encode(), C.byref(n), C.byref(ms)))
         return int(n.value), float(ms.value)
+
+
+class KKTBatch:
+    """Several problems (e.g. one per frequency, on uneven grids) advanced together.
+
+    Factorisations and block solves of all problems are single persistent launches;
+    ``newton_step`` runs the problems' FGMRES iterations in lockstep, optionally
+    replaying each Krylov column's preconditioner and KKT matvec from a captured
+    hipGraph.  The batch orders all work on one stream (the problems' streams are
+    set to it); destroy the batch before its problems."""
+
+    def __init__(self, problems, stream=None):
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (C.c_void_p * n)(*[q._h.value for q in self.problems])
+        self._b = C.c_void_p()
+        # a stream of the batch's own (None): the library creates a capturable one
+        h = C.c_void_p(stream.cuda_stream) if stream is not None else C.c_void_p(None)
+        check(lib().kf_batch_create(arr, n, h, C.byref(self._b)))
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib().kf_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self, which=1):
+        t = C.c_double()
+        torch.cuda.current_stream().synchronize()
+        check(lib().kf_batch_factor(self._b, int(which), C.byref(t)))
+        return t.value
+
+    def helmholtz_solve(self, rhs, adjoint=False, prec="c128"):
+        pv = _PREC[prec]
+        dt = torch.complex64 if pv == KF_C64 else torch.complex128
+        xs = [torch.empty_like(r) for r in rhs]
+        n = len(self.problems)
+        torch.cuda.current_stream().synchronize()   # inputs from the caller's stream are complete
+        rp = (C.c_void_p * n)(*[_ptr(r, dt, q.K * q.Nu, "rhs").value for r, q in zip(rhs, self.problems)])
+        xp = (C.c_void_p * n)(*[_ptr(x).value for x in xs])
+        check(lib().helmholtz_solve_batched(self._b, int(adjoint), pv, rp, xp))
+        return xs
+
+    def newton_step(self, d_obs, rtol=1e-6, restart=30, maxit=200, pc="exact", update_in_place=True,
+                    use_graph=True, want_xi=True):
+        """Returns (list of xi or None, list of gamma_{n+1}, list of stats dicts)."""
+        n = len(self.problems)
+        o = KfNewtonOpts()
+        o.rtol, o.restart, o.maxit, o.pc = float(rtol), int(restart), int(maxit), _PC[pc]
+        o.fwd_prec, o.fwd_rtol, o.misfit_after = KF_C128, 1e-10, 0
+        xis = [q.empty_xi() for q in self.problems] if want_xi else [None] * n
+        gs = [torch.empty((q.nz, q.nx), dtype=torch.float64, device=q.device) for q in self.problems]
+        dp = (C.c_void_p * n)(*[_ptr(d, torch.complex128, q.K * q.nrec, "d_obs").value
+                                for d, q in zip(d_obs, self.problems)])
+        xp = (C.c_void_p * n)(*[(x.data_ptr() if x is not None else None) for x in xis])
+        gp = (C.c_void_p * n)(*[g.data_ptr() for g in gs])
+        st = (KfNewtonStats * n)()
+        torch.cuda.current_stream().synchronize()   # inputs from the caller's stream are complete
+        s = check(lib().newton_step_batched(self._b, dp, C.byref(o), xp, gp, int(bool(update_in_place)),
+                                            int(bool(use_graph)), st), allow=(KF_ENOCONV,))
+        out = []
+        for k in range(n):
+            d = {f: getattr(st[k], f) for f, _ in KfNewtonStats._fields_ if f != "rel_res_hist"}
+            d["rel_res_hist"] = list(st[k].rel_res_hist[:max(0, st[k].outer_iters)])
+            d["converged"] = s != KF_ENOCONV
+            out.append(d)
+        if update_in_place:
+            for q in self.problems:
+                q.gamma_token = getattr(q, "gamma_token", 0) + 1
+        return xis, gs, out
