@@ -143,6 +143,16 @@ kf_status kf_set_background(kf_problem *p, const void *u_n);
 kf_status kf_get_background(kf_problem *p, void *u_n_out);
 /* Change the stream used by subsequent calls. */
 kf_status kf_set_stream(kf_problem *p, void *hip_stream);
+/* Shape of the block solver (any time; a change invalidates the factorisation).
+ * chunks: the grid columns are cut into `chunks` pieces by chunks - 1 separator columns;
+ * every piece is factorised and swept independently and a block-tridiagonal system on
+ * the separators (their Schur complement) joins them, so more chunks means more parallel
+ * work and shorter sequential sweeps, plus a longer separator chain.  1 <= chunks <=
+ * min(64, (nx + 1) / 2); 0 picks round(sqrt(nx / 2)) (1 below nx = 32).
+ * sources_per_group: right-hand sides per workgroup in the block solves, 1, 2 or 4
+ * (0 = 1).  Results do not depend on either beyond rounding. */
+kf_status kf_set_solver_shape(kf_problem *p, int32_t chunks, int32_t sources_per_group);
+kf_status kf_get_solver_shape(kf_problem *p, int32_t *chunks /*[host]*/, int32_t *sources_per_group /*[host]*/);
 /* Build the block factorisation of A(gamma, omega) now (it is otherwise built on the first
  * solve that needs it).  `which`: bit 0 = FP64 factors, bit 1 = complex64 copy. */
 kf_status kf_factor(kf_problem *p, int32_t which, double *t_ms /*[host], may be NULL*/);

@@ -62,6 +62,8 @@ _SIGNATURES = {
     "kf_get_background": (C.c_int, [P, P]),
     "kf_set_stream": (C.c_int, [P, P]),
     "kf_factor": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double)]),
+    "kf_set_solver_shape": (C.c_int, [P, C.c_int32, C.c_int32]),
+    "kf_get_solver_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "kf_stencil_apply": (C.c_int, [P, C.c_int32, C.c_int32, P, P]),
     "helmholtz_solve": (C.c_int, [P, C.c_int32, C.c_int32, P, P, C.c_double, C.c_int32,
                                   C.POINTER(KfSolveStats)]),

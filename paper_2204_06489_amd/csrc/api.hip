@@ -40,13 +40,13 @@ static hipEvent_t take_event(kf_problem *p) {
   return e;
 }
 ProfScope::ProfScope(kf_problem *p_, int id_) : p(p_), id(id_) {
-  if (!p->prof) return;
+  if (!p || id < 0 || !p->prof) return;
   a = take_event(p);
   b = take_event(p);
   if (a) hipEventRecord(a, p->stream);
 }
 ProfScope::~ProfScope() {
-  if (!p->prof || !a || !b) return;
+  if (!p || id < 0 || !p->prof || !a || !b) return;
   hipEventRecord(b, p->stream);
   p->pending[id].push_back({a, b});
 }
@@ -125,7 +125,8 @@ static void free_all(kf_problem *p) {
   dfree(p->gamma); dfree(p->xn); dfree(p->ixh); dfree(p->zn); dfree(p->izh);
   dfree(p->d_src); dfree(p->d_rnode); dfree(p->d_wsq); dfree(p->d_rec); dfree(p->d_w);
   dfree(p->d_rptr); dfree(p->d_rlist); dfree(p->d_r); dfree(p->d_wr);
-  dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->xmid); dfree(p->xmid32);
+  dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->d_part);
+  dfree(p->V64); dfree(p->W64); dfree(p->V32); dfree(p->W32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
   if (p->host_pinned) hipHostFree(p->host_pinned);
@@ -197,7 +198,6 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   p->Nu = (int64_t)p->nx * p->nz; p->Ng = (int64_t)p->nxc * p->nzc; p->Nxi = 2 * p->K * p->Nu + p->Ng;
   p->h = desc->h; p->omega = desc->omega; p->eps = desc->eps;
   p->stream = (hipStream_t)hip_stream;
-  p->mid = p->nx / 2;
   p->src_ix.assign(desc->src_ix, desc->src_ix + p->K);
   p->src_iz.assign(desc->src_iz, desc->src_iz + p->K);
   p->rec_ix.assign(desc->rec_ix, desc->rec_ix + p->nrec);
@@ -242,8 +242,7 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   p->kkt_groups_max = (int)std::min<size_t>(K, 64);
   ALLOC(p->ys_part, (size_t)p->kkt_groups_max * p->Ng);
   ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m);
-  ALLOC(p->fac_work, 2 * (m * m + 16 * m));
-  ALLOC(p->xmid, K * m); ALLOC(p->xmid32, K * m);
+  ALLOC(p->d_part, 3 * KF_MAX_CHUNKS);
   ALLOC(p->vec_a, K * Nu); ALLOC(p->vec_b, K * Nu); ALLOC(p->vec_c, K * Nu); ALLOC(p->vec_d, K * Nu);
   ALLOC(p->red, (size_t)1024 * 2 * 256 + K * 64);
   ALLOC(p->red_out, std::max<size_t>(K, 1024));
@@ -272,6 +271,7 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   }
   if (st == KF_OK) st = launch_pml(p, p->d);
   if (st == KF_OK && hipStreamSynchronize(p->stream) != hipSuccess) st = fail(KF_EHIP, "stream synchronize failed");
+  if (st == KF_OK) st = blu_set_shape(p, 0, 0);
   if (st != KF_OK) { free_all(p); delete p; return st; }
   *out = p;
   return KF_OK;
@@ -288,6 +288,18 @@ extern "C" kf_status kf_destroy(kf_problem *p) {
 extern "C" kf_status kf_set_stream(kf_problem *p, void *s) {
   CHECK_ST(check_p(p));
   p->stream = (hipStream_t)s;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_set_solver_shape(kf_problem *p, int32_t chunks, int32_t sources_per_group) {
+  CHECK_ST(check_p(p));
+  return blu_set_shape(p, chunks, sources_per_group);
+}
+
+extern "C" kf_status kf_get_solver_shape(kf_problem *p, int32_t *chunks, int32_t *sources_per_group) {
+  CHECK_ST(check_p(p));
+  if (chunks) *chunks = p->P;
+  if (sources_per_group) *sources_per_group = p->ns;
   return KF_OK;
 }
 
@@ -763,7 +775,6 @@ struct kf_batch {
   std::vector<hipStream_t> prev_stream;  // each problem's stream before it joined the batch
   hipStream_t stream = nullptr;
   bool own_stream = false;                // created here (a NULL stream cannot be captured)
-  unsigned int *counter = nullptr;      // work-list counter of the persistent kernels
   std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;  // (Krylov column, problem mask)
   int graph_pc = -1;
 };
@@ -793,7 +804,6 @@ extern "C" kf_status kf_batch_create(kf_problem *const *problems, int32_t n, voi
     b->prev_stream.push_back(p->stream);
     p->stream = b->stream;
   }
-  if (dalloc(&b->counter, 1) != KF_OK) { delete b; return KF_ENOMEM; }
   *out = b;
   return KF_OK;
 }
@@ -802,7 +812,6 @@ extern "C" kf_status kf_batch_destroy(kf_batch *b) {
   if (!b) return KF_OK;
   hipStreamSynchronize(b->stream);
   batch_drop_graphs(b);
-  dfree(b->counter);
   for (size_t q = 0; q < b->p.size(); ++q) b->p[q]->stream = b->prev_stream[q];
   if (b->own_stream) hipStreamDestroy(b->stream);
   delete b;
@@ -813,7 +822,7 @@ extern "C" kf_status kf_batch_factor(kf_batch *b, int32_t which, double *t_ms) {
   if (!b) return fail(KF_EINVAL, "batch is NULL");
   HIP_TRY(hipStreamSynchronize(b->stream));
   auto t0 = std::chrono::steady_clock::now();
-  CHECK_ST(blu_factor_batch(b->p, which, b->stream, b->counter));
+  CHECK_ST(blu_factor_batch(b->p, which, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   if (t_ms) *t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return KF_OK;
@@ -825,13 +834,13 @@ extern "C" kf_status helmholtz_solve_batched(kf_batch *b, int32_t adjoint, int32
   for (size_t q = 0; q < b->p.size(); ++q)
     if (!rhs[q] || !x[q]) return fail(KF_EINVAL, "null field pointer");
   if (prec == KF_C128) {
-    CHECK_ST(blu_factor_batch(b->p, 1, b->stream, b->counter));
+    CHECK_ST(blu_factor_batch(b->p, 1, b->stream));
     CHECK_ST((blu_solve_batch<double, double2>(b->p, adjoint, (const double2 *const *)rhs, (double2 *const *)x,
-                                                b->stream, b->counter)));
+                                                b->stream)));
   } else if (prec == KF_C64) {
-    CHECK_ST(blu_factor_batch(b->p, 3, b->stream, b->counter));
+    CHECK_ST(blu_factor_batch(b->p, 3, b->stream));
     CHECK_ST((blu_solve_batch<float, float2>(b->p, adjoint, (const float2 *const *)rhs, (float2 *const *)x,
-                                              b->stream, b->counter)));
+                                              b->stream)));
   } else {
     return fail(KF_EINVAL, "batched solve supports KF_C128 and KF_C64");
   }
@@ -853,12 +862,12 @@ static kf_status batch_column(kf_batch *b, const std::vector<kf_problem *> &sel,
     zu[q] = p->Z + (size_t)j * N;
     zl[q] = zu[q] + Ku + p->Ng;
   }
-  if (pc == KF_PC_EXACT) CHECK_ST((blu_solve_batch<double, double2>(sel, 1, yu.data(), zl.data(), b->stream, b->counter)));
-  else CHECK_ST((blu_solve_batch<float, double2>(sel, 1, yu.data(), zl.data(), b->stream, b->counter)));
+  if (pc == KF_PC_EXACT) CHECK_ST((blu_solve_batch<double, double2>(sel, 1, yu.data(), zl.data(), b->stream)));
+  else CHECK_ST((blu_solve_batch<float, double2>(sel, 1, yu.data(), zl.data(), b->stream)));
   for (size_t q = 0; q < n; ++q) CHECK_ST(launch_precond_stage2(sel[q], sel[q]->V + (size_t)j * sel[q]->Nxi, zu[q]));
   std::vector<const double2 *> zin(zu.begin(), zu.end());
-  if (pc == KF_PC_EXACT) CHECK_ST((blu_solve_batch<double, double2>(sel, 0, zin.data(), zu.data(), b->stream, b->counter)));
-  else CHECK_ST((blu_solve_batch<float, double2>(sel, 0, zin.data(), zu.data(), b->stream, b->counter)));
+  if (pc == KF_PC_EXACT) CHECK_ST((blu_solve_batch<double, double2>(sel, 0, zin.data(), zu.data(), b->stream)));
+  else CHECK_ST((blu_solve_batch<float, double2>(sel, 0, zin.data(), zu.data(), b->stream)));
   for (size_t q = 0; q < n; ++q) CHECK_ST(launch_kkt_apply(sel[q], zu[q], sel[q]->V + (size_t)(j + 1) * sel[q]->Nxi));
   return KF_OK;
 }
@@ -914,7 +923,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
   for (kf_problem *p : b->p) CHECK_ST(ensure_krylov(p, m));
   HIP_TRY(hipStreamSynchronize(b->stream));
   auto t = std::chrono::steady_clock::now();
-  CHECK_ST(blu_factor_batch(b->p, o->pc == KF_PC_INEXACT ? 3 : 1, b->stream, b->counter));
+  CHECK_ST(blu_factor_batch(b->p, o->pc == KF_PC_INEXACT ? 3 : 1, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   const double t_fac = ms_since(t);
   t = std::chrono::steady_clock::now();
@@ -926,7 +935,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
       f[q] = b->p[q]->vec_c;
       u[q] = b->p[q]->u_n;
     }
-    CHECK_ST((blu_solve_batch<double, double2>(b->p, 0, f.data(), u.data(), b->stream, b->counter)));
+    CHECK_ST((blu_solve_batch<double, double2>(b->p, 0, f.data(), u.data(), b->stream)));
     for (kf_problem *p : b->p) p->have_un = true;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));

@@ -1,23 +1,45 @@
-// Block-tridiagonal LU of the 5-point Helmholtz operator, swept over grid columns
-// from both ends, and the batched forward / adjoint solves built on it.
+// Block-tridiagonal LU of the 5-point Helmholtz operator over grid columns, in a
+// partitioned form that keeps the whole GPU busy, and the batched forward / adjoint
+// solves built on it.
 //
 // With unknowns grouped by grid column i (block size m = nz), A of Section 2 is
 // block tridiagonal:  C_i x_{i-1} + D_i x_i + C_{i+1} x_{i+1} = b_i,
 // D_i the (tridiagonal) column operator and C_i = diag(coupling of column i-1 and
 // column i), the same in both directions because A is complex symmetric.
 //
-// Factorisation (FP64), meeting at column `mid`:
-//   left   S_0 = D_0,            S_i = D_i - C_i T_{i-1} C_i,          i < mid
-//   right  S_{n-1} = D_{n-1},    S_i = D_i - C_{i+1} T_{i+1} C_{i+1},  i > mid
-//   middle S_mid = D_mid - C_mid T_{mid-1} C_mid - C_{mid+1} T_{mid+1} C_{mid+1}
-//   T_i = S_i^-1 (dense Gauss-Jordan with partial pivoting), stored transposed.
-// Solve: forward sweeps from both ends, the middle column, then back-substitution
-// outward.  The adjoint uses A^H = conj(A):  A^H x = b  <=>  A conj(x) = conj(b).
+// Partition.  P - 1 separator columns s_1 < ... < s_{P-1} cut the columns into P
+// chunks; chunk c holds the interior columns [a_c, b_c] and its meeting column mid_c.
+// With the interior unknowns first, A = [A_II A_IS; A_SI A_SS], A_II block diagonal
+// over chunks (each chunk block tridiagonal, Dirichlet at its separators).
+//
+// Factorisation (FP64):
+//  1. every chunk: twisted LU from both ends, meeting at mid_c,
+//       left   S_a = D_a,  S_i = D_i - C_i T_{i-1} C_i               a < i < mid
+//       right  S_b = D_b,  S_i = D_i - C_{i+1} T_{i+1} C_{i+1}       mid < i < b
+//       middle S_mid = D_mid - C_mid T_{mid-1} C_mid - C_{mid+1} T_{mid+1} C_{mid+1}
+//     T_i = S_i^-1 (dense Gauss-Jordan with partial pivoting), stored transposed;
+//  2. spikes: V^c = A_c^-1 E_a C_{a}  and  W^c = A_c^-1 E_b C_{b+1}, the chunk's
+//     response to its left and right separator (m x m per column, by chunk solves
+//     whose m right-hand sides are the coupling weights at one end column);
+//  3. the reduced (Schur complement) system on the separators,
+//       R_jj     = D_{s_j} - C_{s_j} W^{j-1}_{b} - C_{s_j+1} V^{j}_{a}
+//       R_{j,j-1} = -C_{s_j} V^{j-1}_{b},   R_{j,j+1} = -C_{s_j+1} W^{j}_{a},
+//     block LU with S_1 = R_11, S_j = R_jj - R_{j,j-1} U_{j-1}, T_j = S_j^-1,
+//     N_j = T_j R_{j,j-1}, U_j = T_j R_{j,j+1}; T_j, N_j, U_j sit in the separator
+//     column's slots of T, V and W.
+// Solve A x = b:
+//  1. z = A_II^-1 b_I by the chunks' twisted sweeps (all chunks at once);
+//  2. reduced right-hand side g_j = b_{s_j} - C_{s_j} z_{b} - C_{s_j+1} z_{a}, then
+//     y_j = T_j g_j - N_j y_{j-1} and x_j = y_j - U_j x_{j+1} on the separators;
+//  3. x_I = z - V x_{s_left} - W x_{s_right} (every interior column at once).
+// P = 1 is the plain twisted LU of the whole grid.  The adjoint uses
+// A^H = conj(A):  A^H x = b  <=>  A conj(x) = conj(b).
 //
 // Every source shares the factors, so one factorisation per (gamma, omega) serves
 // all K forward and adjoint block solves of the stacked system (Section 2) and
 // every preconditioner application (Section 5).
 #include "common.h"
+
 
 namespace {
 
@@ -234,49 +256,6 @@ __device__ __forceinline__ void build_schur(const Grid &g, int m, int i, const d
   __syncthreads();
 }
 
-// blockIdx.x = 0: left sweep over columns 0..mid-1; 1: right sweep over nx-1..mid+1.
-// mode 1: the middle column (one block).  work: per block an m x m matrix and an
-// NB x m staging area.
-template <int NB, int RMAX>
-__device__ __forceinline__ void blu_factor_body(const Grid &g, int mid, int mode, int side, double2 *T, double2 *work,
-                                                unsigned char *smem) {
-  const int m = g.nz;
-  double2 *pan = (double2 *)smem;          // [m][NB]
-  double2 *x1 = pan + (size_t)m * NB;      // [NB][m]
-  double2 *cw = x1 + (size_t)m * NB;       // [2][m]
-  double2 *prow = cw + 2 * (size_t)m;      // [2][NB] row exchange buffer
-  int *piv = (int *)(prow + 2 * NB);       // [m]
-  int *perm = piv + m;                     // [m]
-  const size_t mm = (size_t)m * m;
-  double2 *S = work + (size_t)side * (mm + (size_t)NB_MAX * m);
-  double2 *tmp = S + mm;
-  if (mode == 0) {
-    if (side == 0) {
-      for (int i = 0; i < mid; ++i) {
-        build_schur(g, m, i, i > 0 ? T + (size_t)(i - 1) * mm : nullptr, i > 0 ? i : -1, nullptr, -1, S, cw);
-        gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, pan, x1, prow, piv, perm, tmp);
-      }
-    } else {
-      for (int i = g.nx - 1; i > mid; --i) {
-        bool has = i + 1 < g.nx;
-        build_schur(g, m, i, has ? T + (size_t)(i + 1) * mm : nullptr, has ? i + 1 : -1, nullptr, -1, S, cw);
-        gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, pan, x1, prow, piv, perm, tmp);
-      }
-    }
-  } else {
-    bool hl = mid > 0, hr = mid + 1 < g.nx;
-    build_schur(g, m, mid, hl ? T + (size_t)(mid - 1) * mm : nullptr, hl ? mid : -1,
-                hr ? T + (size_t)(mid + 1) * mm : nullptr, hr ? mid + 1 : -1, S, cw);
-    gj_invert_store<NB, RMAX>(S, m, T + (size_t)mid * mm, pan, x1, prow, piv, perm, tmp);
-  }
-}
-
-template <int NB, int RMAX, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_blu_factor(Grid g, int mid, double2 *T, double2 *work) {
-  extern __shared__ unsigned char smem[];
-  blu_factor_body<NB, RMAX>(g, mid, MODE, blockIdx.x, T, work, smem);
-}
-
 template <typename R> __device__ inline cplx<R> to_r(double2 a) { return mk<R>((R)a.x, (R)a.y); }
 template <typename R> __device__ inline cplx<R> to_r(float2 a) { return mk<R>((R)a.x, (R)a.y); }
 template <typename IO> __device__ inline IO from_r(double2 a);
@@ -286,10 +265,22 @@ template <typename IO> __device__ inline IO from_r(float2 a);
 template <> __device__ inline double2 from_r<double2>(float2 a) { return make_double2(a.x, a.y); }
 template <> __device__ inline float2 from_r<float2>(float2 a) { return a; }
 
-// y[s][j] = sum_l T_i[j][l] w[s][l] for the rows j = threadIdx.x < m.  The l-range is
+// Solves of A^H run in the conjugated domain: right-hand sides are read conjugated
+// and every value stored in x (intermediate or final) is conjugated on the way in and
+// out, so the phases exchange values through x unchanged.
+template <typename R, bool ADJ, typename IO> __device__ inline cplx<R> ld_io(const IO &v) {
+  cplx<R> r = to_r<R>(v);
+  return ADJ ? cconj(r) : r;
+}
+template <bool ADJ, typename IO, typename C> __device__ inline void st_io(IO &dst, C v) {
+  dst = from_r<IO>(ADJ ? cconj(v) : v);
+}
+
+// y[s][j] = sum_l T[j][l] w[s][l] for the rows j = threadIdx.x < m.  The l-range is
 // split over the blockDim.y wave groups (more loads in flight per column step); the
 // partial sums meet in LDS and the complete result is valid in threads with
-// threadIdx.y == 0.  Tt is T_i stored transposed, so lanes read consecutive rows.
+// threadIdx.y == 0.  Tt is T stored transposed (column-major T), so lanes read
+// consecutive rows.
 template <typename R, int NS>
 __device__ inline void col_matvec(const cplx<R> *__restrict__ Tt, int m, const cplx<R> *w, cplx<R> *part,
                                   cplx<R> (&acc)[NS]) {
@@ -319,12 +310,345 @@ __device__ inline void col_matvec(const cplx<R> *__restrict__ Tt, int m, const c
   }
 }
 
-// Forward sweeps: side 0 computes y_i for i = 0..mid-1, side 1 for i = nx-1..mid+1.
-// T: factors of type cplx<R> ([nx][m][m], transposed); b, x: IO type [K][nz][nx].
-// Block (roundup64(m), G): thread (j, 0) owns row j of every column vector.
+// ---------------------------------------------------------------------------
+// Work items.  One launch covers every item of every problem of a batch (a single
+// problem is a batch of one).  Workgroups are dealt to the 8 XCDs in turn; the item
+// of a workgroup is chosen so that each XCD receives one contiguous range of items,
+// and the items of one chunk (its source groups) share that XCD's L2 copy of the
+// chunk's factors.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int item_of_block(int total) {
+  const int bk = blockIdx.x, x = bk & 7, r = bk >> 3;
+  const int per = total >> 3, rem = total & 7;
+  return x * per + min(x, rem) + r;
+}
+
+__device__ __forceinline__ int find_problem(const int *first, int nprob, int item) {
+  int q = 0;
+  while (q + 1 < nprob && first[q + 1] <= item) ++q;
+  return q;
+}
+
+struct Chunk { int a, b, mid; };
+// part: [P][3] = (a_c, b_c, mid_c); separator j (1..P-1) is column b_{j-1} + 1
+__device__ __forceinline__ Chunk chunk_of(const int *part, int c) { return Chunk{part[3 * c], part[3 * c + 1], part[3 * c + 2]}; }
+__device__ __forceinline__ int separator(const int *part, int j) { return part[3 * (j - 1) + 1] + 1; }
+
+// ---------------------------------------------------------------------------
+// factorisation kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 *work_slot(const FactorProblem &pp, int slot) {
+  const size_t m = pp.g.nz;
+  return pp.work + (size_t)slot * (m * m + (size_t)NB_MAX * m);
+}
+
+struct FacLds {
+  double2 *pan, *x1, *cw, *prow;
+  int *piv, *perm;
+};
+template <int NB> __device__ __forceinline__ FacLds fac_lds(unsigned char *smem, int m) {
+  FacLds L;
+  L.pan = (double2 *)smem;                 // [m][NB]
+  L.x1 = L.pan + (size_t)m * NB;           // [NB][m]
+  L.cw = L.x1 + (size_t)m * NB;            // [2][m]
+  L.prow = L.cw + 2 * (size_t)m;           // [2][NB] row exchange buffer
+  L.piv = (int *)(L.prow + 2 * NB);        // [m]
+  L.perm = L.piv + m;                      // [m]
+  return L;
+}
+
+// side 0: left sweep over a..mid-1; side 1: right sweep over b..mid+1.  S: an m x m
+// work matrix followed by an NB_MAX x m staging area.
+template <int NB, int RMAX>
+__device__ __forceinline__ void factor_side_body(const Grid &g, Chunk ch, int side, double2 *T, double2 *S,
+                                                 unsigned char *smem) {
+  const int m = g.nz;
+  const size_t mm = (size_t)m * m;
+  FacLds L = fac_lds<NB>(smem, m);
+  double2 *tmp = S + mm;
+  if (side == 0) {
+    for (int i = ch.a; i < ch.mid; ++i) {
+      const bool has = i > ch.a;
+      build_schur(g, m, i, has ? T + (size_t)(i - 1) * mm : nullptr, has ? i : -1, nullptr, -1, S, L.cw);
+      gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, L.pan, L.x1, L.prow, L.piv, L.perm, tmp);
+    }
+  } else {
+    for (int i = ch.b; i > ch.mid; --i) {
+      const bool has = i < ch.b;
+      build_schur(g, m, i, has ? T + (size_t)(i + 1) * mm : nullptr, has ? i + 1 : -1, nullptr, -1, S, L.cw);
+      gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, L.pan, L.x1, L.prow, L.piv, L.perm, tmp);
+    }
+  }
+}
+
+template <int NB, int RMAX>
+__device__ __forceinline__ void factor_mid_body(const Grid &g, Chunk ch, double2 *T, double2 *S, unsigned char *smem) {
+  const int m = g.nz;
+  const size_t mm = (size_t)m * m;
+  FacLds L = fac_lds<NB>(smem, m);
+  const bool hl = ch.mid > ch.a, hr = ch.mid < ch.b;
+  build_schur(g, m, ch.mid, hl ? T + (size_t)(ch.mid - 1) * mm : nullptr, hl ? ch.mid : -1,
+              hr ? T + (size_t)(ch.mid + 1) * mm : nullptr, hr ? ch.mid + 1 : -1, S, L.cw);
+  gj_invert_store<NB, RMAX>(S, m, T + (size_t)ch.mid * mm, L.pan, L.x1, L.prow, L.piv, L.perm, S + mm);
+}
+
+// MODE 0: item = (chunk, side); MODE 1: item = chunk (its middle column)
+template <int NB, int RMAX, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_factor_chunks(FactorBatch bt) {
+  extern __shared__ unsigned char smem[];
+  const int item = item_of_block(bt.total);
+  const int q = find_problem(bt.first, bt.n, item);
+  const FactorProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  if (MODE == 0)
+    factor_side_body<NB, RMAX>(pp.g, chunk_of(pp.part, local >> 1), local & 1, pp.T, work_slot(pp, local), smem);
+  else
+    factor_mid_body<NB, RMAX>(pp.g, chunk_of(pp.part, local), pp.T, work_slot(pp, 2 * local), smem);
+}
+
+// Spike of chunk ch for the right-hand-side columns s0 .. s0+NSP-1:
+//   which 0: V = A_c^-1 E_a C_a     (unit coupling weights at column a)
+//   which 1: W = A_c^-1 E_b C_{b+1} (at column b)
+// by the chunk's twisted solve: forward from the loaded end to mid, the middle
+// column, then back-substitution on both sides (the unloaded side's forward values
+// are zero).  Out[i] holds the m x m block of column i, transposed like T.
+template <int NSP>
+__device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, int s0, const double2 *__restrict__ T,
+                                           double2 *Out, unsigned char *smem) {
+  using C = double2;
+  const int m = g.nz;
+  const size_t mm = (size_t)m * m;
+  C *w = (C *)smem;          // [NSP][m]
+  C *part = w + NSP * m;     // [G-1][NSP][m]
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
+  const int ecol = which == 0 ? ch.a : ch.b + 1;   // coupling column of the unit right-hand side
+  const int rcol = which == 0 ? ch.a : ch.b;       // column it sits in
+  C rhs[NSP], cur[NSP], xm[NSP];
+#pragma unroll
+  for (int t = 0; t < NSP; ++t) {
+    rhs[t] = (owner && j == s0 + t) ? coupling_x(g, ecol, j) : make_double2(0.0, 0.0);
+    cur[t] = make_double2(0.0, 0.0);
+  }
+  auto store = [&](int i, int t, C v) {
+    if (owner && s0 + t < m) Out[(size_t)i * mm + (size_t)(s0 + t) * m + j] = v;
+  };
+  // forward sweep from the loaded end
+  const int fcnt = which == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+  for (int step = 0; step < fcnt; ++step) {
+    const int i = which == 0 ? ch.a + step : ch.b - step;
+    const int cc = which == 0 ? i : i + 1;
+    if (owner) {
+      const C cj = coupling_x(g, cc, j);
+#pragma unroll
+      for (int t = 0; t < NSP; ++t) w[t * m + j] = step == 0 ? rhs[t] : csub(make_double2(0.0, 0.0), cmul(cj, cur[t]));
+    }
+    __syncthreads();
+    C acc[NSP];
+    col_matvec<double, NSP>(T + (size_t)i * mm, m, w, part, acc);
+#pragma unroll
+    for (int t = 0; t < NSP; ++t) {
+      cur[t] = acc[t];
+      store(i, t, acc[t]);
+    }
+    __syncthreads();
+  }
+  // middle column
+  if (owner) {
+    const int cc = which == 0 ? ch.mid : ch.mid + 1;
+    const C cj = fcnt > 0 ? coupling_x(g, cc, j) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < NSP; ++t) {
+      C r = rcol == ch.mid ? rhs[t] : make_double2(0.0, 0.0);
+      if (fcnt > 0) r = csub(r, cmul(cj, cur[t]));
+      w[t * m + j] = r;
+    }
+  }
+  __syncthreads();
+  {
+    C acc[NSP];
+    col_matvec<double, NSP>(T + (size_t)ch.mid * mm, m, w, part, acc);
+#pragma unroll
+    for (int t = 0; t < NSP; ++t) {
+      xm[t] = acc[t];
+      store(ch.mid, t, acc[t]);
+    }
+  }
+  __syncthreads();
+  // back-substitution outward: x_i = y_i - T_i C x_prev (y_i = 0 on the unloaded side)
+  for (int side = 0; side < 2; ++side) {
+    const bool loaded = (side == 0) == (which == 0);
+    const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+#pragma unroll
+    for (int t = 0; t < NSP; ++t) cur[t] = xm[t];
+    for (int step = 0; step < cnt; ++step) {
+      const int i = side == 0 ? ch.mid - 1 - step : ch.mid + 1 + step;
+      const int cc = side == 0 ? i + 1 : i;
+      C y[NSP];
+      if (owner) {
+        const C cj = coupling_x(g, cc, j);
+#pragma unroll
+        for (int t = 0; t < NSP; ++t) {
+          w[t * m + j] = cmul(cj, cur[t]);
+          y[t] = (loaded && s0 + t < m) ? Out[(size_t)i * mm + (size_t)(s0 + t) * m + j] : make_double2(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+      C acc[NSP];
+      col_matvec<double, NSP>(T + (size_t)i * mm, m, w, part, acc);
+      if (owner)
+#pragma unroll
+        for (int t = 0; t < NSP; ++t) {
+          cur[t] = csub(y[t], acc[t]);
+          store(i, t, cur[t]);
+        }
+      __syncthreads();
+    }
+  }
+}
+
+// item = (spike job, column group); jobs 0..P-2: W of chunks 0..P-2, then V of
+// chunks 1..P-1.
+template <int NSP>
+__global__ void k_spikes(FactorBatch bt) {
+  extern __shared__ unsigned char smem[];
+  const int item = item_of_block(bt.total);
+  const int q = find_problem(bt.first, bt.n, item);
+  const FactorProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int gm = (pp.g.nz + NSP - 1) / NSP;
+  const int job = local / gm, grp = local - job * gm;
+  const int which = job < pp.P - 1 ? 1 : 0;
+  const int c = which == 1 ? job : job - (pp.P - 1) + 1;
+  spike_body<NSP>(pp.g, chunk_of(pp.part, c), which, grp * NSP, pp.T, which == 0 ? pp.V : pp.W, smem);
+}
+
+// ---- reduced system on the separators (one step j for every problem that has it) ----
+// Z = alpha X diag(d) Y, column-major m x m (d_k = coupling weight of column dcol, or 1)
+struct GemmJob {
+  Grid g;
+  int dcol;
+  double alpha;
+  const double2 *X, *Y;
+  double2 *Z;
+};
+constexpr int GEMM_JOBS_MAX = 2 * KF_BATCH_MAX;
+struct GemmBatch {
+  int n;
+  GemmJob j[GEMM_JOBS_MAX];
+};
+
+// 32 x 32 output tile per workgroup, k in slabs of 16 through LDS; each of the 256
+// threads owns a 2 x 2 block of the tile.
+__global__ __launch_bounds__(256) void k_gemm_cm(GemmBatch gb) {
+  const GemmJob &J = gb.j[blockIdx.y];
+  const int m = J.g.nz;
+  const int nt = (m + 31) / 32;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int r0 = (blockIdx.x % nt) * 32, c0 = (blockIdx.x / nt) * 32;
+  __shared__ double2 xs[16][33], ys[16][33];
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
+  double2 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = t + 256 * u;
+      {  // X[r0 + rr][k0 + kk] (column-major: contiguous in rr)
+        const int kk = e >> 5, rr = e & 31;
+        const int r = r0 + rr, k = k0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (r < m && k < m) {
+          v = J.X[(size_t)k * m + r];
+          if (J.dcol >= 0) v = cmul(v, coupling_x(J.g, J.dcol, k));
+        }
+        xs[kk][rr] = v;
+      }
+      {  // Y[k0 + kk][c0 + cc] (contiguous in kk)
+        const int cc = e >> 4, kk = e & 15;
+        const int c = c0 + cc, k = k0 + kk;
+        ys[kk][cc] = (c < m && k < m) ? J.Y[(size_t)c * m + k] : make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double2 x0 = xs[kk][tr], x1 = xs[kk][tr + 16];
+      const double2 y0 = ys[kk][tc], y1 = ys[kk][tc + 16];
+      cfma(acc[0][0], x0, y0);
+      cfma(acc[0][1], x0, y1);
+      cfma(acc[1][0], x1, y0);
+      cfma(acc[1][1], x1, y1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int r = r0 + tr + 16 * a, c = c0 + tc + 16 * b;
+      if (r < m && c < m) J.Z[(size_t)c * m + r] = cscale(acc[a][b], J.alpha);
+    }
+}
+
+// S_j (row-major) = D_s - C_s (W^{j-1}_b - G1) - C_{s+1} V^j_a, s = s_j; G1 = V^{j-1}_b U_{j-1}
+// (absent for j = 1).  All m x m inputs column-major.
+struct ReducedJob {
+  Grid g;
+  int sep;
+  const double2 *Wb, *Va, *G1;
+  double2 *S;
+};
+struct ReducedBatch {
+  int n;
+  ReducedJob j[KF_BATCH_MAX];
+};
+
+__global__ void k_reduced_S(ReducedBatch rb) {
+  const ReducedJob &J = rb.j[blockIdx.y];
+  const int m = J.g.nz;
+  const size_t mm = (size_t)m * m;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (size_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e / m), r = (int)(e % m);
+    double2 wv = J.Wb[e];
+    if (J.G1) wv = csub(wv, J.G1[e]);
+    double2 v = csub(make_double2(0.0, 0.0), cmul(coupling_x(J.g, J.sep, r), wv));
+    v = csub(v, cmul(coupling_x(J.g, J.sep + 1, r), J.Va[e]));
+    if (l >= r - 1 && l <= r + 1) {
+      const Stencil5 s = stencil_at(J.g, J.sep, r);
+      v = cadd(v, l == r ? s.cc : (l < r ? s.czm : s.czp));
+    }
+    J.S[(size_t)r * m + l] = v;
+  }
+}
+
+struct InvertJob {
+  int m;
+  double2 *S, *Tout;   // S: m x m row-major followed by NB_MAX x m staging
+};
+struct InvertBatch {
+  int n;
+  InvertJob j[KF_BATCH_MAX];
+};
+template <int NB, int RMAX, int NT>
+__global__ __launch_bounds__(NT) void k_invert(InvertBatch ib) {
+  extern __shared__ unsigned char smem[];
+  const InvertJob &J = ib.j[blockIdx.x];
+  FacLds L = fac_lds<NB>(smem, J.m);
+  gj_invert_store<NB, RMAX>(J.S, J.m, J.Tout, L.pan, L.x1, L.prow, L.piv, L.perm, J.S + (size_t)J.m * J.m);
+}
+
+// ---------------------------------------------------------------------------
+// solve phases (R: compute type, IO: storage type of b and x)
+// ---------------------------------------------------------------------------
+// 0: chunk forward sweeps, item (chunk, side, group): side 0 computes y_i for
+//    i = a..mid-1, side 1 for i = b..mid+1
 template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void blu_fwd_body(const Grid &g, int K, int mid, const cplx<R> *__restrict__ T,
-                                             const IO *b, IO *x, int group, int side, unsigned char *smem) {
+__device__ __forceinline__ void fwd_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, const IO *b,
+                                         IO *x, int group, int side, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
   C *v = (C *)smem;          // [NS][m] previous y
@@ -335,8 +659,8 @@ __device__ __forceinline__ void blu_fwd_body(const Grid &g, int K, int mid, cons
   const int k0 = group * NS;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
-  const int cnt = side == 0 ? mid : g.nx - 1 - mid;
-  auto col_of = [&](int step) { return side == 0 ? step : g.nx - 1 - step; };
+  const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+  auto col_of = [&](int step) { return side == 0 ? ch.a + step : ch.b - step; };
   IO bnext[NS];
   if (owner && cnt > 0)
 #pragma unroll
@@ -351,8 +675,7 @@ __device__ __forceinline__ void blu_fwd_body(const Grid &g, int K, int mid, cons
       for (int s = 0; s < NS; ++s) {
         C r = mk<R>(0, 0);
         if (k0 + s < K) {
-          r = to_r<R>(bnext[s]);
-          if (ADJ) r = cconj(r);
+          r = ld_io<R, ADJ>(bnext[s]);
           if (step > 0) r = csub(r, cmul(cj, v[s * m + j]));
         }
         w[s * m + j] = r;
@@ -370,17 +693,101 @@ __device__ __forceinline__ void blu_fwd_body(const Grid &g, int K, int mid, cons
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         v[s * m + j] = acc[s];
-        if (k0 + s < K) x[(k0 + s) * Nu + (size_t)j * g.nx + i] = from_r<IO>(acc[s]);
+        if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i], acc[s]);
       }
     }
     __syncthreads();
   }
 }
 
-// Middle column: x_mid = T_mid (b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}).
+// 1: middle column of each chunk, x_mid = T_mid (b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1})
 template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void blu_mid_body(const Grid &g, int K, int mid, const cplx<R> *__restrict__ T,
-                                             const IO *b, IO *x, cplx<R> *xmid, int group, unsigned char *smem) {
+__device__ __forceinline__ void mid_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, const IO *b,
+                                         IO *x, int group, unsigned char *smem) {
+  using C = cplx<R>;
+  const int m = g.nz;
+  C *w = (C *)smem;
+  C *part = w + 2 * NS * m;
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
+  const int k0 = group * NS;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t mm = (size_t)m * m;
+  const int i = ch.mid;
+  if (owner) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int k = k0 + s;
+      C r = mk<R>(0, 0);
+      if (k < K) {
+        const size_t base = k * Nu + (size_t)j * g.nx;
+        r = ld_io<R, ADJ>(b[base + i]);
+        if (i > ch.a) r = csub(r, cmul(to_r<R>(coupling_x(g, i, j)), ld_io<R, ADJ>(x[base + i - 1])));
+        if (i < ch.b) r = csub(r, cmul(to_r<R>(coupling_x(g, i + 1, j)), ld_io<R, ADJ>(x[base + i + 1])));
+      }
+      w[s * m + j] = r;
+    }
+  }
+  __syncthreads();
+  C acc[NS];
+  col_matvec<R, NS>(T + (size_t)i * mm, m, w, part, acc);
+  if (owner)
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i], acc[s]);
+}
+
+// 2: back-substitution outward from the middle: side 0: x_i = y_i - T_i C_{i+1} x_{i+1}
+//    (i = mid-1..a); side 1: x_i = y_i - T_i C_i x_{i-1} (i = mid+1..b)
+template <typename R, typename IO, bool ADJ, int NS>
+__device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, IO *x,
+                                         int group, int side, unsigned char *smem) {
+  using C = cplx<R>;
+  const int m = g.nz;
+  C *w = (C *)smem;          // [NS][m] coupled previous x
+  C *part = w + 2 * NS * m;
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
+  const int k0 = group * NS;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t mm = (size_t)m * m;
+  const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+  C xr[NS];
+  if (owner && cnt > 0)
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      xr[s] = (k0 + s < K) ? ld_io<R, ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + ch.mid]) : mk<R>(0, 0);
+  for (int step = 0; step < cnt; ++step) {
+    const int i = side == 0 ? ch.mid - 1 - step : ch.mid + 1 + step;
+    const int cc = side == 0 ? i + 1 : i;
+    C yv[NS];
+    if (owner) {
+      C cj = to_r<R>(coupling_x(g, cc, j));
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        w[s * m + j] = cmul(cj, xr[s]);
+        yv[s] = (k0 + s < K) ? ld_io<R, ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i]) : mk<R>(0, 0);
+      }
+    }
+    __syncthreads();
+    C acc[NS];
+    col_matvec<R, NS>(T + (size_t)i * mm, m, w, part, acc);
+    if (owner) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        xr[s] = csub(yv[s], acc[s]);
+        if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i], xr[s]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// 3: reduced right-hand side of separator j, t_j = T_j (b_s - C_s z_{s-1} - C_{s+1} z_{s+1}),
+//    stored at column s
+template <typename R, typename IO, bool ADJ, int NS>
+__device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, const cplx<R> *__restrict__ T,
+                                             const IO *b, IO *x, int group, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
   C *w = (C *)smem;
@@ -391,158 +798,169 @@ __device__ __forceinline__ void blu_mid_body(const Grid &g, int K, int mid, cons
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
   if (owner) {
+    const C cl = to_r<R>(coupling_x(g, s_col, j)), cr = to_r<R>(coupling_x(g, s_col + 1, j));
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      int k = k0 + s;
       C r = mk<R>(0, 0);
-      if (k < K) {
-        const size_t base = k * Nu + (size_t)j * g.nx;
-        r = to_r<R>(b[base + mid]);
-        if (ADJ) r = cconj(r);
-        if (mid > 0) r = csub(r, cmul(to_r<R>(coupling_x(g, mid, j)), to_r<R>(x[base + mid - 1])));
-        if (mid + 1 < g.nx) r = csub(r, cmul(to_r<R>(coupling_x(g, mid + 1, j)), to_r<R>(x[base + mid + 1])));
+      if (k0 + s < K) {
+        const size_t base = (k0 + s) * Nu + (size_t)j * g.nx + s_col;
+        r = ld_io<R, ADJ>(b[base]);
+        r = csub(r, cmul(cl, ld_io<R, ADJ>(x[base - 1])));
+        r = csub(r, cmul(cr, ld_io<R, ADJ>(x[base + 1])));
       }
       w[s * m + j] = r;
     }
   }
   __syncthreads();
   C acc[NS];
-  col_matvec<R, NS>(T + (size_t)mid * mm, m, w, part, acc);
-  if (owner) {
+  col_matvec<R, NS>(T + (size_t)s_col * mm, m, w, part, acc);
+  if (owner)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      int k = k0 + s;
-      if (k < K) {
-        xmid[(size_t)k * m + j] = acc[s];
-        x[k * Nu + (size_t)j * g.nx + mid] = from_r<IO>(ADJ ? cconj(acc[s]) : acc[s]);
-      }
-    }
-  }
+    for (int s = 0; s < NS; ++s)
+      if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + s_col], acc[s]);
 }
 
-// Back-substitution outward from the middle: side 0: x_i = y_i - T_i C_{i+1} x_{i+1}
-// (i = mid-1..0); side 1: x_i = y_i - T_i C_i x_{i-1} (i = mid+1..nx-1).
+// 4: the separators' block LU: y_j = t_j - N_j y_{j-1} (j = 2..P-1), then
+//    x_j = y_j - U_j x_{j+1} (j = P-2..1); N_j, U_j in the V, W slots of column s_j
 template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void blu_bwd_body(const Grid &g, int K, int mid, const cplx<R> *__restrict__ T, IO *x,
-                                             const cplx<R> *xmid, int group, int side, unsigned char *smem) {
+__device__ __forceinline__ void red_chain_body(const Grid &g, int K, int P, const int *part_cols,
+                                               const cplx<R> *__restrict__ V, const cplx<R> *__restrict__ W, IO *x,
+                                               int group, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
-  C *w = (C *)smem;          // [NS][m] coupled previous x
+  C *w = (C *)smem;
   C *part = w + 2 * NS * m;
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
-  C xr[NS];
+  auto at = [&](int s, int col) -> IO & { return x[(k0 + s) * Nu + (size_t)j * g.nx + col]; };
+  C cur[NS];
   if (owner)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) xr[s] = (k0 + s < K) ? xmid[(size_t)(k0 + s) * m + j] : mk<R>(0, 0);
-  const int cnt = side == 0 ? mid : g.nx - 1 - mid;
-  for (int step = 0; step < cnt; ++step) {
-    const int i = side == 0 ? mid - 1 - step : mid + 1 + step;
-    const int cc = side == 0 ? i + 1 : i;
-    IO yv[NS];
-    if (owner) {
-      C cj = to_r<R>(coupling_x(g, cc, j));
+    for (int s = 0; s < NS; ++s) cur[s] = (k0 + s < K) ? ld_io<R, ADJ>(at(s, separator(part_cols, 1))) : mk<R>(0, 0);
+  for (int jj = 2; jj < P; ++jj) {
+    const int sc = separator(part_cols, jj);
+    C t[NS];
+    if (owner)
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        w[s * m + j] = cmul(cj, xr[s]);
-        if (k0 + s < K) yv[s] = x[(k0 + s) * Nu + (size_t)j * g.nx + i];   // y_i, used after the matvec
+        w[s * m + j] = cur[s];
+        t[s] = (k0 + s < K) ? ld_io<R, ADJ>(at(s, sc)) : mk<R>(0, 0);
       }
-    }
     __syncthreads();
     C acc[NS];
-    col_matvec<R, NS>(T + (size_t)i * mm, m, w, part, acc);
-    if (owner) {
+    col_matvec<R, NS>(V + (size_t)sc * mm, m, w, part, acc);
+    if (owner)
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (k0 + s < K) {
-          C xi = csub(to_r<R>(yv[s]), acc[s]);
-          xr[s] = xi;
-          x[(k0 + s) * Nu + (size_t)j * g.nx + i] = from_r<IO>(ADJ ? cconj(xi) : xi);
-        }
+        cur[s] = csub(t[s], acc[s]);
+        if (k0 + s < K) st_io<ADJ>(at(s, sc), cur[s]);
       }
+    __syncthreads();
+  }
+  for (int jj = P - 2; jj >= 1; --jj) {
+    const int sc = separator(part_cols, jj);
+    C t[NS];
+    if (owner)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        w[s * m + j] = cur[s];
+        t[s] = (k0 + s < K) ? ld_io<R, ADJ>(at(s, sc)) : mk<R>(0, 0);
+      }
+    __syncthreads();
+    C acc[NS];
+    col_matvec<R, NS>(W + (size_t)sc * mm, m, w, part, acc);
+    if (owner)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        cur[s] = csub(t[s], acc[s]);
+        if (k0 + s < K) st_io<ADJ>(at(s, sc), cur[s]);
+      }
+    __syncthreads();
+  }
+}
+
+// 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}, item (chunk,
+//    block of CB columns, group)
+constexpr int CORR_CB = 4;
+template <typename R, typename IO, bool ADJ, int NS>
+__device__ __forceinline__ void correct_body(const Grid &g, int K, int P, const int *part_cols, int c, int blk,
+                                             const cplx<R> *__restrict__ V, const cplx<R> *__restrict__ W, IO *x,
+                                             int group, unsigned char *smem) {
+  using C = cplx<R>;
+  const Chunk ch = chunk_of(part_cols, c);
+  const int i0 = ch.a + blk * CORR_CB;
+  if (i0 > ch.b) return;   // uniform over the workgroup
+  const int i1 = min(ch.b, i0 + CORR_CB - 1);
+  const int m = g.nz;
+  C *wl = (C *)smem;         // [NS][m]
+  C *wr = wl + NS * m;       // [NS][m]
+  C *part = wr + NS * m;
+  const int j = threadIdx.x;
+  const bool owner = threadIdx.y == 0 && j < m;
+  const int k0 = group * NS;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t mm = (size_t)m * m;
+  const bool hl = c > 0, hr = c < P - 1;
+  const int sl = hl ? ch.a - 1 : 0, sr = hr ? ch.b + 1 : 0;
+  if (owner)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bool in = k0 + s < K;
+      const size_t base = (k0 + s) * Nu + (size_t)j * g.nx;
+      wl[s * m + j] = (in && hl) ? ld_io<R, ADJ>(x[base + sl]) : mk<R>(0, 0);
+      wr[s * m + j] = (in && hr) ? ld_io<R, ADJ>(x[base + sr]) : mk<R>(0, 0);
     }
-    __syncthreads();
-  }
-}
-
-template <typename R, typename IO, bool ADJ, int NS>
-__global__ void k_blu_fwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x) {
-  extern __shared__ unsigned char smem[];
-  blu_fwd_body<R, IO, ADJ, NS>(g, K, mid, T, b, x, blockIdx.x, blockIdx.y, smem);
-}
-template <typename R, typename IO, bool ADJ, int NS>
-__global__ void k_blu_mid(Grid g, int K, int mid, const cplx<R> *__restrict__ T, const IO *b, IO *x, cplx<R> *xmid) {
-  extern __shared__ unsigned char smem[];
-  blu_mid_body<R, IO, ADJ, NS>(g, K, mid, T, b, x, xmid, blockIdx.x, smem);
-}
-template <typename R, typename IO, bool ADJ, int NS>
-__global__ void k_blu_bwd(Grid g, int K, int mid, const cplx<R> *__restrict__ T, IO *x, const cplx<R> *xmid) {
-  extern __shared__ unsigned char smem[];
-  blu_bwd_body<R, IO, ADJ, NS>(g, K, mid, T, x, xmid, blockIdx.x, blockIdx.y, smem);
-}
-
-// ---------------------------------------------------------------------------
-// Persistent work-list kernels for a batch of problems (several frequencies on
-// uneven grids).  A fixed grid of workgroups drains one list of items covering every
-// problem: a workgroup takes the next item index from a device counter, decodes
-// (problem, source group, side) and runs the same body as the single-problem kernel.
-// The loop ends for the whole workgroup at once when the list is exhausted, so every
-// wave reaches the exit.  The counter is cleared by a kernel launched just before.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int next_item(unsigned int *counter, int *slot) {
-  if (threadIdx.x == 0 && threadIdx.y == 0) *slot = (int)atomicAdd(counter, 1u);
   __syncthreads();
-  const int item = *slot;
-  __syncthreads();
-  return item;
-}
-
-__device__ __forceinline__ int find_problem(const int *first, int nprob, int item) {
-  int q = 0;
-  while (q + 1 < nprob && first[q + 1] <= item) ++q;
-  return q;
-}
-
-template <typename R, typename IO, bool ADJ, int NS, int PHASE>
-__global__ void k_blu_sweep_batch(SweepBatch bt, unsigned int *counter) {
-  extern __shared__ unsigned char smem[];
-  __shared__ int slot;
-  for (;;) {
-    const int item = next_item(counter, &slot);
-    if (item >= bt.total) break;
-    const int q = find_problem(bt.first, bt.n, item);
-    const SweepProblem &pp = bt.p[q];
-    const int local = item - bt.first[q];
-    const cplx<R> *T = (const cplx<R> *)pp.T;
-    if (PHASE == 0)
-      blu_fwd_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.mid, T, (const IO *)pp.b, (IO *)pp.x, local >> 1, local & 1, smem);
-    else if (PHASE == 1)
-      blu_mid_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.mid, T, (const IO *)pp.b, (IO *)pp.x, (cplx<R> *)pp.xmid, local, smem);
-    else
-      blu_bwd_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.mid, T, (IO *)pp.x, (const cplx<R> *)pp.xmid, local >> 1, local & 1,
-                                   smem);
+  for (int i = i0; i <= i1; ++i) {
+    C acc[NS], acc2[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
+    if (hl) col_matvec<R, NS>(V + (size_t)i * mm, m, wl, part, acc);
+    if (hl && hr) __syncthreads();   // part is reused
+    if (hr) {
+      col_matvec<R, NS>(W + (size_t)i * mm, m, wr, part, acc2);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[s] = cadd(acc[s], acc2[s]);
+    }
+    if (owner)
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (k0 + s < K) {
+          IO &d = x[(k0 + s) * Nu + (size_t)j * g.nx + i];
+          st_io<ADJ>(d, csub(ld_io<R, ADJ>(d), acc[s]));
+        }
     __syncthreads();
   }
 }
 
-template <int NB, int RMAX, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_blu_factor_batch(FactorBatch bt, unsigned int *counter) {
+template <typename R, typename IO, bool ADJ, int NS, int PH>
+__global__ void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
-  __shared__ int slot;
-  for (;;) {
-    const int item = next_item(counter, &slot);
-    if (item >= bt.total) break;
-    const int q = find_problem(bt.first, bt.n, item);
-    const FactorProblem &pp = bt.p[q];
-    blu_factor_body<NB, RMAX>(pp.g, pp.mid, MODE, item - bt.first[q], pp.T, pp.work, smem);
-    __syncthreads();
-  }
+  const int item = item_of_block(bt.total);
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int G = (pp.K + NS - 1) / NS;
+  const int grp = local % G, rest = local / G;
+  const cplx<R> *T = (const cplx<R> *)pp.T;
+  if (PH == 0)
+    fwd_body<R, IO, ADJ, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, (const IO *)pp.b, (IO *)pp.x, grp, rest & 1, smem);
+  else if (PH == 1)
+    mid_body<R, IO, ADJ, NS>(pp.g, pp.K, chunk_of(pp.part, rest), T, (const IO *)pp.b, (IO *)pp.x, grp, smem);
+  else if (PH == 2)
+    bwd_body<R, IO, ADJ, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, (IO *)pp.x, grp, rest & 1, smem);
+  else if (PH == 3)
+    red_rhs_body<R, IO, ADJ, NS>(pp.g, pp.K, separator(pp.part, rest + 1), T, (const IO *)pp.b, (IO *)pp.x, grp, smem);
+  else if (PH == 4)
+    red_chain_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.P, pp.part, (const cplx<R> *)pp.V, (const cplx<R> *)pp.W,
+                                   (IO *)pp.x, grp, smem);
+  else
+    correct_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.P, pp.part, rest / pp.ncb, rest % pp.ncb, (const cplx<R> *)pp.V,
+                                 (const cplx<R> *)pp.W, (IO *)pp.x, grp, smem);
 }
-
-__global__ void k_zero_u32(unsigned int *c) { *c = 0u; }
 
 // block shape of the sweeps: x covers the rows, y splits each dot product
 inline dim3 sweep_block(int m) {
@@ -563,74 +981,268 @@ inline dim3 sweep_block(int m) {
     }                                                                               \
   } while (0)
 
-kf_status blu_factor(kf_problem *p, int which) {
+// ---------------------------------------------------------------------------
+// partition of the columns
+// ---------------------------------------------------------------------------
+int blu_auto_chunks(int nx, int nz, int K) {
+  (void)nz; (void)K;
+  if (nx < 32) return 1;
+  int P = (int)std::lround(std::sqrt(nx / 2.0));
+  return std::max(1, std::min({P, KF_MAX_CHUNKS, (nx + 1) / 2}));
+}
+
+kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
+  if (chunks == 0) chunks = blu_auto_chunks(p->nx, p->nz, p->K);
+  if (chunks < 1 || chunks > KF_MAX_CHUNKS || 2 * chunks - 1 > p->nx) {
+    set_error("chunks must be in 1 .. min(64, (nx + 1) / 2)");
+    return KF_EINVAL;
+  }
+  if (ns == 0) ns = 1;
+  if (ns != 1 && ns != 2 && ns != 4) {
+    set_error("sources per workgroup must be 1, 2 or 4");
+    return KF_EINVAL;
+  }
+  p->ns = ns;
+  if (chunks == p->P && !p->part.empty()) return KF_OK;
   const int m = p->nz;
   const size_t mm = (size_t)m * m;
-  if (which & 1) {
-    if (!p->have_T64) {
-      Grid g = p->grid();
-      auto launch = [&](auto sides, auto middle, int nb, int nthreads) -> kf_status {
-        size_t smem = (2 * (size_t)m * nb + 2 * (size_t)m + 2 * nb) * sizeof(double2) + 2 * (size_t)m * sizeof(int);
-        HIP_TRY(hipFuncSetAttribute((const void *)sides, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        HIP_TRY(hipFuncSetAttribute((const void *)middle, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        {
-          ProfScope ps(p, PROF_FACTOR);
-          hipLaunchKernelGGL(sides, dim3(2), dim3(nthreads), smem, p->stream, g, p->mid, p->T64, p->fac_work);
-          LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(middle, dim3(1), dim3(nthreads), smem, p->stream, g, p->mid, p->T64, p->fac_work);
-        LAUNCH_CHECK();
-        return KF_OK;
-      };
-      // panel width and rows per lane of the register-resident panel, by column height
-      // (the register-resident panel needs the larger VGPR budget of 256-thread groups
-      //  once a lane owns five or more rows)
-      kf_status st = m <= 128 ? launch(k_blu_factor<8, 2, 512, 0>, k_blu_factor<8, 2, 512, 1>, 8, 512)
-                   : m <= 192 ? launch(k_blu_factor<8, 3, 512, 0>, k_blu_factor<8, 3, 512, 1>, 8, 512)
-                   : m <= 320 ? launch(k_blu_factor<8, 5, 256, 0>, k_blu_factor<8, 5, 256, 1>, 8, 256)
-                              : launch(k_blu_factor<8, 8, 256, 0>, k_blu_factor<8, 8, 256, 1>, 8, 256);
-      if (st != KF_OK) return st;
-      p->have_T64 = true;
-    }
+  // P chunks around P - 1 separators, interior lengths as even as possible
+  std::vector<int> part(3 * chunks);
+  const int n_int = p->nx - (chunks - 1), base = n_int / chunks, extra = n_int % chunks;
+  int a = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const int L = base + (c < extra ? 1 : 0);
+    part[3 * c] = a;
+    part[3 * c + 1] = a + L - 1;
+    part[3 * c + 2] = a + L / 2;
+    a += L + 1;
   }
-  if (which & 2) {
-    if (!p->have_T64) {
-      kf_status st = blu_factor(p, 1);
-      if (st != KF_OK) return st;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  HIP_TRY(hipMemcpy(p->d_part, part.data(), sizeof(int) * part.size(), hipMemcpyHostToDevice));
+  const size_t slots = 2 * (size_t)chunks;
+  if (slots > p->fac_slots) {
+    if (p->fac_work) HIP_TRY(hipFree(p->fac_work));
+    p->fac_work = nullptr;
+    p->fac_slots = 0;
+    HIP_TRY(hipMalloc((void **)&p->fac_work, sizeof(double2) * slots * (mm + (size_t)NB_MAX * m)));
+    p->fac_slots = slots;
+  }
+  if (chunks > 1 && !p->V64) {
+    const size_t n = (size_t)p->nx * mm;
+    HIP_TRY(hipMalloc((void **)&p->V64, sizeof(double2) * n));
+    HIP_TRY(hipMalloc((void **)&p->W64, sizeof(double2) * n));
+    HIP_TRY(hipMalloc((void **)&p->V32, sizeof(float2) * n));
+    HIP_TRY(hipMalloc((void **)&p->W32, sizeof(float2) * n));
+  }
+  p->part = part;
+  p->P = chunks;
+  int lmax = 0;
+  for (int c = 0; c < chunks; ++c) lmax = std::max(lmax, part[3 * c + 1] - part[3 * c] + 1);
+  p->ncb = (lmax + CORR_CB - 1) / CORR_CB;
+  p->have_T64 = p->have_T32 = false;
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// factorisation of a batch of problems (a single problem is a batch of one)
+// ---------------------------------------------------------------------------
+namespace {
+template <int NB, int RMAX, int NT>
+kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, int m_max) {
+  const size_t smem = (2 * (size_t)m_max * NB + 2 * (size_t)m_max + 2 * NB) * sizeof(double2) + 2 * (size_t)m_max * sizeof(int);
+  HIP_TRY(hipFuncSetAttribute((const void *)k_factor_chunks<NB, RMAX, NT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  HIP_TRY(hipFuncSetAttribute((const void *)k_factor_chunks<NB, RMAX, NT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  HIP_TRY(hipFuncSetAttribute((const void *)k_invert<NB, RMAX, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  FactorBatch bt{};
+  bt.n = (int)ps.size();
+  for (int q = 0; q < bt.n; ++q) {
+    kf_problem *p = ps[q];
+    bt.p[q] = FactorProblem{p->grid(), p->P, p->d_part, p->T64, p->V64, p->W64, p->fac_work};
+  }
+  // 1. chunks: both sides, then the middle columns
+  for (int mode = 0; mode < 2; ++mode) {
+    int tot = 0;
+    for (int q = 0; q < bt.n; ++q) {
+      bt.first[q] = tot;
+      tot += (mode == 0 ? 2 : 1) * ps[q]->P;
     }
-    if (!p->have_T32) {
-      kf_status st = launch_copy_c128_to_c64(p, (int64_t)p->nx * mm, p->T64, p->T32);
-      if (st != KF_OK) return st;
-      p->have_T32 = true;
+    bt.first[bt.n] = bt.total = tot;
+    if (mode == 0) hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 0>), dim3(tot), dim3(NT), smem, s, bt);
+    else hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 1>), dim3(tot), dim3(NT), smem, s, bt);
+    LAUNCH_CHECK();
+  }
+  // 2. spikes
+  constexpr int NSP = 2;
+  int tot = 0, pmax = 1;
+  for (int q = 0; q < bt.n; ++q) {
+    bt.first[q] = tot;
+    tot += 2 * (ps[q]->P - 1) * ((ps[q]->nz + NSP - 1) / NSP);
+    pmax = std::max(pmax, ps[q]->P);
+  }
+  bt.first[bt.n] = bt.total = tot;
+  if (tot == 0) return KF_OK;
+  const dim3 blk = sweep_block(m_max);
+  const size_t smem_sp = (1 + (blk.y - 1)) * NSP * (size_t)m_max * sizeof(double2);
+  HIP_TRY(hipFuncSetAttribute((const void *)k_spikes<NSP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
+  hipLaunchKernelGGL((k_spikes<NSP>), dim3(tot), blk, smem_sp, s, bt);
+  LAUNCH_CHECK();
+  // 3. the separators' block LU, one separator at a time
+  for (int j = 1; j < pmax; ++j) {
+    GemmBatch g1{}, nu{};
+    ReducedBatch rb{};
+    InvertBatch ib{};
+    int tiles = 0;
+    for (kf_problem *p : ps) {
+      if (p->P - 1 < j) continue;
+      const int m = p->nz;
+      const size_t mm = (size_t)m * m;
+      const size_t slot = mm + (size_t)NB_MAX * m;
+      const int sc = p->part[3 * (j - 1) + 1] + 1;   // s_j; b_{j-1} = sc - 1, a_j = sc + 1
+      double2 *S = p->fac_work, *G1 = p->fac_work + slot;
+      tiles = std::max(tiles, ((m + 31) / 32) * ((m + 31) / 32));
+      if (j >= 2) {
+        const int sp = p->part[3 * (j - 2) + 1] + 1;  // s_{j-1}
+        g1.j[g1.n++] = GemmJob{p->grid(), -1, 1.0, p->V64 + (size_t)(sc - 1) * mm, p->W64 + (size_t)sp * mm, G1};
+        nu.j[nu.n++] = GemmJob{p->grid(), sc, -1.0, p->T64 + (size_t)sc * mm, p->V64 + (size_t)(sc - 1) * mm,
+                               p->V64 + (size_t)sc * mm};
+      }
+      if (j <= p->P - 2)
+        nu.j[nu.n++] = GemmJob{p->grid(), sc + 1, -1.0, p->T64 + (size_t)sc * mm, p->W64 + (size_t)(sc + 1) * mm,
+                               p->W64 + (size_t)sc * mm};
+      rb.j[rb.n++] = ReducedJob{p->grid(), sc, p->W64 + (size_t)(sc - 1) * mm, p->V64 + (size_t)(sc + 1) * mm,
+                                j >= 2 ? G1 : nullptr, S};
+      ib.j[ib.n++] = InvertJob{m, S, p->T64 + (size_t)sc * mm};
+    }
+    if (g1.n) {
+      hipLaunchKernelGGL(k_gemm_cm, dim3(tiles, g1.n), dim3(256), 0, s, g1);
+      LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_reduced_S, dim3(std::min(1024, (m_max * m_max + 255) / 256), rb.n), dim3(256), 0, s, rb);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_invert<NB, RMAX, NT>), dim3(ib.n), dim3(NT), smem, s, ib);
+    LAUNCH_CHECK();
+    if (nu.n) {
+      hipLaunchKernelGGL(k_gemm_cm, dim3(tiles, nu.n), dim3(256), 0, s, nu);
+      LAUNCH_CHECK();
     }
   }
   return KF_OK;
 }
+}  // namespace
 
-namespace {
-template <typename R, typename IO, bool ADJ>
-kf_status sweep(kf_problem *p, const cplx<R> *T, const IO *rhs, IO *x, cplx<R> *xmid) {
-  ProfScope ps(p, PROF_SWEEP);
-  constexpr int NS = 1;
-  const int m = p->nz;
-  Grid g = p->grid();
-  int groups = (p->K + NS - 1) / NS;
-  dim3 blk = sweep_block(m);
-  size_t smem = (2 + (blk.y - 1)) * NS * m * sizeof(cplx<R>);
-  const bool fp32 = sizeof(R) == sizeof(float);
-  {
-    ProfScope pf(p, fp32 ? PROF_FWD32 : PROF_FWD64);
-    hipLaunchKernelGGL((k_blu_fwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x);
-    LAUNCH_CHECK();
+kf_status blu_factor_batch(const std::vector<kf_problem *> &all, int which, hipStream_t s) {
+  std::vector<kf_problem *> ps;
+  int m_max = 0;
+  for (kf_problem *p : all)
+    if ((which & 3) && !p->have_T64) { ps.push_back(p); m_max = std::max(m_max, p->nz); }
+  if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
+  if (!ps.empty()) {
+    // panel width and rows per lane of the register-resident panel, by column height
+    // (the register-resident panel needs the larger VGPR budget of 256-thread groups
+    //  once a lane owns five or more rows)
+    kf_status st = m_max <= 128 ? factor64_launch<8, 2, 512>(ps, s, m_max)
+                 : m_max <= 192 ? factor64_launch<8, 3, 512>(ps, s, m_max)
+                 : m_max <= 320 ? factor64_launch<8, 5, 256>(ps, s, m_max)
+                                : factor64_launch<8, 8, 256>(ps, s, m_max);
+    if (st != KF_OK) return st;
+    for (kf_problem *p : ps) p->have_T64 = true;
   }
-  hipLaunchKernelGGL((k_blu_mid<R, IO, ADJ, NS>), dim3(groups), blk, smem, p->stream, g, p->K, p->mid, T, rhs, x, xmid);
-  LAUNCH_CHECK();
-  {
-    ProfScope pb(p, fp32 ? PROF_BWD32 : PROF_BWD64);
-    hipLaunchKernelGGL((k_blu_bwd<R, IO, ADJ, NS>), dim3(groups, 2), blk, smem, p->stream, g, p->K, p->mid, T, x, xmid);
+  if (which & 2)
+    for (kf_problem *p : all)
+      if (!p->have_T32) {
+        const int64_t n = (int64_t)p->nx * p->nz * p->nz;
+        kf_status st = launch_copy_c128_to_c64(p, n, p->T64, p->T32);
+        if (st == KF_OK && p->P > 1) st = launch_copy_c128_to_c64(p, n, p->V64, p->V32);
+        if (st == KF_OK && p->P > 1) st = launch_copy_c128_to_c64(p, n, p->W64, p->W32);
+        if (st != KF_OK) return st;
+        p->have_T32 = true;
+      }
+  return KF_OK;
+}
+
+kf_status blu_factor(kf_problem *p, int which) {
+  if (which & 3) {
+    if (!p->have_T64) {
+      ProfScope ps(p, PROF_FACTOR);
+      kf_status st = blu_factor_batch({p}, 1, p->stream);
+      if (st != KF_OK) return st;
+    }
+    if ((which & 2) && !p->have_T32) return blu_factor_batch({p}, 2, p->stream);
+  }
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solves of a batch of problems: six phases, one launch each
+// ---------------------------------------------------------------------------
+namespace {
+template <typename R, typename IO, bool ADJ, int NS>
+kf_status solve_phases(const std::vector<kf_problem *> &ps, const IO *const *rhs, IO *const *x, hipStream_t s,
+                       kf_problem *prof) {
+  const bool fp32 = sizeof(R) == sizeof(float);
+  SweepBatch bt{};
+  bt.n = (int)ps.size();
+  int m_max = 0;
+  for (int q = 0; q < bt.n; ++q) {
+    kf_problem *p = ps[q];
+    m_max = std::max(m_max, p->nz);
+    bt.p[q] = SweepProblem{p->grid(), p->K, p->P, p->ncb, p->d_part,
+                           fp32 ? (const void *)p->T32 : (const void *)p->T64,
+                           fp32 ? (const void *)p->V32 : (const void *)p->V64,
+                           fp32 ? (const void *)p->W32 : (const void *)p->W64, rhs[q], x[q]};
+  }
+  const dim3 blk = sweep_block(m_max);
+  const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
+  for (int ph = 0; ph < 6; ++ph) {
+    int tot = 0;
+    for (int q = 0; q < bt.n; ++q) {
+      const kf_problem *p = ps[q];
+      const int G = (p->K + NS - 1) / NS;
+      bt.first[q] = tot;
+      tot += ph == 0 || ph == 2 ? 2 * p->P * G
+           : ph == 1            ? p->P * G
+           : ph == 3            ? (p->P - 1) * G
+           : ph == 4            ? (p->P > 2 ? G : 0)
+                                : (p->P > 1 ? p->P * p->ncb * G : 0);
+    }
+    bt.first[bt.n] = bt.total = tot;
+    if (tot == 0) continue;
+    ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : -1);
+#define SOLVE_PHASE(PH)                                                                                       \
+  do {                                                                                                        \
+    if (smem > 65536)                                                                                         \
+      HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, IO, ADJ, NS, PH>,                                  \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));                    \
+    hipLaunchKernelGGL((k_solve<R, IO, ADJ, NS, PH>), dim3(tot), blk, smem, s, bt);                           \
+  } while (0)
+    switch (ph) {
+      case 0: SOLVE_PHASE(0); break;
+      case 1: SOLVE_PHASE(1); break;
+      case 2: SOLVE_PHASE(2); break;
+      case 3: SOLVE_PHASE(3); break;
+      case 4: SOLVE_PHASE(4); break;
+      default: SOLVE_PHASE(5); break;
+    }
+#undef SOLVE_PHASE
     LAUNCH_CHECK();
   }
   return KF_OK;
+}
+
+template <typename R, typename IO>
+kf_status solve_dispatch(const std::vector<kf_problem *> &ps, int adjoint, const IO *const *rhs, IO *const *x,
+                         hipStream_t s, kf_problem *prof) {
+  if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
+  const bool fp32 = sizeof(R) == sizeof(float);
+  int ns = 4;
+  for (kf_problem *p : ps) {
+    if (!(fp32 ? p->have_T32 : p->have_T64)) { set_error("block solve before factorisation"); return KF_ESTATE; }
+    ns = std::min(ns, p->ns);
+  }
+  ProfScope sw(prof, PROF_SWEEP);
+  if (ns >= 4) return adjoint ? solve_phases<R, IO, true, 4>(ps, rhs, x, s, prof) : solve_phases<R, IO, false, 4>(ps, rhs, x, s, prof);
+  if (ns == 2) return adjoint ? solve_phases<R, IO, true, 2>(ps, rhs, x, s, prof) : solve_phases<R, IO, false, 2>(ps, rhs, x, s, prof);
+  return adjoint ? solve_phases<R, IO, true, 1>(ps, rhs, x, s, prof) : solve_phases<R, IO, false, 1>(ps, rhs, x, s, prof);
 }
 }  // namespace
 
@@ -638,127 +1250,30 @@ template <>
 kf_status blu_solve<double>(kf_problem *p, int adjoint, const double2 *rhs, double2 *x) {
   kf_status st = blu_factor(p, 1);
   if (st != KF_OK) return st;
-  return adjoint ? sweep<double, double2, true>(p, p->T64, rhs, x, p->xmid)
-                 : sweep<double, double2, false>(p, p->T64, rhs, x, p->xmid);
+  return solve_dispatch<double, double2>({p}, adjoint, &rhs, &x, p->stream, p);
 }
 template <>
 kf_status blu_solve<float>(kf_problem *p, int adjoint, const float2 *rhs, float2 *x) {
   kf_status st = blu_factor(p, 2);
   if (st != KF_OK) return st;
-  return adjoint ? sweep<float, float2, true>(p, p->T32, rhs, x, p->xmid32)
-                 : sweep<float, float2, false>(p, p->T32, rhs, x, p->xmid32);
+  return solve_dispatch<float, float2>({p}, adjoint, &rhs, &x, p->stream, p);
 }
 kf_status blu_solve_mixed_io(kf_problem *p, int adjoint, const double2 *rhs, double2 *x) {
   kf_status st = blu_factor(p, 2);
   if (st != KF_OK) return st;
-  return adjoint ? sweep<float, double2, true>(p, p->T32, rhs, x, p->xmid32)
-                 : sweep<float, double2, false>(p, p->T32, rhs, x, p->xmid32);
-}
-
-// ---------------------------------------------------------------------------
-// batch launchers: every problem of the batch in one persistent launch per phase
-// ---------------------------------------------------------------------------
-namespace {
-template <int NB, int RMAX, int NT>
-kf_status factor_batch_launch(const std::vector<kf_problem *> &ps, hipStream_t s, unsigned int *counter, int m_max) {
-  FactorBatch bt{};
-  bt.n = (int)ps.size();
-  size_t smem = (2 * (size_t)m_max * NB + 2 * (size_t)m_max + 2 * NB) * sizeof(double2) + 2 * (size_t)m_max * sizeof(int);
-  HIP_TRY(hipFuncSetAttribute((const void *)k_blu_factor_batch<NB, RMAX, NT, 0>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  HIP_TRY(hipFuncSetAttribute((const void *)k_blu_factor_batch<NB, RMAX, NT, 1>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  for (int mode = 0; mode < 2; ++mode) {
-    int tot = 0;
-    for (int q = 0; q < bt.n; ++q) {
-      kf_problem *p = ps[q];
-      bt.first[q] = tot;
-      bt.p[q] = FactorProblem{p->grid(), p->mid, p->T64, p->fac_work};
-      tot += mode == 0 ? 2 : 1;
-    }
-    bt.first[bt.n] = tot;
-    bt.total = tot;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
-    LAUNCH_CHECK();
-    if (mode == 0) hipLaunchKernelGGL((k_blu_factor_batch<NB, RMAX, NT, 0>), dim3(tot), dim3(NT), smem, s, bt, counter);
-    else hipLaunchKernelGGL((k_blu_factor_batch<NB, RMAX, NT, 1>), dim3(tot), dim3(NT), smem, s, bt, counter);
-    LAUNCH_CHECK();
-  }
-  return KF_OK;
-}
-}  // namespace
-
-kf_status blu_factor_batch(const std::vector<kf_problem *> &all, int which, hipStream_t s, unsigned int *counter) {
-  std::vector<kf_problem *> ps;
-  int m_max = 0;
-  for (kf_problem *p : all)
-    if ((which & 3) && !p->have_T64) { ps.push_back(p); m_max = std::max(m_max, p->nz); }
-  if (!ps.empty()) {
-    if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
-    kf_status st = m_max <= 128 ? factor_batch_launch<8, 2, 512>(ps, s, counter, m_max)
-                 : m_max <= 192 ? factor_batch_launch<8, 3, 512>(ps, s, counter, m_max)
-                 : m_max <= 320 ? factor_batch_launch<8, 5, 256>(ps, s, counter, m_max)
-                                : factor_batch_launch<8, 8, 256>(ps, s, counter, m_max);
-    if (st != KF_OK) return st;
-    for (kf_problem *p : ps) p->have_T64 = true;
-  }
-  if (which & 2)
-    for (kf_problem *p : all)
-      if (!p->have_T32) {
-        const size_t mm = (size_t)p->nz * p->nz;
-        kf_status st = launch_copy_c128_to_c64(p, (int64_t)p->nx * mm, p->T64, p->T32);
-        if (st != KF_OK) return st;
-        p->have_T32 = true;
-      }
-  return KF_OK;
+  return solve_dispatch<float, double2>({p}, adjoint, &rhs, &x, p->stream, p);
 }
 
 // rhs[q], x[q]: IO-typed fields of problem q; R = double uses the FP64 factors, float
 // the complex64 ones.
 template <typename R, typename IO>
 kf_status blu_solve_batch(const std::vector<kf_problem *> &ps, int adjoint, const IO *const *rhs, IO *const *x,
-                          hipStream_t s, unsigned int *counter) {
-  constexpr int NS = 1;
-  const bool fp32 = sizeof(R) == sizeof(float);
-  SweepBatch bt{};
-  bt.n = (int)ps.size();
-  if (bt.n > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
-  int m_max = 0;
-  for (int q = 0; q < bt.n; ++q) {
-    kf_problem *p = ps[q];
-    if (!(fp32 ? p->have_T32 : p->have_T64)) { set_error("batch solve before factorisation"); return KF_ESTATE; }
-    m_max = std::max(m_max, p->nz);
-    bt.p[q] = SweepProblem{p->grid(), p->K, p->mid, fp32 ? (const void *)p->T32 : (const void *)p->T64,
-                           rhs[q], x[q], fp32 ? (void *)p->xmid32 : (void *)p->xmid};
-  }
-  dim3 blk = sweep_block(m_max);
-  size_t smem = (2 + (blk.y - 1)) * NS * m_max * sizeof(cplx<R>);
-  for (int phase = 0; phase < 3; ++phase) {
-    int tot = 0;
-    for (int q = 0; q < bt.n; ++q) {
-      bt.first[q] = tot;
-      const int groups = (ps[q]->K + NS - 1) / NS;
-      tot += phase == 1 ? groups : 2 * groups;
-    }
-    bt.first[bt.n] = tot;
-    bt.total = tot;
-    const unsigned grid = (unsigned)std::min(tot, 1024);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
-    LAUNCH_CHECK();
-#define SWEEP_PHASE(PH)                                                                                     \
-  if (adjoint) hipLaunchKernelGGL((k_blu_sweep_batch<R, IO, true, NS, PH>), dim3(grid), blk, smem, s, bt, counter); \
-  else hipLaunchKernelGGL((k_blu_sweep_batch<R, IO, false, NS, PH>), dim3(grid), blk, smem, s, bt, counter);
-    if (phase == 0) { SWEEP_PHASE(0) }
-    else if (phase == 1) { SWEEP_PHASE(1) }
-    else { SWEEP_PHASE(2) }
-#undef SWEEP_PHASE
-    LAUNCH_CHECK();
-  }
-  return KF_OK;
+                          hipStream_t s) {
+  return solve_dispatch<R, IO>(ps, adjoint, rhs, x, s, nullptr);
 }
 template kf_status blu_solve_batch<double, double2>(const std::vector<kf_problem *> &, int, const double2 *const *,
-                                                    double2 *const *, hipStream_t, unsigned int *);
+                                                    double2 *const *, hipStream_t);
 template kf_status blu_solve_batch<float, double2>(const std::vector<kf_problem *> &, int, const double2 *const *,
-                                                   double2 *const *, hipStream_t, unsigned int *);
+                                                   double2 *const *, hipStream_t);
 template kf_status blu_solve_batch<float, float2>(const std::vector<kf_problem *> &, int, const float2 *const *,
-                                                  float2 *const *, hipStream_t, unsigned int *);
+                                                  float2 *const *, hipStream_t);

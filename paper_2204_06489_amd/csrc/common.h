@@ -87,13 +87,14 @@ __device__ inline double2 coupling_x(const Grid &g, int i, int j) {
 // batch descriptors, passed by value to the persistent work-list kernels
 // ---------------------------------------------------------------------------
 constexpr int KF_BATCH_MAX = 8;
+constexpr int KF_MAX_CHUNKS = 64;   // column chunks of the partitioned factorisation
 struct SweepProblem {
   Grid g;
-  int K, mid;
-  const void *T;       // factors (c128 or c64)
+  int K, P, ncb;       // sources, chunks, correction blocks per chunk
+  const int *part;     // [P][3]: first, last and meeting column of each chunk (device)
+  const void *T, *V, *W;   // factors and spikes (c128 or c64)
   const void *b;       // right-hand sides (IO type)
   void *x;             // solutions (IO type)
-  void *xmid;          // middle-column buffer (compute type)
 };
 struct SweepBatch {
   int n, total;
@@ -102,8 +103,9 @@ struct SweepBatch {
 };
 struct FactorProblem {
   Grid g;
-  int mid;
-  double2 *T, *work;
+  int P;
+  const int *part;
+  double2 *T, *V, *W, *work;
 };
 struct FactorBatch {
   int n, total;
@@ -141,14 +143,19 @@ struct kf_problem {
   int kkt_groups_max = 0;
   bool have_un = false;
 
-  // block factorisation (column sweep, both ends)
-  int mid = 0;                                 // meeting column
+  // partitioned block factorisation over grid columns
+  int P = 0;                                   // chunks
+  int ns = 1;                                  // sources per workgroup in the block solves
+  int ncb = 1;                                 // correction blocks per chunk
+  std::vector<int> part;                       // [P][3] first, last, meeting column of each chunk
+  int *d_part = nullptr;                       // device copy (KF_MAX_CHUNKS * 3)
   double2 *T64 = nullptr;                      // [nx][nz][nz], T_i stored transposed
   float2 *T32 = nullptr;                       // complex64 copy
+  double2 *V64 = nullptr, *W64 = nullptr;      // spikes and separator blocks (P > 1)
+  float2 *V32 = nullptr, *W32 = nullptr;
   bool have_T64 = false, have_T32 = false;
-  double2 *fac_work = nullptr;                 // factorisation scratch
-  double2 *xmid = nullptr;                     // [K][nz] middle-column solve buffer (c128)
-  float2 *xmid32 = nullptr;
+  double2 *fac_work = nullptr;                 // factorisation scratch, fac_slots work matrices
+  size_t fac_slots = 0;
 
   // scratch
   double2 *vec_a = nullptr, *vec_b = nullptr, *vec_c = nullptr, *vec_d = nullptr;  // [K][nz][nx] each
@@ -210,15 +217,17 @@ kf_status launch_copy_c128_to_c64(kf_problem *p, int64_t n, const double2 *x, fl
 kf_status launch_copy_c64_to_c128(kf_problem *p, int64_t n, const float2 *x, double2 *y);
 
 // block factorisation and sweeps
+int blu_auto_chunks(int nx, int nz, int K);
+kf_status blu_set_shape(kf_problem *p, int chunks, int ns);   // chunks 0 = automatic, ns 0 = 1
 kf_status blu_factor(kf_problem *p, int which);
 template <typename R> kf_status blu_solve(kf_problem *p, int adjoint, const cplx<R> *rhs, cplx<R> *x);
 kf_status blu_solve_mixed_io(kf_problem *p, int adjoint, const double2 *rhs, double2 *x);  // c64 factors, c128 I/O
 
 // batches: persistent work-list kernels over several problems (one launch per phase)
-kf_status blu_factor_batch(const std::vector<kf_problem *> &ps, int which, hipStream_t s, unsigned int *counter);
+kf_status blu_factor_batch(const std::vector<kf_problem *> &ps, int which, hipStream_t s);
 template <typename R, typename IO>
 kf_status blu_solve_batch(const std::vector<kf_problem *> &ps, int adjoint, const IO *const *rhs, IO *const *x,
-                          hipStream_t s, unsigned int *counter);
+                          hipStream_t s);
 
 // reductions (deterministic, fixed order)
 kf_status per_source_norms(kf_problem *p, const double2 *x, int64_t n_per, int K, double *out_host);

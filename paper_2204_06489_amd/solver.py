@@ -151,6 +151,18 @@ class KKTProblem:
         check(lib().kf_factor(self._h, int(which), C.byref(t)))
         return t.value
 
+    def set_solver_shape(self, chunks=0, sources_per_group=0):
+        """Column chunks of the partitioned block factorisation (0 = automatic) and
+        right-hand sides per workgroup in the block solves (0 = 1)."""
+        torch.cuda.current_stream().synchronize()
+        check(lib().kf_set_solver_shape(self._h, int(chunks), int(sources_per_group)))
+
+    @property
+    def solver_shape(self):
+        c, s = C.c_int32(), C.c_int32()
+        check(lib().kf_get_solver_shape(self._h, C.byref(c), C.byref(s)))
+        return c.value, s.value
+
     def sources(self):
         f = self.empty_field()
         check(lib().kf_sources(self._h, _ptr(f)))
