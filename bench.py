@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-kkt", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the automatic solver shape")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -185,6 +186,9 @@ def bench_c4(args, torch, KKTProblem):
         log(args, f"c4 problem {inp['nx']}x{inp['nz']} f={inp['freq']:g} Hz K={inp['K']}")
         ds.append(observed_data(inp, torch, KKTProblem))
         probs.append(KKTProblem.from_inputs(inp, reg_on_update=True))
+        if not args.no_autotune:
+            best = probs[-1].autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)[0]
+            log(args, f"  autotuned shape P={best['chunks']} ns={best['sources_per_group']}")
     g0 = [torch.as_tensor(inp["gamma0"]).cuda() for inp in inps]
 
     def reset():
@@ -269,6 +273,12 @@ def main():
     log(args, f"workload {args.config} f={inp['freq']} Hz grid {inp['nx']}x{inp['nz']} K={inp['K']}")
     d = observed_data(inp, torch, KKTProblem)
     p = KKTProblem.from_inputs(inp, reg_on_update=True)
+    if not args.no_autotune:
+        # shape of the block solver for this grid (setup, outside the timed region)
+        table = p.autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)
+        log(args, "autotune: " + ", ".join(f"P={r['chunks']} ns={r['sources_per_group']}: "
+                                            f"{r['t_factor_ms']:.1f}+100x{r['t_solve_ms']:.3f} ms"
+                                            for r in table[:4]))
     opts = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec="c128",
                 update_in_place=True, want_xi=False)
     for w in range(args.warmup):
@@ -316,7 +326,8 @@ def main():
                                 f"{len(inp['rec_ix'])} receivers, {inp['freq']:g} Hz, "
                                 f"{'inexact' if args.pc == 'inexact' else 'exact'} block-triangular "
                                 f"preconditioner, FGMRES({args.restart}) to {args.rtol:g}, b_s = 0"),
-                   "global_batch": inp["K"], "parallelism": "single GPU"},
+                   "global_batch": inp["K"], "parallelism": "single GPU",
+                   "solver_shape": dict(zip(("chunks", "sources_per_group"), p.solver_shape))},
         "roofline": roof,
         "breakdown_ms": {"factor": mean("t_factor_ms"), "forward": mean("t_forward_ms"),
                          "precond": mean("t_precond_ms"), "matvec": mean("t_matvec_ms"),

@@ -113,6 +113,7 @@ typedef struct {
   double t_orth_ms;        /* orthogonalisation, Givens, updates */
   double t_total_ms;       /* whole call */
   int32_t fwd_refine_iters;/* refinement sweeps of the forward solve (KF_MIXED) */
+  int32_t reorth_passes;   /* Arnoldi steps that needed the second Gram-Schmidt pass */
 } kf_newton_stats;
 
 typedef struct {
@@ -149,10 +150,26 @@ kf_status kf_set_stream(kf_problem *p, void *hip_stream);
  * the separators (their Schur complement) joins them, so more chunks means more parallel
  * work and shorter sequential sweeps, plus a longer separator chain.  1 <= chunks <=
  * min(64, (nx + 1) / 2); 0 picks round(sqrt(nx / 2)) (1 below nx = 32).
- * sources_per_group: right-hand sides per workgroup in the block solves, 1, 2 or 4
- * (0 = 1).  Results do not depend on either beyond rounding. */
+ * sources_per_group: right-hand sides per workgroup in the block solves, 1, 2, 4 or 8
+ * (0 = 1; FP64 solves use at most 4).  Results do not depend on either beyond rounding. */
 kf_status kf_set_solver_shape(kf_problem *p, int32_t chunks, int32_t sources_per_group);
 kf_status kf_get_solver_shape(kf_problem *p, int32_t *chunks /*[host]*/, int32_t *sources_per_group /*[host]*/);
+/* Autotuner of the solver shape: for chunk counts around the automatic choice (and 1) it
+ * builds the factorisation (FP64, plus the complex64 copy when prec = KF_C64), and for
+ * each sources_per_group it times forward and adjoint block solves of all K sources
+ * (complex64 sweeps with c128 I/O when prec = KF_C64, as in the inexact preconditioner;
+ * FP64 otherwise) with HIP events on the problem's stream.  The score of a shape is
+ * t_factor + solves_per_factor * t_solve; the best is set on the problem and remembered
+ * for the process, keyed by (nx, nz, K, prec): later kf_create calls of that size start
+ * from it.  A solve after the call rebuilds the factorisation if the chosen shape was not
+ * the last one measured.  table (may be
+ * NULL) receives up to table_len measured entries, n_table their number. */
+typedef struct {
+  int32_t chunks, sources_per_group;
+  double t_factor_ms, t_solve_ms, score_ms;
+} kf_tune_entry;
+kf_status kf_autotune(kf_problem *p, int32_t prec, double solves_per_factor, kf_tune_entry *table /*[host]*/,
+                      int32_t table_len, int32_t *n_table /*[host], may be NULL*/);
 /* Build the block factorisation of A(gamma, omega) now (it is otherwise built on the first
  * solve that needs it).  `which`: bit 0 = FP64 factors, bit 1 = complex64 copy. */
 kf_status kf_factor(kf_problem *p, int32_t which, double *t_ms /*[host], may be NULL*/);
@@ -214,10 +231,12 @@ kf_status kf_sizes(kf_problem *p, int64_t *out /*[host][6]*/);
 kf_status kf_profile_enable(kf_problem *p, int32_t on);
 /* Read accumulated (launch count, total milliseconds) of a kernel family:
  * "kkt_apply" (the fused kernel, without the receiver term), "stencil", "blu_factor" (the
- * two-sided sweep of the factorisation, without the middle column), "blu_sweep" (a whole
- * block solve), "blu_fwd_c128",
- * "blu_fwd_c64", "blu_bwd_c128", "blu_bwd_c64" (the forward-sweep and back-substitution
- * kernels alone), "precond_stage", "orth", "reduce".  Unknown names give KF_EINVAL. */
+ * whole FP64 factorisation: chunks, spikes and separator system), "blu_sweep" (a whole
+ * block solve), "blu_fwd_c128", "blu_fwd_c64", "blu_bwd_c128", "blu_bwd_c64" (the chunks'
+ * forward-sweep and back-substitution launches), "blu_mid", "blu_reduced_rhs",
+ * "blu_chain", "blu_correct" (the middle columns, the separators' right-hand sides, the
+ * separator chain and the interior correction), "precond_stage", "orth", "reduce".
+ * Unknown names give KF_EINVAL. */
 kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
 
 /* ---- batches: several problems (e.g. frequencies on uneven grids) advanced together ----

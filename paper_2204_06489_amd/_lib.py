@@ -43,7 +43,13 @@ class KfNewtonStats(C.Structure):
         ("phi_before", C.c_double), ("ds_imag_ratio", C.c_double), ("t_factor_ms", C.c_double),
         ("t_forward_ms", C.c_double), ("t_precond_ms", C.c_double), ("t_matvec_ms", C.c_double),
         ("t_orth_ms", C.c_double), ("t_total_ms", C.c_double), ("fwd_refine_iters", C.c_int32),
+        ("reorth_passes", C.c_int32),
     ]
+
+
+class KfTuneEntry(C.Structure):
+    _fields_ = [("chunks", C.c_int32), ("sources_per_group", C.c_int32), ("t_factor_ms", C.c_double),
+                ("t_solve_ms", C.c_double), ("score_ms", C.c_double)]
 
 
 class KfSolveStats(C.Structure):
@@ -64,6 +70,7 @@ _SIGNATURES = {
     "kf_factor": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double)]),
     "kf_set_solver_shape": (C.c_int, [P, C.c_int32, C.c_int32]),
     "kf_get_solver_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "kf_autotune": (C.c_int, [P, C.c_int32, C.c_double, C.POINTER(KfTuneEntry), C.c_int32, C.POINTER(C.c_int32)]),
     "kf_stencil_apply": (C.c_int, [P, C.c_int32, C.c_int32, P, P]),
     "helmholtz_solve": (C.c_int, [P, C.c_int32, C.c_int32, P, P, C.c_double, C.c_int32,
                                   C.POINTER(KfSolveStats)]),

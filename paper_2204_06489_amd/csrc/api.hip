@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 
 // ---------------------------------------------------------------------------
 // errors
@@ -125,7 +126,7 @@ static void free_all(kf_problem *p) {
   dfree(p->gamma); dfree(p->xn); dfree(p->ixh); dfree(p->zn); dfree(p->izh);
   dfree(p->d_src); dfree(p->d_rnode); dfree(p->d_wsq); dfree(p->d_rec); dfree(p->d_w);
   dfree(p->d_rptr); dfree(p->d_rlist); dfree(p->d_r); dfree(p->d_wr);
-  dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->d_part);
+  dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->d_part); dfree(p->sol64); dfree(p->sol32);
   dfree(p->V64); dfree(p->W64); dfree(p->V32); dfree(p->W32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
@@ -181,6 +182,8 @@ static kf_status check_p(kf_problem *p) {
 // ---------------------------------------------------------------------------
 // create / destroy / state
 // ---------------------------------------------------------------------------
+kf_status tuned_shape(const kf_problem *p, int prec, int *chunks, int *ns);
+
 extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t gamma_on_device, void *hip_stream,
                                kf_problem **out) {
   if (!out) return fail(KF_EINVAL, "out is NULL");
@@ -243,6 +246,7 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   ALLOC(p->ys_part, (size_t)p->kkt_groups_max * p->Ng);
   ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m);
   ALLOC(p->d_part, 3 * KF_MAX_CHUNKS);
+  ALLOC(p->sol64, K * Nu); ALLOC(p->sol32, K * Nu);
   ALLOC(p->vec_a, K * Nu); ALLOC(p->vec_b, K * Nu); ALLOC(p->vec_c, K * Nu); ALLOC(p->vec_d, K * Nu);
   ALLOC(p->red, (size_t)1024 * 2 * 256 + K * 64);
   ALLOC(p->red_out, std::max<size_t>(K, 1024));
@@ -271,7 +275,11 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   }
   if (st == KF_OK) st = launch_pml(p, p->d);
   if (st == KF_OK && hipStreamSynchronize(p->stream) != hipSuccess) st = fail(KF_EHIP, "stream synchronize failed");
-  if (st == KF_OK) st = blu_set_shape(p, 0, 0);
+  if (st == KF_OK) {   // the shape the autotuner found for this size, if any
+    int c = 0, ns = 0;
+    if (tuned_shape(p, KF_C64, &c, &ns) != KF_OK) tuned_shape(p, KF_C128, &c, &ns);
+    st = blu_set_shape(p, c, ns);
+  }
   if (st != KF_OK) { free_all(p); delete p; return st; }
   *out = p;
   return KF_OK;
@@ -343,6 +351,101 @@ extern "C" kf_status kf_factor(kf_problem *p, int32_t which, double *t_ms) {
   CHECK_ST(blu_factor(p, which));
   HIP_TRY(hipStreamSynchronize(p->stream));
   if (t_ms) *t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner of the block solver's shape (chunks x sources per workgroup)
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int nx, nz, K, prec;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(nx, nz, K, prec) < std::tie(o.nx, o.nz, o.K, o.prec);
+  }
+};
+std::map<TuneKey, std::pair<int, int>> &tune_cache() {
+  static std::map<TuneKey, std::pair<int, int>> c;
+  return c;
+}
+
+// ms between two events recorded on p->stream around fn()
+template <typename F> kf_status timed(kf_problem *p, F fn, double *ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return fail(KF_EHIP, "hipEventCreate failed"); }
+  kf_status st = KF_OK;
+  if (hipEventRecord(a, p->stream) != hipSuccess) st = fail(KF_EHIP, "hipEventRecord failed");
+  if (st == KF_OK) st = fn();
+  if (st == KF_OK && hipEventRecord(b, p->stream) != hipSuccess) st = fail(KF_EHIP, "hipEventRecord failed");
+  if (st == KF_OK && hipEventSynchronize(b) != hipSuccess) st = fail(KF_EHIP, "hipEventSynchronize failed");
+  float f = 0.f;
+  if (st == KF_OK && hipEventElapsedTime(&f, a, b) != hipSuccess) st = fail(KF_EHIP, "hipEventElapsedTime failed");
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *ms = f;
+  return st;
+}
+}  // namespace
+
+kf_status tuned_shape(const kf_problem *p, int prec, int *chunks, int *ns) {
+  auto it = tune_cache().find(TuneKey{p->nx, p->nz, p->K, prec});
+  if (it == tune_cache().end()) return KF_EINVAL;
+  *chunks = it->second.first;
+  *ns = it->second.second;
+  return KF_OK;
+}
+
+extern "C" kf_status kf_autotune(kf_problem *p, int32_t prec, double solves_per_factor, kf_tune_entry *table,
+                                 int32_t table_len, int32_t *n_table) {
+  CHECK_ST(check_p(p));
+  if (prec != KF_C128 && prec != KF_C64) return fail(KF_EINVAL, "prec must be KF_C128 or KF_C64");
+  if (!(solves_per_factor >= 0.0) || !std::isfinite(solves_per_factor))
+    return fail(KF_EINVAL, "solves_per_factor must be >= 0");
+  if (table_len < 0 || (table_len > 0 && !table)) return fail(KF_EINVAL, "table is NULL");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const int pmax = std::min(KF_MAX_CHUNKS, (p->nx + 1) / 2);
+  const int a = std::max(1, (int)std::lround(std::sqrt(p->nx / 2.0)));
+  std::vector<int> cand;
+  for (double f : {0.0, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0}) {
+    int c = f == 0.0 ? 1 : std::max(1, std::min(pmax, (int)std::lround(f * a)));
+    if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+  }
+  const int64_t n = (int64_t)p->K * p->Nu;
+  HIP_TRY(hipMemsetAsync(p->vec_a, 0, sizeof(double2) * n, p->stream));
+  const int which = prec == KF_C64 ? 3 : 1;
+  auto solve = [&](int adj) -> kf_status {
+    return prec == KF_C64 ? blu_solve_mixed_io(p, adj, p->vec_a, p->vec_b) : blu_solve<double>(p, adj, p->vec_a, p->vec_b);
+  };
+  int count = 0, best_c = 1, best_ns = 1;
+  double best = INFINITY;
+  for (int c : cand) {
+    CHECK_ST(blu_set_shape(p, c, 1));
+    double tf = 0.0;
+    CHECK_ST(timed(p, [&]() { return blu_factor(p, which); }, &tf));
+    for (int ns : {1, 2, 4, 8}) {
+      if (ns > 1 && (ns + 1) / 2 >= p->K) break;   // no group would be filled
+      CHECK_ST(blu_set_shape(p, c, ns));
+      CHECK_ST(solve(0));   // warm-up (first launch of this kernel shape)
+      double ts = 0.0;
+      CHECK_ST(timed(p, [&]() {
+        for (int r = 0; r < 2; ++r) {
+          kf_status st = solve(0);
+          if (st == KF_OK) st = solve(1);
+          if (st != KF_OK) return st;
+        }
+        return KF_OK;
+      }, &ts));
+      ts /= 4.0;
+      const double score = tf + solves_per_factor * ts;
+      if (count < table_len) table[count] = kf_tune_entry{c, ns, tf, ts, score};
+      ++count;
+      if (score < best) { best = score; best_c = c; best_ns = ns; }
+    }
+  }
+  CHECK_ST(blu_set_shape(p, best_c, best_ns));
+  tune_cache()[TuneKey{p->nx, p->nz, p->K, prec}] = {best_c, best_ns};
+  if (n_table) *n_table = count;
   return KF_OK;
 }
 
@@ -508,11 +611,31 @@ static kf_status ensure_krylov(kf_problem *p, int m) {
 }
 
 struct FgmresOut {
-  int iters = 0, restarts = 0;
+  int iters = 0, restarts = 0, reorth = 0;
   double rel_res = 1.0;
   std::vector<double> hist;
   double ph[PH_N] = {0, 0, 0};
 };
+
+// Orthogonalise Vn = V_{j+1} against V_0..V_j in FP64 by classical Gram-Schmidt with
+// reorthogonalisation (CGS2) in three sweeps over the basis: the dot products h1, the
+// first update fused with the second pass's dot products h2 and |Vn'|, and the second
+// update fused with the final norm.  The second update runs only when the DGKS test
+// finds that the first pass cancelled most of Vn (|Vn'| < |Vn| / sqrt 2); the test runs
+// on the device and a declined update's launches do nothing, so the step needs no host
+// round trip.  scal[0] receives |Vn| after the last pass; scal[6] holds the flag.
+constexpr double DGKS_ETA = 0.70710678118654752;
+static kf_status gram_schmidt(kf_problem *p, int j, double2 *Vn, double2 *h1, double2 *h2, double *scal) {
+  const int64_t N = p->Nxi;
+  int *flag = (int *)(scal + 6);
+  CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
+  // first update fused with the second pass's dot products and the norm
+  CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h1, Vn, N, h2, scal + 0));
+  CHECK_ST(reorth_test(p, j + 1, h1, scal + 0, DGKS_ETA, h2, flag));
+  // second update fused with the final norm (nothing when the test declines it)
+  CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h2, Vn, N, nullptr, scal + 0, flag));
+  return KF_OK;
+}
 
 static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, double tol, int m, int maxit,
                         FgmresOut &o) {
@@ -564,17 +687,14 @@ static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, dou
       CHECK_ST(launch_kkt_apply(p, Zj, Vn));
       pt.stop();
       pt.start(PH_ORTH);
-      CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
-      CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h1, -1.0, Vn, N));
-      CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h2));
-      CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h2, -1.0, Vn, N));
-      CHECK_ST(norm_c128(p, Vn, N, scal + 0));
+      CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal));
       CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
       CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
       pt.stop();
-      HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 7 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
       HIP_TRY(hipStreamSynchronize(p->stream));
       const double hn = p->host_pinned[0], est = p->host_pinned[2] / bnorm;
+      o.reorth += *(const int *)(p->host_pinned + 6);
       ++total;
       nj = j + 1;
       o.hist.push_back(est);
@@ -669,6 +789,7 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   kf_status fst = fgmres(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->restart, o->maxit, fo);
   if (fst != KF_OK && fst != KF_ENOCONV) return fst;
   S.outer_iters = fo.iters;
+  S.reorth_passes = fo.reorth;
   S.restarts = fo.restarts;
   S.rel_res = fo.rel_res;
   for (size_t q = 1; q < fo.hist.size() && q <= 512; ++q) S.rel_res_hist[q - 1] = fo.hist[q];
@@ -744,7 +865,8 @@ extern "C" kf_status helmholtz_adjoint_gradient(kf_problem *p, int32_t prec, con
 // ---------------------------------------------------------------------------
 static const char *prof_names[PROF_N] = {"kkt_apply", "stencil",     "blu_factor",  "blu_sweep",
                                          "precond_stage", "orth",  "reduce",      "blu_fwd_c128",
-                                         "blu_fwd_c64",   "blu_bwd_c128", "blu_bwd_c64"};
+                                         "blu_fwd_c64",   "blu_bwd_c128", "blu_bwd_c64", "blu_mid",
+                                         "blu_reduced_rhs", "blu_chain", "blu_correct"};
 
 extern "C" kf_status kf_profile_enable(kf_problem *p, int32_t on) {
   CHECK_ST(check_p(p));
@@ -960,7 +1082,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
   }
   // lockstep flexible GMRES
   std::vector<bool> done(n, false);
-  std::vector<int> total(n, 0);
+  std::vector<int> total(n, 0), reorth(n, 0);
   std::vector<std::vector<double>> hist(n);
   kf_status status = KF_OK;
   for (int q = 0; q < n; ++q) if (bnorm[q] == 0.0) { done[q] = true; S[q].rel_res = 0.0; }
@@ -1017,16 +1139,13 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
                 *y = h2 + (m + 1);
         double *scal = (double *)(y + m + 8);
         double2 *Vn = p->V + (size_t)(j + 1) * N;
-        CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
-        CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h1, -1.0, Vn, N));
-        CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h2));
-        CHECK_ST(multiaxpy_c128(p, p->V, j + 1, h2, -1.0, Vn, N));
-        CHECK_ST(norm_c128(p, Vn, N, scal + 0));
+        CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal));
         CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
         CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
-        HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 7 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
         const double hn = p->host_pinned[0], est = p->host_pinned[2] / bnorm[q];
+        reorth[q] += *(const int *)(p->host_pinned + 6);
         total[q] += 1;
         nj[q] = j + 1;
         hist[q].push_back(est);
@@ -1055,6 +1174,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
     const size_t Ku = (size_t)p->K * p->Nu;
     const double2 *ds = p->xi_x + Ku;
     S[q].outer_iters = total[q];
+    S[q].reorth_passes = reorth[q];
     for (size_t r = 0; r < hist[q].size() && r < 512; ++r) S[q].rel_res_hist[r] = hist[q][r];
     double dsn = host_norm(p, ds, p->Ng, &e); CHECK_ST(e);
     CHECK_ST(imag_part(p, p->Ng, ds, p->vec_a));

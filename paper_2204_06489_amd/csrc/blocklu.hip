@@ -256,46 +256,38 @@ __device__ __forceinline__ void build_schur(const Grid &g, int m, int i, const d
   __syncthreads();
 }
 
-template <typename R> __device__ inline cplx<R> to_r(double2 a) { return mk<R>((R)a.x, (R)a.y); }
-template <typename R> __device__ inline cplx<R> to_r(float2 a) { return mk<R>((R)a.x, (R)a.y); }
-template <typename IO> __device__ inline IO from_r(double2 a);
-template <> __device__ inline double2 from_r<double2>(double2 a) { return a; }
-template <> __device__ inline float2 from_r<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
-template <typename IO> __device__ inline IO from_r(float2 a);
-template <> __device__ inline double2 from_r<double2>(float2 a) { return make_double2(a.x, a.y); }
-template <> __device__ inline float2 from_r<float2>(float2 a) { return a; }
-
-// Solves of A^H run in the conjugated domain: right-hand sides are read conjugated
-// and every value stored in x (intermediate or final) is conjugated on the way in and
-// out, so the phases exchange values through x unchanged.
-template <typename R, bool ADJ, typename IO> __device__ inline cplx<R> ld_io(const IO &v) {
-  cplx<R> r = to_r<R>(v);
-  return ADJ ? cconj(r) : r;
-}
-template <bool ADJ, typename IO, typename C> __device__ inline void st_io(IO &dst, C v) {
-  dst = from_r<IO>(ADJ ? cconj(v) : v);
-}
-
 // y[s][j] = sum_l T[j][l] w[s][l] for the rows j = threadIdx.x < m.  The l-range is
 // split over the blockDim.y wave groups (more loads in flight per column step); the
 // partial sums meet in LDS and the complete result is valid in threads with
 // threadIdx.y == 0.  Tt is T stored transposed (column-major T), so lanes read
-// consecutive rows.
-template <typename R, int NS>
+// consecutive rows.  A group walks its range in blocks of MV_U columns whose loads are
+// all issued before the first use; the last block is padded (addresses clamped to the
+// range, weights zero), so no element pays a load latency of its own.
+// MV_U: 8 where many workgroups share the chip (their number hides the latency and
+// fewer registers keep more of them resident), 16 on the sequential chains that only a
+// few workgroups walk (every step's latency is exposed there).
+template <typename R, int NS, int MV_U = 8>
 __device__ inline void col_matvec(const cplx<R> *__restrict__ Tt, int m, const cplx<R> *w, cplx<R> *part,
                                   cplx<R> (&acc)[NS]) {
   using C = cplx<R>;
   const int j = threadIdx.x, gy = threadIdx.y, G = blockDim.y;
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
-  if (j < m) {
-    const int chunk = (m + G - 1) / G;
-    const int l0 = gy * chunk, l1 = min(m, l0 + chunk);
-#pragma unroll 8
-    for (int l = l0; l < l1; ++l) {
-      C t = Tt[(size_t)l * m + j];
+  const int chunk = (m + G - 1) / G;
+  const int l0 = gy * chunk, l1 = min(m, l0 + chunk);
+  const int jc = min(j, m - 1);   // rows past m compute a copy of row m - 1, never stored
+  for (int lb = l0; lb < l1; lb += MV_U) {
+    C t[MV_U];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) cfma(acc[s], t, w[s * m + l]);
+    for (int u = 0; u < MV_U; ++u) t[u] = Tt[(size_t)min(lb + u, l1 - 1) * m + jc];
+#pragma unroll
+    for (int u = 0; u < MV_U; ++u) {
+      const bool in = lb + u < l1;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const C wv = w[s * m + min(lb + u, l1 - 1)];
+        cfma(acc[s], t[u], in ? wv : mk<R>(0, 0));
+      }
     }
   }
   if (G > 1) {
@@ -445,7 +437,7 @@ __device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, i
     }
     __syncthreads();
     C acc[NSP];
-    col_matvec<double, NSP>(T + (size_t)i * mm, m, w, part, acc);
+    col_matvec<double, NSP, 16>(T + (size_t)i * mm, m, w, part, acc);
 #pragma unroll
     for (int t = 0; t < NSP; ++t) {
       cur[t] = acc[t];
@@ -467,7 +459,7 @@ __device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, i
   __syncthreads();
   {
     C acc[NSP];
-    col_matvec<double, NSP>(T + (size_t)ch.mid * mm, m, w, part, acc);
+    col_matvec<double, NSP, 16>(T + (size_t)ch.mid * mm, m, w, part, acc);
 #pragma unroll
     for (int t = 0; t < NSP; ++t) {
       xm[t] = acc[t];
@@ -495,7 +487,7 @@ __device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, i
       }
       __syncthreads();
       C acc[NSP];
-      col_matvec<double, NSP>(T + (size_t)i * mm, m, w, part, acc);
+      col_matvec<double, NSP, 16>(T + (size_t)i * mm, m, w, part, acc);
       if (owner)
 #pragma unroll
         for (int t = 0; t < NSP; ++t) {
@@ -510,7 +502,7 @@ __device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, i
 // item = (spike job, column group); jobs 0..P-2: W of chunks 0..P-2, then V of
 // chunks 1..P-1.
 template <int NSP>
-__global__ void k_spikes(FactorBatch bt) {
+__global__ __launch_bounds__(512) void k_spikes(FactorBatch bt) {
   extern __shared__ unsigned char smem[];
   const int item = item_of_block(bt.total);
   const int q = find_problem(bt.first, bt.n, item);
@@ -642,49 +634,51 @@ __global__ __launch_bounds__(NT) void k_invert(InvertBatch ib) {
 }
 
 // ---------------------------------------------------------------------------
-// solve phases (R: compute type, IO: storage type of b and x)
+// solve phases.  They work in place on a column-major copy X of the right-hand
+// sides ([K][nx][nz], compute type: column i of source k is X + (k nx + i) m), so a
+// workgroup reads and writes whole columns with consecutive lanes.  The copy is
+// made and undone by the transposes below; solves of A^H conjugate there
+// (A^H x = b  <=>  A conj(x) = conj(b)), so the phases only ever solve with A.
 // ---------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ cplx<R> *colp(void *X, const Grid &g, int k, int i) {
+  return (cplx<R> *)X + ((size_t)k * g.nx + i) * g.nz;
+}
+
 // 0: chunk forward sweeps, item (chunk, side, group): side 0 computes y_i for
 //    i = a..mid-1, side 1 for i = b..mid+1
-template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void fwd_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, const IO *b,
-                                         IO *x, int group, int side, unsigned char *smem) {
+template <typename R, int NS>
+__device__ __forceinline__ void fwd_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, void *X,
+                                         int group, int side, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
-  C *v = (C *)smem;          // [NS][m] previous y
-  C *w = v + NS * m;         // [NS][m] right-hand side of this column
-  C *part = w + NS * m;      // [G-1][NS][m] partial sums
+  C *w = (C *)smem;          // [NS][m] right-hand side of this column
+  C *part = w + 2 * NS * m;  // [G-1][NS][m] partial sums
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
-  const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
   const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
   auto col_of = [&](int step) { return side == 0 ? ch.a + step : ch.b - step; };
-  IO bnext[NS];
+  C prev[NS], bnext[NS];
   if (owner && cnt > 0)
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (k0 + s < K) bnext[s] = b[(k0 + s) * Nu + (size_t)j * g.nx + col_of(0)];
+    for (int s = 0; s < NS; ++s) bnext[s] = k0 + s < K ? colp<R>(X, g, k0 + s, col_of(0))[j] : mk<R>(0, 0);
   for (int step = 0; step < cnt; ++step) {
     const int i = col_of(step);
     const int cc = side == 0 ? i : i + 1;  // coupling column to the previous block
     if (owner) {
-      C cj = step > 0 ? to_r<R>(coupling_x(g, cc, j)) : mk<R>(0, 0);
+      const C cj = step > 0 ? ccast<R>(coupling_x(g, cc, j)) : mk<R>(0, 0);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        C r = mk<R>(0, 0);
-        if (k0 + s < K) {
-          r = ld_io<R, ADJ>(bnext[s]);
-          if (step > 0) r = csub(r, cmul(cj, v[s * m + j]));
-        }
+        C r = bnext[s];
+        if (step > 0) r = csub(r, cmul(cj, prev[s]));
         w[s * m + j] = r;
       }
       // prefetch the next column's right-hand side while the matvec runs
       if (step + 1 < cnt)
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-          if (k0 + s < K) bnext[s] = b[(k0 + s) * Nu + (size_t)j * g.nx + col_of(step + 1)];
+          bnext[s] = k0 + s < K ? colp<R>(X, g, k0 + s, col_of(step + 1))[j] : mk<R>(0, 0);
     }
     __syncthreads();
     C acc[NS];
@@ -692,8 +686,8 @@ __device__ __forceinline__ void fwd_body(const Grid &g, int K, Chunk ch, const c
     if (owner) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        v[s * m + j] = acc[s];
-        if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i], acc[s]);
+        prev[s] = acc[s];
+        if (k0 + s < K) colp<R>(X, g, k0 + s, i)[j] = acc[s];
       }
     }
     __syncthreads();
@@ -701,9 +695,9 @@ __device__ __forceinline__ void fwd_body(const Grid &g, int K, Chunk ch, const c
 }
 
 // 1: middle column of each chunk, x_mid = T_mid (b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1})
-template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void mid_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, const IO *b,
-                                         IO *x, int group, unsigned char *smem) {
+template <typename R, int NS>
+__device__ __forceinline__ void mid_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, void *X,
+                                         int group, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
   C *w = (C *)smem;
@@ -711,8 +705,6 @@ __device__ __forceinline__ void mid_body(const Grid &g, int K, Chunk ch, const c
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
-  const size_t Nu = (size_t)g.nx * g.nz;
-  const size_t mm = (size_t)m * m;
   const int i = ch.mid;
   if (owner) {
 #pragma unroll
@@ -720,27 +712,26 @@ __device__ __forceinline__ void mid_body(const Grid &g, int K, Chunk ch, const c
       const int k = k0 + s;
       C r = mk<R>(0, 0);
       if (k < K) {
-        const size_t base = k * Nu + (size_t)j * g.nx;
-        r = ld_io<R, ADJ>(b[base + i]);
-        if (i > ch.a) r = csub(r, cmul(to_r<R>(coupling_x(g, i, j)), ld_io<R, ADJ>(x[base + i - 1])));
-        if (i < ch.b) r = csub(r, cmul(to_r<R>(coupling_x(g, i + 1, j)), ld_io<R, ADJ>(x[base + i + 1])));
+        r = colp<R>(X, g, k, i)[j];
+        if (i > ch.a) r = csub(r, cmul(ccast<R>(coupling_x(g, i, j)), colp<R>(X, g, k, i - 1)[j]));
+        if (i < ch.b) r = csub(r, cmul(ccast<R>(coupling_x(g, i + 1, j)), colp<R>(X, g, k, i + 1)[j]));
       }
       w[s * m + j] = r;
     }
   }
   __syncthreads();
   C acc[NS];
-  col_matvec<R, NS>(T + (size_t)i * mm, m, w, part, acc);
+  col_matvec<R, NS>(T + (size_t)i * m * m, m, w, part, acc);
   if (owner)
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i], acc[s]);
+      if (k0 + s < K) colp<R>(X, g, k0 + s, i)[j] = acc[s];
 }
 
 // 2: back-substitution outward from the middle: side 0: x_i = y_i - T_i C_{i+1} x_{i+1}
 //    (i = mid-1..a); side 1: x_i = y_i - T_i C_i x_{i-1} (i = mid+1..b)
-template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, IO *x,
+template <typename R, int NS>
+__device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const cplx<R> *__restrict__ T, void *X,
                                          int group, int side, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
@@ -749,24 +740,22 @@ __device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const c
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
-  const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
   const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
   C xr[NS];
   if (owner && cnt > 0)
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      xr[s] = (k0 + s < K) ? ld_io<R, ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + ch.mid]) : mk<R>(0, 0);
+    for (int s = 0; s < NS; ++s) xr[s] = k0 + s < K ? colp<R>(X, g, k0 + s, ch.mid)[j] : mk<R>(0, 0);
   for (int step = 0; step < cnt; ++step) {
     const int i = side == 0 ? ch.mid - 1 - step : ch.mid + 1 + step;
     const int cc = side == 0 ? i + 1 : i;
     C yv[NS];
     if (owner) {
-      C cj = to_r<R>(coupling_x(g, cc, j));
+      const C cj = ccast<R>(coupling_x(g, cc, j));
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         w[s * m + j] = cmul(cj, xr[s]);
-        yv[s] = (k0 + s < K) ? ld_io<R, ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i]) : mk<R>(0, 0);
+        yv[s] = k0 + s < K ? colp<R>(X, g, k0 + s, i)[j] : mk<R>(0, 0);
       }
     }
     __syncthreads();
@@ -776,7 +765,7 @@ __device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const c
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         xr[s] = csub(yv[s], acc[s]);
-        if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + i], xr[s]);
+        if (k0 + s < K) colp<R>(X, g, k0 + s, i)[j] = xr[s];
       }
     }
     __syncthreads();
@@ -785,9 +774,9 @@ __device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const c
 
 // 3: reduced right-hand side of separator j, t_j = T_j (b_s - C_s z_{s-1} - C_{s+1} z_{s+1}),
 //    stored at column s
-template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, const cplx<R> *__restrict__ T,
-                                             const IO *b, IO *x, int group, unsigned char *smem) {
+template <typename R, int NS>
+__device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, const cplx<R> *__restrict__ T, void *X,
+                                             int group, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
   C *w = (C *)smem;
@@ -795,36 +784,33 @@ __device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, co
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
-  const size_t Nu = (size_t)g.nx * g.nz;
-  const size_t mm = (size_t)m * m;
   if (owner) {
-    const C cl = to_r<R>(coupling_x(g, s_col, j)), cr = to_r<R>(coupling_x(g, s_col + 1, j));
+    const C cl = ccast<R>(coupling_x(g, s_col, j)), cr = ccast<R>(coupling_x(g, s_col + 1, j));
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       C r = mk<R>(0, 0);
       if (k0 + s < K) {
-        const size_t base = (k0 + s) * Nu + (size_t)j * g.nx + s_col;
-        r = ld_io<R, ADJ>(b[base]);
-        r = csub(r, cmul(cl, ld_io<R, ADJ>(x[base - 1])));
-        r = csub(r, cmul(cr, ld_io<R, ADJ>(x[base + 1])));
+        r = colp<R>(X, g, k0 + s, s_col)[j];
+        r = csub(r, cmul(cl, colp<R>(X, g, k0 + s, s_col - 1)[j]));
+        r = csub(r, cmul(cr, colp<R>(X, g, k0 + s, s_col + 1)[j]));
       }
       w[s * m + j] = r;
     }
   }
   __syncthreads();
   C acc[NS];
-  col_matvec<R, NS>(T + (size_t)s_col * mm, m, w, part, acc);
+  col_matvec<R, NS>(T + (size_t)s_col * m * m, m, w, part, acc);
   if (owner)
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (k0 + s < K) st_io<ADJ>(x[(k0 + s) * Nu + (size_t)j * g.nx + s_col], acc[s]);
+      if (k0 + s < K) colp<R>(X, g, k0 + s, s_col)[j] = acc[s];
 }
 
 // 4: the separators' block LU: y_j = t_j - N_j y_{j-1} (j = 2..P-1), then
 //    x_j = y_j - U_j x_{j+1} (j = P-2..1); N_j, U_j in the V, W slots of column s_j
-template <typename R, typename IO, bool ADJ, int NS>
+template <typename R, int NS>
 __device__ __forceinline__ void red_chain_body(const Grid &g, int K, int P, const int *part_cols,
-                                               const cplx<R> *__restrict__ V, const cplx<R> *__restrict__ W, IO *x,
+                                               const cplx<R> *__restrict__ V, const cplx<R> *__restrict__ W, void *X,
                                                int group, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
@@ -833,111 +819,134 @@ __device__ __forceinline__ void red_chain_body(const Grid &g, int K, int P, cons
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
-  const size_t Nu = (size_t)g.nx * g.nz;
   const size_t mm = (size_t)m * m;
-  auto at = [&](int s, int col) -> IO & { return x[(k0 + s) * Nu + (size_t)j * g.nx + col]; };
   C cur[NS];
   if (owner)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) cur[s] = (k0 + s < K) ? ld_io<R, ADJ>(at(s, separator(part_cols, 1))) : mk<R>(0, 0);
-  for (int jj = 2; jj < P; ++jj) {
-    const int sc = separator(part_cols, jj);
-    C t[NS];
-    if (owner)
+    for (int s = 0; s < NS; ++s) cur[s] = k0 + s < K ? colp<R>(X, g, k0 + s, separator(part_cols, 1))[j] : mk<R>(0, 0);
+  for (int pass = 0; pass < 2; ++pass) {   // forward over j = 2..P-1, then back over j = P-2..1
+    for (int step = 0; step < P - 2; ++step) {
+      const int jj = pass == 0 ? 2 + step : P - 2 - step;
+      const int sc = separator(part_cols, jj);
+      C t[NS];
+      if (owner)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        w[s * m + j] = cur[s];
-        t[s] = (k0 + s < K) ? ld_io<R, ADJ>(at(s, sc)) : mk<R>(0, 0);
-      }
-    __syncthreads();
-    C acc[NS];
-    col_matvec<R, NS>(V + (size_t)sc * mm, m, w, part, acc);
-    if (owner)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        cur[s] = csub(t[s], acc[s]);
-        if (k0 + s < K) st_io<ADJ>(at(s, sc), cur[s]);
-      }
-    __syncthreads();
-  }
-  for (int jj = P - 2; jj >= 1; --jj) {
-    const int sc = separator(part_cols, jj);
-    C t[NS];
-    if (owner)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        w[s * m + j] = cur[s];
-        t[s] = (k0 + s < K) ? ld_io<R, ADJ>(at(s, sc)) : mk<R>(0, 0);
-      }
-    __syncthreads();
-    C acc[NS];
-    col_matvec<R, NS>(W + (size_t)sc * mm, m, w, part, acc);
-    if (owner)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        cur[s] = csub(t[s], acc[s]);
-        if (k0 + s < K) st_io<ADJ>(at(s, sc), cur[s]);
-      }
-    __syncthreads();
-  }
-}
-
-// 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}, item (chunk,
-//    block of CB columns, group)
-constexpr int CORR_CB = 4;
-template <typename R, typename IO, bool ADJ, int NS>
-__device__ __forceinline__ void correct_body(const Grid &g, int K, int P, const int *part_cols, int c, int blk,
-                                             const cplx<R> *__restrict__ V, const cplx<R> *__restrict__ W, IO *x,
-                                             int group, unsigned char *smem) {
-  using C = cplx<R>;
-  const Chunk ch = chunk_of(part_cols, c);
-  const int i0 = ch.a + blk * CORR_CB;
-  if (i0 > ch.b) return;   // uniform over the workgroup
-  const int i1 = min(ch.b, i0 + CORR_CB - 1);
-  const int m = g.nz;
-  C *wl = (C *)smem;         // [NS][m]
-  C *wr = wl + NS * m;       // [NS][m]
-  C *part = wr + NS * m;
-  const int j = threadIdx.x;
-  const bool owner = threadIdx.y == 0 && j < m;
-  const int k0 = group * NS;
-  const size_t Nu = (size_t)g.nx * g.nz;
-  const size_t mm = (size_t)m * m;
-  const bool hl = c > 0, hr = c < P - 1;
-  const int sl = hl ? ch.a - 1 : 0, sr = hr ? ch.b + 1 : 0;
-  if (owner)
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const bool in = k0 + s < K;
-      const size_t base = (k0 + s) * Nu + (size_t)j * g.nx;
-      wl[s * m + j] = (in && hl) ? ld_io<R, ADJ>(x[base + sl]) : mk<R>(0, 0);
-      wr[s * m + j] = (in && hr) ? ld_io<R, ADJ>(x[base + sr]) : mk<R>(0, 0);
-    }
-  __syncthreads();
-  for (int i = i0; i <= i1; ++i) {
-    C acc[NS], acc2[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
-    if (hl) col_matvec<R, NS>(V + (size_t)i * mm, m, wl, part, acc);
-    if (hl && hr) __syncthreads();   // part is reused
-    if (hr) {
-      col_matvec<R, NS>(W + (size_t)i * mm, m, wr, part, acc2);
-#pragma unroll
-      for (int s = 0; s < NS; ++s) acc[s] = cadd(acc[s], acc2[s]);
-    }
-    if (owner)
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (k0 + s < K) {
-          IO &d = x[(k0 + s) * Nu + (size_t)j * g.nx + i];
-          st_io<ADJ>(d, csub(ld_io<R, ADJ>(d), acc[s]));
+        for (int s = 0; s < NS; ++s) {
+          w[s * m + j] = cur[s];
+          t[s] = k0 + s < K ? colp<R>(X, g, k0 + s, sc)[j] : mk<R>(0, 0);
         }
-    __syncthreads();
+      __syncthreads();
+      C acc[NS];
+      col_matvec<R, NS, (sizeof(R) == 4 && NS <= 2) ? 16 : 8>((pass == 0 ? V : W) + (size_t)sc * mm, m, w, part, acc);
+      if (owner)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          cur[s] = csub(t[s], acc[s]);
+          if (k0 + s < K) colp<R>(X, g, k0 + s, sc)[j] = cur[s];
+        }
+      __syncthreads();
+    }
   }
 }
 
-template <typename R, typename IO, bool ADJ, int NS, int PH>
-__global__ void k_solve(SweepBatch bt) {
+// 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}.  A workgroup
+//    takes one interior column and a tile of KT sources: the two separator vectors of
+//    the tile are staged in LDS, and thread (lane, group) accumulates rows lane + 64 u
+//    for KT / 4 sources, so each element of V_i and W_i is read once per tile and every
+//    LDS value feeds several rows.  item = (chunk, column of the chunk, source tile).
+constexpr int CORR_CB = 1;
+template <typename R> struct CorrTile { static constexpr int KT = 16; };
+template <> struct CorrTile<double> { static constexpr int KT = 8; };
+
+// acc[u][t] += sum_l (V_i[r_u][l] xl[t][l] + W_i[r_u][l] xr[t][l]); the loop body has no
+// branches (row addresses are clamped to the column, rows past m are never stored), so
+// the loads of consecutive l overlap.
+template <typename R, int RU, int SPT, bool HL, bool HR>
+__device__ __forceinline__ void correct_acc(const cplx<R> *__restrict__ Vi, const cplx<R> *__restrict__ Wi, int m,
+                                            const cplx<R> *xl, const cplx<R> *xr, int lane, cplx<R> (&acc)[RU][SPT]) {
+  using C = cplx<R>;
+  int rr[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) rr[u] = min(lane + 64 * u, m - 1);
+#pragma unroll 4
+  for (int l = 0; l < m; ++l) {
+    C a[SPT], bb[SPT], v[RU], w[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      if (HL) v[u] = Vi[(size_t)l * m + rr[u]];
+      if (HR) w[u] = Wi[(size_t)l * m + rr[u]];
+    }
+#pragma unroll
+    for (int t = 0; t < SPT; ++t) {
+      if (HL) a[t] = xl[t * m + l];
+      if (HR) bb[t] = xr[t * m + l];
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        if (HL) cfma(acc[u][t], v[u], a[t]);
+        if (HR) cfma(acc[u][t], w[u], bb[t]);
+      }
+  }
+}
+
+template <typename R, int RU>
+__global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
+  extern __shared__ unsigned char smem[];
+  using C = cplx<R>;
+  constexpr int KT = CorrTile<R>::KT, SPT = KT / 4;   // rows per thread RU: m <= 64 RU
+  const int item = item_of_block(bt.total);
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int tiles = (pp.K + KT - 1) / KT;
+  const int tile = local % tiles, rest = local / tiles;
+  const int c = rest / pp.ncb, u0 = rest % pp.ncb;
+  const Chunk ch = chunk_of(pp.part, c);
+  const int i = ch.a + u0;
+  if (i > ch.b) return;   // uniform over the workgroup
+  const Grid &g = pp.g;
+  const int m = g.nz, K = pp.K;
+  const size_t mm = (size_t)m * m;
+  const bool hl = c > 0, hr = c < pp.P - 1;
+  C *xl = (C *)smem;        // [KT][m] left separator values of the tile
+  C *xr = xl + KT * m;      // [KT][m] right separator values
+  const int k0 = tile * KT;
+  for (int e = threadIdx.x; e < KT * m; e += blockDim.x) {
+    const int sidx = e / m, l = e - sidx * m, k = k0 + sidx;
+    xl[e] = (hl && k < K) ? colp<R>(pp.x, g, k, ch.a - 1)[l] : mk<R>(0, 0);
+    xr[e] = (hr && k < K) ? colp<R>(pp.x, g, k, ch.b + 1)[l] : mk<R>(0, 0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const C *Vi = (const C *)pp.V + (size_t)i * mm, *Wi = (const C *)pp.W + (size_t)i * mm;
+  C acc[RU][SPT];
+#pragma unroll
+  for (int u = 0; u < RU; ++u)
+#pragma unroll
+    for (int t = 0; t < SPT; ++t) acc[u][t] = mk<R>(0, 0);
+  const C *gl = xl + grp * SPT * m, *gr = xr + grp * SPT * m;
+  if (hl && hr) correct_acc<R, RU, SPT, true, true>(Vi, Wi, m, gl, gr, lane, acc);
+  else if (hl) correct_acc<R, RU, SPT, true, false>(Vi, Wi, m, gl, gr, lane, acc);
+  else correct_acc<R, RU, SPT, false, true>(Vi, Wi, m, gl, gr, lane, acc);
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const int r = lane + 64 * u;
+    if (r < m)
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        const int k = k0 + grp * SPT + t;
+        if (k < K) {
+          C *d = colp<R>(pp.x, g, k, i) + r;
+          *d = csub(*d, acc[u][t]);
+        }
+      }
+  }
+}
+
+template <typename R, int NS, int PH>
+__global__ __launch_bounds__(512) void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
   const int item = item_of_block(bt.total);
   const int q = find_problem(bt.first, bt.n, item);
@@ -947,25 +956,67 @@ __global__ void k_solve(SweepBatch bt) {
   const int grp = local % G, rest = local / G;
   const cplx<R> *T = (const cplx<R> *)pp.T;
   if (PH == 0)
-    fwd_body<R, IO, ADJ, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, (const IO *)pp.b, (IO *)pp.x, grp, rest & 1, smem);
+    fwd_body<R, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, pp.x, grp, rest & 1, smem);
   else if (PH == 1)
-    mid_body<R, IO, ADJ, NS>(pp.g, pp.K, chunk_of(pp.part, rest), T, (const IO *)pp.b, (IO *)pp.x, grp, smem);
+    mid_body<R, NS>(pp.g, pp.K, chunk_of(pp.part, rest), T, pp.x, grp, smem);
   else if (PH == 2)
-    bwd_body<R, IO, ADJ, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, (IO *)pp.x, grp, rest & 1, smem);
+    bwd_body<R, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, pp.x, grp, rest & 1, smem);
   else if (PH == 3)
-    red_rhs_body<R, IO, ADJ, NS>(pp.g, pp.K, separator(pp.part, rest + 1), T, (const IO *)pp.b, (IO *)pp.x, grp, smem);
-  else if (PH == 4)
-    red_chain_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.P, pp.part, (const cplx<R> *)pp.V, (const cplx<R> *)pp.W,
-                                   (IO *)pp.x, grp, smem);
+    red_rhs_body<R, NS>(pp.g, pp.K, separator(pp.part, rest + 1), T, pp.x, grp, smem);
   else
-    correct_body<R, IO, ADJ, NS>(pp.g, pp.K, pp.P, pp.part, rest / pp.ncb, rest % pp.ncb, (const cplx<R> *)pp.V,
-                                 (const cplx<R> *)pp.W, (IO *)pp.x, grp, smem);
+    red_chain_body<R, NS>(pp.g, pp.K, pp.P, pp.part, (const cplx<R> *)pp.V, (const cplx<R> *)pp.W, pp.x, grp, smem);
+}
+
+// Row-major fields [K][nz][nx] (IO type) to the column-major compute copy [K][nx][nz]
+// and back, through 32 x 32 LDS tiles (coalesced on both sides); ADJ conjugates.
+// grid (ceil(nx/32), ceil(nz/32), K), block (32, 8).
+template <typename R, typename IO, bool ADJ>
+__global__ __launch_bounds__(256) void k_to_colmajor(Grid g, const IO *__restrict__ in, cplx<R> *__restrict__ out) {
+  __shared__ cplx<R> tile[32][33];
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, k = blockIdx.z;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int j = j0 + r, i = i0 + threadIdx.x;
+    if (j < g.nz && i < g.nx) {
+      const IO v = in[k * Nu + (size_t)j * g.nx + i];
+      cplx<R> c = mk<R>((R)v.x, (R)v.y);
+      tile[r][threadIdx.x] = ADJ ? cconj(c) : c;
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + threadIdx.x;
+    if (i < g.nx && j < g.nz) out[k * Nu + (size_t)i * g.nz + j] = tile[threadIdx.x][r];
+  }
+}
+template <typename R, typename IO, bool ADJ>
+__global__ __launch_bounds__(256) void k_from_colmajor(Grid g, const cplx<R> *__restrict__ in, IO *__restrict__ out) {
+  __shared__ cplx<R> tile[32][33];
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, k = blockIdx.z;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + threadIdx.x;
+    if (i < g.nx && j < g.nz) tile[threadIdx.x][r] = in[k * Nu + (size_t)i * g.nz + j];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int j = j0 + r, i = i0 + threadIdx.x;
+    if (j < g.nz && i < g.nx) {
+      cplx<R> c = tile[r][threadIdx.x];
+      if (ADJ) c = cconj(c);
+      IO v;
+      v.x = c.x;
+      v.y = c.y;
+      out[k * Nu + (size_t)j * g.nx + i] = v;
+    }
+  }
 }
 
 // block shape of the sweeps: x covers the rows, y splits each dot product
+// (at most 512 threads, so a thread may hold up to 256 VGPRs)
 inline dim3 sweep_block(int m) {
   int rj = ((m + 63) / 64) * 64;
-  int gy = 1024 / rj;
+  int gy = 512 / rj;
   gy = gy > 4 ? 4 : (gy < 1 ? 1 : gy);
   return dim3(rj, gy);
 }
@@ -998,8 +1049,8 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     return KF_EINVAL;
   }
   if (ns == 0) ns = 1;
-  if (ns != 1 && ns != 2 && ns != 4) {
-    set_error("sources per workgroup must be 1, 2 or 4");
+  if (ns != 1 && ns != 2 && ns != 4 && ns != 8) {
+    set_error("sources per workgroup must be 1, 2, 4 or 8");
     return KF_EINVAL;
   }
   p->ns = ns;
@@ -1173,12 +1224,12 @@ kf_status blu_factor(kf_problem *p, int which) {
 }
 
 // ---------------------------------------------------------------------------
-// solves of a batch of problems: six phases, one launch each
+// solves of a batch of problems: the column-major copy, six phases (one launch
+// each, covering every problem), and the copy back
 // ---------------------------------------------------------------------------
 namespace {
-template <typename R, typename IO, bool ADJ, int NS>
-kf_status solve_phases(const std::vector<kf_problem *> &ps, const IO *const *rhs, IO *const *x, hipStream_t s,
-                       kf_problem *prof) {
+template <typename R, int NS>
+kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_problem *prof) {
   const bool fp32 = sizeof(R) == sizeof(float);
   SweepBatch bt{};
   bt.n = (int)ps.size();
@@ -1189,10 +1240,12 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, const IO *const *rhs
     bt.p[q] = SweepProblem{p->grid(), p->K, p->P, p->ncb, p->d_part,
                            fp32 ? (const void *)p->T32 : (const void *)p->T64,
                            fp32 ? (const void *)p->V32 : (const void *)p->V64,
-                           fp32 ? (const void *)p->W32 : (const void *)p->W64, rhs[q], x[q]};
+                           fp32 ? (const void *)p->W32 : (const void *)p->W64,
+                           fp32 ? (void *)p->sol32 : (void *)p->sol64};
   }
   const dim3 blk = sweep_block(m_max);
   const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
+  static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
   for (int ph = 0; ph < 6; ++ph) {
     int tot = 0;
     for (int q = 0; q < bt.n; ++q) {
@@ -1203,17 +1256,17 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, const IO *const *rhs
            : ph == 1            ? p->P * G
            : ph == 3            ? (p->P - 1) * G
            : ph == 4            ? (p->P > 2 ? G : 0)
-                                : (p->P > 1 ? p->P * p->ncb * G : 0);
+                                : (p->P > 1 ? p->P * p->ncb * ((p->K + CorrTile<R>::KT - 1) / CorrTile<R>::KT) : 0);
     }
     bt.first[bt.n] = bt.total = tot;
     if (tot == 0) continue;
-    ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : -1);
+    ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
 #define SOLVE_PHASE(PH)                                                                                       \
   do {                                                                                                        \
     if (smem > 65536)                                                                                         \
-      HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, IO, ADJ, NS, PH>,                                  \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));                    \
-    hipLaunchKernelGGL((k_solve<R, IO, ADJ, NS, PH>), dim3(tot), blk, smem, s, bt);                           \
+      HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, PH>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                  (int)smem));                                                                \
+    hipLaunchKernelGGL((k_solve<R, NS, PH>), dim3(tot), blk, smem, s, bt);                                   \
   } while (0)
     switch (ph) {
       case 0: SOLVE_PHASE(0); break;
@@ -1221,9 +1274,58 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, const IO *const *rhs
       case 2: SOLVE_PHASE(2); break;
       case 3: SOLVE_PHASE(3); break;
       case 4: SOLVE_PHASE(4); break;
-      default: SOLVE_PHASE(5); break;
+      default: {
+        const size_t smem_c = 2 * (size_t)m_max * CorrTile<R>::KT * sizeof(cplx<R>);
+        const int ru = (m_max + 63) / 64;
+#define CORRECT(RUV)                                                                                        \
+  do {                                                                                                      \
+    if (smem_c > 65536)                                                                                     \
+      HIP_TRY(hipFuncSetAttribute((const void *)k_correct<R, RUV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                  (int)smem_c));                                                            \
+    hipLaunchKernelGGL((k_correct<R, RUV>), dim3(tot), dim3(256), smem_c, s, bt);                          \
+  } while (0)
+        switch (ru) {
+          case 1: CORRECT(1); break;
+          case 2: CORRECT(2); break;
+          case 3: CORRECT(3); break;
+          case 4: CORRECT(4); break;
+          case 5: CORRECT(5); break;
+          case 6: CORRECT(6); break;
+          case 7: CORRECT(7); break;
+          default: CORRECT(8); break;
+        }
+#undef CORRECT
+      }
     }
 #undef SOLVE_PHASE
+    LAUNCH_CHECK();
+  }
+  return KF_OK;
+}
+
+template <typename R, typename IO, bool ADJ>
+kf_status solve_copies(const std::vector<kf_problem *> &ps, const IO *const *rhs, IO *const *x, hipStream_t s,
+                       int ns, kf_problem *prof) {
+  const bool fp32 = sizeof(R) == sizeof(float);
+  for (size_t q = 0; q < ps.size(); ++q) {
+    kf_problem *p = ps[q];
+    const dim3 grid((p->nx + 31) / 32, (p->nz + 31) / 32, p->K);
+    hipLaunchKernelGGL((k_to_colmajor<R, IO, ADJ>), grid, dim3(32, 8), 0, s, p->grid(), rhs[q],
+                       (cplx<R> *)(fp32 ? (void *)p->sol32 : (void *)p->sol64));
+    LAUNCH_CHECK();
+  }
+  // FP64 sweeps use at most 4 right-hand sides per workgroup (register budget)
+  constexpr int NS_MAX = sizeof(R) == 4 ? 8 : 4;
+  kf_status st = ns >= 8 ? solve_phases<R, NS_MAX>(ps, s, prof)
+               : ns >= 4 ? solve_phases<R, 4>(ps, s, prof)
+               : ns >= 2 ? solve_phases<R, 2>(ps, s, prof)
+                         : solve_phases<R, 1>(ps, s, prof);
+  if (st != KF_OK) return st;
+  for (size_t q = 0; q < ps.size(); ++q) {
+    kf_problem *p = ps[q];
+    const dim3 grid((p->nx + 31) / 32, (p->nz + 31) / 32, p->K);
+    hipLaunchKernelGGL((k_from_colmajor<R, IO, ADJ>), grid, dim3(32, 8), 0, s, p->grid(),
+                       (const cplx<R> *)(fp32 ? (void *)p->sol32 : (void *)p->sol64), x[q]);
     LAUNCH_CHECK();
   }
   return KF_OK;
@@ -1234,15 +1336,13 @@ kf_status solve_dispatch(const std::vector<kf_problem *> &ps, int adjoint, const
                          hipStream_t s, kf_problem *prof) {
   if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
   const bool fp32 = sizeof(R) == sizeof(float);
-  int ns = 4;
+  int ns = 8;
   for (kf_problem *p : ps) {
     if (!(fp32 ? p->have_T32 : p->have_T64)) { set_error("block solve before factorisation"); return KF_ESTATE; }
     ns = std::min(ns, p->ns);
   }
   ProfScope sw(prof, PROF_SWEEP);
-  if (ns >= 4) return adjoint ? solve_phases<R, IO, true, 4>(ps, rhs, x, s, prof) : solve_phases<R, IO, false, 4>(ps, rhs, x, s, prof);
-  if (ns == 2) return adjoint ? solve_phases<R, IO, true, 2>(ps, rhs, x, s, prof) : solve_phases<R, IO, false, 2>(ps, rhs, x, s, prof);
-  return adjoint ? solve_phases<R, IO, true, 1>(ps, rhs, x, s, prof) : solve_phases<R, IO, false, 1>(ps, rhs, x, s, prof);
+  return adjoint ? solve_copies<R, IO, true>(ps, rhs, x, s, ns, prof) : solve_copies<R, IO, false>(ps, rhs, x, s, ns, prof);
 }
 }  // namespace
 

@@ -93,8 +93,7 @@ struct SweepProblem {
   int K, P, ncb;       // sources, chunks, correction blocks per chunk
   const int *part;     // [P][3]: first, last and meeting column of each chunk (device)
   const void *T, *V, *W;   // factors and spikes (c128 or c64)
-  const void *b;       // right-hand sides (IO type)
-  void *x;             // solutions (IO type)
+  void *x;             // right-hand sides in, solutions out: column-major [K][nx][nz] (compute type)
 };
 struct SweepBatch {
   int n, total;
@@ -156,6 +155,8 @@ struct kf_problem {
   bool have_T64 = false, have_T32 = false;
   double2 *fac_work = nullptr;                 // factorisation scratch, fac_slots work matrices
   size_t fac_slots = 0;
+  double2 *sol64 = nullptr;                    // [K][nx][nz] column-major solve copy (c128)
+  float2 *sol32 = nullptr;                     // the same for complex64 sweeps
 
   // scratch
   double2 *vec_a = nullptr, *vec_b = nullptr, *vec_c = nullptr, *vec_d = nullptr;  // [K][nz][nx] each
@@ -179,7 +180,8 @@ struct kf_problem {
 };
 
 enum ProfId { PROF_KKT = 0, PROF_STENCIL, PROF_FACTOR, PROF_SWEEP, PROF_PRECOND, PROF_ORTH, PROF_REDUCE,
-              PROF_FWD64, PROF_FWD32, PROF_BWD64, PROF_BWD32, PROF_N };
+              PROF_FWD64, PROF_FWD32, PROF_BWD64, PROF_BWD32, PROF_MID, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT,
+              PROF_N };
 
 // error plumbing
 void set_error(const std::string &msg);
@@ -232,9 +234,18 @@ kf_status blu_solve_batch(const std::vector<kf_problem *> &ps, int adjoint, cons
 // reductions (deterministic, fixed order)
 kf_status per_source_norms(kf_problem *p, const double2 *x, int64_t n_per, int K, double *out_host);
 kf_status dot_c128(kf_problem *p, const double2 *a, const double2 *b, int64_t n, double2 *out_dev);
-kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev);
-kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev);
-kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w, int64_t n);
+// `active` (device int, may be NULL): the launch does nothing when *active == 0
+kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev, const int *active = nullptr);
+kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev,
+                        const int *active = nullptr);
+kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w,
+                         int64_t n, const int *active = nullptr);
+// w <- w - V h, then h_out = V^H w (may be NULL) and nrm_out = |w|, in one sweep over V
+kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *h, double2 *w, int64_t n,
+                        double2 *h_out, double *nrm_out, const int *active = nullptr);
+// DGKS test after one Gram-Schmidt pass: *flag = 1 if a second pass is needed, else h2 = 0
+kf_status reorth_test(kf_problem *p, int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2,
+                      int *flag);
 // FGMRES small dense algebra on the device (single-thread kernels)
 kf_status arnoldi_finish(kf_problem *p, int j, int m, const double2 *h1, const double2 *h2, const double *nrm,
                          double2 *H, double2 *cs, double2 *sn, double2 *g, double *resid);

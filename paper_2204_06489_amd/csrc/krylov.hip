@@ -8,6 +8,7 @@ namespace {
 constexpr int RB = 256;      // reduction block size (4 wavefronts)
 constexpr int RG = 1024;     // reduction grid size (fixed => fixed summation order)
 constexpr int MDOT = 8;      // vectors per multi-dot pass
+constexpr int FDOT = 8;      // dot products carried by the fused update-and-dot pass
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -15,30 +16,44 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// block-wide sum of NV doubles per thread; result valid in thread 0
+// block-wide sum of NV doubles per thread; result valid in thread 0.  The values go
+// through LDS eight at a time (lds: [8][RB] doubles, plus NV results), so that the
+// compiler does not keep NV wave reductions in flight at once: the order of the sums
+// is fixed, the register footprint small.
 template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double *lds /*[NV][RB/64]*/) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__device__ inline void block_sum(double (&v)[NV], double *lds /*[8 * RB + NV]*/) {
+  double *res = lds + 8 * RB;
+  const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double s = wave_sum(v[q]);
-    if (lane == 0) lds[q * (RB / 64) + wid] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  for (int c0 = 0; c0 < NV; c0 += 8) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
+    for (int k = 0; k < 8; ++k)
+      if (c0 + k < NV) lds[k * RB + tid] = v[c0 + k];
+    __syncthreads();
+    // 8 rows of RB values: 32 lanes per row, each adds RB / 32 values, then a
+    // 32-lane shuffle tree
+    {
+      const int k = tid >> 5, l = tid & 31;
       double s = 0.0;
-      for (int w = 0; w < RB / 64; ++w) s += lds[q * (RB / 64) + w];
-      v[q] = s;
+      if (k < 8 && c0 + k < NV) {
+#pragma unroll
+        for (int i = 0; i < RB / 32; ++i) s += lds[k * RB + l + 32 * i];
+      }
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+      if (k < 8 && l == 0 && c0 + k < NV) res[c0 + k] = s;
     }
+    __syncthreads();
   }
+  if (tid == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = res[q];
 }
 
 // partial[blockIdx][0..1] = sum conj(a) b over the block's grid-stride share
 __global__ __launch_bounds__(RB) void k_dot_partial(const double2 *__restrict__ a, const double2 *__restrict__ b,
                                                     int64_t n, double *partial) {
-  __shared__ double lds[2 * RB / 64];
+  __shared__ double lds[8 * RB + 2];
   double v[2] = {0.0, 0.0};
   for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
     double2 x = a[t], y = b[t];
@@ -49,8 +64,10 @@ __global__ __launch_bounds__(RB) void k_dot_partial(const double2 *__restrict__ 
   if (threadIdx.x == 0) { partial[2 * blockIdx.x] = v[0]; partial[2 * blockIdx.x + 1] = v[1]; }
 }
 
-__global__ __launch_bounds__(RB) void k_norm2_partial(const double2 *__restrict__ a, int64_t n, double *partial) {
-  __shared__ double lds[RB / 64];
+__global__ __launch_bounds__(RB) void k_norm2_partial(const double2 *__restrict__ a, int64_t n, double *partial,
+                                                      const int *active) {
+  if (active && *active == 0) return;
+  __shared__ double lds[8 * RB + 1];
   double v[1] = {0.0};
   for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
     double2 x = a[t];
@@ -62,8 +79,9 @@ __global__ __launch_bounds__(RB) void k_norm2_partial(const double2 *__restrict_
 
 // sum the RG partials of nq quantities in fixed order; out[q] = sum (or sqrt for norms)
 __global__ __launch_bounds__(RB) void k_finish(const double *__restrict__ partial, int nq, int stride, int take_sqrt,
-                                               double *out) {
-  __shared__ double lds[RB / 64];
+                                               double *out, const int *active) {
+  if (active && *active == 0) return;
+  __shared__ double lds[8 * RB + 1];
   for (int q = 0; q < nq; ++q) {
     double v[1] = {0.0};
     for (int b = threadIdx.x; b < RG; b += RB) v[0] += partial[(size_t)b * stride + q];
@@ -77,8 +95,9 @@ __global__ __launch_bounds__(RB) void k_finish(const double *__restrict__ partia
 template <int NQ>
 __global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restrict__ V, int q0, int nv,
                                                          const double2 *__restrict__ w, int64_t n, double *partial,
-                                                         int stride) {
-  __shared__ double lds[2 * NQ * RB / 64];
+                                                         int stride, const int *active) {
+  if (active && *active == 0) return;
+  __shared__ double lds[8 * RB + 2 * NQ];
   double v[2 * NQ];
 #pragma unroll
   for (int q = 0; q < 2 * NQ; ++q) v[q] = 0.0;
@@ -99,9 +118,50 @@ __global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restri
       if (q0 + q / 2 < nv) partial[(size_t)blockIdx.x * stride + 2 * q0 + q] = v[q];
 }
 
+// Fused Gram-Schmidt update: w <- w - sum_{q<nv} V_q h_q, written back, while the same
+// sweep accumulates the dot products V_q^H w (new w) for q < min(nv, FDOT) (WANT_DOTS)
+// and |w|^2 (new w).  partial row of a block: [2 * FDOT dots | norm^2].
+template <bool WANT_DOTS>
+__global__ __launch_bounds__(RB) void k_axpy_dot_partial(const double2 *__restrict__ V, int nv,
+                                                         const double2 *__restrict__ h, double2 *w, int64_t n,
+                                                         double *partial, const int *active) {
+  if (active && *active == 0) return;
+  constexpr int NQ = WANT_DOTS ? FDOT : 0;
+  __shared__ double lds[8 * RB + 2 * FDOT + 1];
+  // h is read with uniform indices (scalar loads): the coefficients sit in SGPRs
+  const double2 *__restrict__ hs = h;
+  double v[2 * NQ + 1];
+#pragma unroll
+  for (int q = 0; q < 2 * NQ + 1; ++q) v[q] = 0.0;
+  const int nd = nv < NQ ? nv : NQ;
+#pragma unroll 1
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
+    double2 y = w[t];
+    double2 x[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      x[q] = q < nd ? V[(size_t)q * n + t] : make_double2(0.0, 0.0);
+      y = csub(y, cmul(x[q], hs[q]));
+    }
+#pragma unroll 1
+    for (int q = NQ; q < nv; ++q) y = csub(y, cmul(V[(size_t)q * n + t], hs[q]));
+    w[t] = y;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      v[2 * q] += x[q].x * y.x + x[q].y * y.y;
+      v[2 * q + 1] += x[q].x * y.y - x[q].y * y.x;
+    }
+    v[2 * NQ] += y.x * y.x + y.y * y.y;
+  }
+  block_sum<2 * NQ + 1>(v, (double *)lds);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 2 * NQ + 1; ++q) partial[(size_t)blockIdx.x * (2 * FDOT + 1) + q] = v[q];
+}
+
 // w += sign * sum_q V_q h_q
 __global__ __launch_bounds__(RB) void k_multiaxpy(const double2 *__restrict__ V, int nv, const double2 *__restrict__ h,
-                                                  double sign, double2 *w, int64_t n) {
+                                                  double sign, double2 *w, int64_t n, const int *active) {
+  if (active && *active == 0) return;
   for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)gridDim.x * RB) {
     double2 acc = w[t];
     for (int q = 0; q < nv; ++q) {
@@ -113,9 +173,23 @@ __global__ __launch_bounds__(RB) void k_multiaxpy(const double2 *__restrict__ V,
   }
 }
 
+// Reorthogonalisation test of Daniel, Gragg, Kaufman and Stewart after one classical
+// Gram-Schmidt pass w' = w - V h: the norm of w before the pass is sqrt(|w'|^2 + |h|^2)
+// (V orthonormal); a second pass is needed only if |w'| < eta |w|.  flag = 1 asks for
+// it; otherwise the second pass's coefficients h2 are zero.
+__global__ void k_reorth_test(int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2, int *flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = nrm_after[0] * nrm_after[0];
+  for (int i = 0; i < nv; ++i) s += cabs2(h1[i]);
+  const int f = nrm_after[0] < eta * sqrt(s) ? 1 : 0;
+  flag[0] = f;
+  if (!f)
+    for (int i = 0; i < nv; ++i) h2[i] = make_double2(0.0, 0.0);
+}
+
 // per-source ||x_k||^2 partials: grid (RG/8, K)
 __global__ __launch_bounds__(RB) void k_src_norm_partial(const double2 *__restrict__ x, int64_t n_per, double *partial) {
-  __shared__ double lds[RB / 64];
+  __shared__ double lds[8 * RB + 1];
   const int k = blockIdx.y;
   const int nb = gridDim.x;
   double v[1] = {0.0};
@@ -151,39 +225,74 @@ kf_status dot_c128(kf_problem *p, const double2 *a, const double2 *b, int64_t n,
   ProfScope ps(p, PROF_REDUCE);
   hipLaunchKernelGGL(k_dot_partial, dim3(RG), dim3(RB), 0, p->stream, a, b, n, p->red);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2, 2, 0, (double *)out_dev);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2, 2, 0, (double *)out_dev, nullptr);
   LAUNCH_CHECK();
   return KF_OK;
 }
 
-kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev) {
+kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev, const int *active) {
   ProfScope ps(p, PROF_REDUCE);
-  hipLaunchKernelGGL(k_norm2_partial, dim3(RG), dim3(RB), 0, p->stream, a, n, p->red);
+  hipLaunchKernelGGL(k_norm2_partial, dim3(RG), dim3(RB), 0, p->stream, a, n, p->red, active);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 1, 1, 1, out_dev);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 1, 1, 1, out_dev, active);
   LAUNCH_CHECK();
   return KF_OK;
 }
 
-kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev) {
+kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev,
+                        const int *active) {
   ProfScope ps(p, PROF_ORTH);
   int stride = 2 * nv;
   for (int q0 = 0; q0 < nv; q0 += MDOT) {
-    hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, p->red, stride);
+    hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, p->red, stride,
+                       active);
     LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev, active);
   LAUNCH_CHECK();
   return KF_OK;
 }
 
 kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w,
-                         int64_t n) {
+                         int64_t n, const int *active) {
   ProfScope ps(p, PROF_ORTH);
   int64_t b = (n + RB - 1) / RB;
   unsigned grid = (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
-  hipLaunchKernelGGL(k_multiaxpy, dim3(grid), dim3(RB), 0, p->stream, V, nv, h_dev, sign, w, n);
+  hipLaunchKernelGGL(k_multiaxpy, dim3(grid), dim3(RB), 0, p->stream, V, nv, h_dev, sign, w, n, active);
   LAUNCH_CHECK();
+  return KF_OK;
+}
+
+// w <- w - V h (nv vectors); then h_out = V^H w and |w| (h_out may be NULL: norm only)
+kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *h, double2 *w, int64_t n,
+                        double2 *h_out, double *nrm_out, const int *active) {
+  ProfScope ps(p, PROF_ORTH);
+  if (nv > 256) { set_error("too many Krylov vectors for the fused update"); return KF_EINVAL; }
+  const int stride = 2 * FDOT + 1;
+  if (h_out) hipLaunchKernelGGL(k_axpy_dot_partial<true>, dim3(RG), dim3(RB), 0, p->stream, V, nv, h, w, n, p->red, active);
+  else hipLaunchKernelGGL(k_axpy_dot_partial<false>, dim3(RG), dim3(RB), 0, p->stream, V, nv, h, w, n, p->red, active);
+  LAUNCH_CHECK();
+  // norm: the last entry of each partial row
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red + (h_out ? 2 * FDOT : 0), 1, stride, 1, nrm_out,
+                     active);
+  LAUNCH_CHECK();
+  if (h_out) {
+    const int nd = nv < FDOT ? nv : FDOT;
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2 * nd, stride, 0, (double *)h_out, active);
+    LAUNCH_CHECK();
+    if (nv > FDOT) {   // the remaining dot products against the updated w
+      double *red2 = p->red + (size_t)RG * stride;
+      const int stride2 = 2 * nv;
+      for (int q0 = FDOT; q0 < nv; q0 += MDOT) {
+        hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, red2, stride2,
+                           active);
+        LAUNCH_CHECK();
+      }
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, red2 + 2 * FDOT, 2 * (nv - FDOT), stride2, 0,
+                         (double *)(h_out + FDOT), active);
+      LAUNCH_CHECK();
+    }
+  }
   return KF_OK;
 }
 
@@ -276,6 +385,13 @@ kf_status arnoldi_finish(kf_problem *p, int j, int m, const double2 *h1, const d
                          double2 *H, double2 *cs, double2 *sn, double2 *g, double *resid) {
   ProfScope ps(p, PROF_ORTH);
   hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, p->stream, j, m, h1, h2, nrm, H, cs, sn, g, resid);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+kf_status reorth_test(kf_problem *p, int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2,
+                      int *flag) {
+  ProfScope ps(p, PROF_ORTH);
+  hipLaunchKernelGGL(k_reorth_test, dim3(1), dim3(64), 0, p->stream, nv, h1, nrm_after, eta, h2, flag);
   LAUNCH_CHECK();
   return KF_OK;
 }

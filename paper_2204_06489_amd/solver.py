@@ -157,6 +157,18 @@ class KKTProblem:
         torch.cuda.current_stream().synchronize()
         check(lib().kf_set_solver_shape(self._h, int(chunks), int(sources_per_group)))
 
+    def autotune(self, prec="c64", solves_per_factor=100.0):
+        """Time solver shapes on this problem and keep the best (see kf_autotune).
+        Returns the measured table as a list of dicts, best first."""
+        from ._lib import KfTuneEntry
+        torch.cuda.current_stream().synchronize()
+        tab = (KfTuneEntry * 64)()
+        n = C.c_int32()
+        check(lib().kf_autotune(self._h, _PREC[prec], float(solves_per_factor), tab, 64, C.byref(n)))
+        rows = [dict(chunks=e.chunks, sources_per_group=e.sources_per_group, t_factor_ms=e.t_factor_ms,
+                     t_solve_ms=e.t_solve_ms, score_ms=e.score_ms) for e in tab[:min(n.value, 64)]]
+        return sorted(rows, key=lambda r: r["score_ms"])
+
     @property
     def solver_shape(self):
         c, s = C.c_int32(), C.c_int32()

@@ -1,0 +1,71 @@
+"""Mixed precision on the 801 x 281, 80-source, 5 Hz workload against the FP64 oracle.
+
+The reference (tests/golden/c2_newton_oracle.npz, written by make_c2_reference.py from
+the oracle alone) is the oracle's Newton step: banded-LU forward solves, the assembled
+KKT matrix and GMRES with the exact block-triangular preconditioner to a relative
+residual of 1e-10.  The GPU step runs with complex64 block solves inside the inexact
+preconditioner and complex64 sweeps with FP64 refinement for u_n, FP64 FGMRES,
+orthogonalisation, residuals and update.  Refined to the same 1e-10, its step, gamma
+update and misfits must agree with the oracle's to 1e-6 relative; the errors of the
+other forms (FP64 throughout, and the 1e-6 tolerance of the timed workload) are
+printed beside it.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2204_06489_amd.solver import KKTProblem  # noqa: E402
+from synthetic.configs import make_problem_inputs  # noqa: E402
+from tests.gpu_cases import rel, to_np  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_newton_oracle.npz")
+
+FORMS = {   # name: (pc, fwd_prec, rtol)
+    "mixed, refined to 1e-10": ("inexact", "mixed", 1e-10),
+    "mixed, 1e-6 (timed form)": ("inexact", "mixed", 1e-6),
+    "FP64, refined to 1e-10": ("exact", "c128", 1e-10),
+}
+
+
+def _step(p, d, g0, pc, fwd, rtol):
+    p.set_gamma(g0)
+    xi, g1, st = p.newton_step(d, rtol=rtol, restart=30, maxit=600, pc=pc, fwd_prec=fwd, fwd_rtol=1e-10,
+                               misfit_after=True, update_in_place=False)
+    return to_np(p.unpack(xi)[1]), to_np(g1), st
+
+
+def test_c2_step_matches_oracle_in_every_precision():
+    ref = np.load(GOLDEN)
+    inp = make_problem_inputs("c2", 0)
+    print(f"[case] c2 {inp['nx']}x{inp['nz']} K={inp['K']} {inp['freq']} Hz", flush=True)
+    p = KKTProblem.from_inputs(inp, reg_on_update=True)
+    d = torch.as_tensor(np.ascontiguousarray(ref["d"])).cuda()
+    g0 = torch.as_tensor(inp["gamma0"]).cuda()
+    rows = {}
+    for name, (pc, fwd, rtol) in FORMS.items():
+        ds, g1, st = _step(p, d, g0, pc, fwd, rtol)
+        assert st["converged"], (name, st["rel_res"])
+        rows[name] = dict(
+            ds=rel(ds, ref["ds"]),
+            gamma=rel(g1, ref["gamma_next"]),
+            misfit_before=abs(st["misfit_before"] - float(ref["misfit_before"])) / float(ref["misfit_before"]),
+            misfit_after=abs(st["misfit_after"] - float(ref["misfit_after"])) / float(ref["misfit_after"]),
+            iters=st["outer_iters"], ms=st["t_total_ms"])
+    print(f"oracle: {int(ref['iterations'])} GMRES iterations, rel. res {float(ref['rel_res']):.1e}, "
+          f"misfit {float(ref['misfit_before']):.6f} -> {float(ref['misfit_after']):.6f}")
+    for name, r in rows.items():
+        print(f"{name:28s} ds {r['ds']:.2e}  gamma {r['gamma']:.2e}  misfit before {r['misfit_before']:.2e}  "
+              f"after {r['misfit_after']:.2e}  ({r['iters']} iterations, {r['ms']:.0f} ms)")
+    for key in ("ds", "gamma", "misfit_before", "misfit_after"):
+        assert rows["mixed, refined to 1e-10"][key] <= 1e-6, key
+        assert rows["FP64, refined to 1e-10"][key] <= 1e-6, key
+    # the timed tolerance: the step is accurate to what a 1e-6 residual allows
+    assert rows["mixed, 1e-6 (timed form)"]["gamma"] <= 1e-5

@@ -19,7 +19,7 @@ SHAPE = dict(nx=67, nz=37, npml=5, K=5)
 
 
 @pytest.mark.parametrize("chunks", [1, 2, 3, 7, 16, 34])
-@pytest.mark.parametrize("ns", [1, 2, 4])
+@pytest.mark.parametrize("ns", [1, 2, 4, 8])
 def test_partitioned_solve_matches_banded_lu(chunks, ns):
     print(f"[case] partition chunks={chunks} ns={ns} {SHAPE}", flush=True)
     inp = tiny_inputs(seed=1, **SHAPE)
@@ -56,8 +56,26 @@ def test_shapes_agree_and_reshape_refactors():
 def test_invalid_shapes_are_rejected():
     inp = tiny_inputs(seed=0, nx=21, nz=15, npml=4, K=2)
     _, gpu = oracle_and_gpu(inp, eps=1.0)
-    for chunks, ns in [(-1, 1), (12, 1), (65, 1), (2, 3), (2, 8)]:
+    for chunks, ns in [(-1, 1), (12, 1), (65, 1), (2, 3), (2, 16)]:
         with pytest.raises(KFError):
             gpu.set_solver_shape(chunks, ns)
     gpu.set_solver_shape(11, 4)    # (nx + 1) / 2 one-column chunks
     assert gpu.solver_shape == (11, 4)
+
+
+def test_autotune_picks_the_fastest_measured_shape_and_stays_exact():
+    inp = tiny_inputs(seed=3, nx=133, nz=37, npml=6, K=9)
+    orc, gpu = oracle_and_gpu(inp, eps=1.0)
+    table = gpu.autotune(prec="c64", solves_per_factor=50.0)
+    print("autotune table (best first):", table[:4])
+    assert len(table) >= 4
+    for r in table:
+        assert r["t_factor_ms"] > 0 and r["t_solve_ms"] > 0
+        assert abs(r["score_ms"] - (r["t_factor_ms"] + 50.0 * r["t_solve_ms"])) <= 1e-9 * r["score_ms"]
+    assert gpu.solver_shape == (table[0]["chunks"], table[0]["sources_per_group"])
+    b = complex_normal(gpu.field_shape, seed=4)
+    x, _ = gpu.helmholtz_solve(to_dev(b), prec="c128")
+    assert rel(to_np(x), orc.lu.solve(b)) <= 1e-10
+    # a new problem of the same size starts from the tuned shape
+    _, gpu2 = oracle_and_gpu(inp, eps=1.0)
+    assert gpu2.solver_shape == gpu.solver_shape
