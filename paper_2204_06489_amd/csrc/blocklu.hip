@@ -854,92 +854,112 @@ __device__ __forceinline__ void red_chain_body(const Grid &g, int K, int P, cons
 //    the tile are staged in LDS, and thread (lane, group) accumulates rows lane + 64 u
 //    for KT / 4 sources, so each element of V_i and W_i is read once per tile and every
 //    LDS value feeds several rows.  item = (chunk, column of the chunk, source tile).
-constexpr int CORR_CB = 1;
-template <typename R> struct CorrTile { static constexpr int KT = 16; };
-template <> struct CorrTile<double> { static constexpr int KT = 8; };
 
-// acc[u][t] += sum_l (V_i[r_u][l] xl[t][l] + W_i[r_u][l] xr[t][l]); the loop body has no
-// branches (row addresses are clamped to the column, rows past m are never stored), so
-// the loads of consecutive l overlap.
-template <typename R, int RU, int SPT, bool HL, bool HR>
-__device__ __forceinline__ void correct_acc(const cplx<R> *__restrict__ Vi, const cplx<R> *__restrict__ Wi, int m,
-                                            const cplx<R> *xl, const cplx<R> *xr, int lane, cplx<R> (&acc)[RU][SPT]) {
-  using C = cplx<R>;
-  int rr[RU];
-#pragma unroll
-  for (int u = 0; u < RU; ++u) rr[u] = min(lane + 64 * u, m - 1);
-#pragma unroll 4
-  for (int l = 0; l < m; ++l) {
-    C a[SPT], bb[SPT], v[RU], w[RU];
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      if (HL) v[u] = Vi[(size_t)l * m + rr[u]];
-      if (HR) w[u] = Wi[(size_t)l * m + rr[u]];
-    }
-#pragma unroll
-    for (int t = 0; t < SPT; ++t) {
-      if (HL) a[t] = xl[t * m + l];
-      if (HR) bb[t] = xr[t * m + l];
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u)
-#pragma unroll
-      for (int t = 0; t < SPT; ++t) {
-        if (HL) cfma(acc[u][t], v[u], a[t]);
-        if (HR) cfma(acc[u][t], w[u], bb[t]);
-      }
-  }
-}
-
-template <typename R, int RU>
+// Per chunk the correction is one dense product: with the interior columns of the chunk
+// stacked (row R = (i - a) m + j), X_I -= [V_stack | W_stack] [x_{s_left}; x_{s_right}],
+// an (L m) x 2m by 2m x K product.  A workgroup computes a 64 x 32 tile (rows x
+// sources), k in slabs of 16 staged in LDS; the next slab is loaded into registers
+// while the current one is multiplied.  Thread (tr, ts) owns rows tr + 16 a and sources
+// ts + 16 b.  item = (chunk, row tile, source tile).
+constexpr int CG_R = 64, CG_S = 32, CG_K = 16;
+template <typename R>
 __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
-  extern __shared__ unsigned char smem[];
   using C = cplx<R>;
-  constexpr int KT = CorrTile<R>::KT, SPT = KT / 4;   // rows per thread RU: m <= 64 RU
+  __shared__ C As[CG_K][CG_R + 1];
+  __shared__ C Bs[CG_K][CG_S + 1];
   const int item = item_of_block(bt.total);
   const int q = find_problem(bt.first, bt.n, item);
   const SweepProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
-  const int tiles = (pp.K + KT - 1) / KT;
-  const int tile = local % tiles, rest = local / tiles;
-  const int c = rest / pp.ncb, u0 = rest % pp.ncb;
+  const int stiles = (pp.K + CG_S - 1) / CG_S;
+  const int st = local % stiles, rest = local / stiles;
+  const int c = rest / pp.ncb, rt = rest % pp.ncb;
   const Chunk ch = chunk_of(pp.part, c);
-  const int i = ch.a + u0;
-  if (i > ch.b) return;   // uniform over the workgroup
   const Grid &g = pp.g;
   const int m = g.nz, K = pp.K;
+  const int rows = (ch.b - ch.a + 1) * m;
+  const int R0 = rt * CG_R;
+  if (R0 >= rows) return;   // uniform over the workgroup
   const size_t mm = (size_t)m * m;
   const bool hl = c > 0, hr = c < pp.P - 1;
-  C *xl = (C *)smem;        // [KT][m] left separator values of the tile
-  C *xr = xl + KT * m;      // [KT][m] right separator values
-  const int k0 = tile * KT;
-  for (int e = threadIdx.x; e < KT * m; e += blockDim.x) {
-    const int sidx = e / m, l = e - sidx * m, k = k0 + sidx;
-    xl[e] = (hl && k < K) ? colp<R>(pp.x, g, k, ch.a - 1)[l] : mk<R>(0, 0);
-    xr[e] = (hr && k < K) ? colp<R>(pp.x, g, k, ch.b + 1)[l] : mk<R>(0, 0);
+  const int lk0 = hl ? 0 : m, lk1 = hr ? 2 * m : m;
+  const C *V = (const C *)pp.V, *W = (const C *)pp.W;
+  const int s0 = st * CG_S;
+  const int tid = threadIdx.x, tr = tid & 15, ts = tid >> 4;
+  // this thread's load slots: A element (row R0 + (e & 63), k e >> 6), B element
+  // (k e & 15, source e >> 4); rows past the chunk load a clamped address and are zeroed
+  int a_col[4], a_j[4], a_ll[4];
+  bool a_ok[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, rr = e & 63;
+    const int row = min(R0 + rr, rows - 1);
+    a_ll[u] = e >> 6;
+    a_ok[u] = R0 + rr < rows;
+    a_col[u] = ch.a + row / m;   // grid column of the row
+    a_j[u] = row % m;
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const C *Vi = (const C *)pp.V + (size_t)i * mm, *Wi = (const C *)pp.W + (size_t)i * mm;
-  C acc[RU][SPT];
+  int b_ll[2], b_ss[2];
 #pragma unroll
-  for (int u = 0; u < RU; ++u)
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + 256 * u;
+    b_ll[u] = e & 15;
+    b_ss[u] = e >> 4;
+  }
+  auto load_slab = [&](int kb, C (&ra)[4], C (&rb)[2]) {
 #pragma unroll
-    for (int t = 0; t < SPT; ++t) acc[u][t] = mk<R>(0, 0);
-  const C *gl = xl + grp * SPT * m, *gr = xr + grp * SPT * m;
-  if (hl && hr) correct_acc<R, RU, SPT, true, true>(Vi, Wi, m, gl, gr, lane, acc);
-  else if (hl) correct_acc<R, RU, SPT, true, false>(Vi, Wi, m, gl, gr, lane, acc);
-  else correct_acc<R, RU, SPT, false, true>(Vi, Wi, m, gl, gr, lane, acc);
+    for (int u = 0; u < 4; ++u) {
+      const int l = kb + a_ll[u], lc = min(l, lk1 - 1);
+      const size_t base = (size_t)a_col[u] * mm + (size_t)(lc < m ? lc : lc - m) * m + a_j[u];
+      const C v = lc < m ? V[base] : W[base];
+      ra[u] = (a_ok[u] && l < lk1) ? v : mk<R>(0, 0);
+    }
 #pragma unroll
-  for (int u = 0; u < RU; ++u) {
-    const int r = lane + 64 * u;
-    if (r < m)
+    for (int u = 0; u < 2; ++u) {
+      const int l = kb + b_ll[u], lc = min(l, lk1 - 1), sidx = s0 + b_ss[u];
+      const int k = min(sidx, K - 1);
+      const C v = colp<R>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
+      rb[u] = (l < lk1 && sidx < K) ? v : mk<R>(0, 0);
+    }
+  };
+  C acc[4][2];
 #pragma unroll
-      for (int t = 0; t < SPT; ++t) {
-        const int k = k0 + grp * SPT + t;
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = mk<R>(0, 0);
+  C ra[4], rb[2];
+  load_slab(lk0, ra, rb);
+  for (int kb = lk0; kb < lk1; kb += CG_K) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) As[a_ll[u]][(tid + 256 * u) & 63] = ra[u];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) Bs[b_ll[u]][b_ss[u]] = rb[u];
+    __syncthreads();
+    if (kb + CG_K < lk1) load_slab(kb + CG_K, ra, rb);   // in flight during the products
+#pragma unroll
+    for (int kk = 0; kk < CG_K; ++kk) {
+      C av[4], bv[2];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) av[x] = As[kk][tr + 16 * x];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[kk][ts + 16 * y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) cfma(acc[x][y], av[x], bv[y]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int row = R0 + tr + 16 * x;
+    if (row < rows)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int k = s0 + ts + 16 * y;
         if (k < K) {
-          C *d = colp<R>(pp.x, g, k, i) + r;
-          *d = csub(*d, acc[u][t]);
+          C *d = colp<R>(pp.x, g, k, ch.a + row / m) + (row % m);
+          *d = csub(*d, acc[x][y]);
         }
       }
   }
@@ -1089,7 +1109,7 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
   p->P = chunks;
   int lmax = 0;
   for (int c = 0; c < chunks; ++c) lmax = std::max(lmax, part[3 * c + 1] - part[3 * c] + 1);
-  p->ncb = (lmax + CORR_CB - 1) / CORR_CB;
+  p->ncb = (lmax * m + CG_R - 1) / CG_R;   // row tiles of the stacked interior correction
   p->have_T64 = p->have_T32 = false;
   return KF_OK;
 }
@@ -1256,7 +1276,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
            : ph == 1            ? p->P * G
            : ph == 3            ? (p->P - 1) * G
            : ph == 4            ? (p->P > 2 ? G : 0)
-                                : (p->P > 1 ? p->P * p->ncb * ((p->K + CorrTile<R>::KT - 1) / CorrTile<R>::KT) : 0);
+                                : (p->P > 1 ? p->P * p->ncb * ((p->K + CG_S - 1) / CG_S) : 0);
     }
     bt.first[bt.n] = bt.total = tot;
     if (tot == 0) continue;
@@ -1274,28 +1294,8 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       case 2: SOLVE_PHASE(2); break;
       case 3: SOLVE_PHASE(3); break;
       case 4: SOLVE_PHASE(4); break;
-      default: {
-        const size_t smem_c = 2 * (size_t)m_max * CorrTile<R>::KT * sizeof(cplx<R>);
-        const int ru = (m_max + 63) / 64;
-#define CORRECT(RUV)                                                                                        \
-  do {                                                                                                      \
-    if (smem_c > 65536)                                                                                     \
-      HIP_TRY(hipFuncSetAttribute((const void *)k_correct<R, RUV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                  (int)smem_c));                                                            \
-    hipLaunchKernelGGL((k_correct<R, RUV>), dim3(tot), dim3(256), smem_c, s, bt);                          \
-  } while (0)
-        switch (ru) {
-          case 1: CORRECT(1); break;
-          case 2: CORRECT(2); break;
-          case 3: CORRECT(3); break;
-          case 4: CORRECT(4); break;
-          case 5: CORRECT(5); break;
-          case 6: CORRECT(6); break;
-          case 7: CORRECT(7); break;
-          default: CORRECT(8); break;
-        }
-#undef CORRECT
-      }
+      default:
+        hipLaunchKernelGGL((k_correct<R>), dim3(tot), dim3(256), 0, s, bt);
     }
 #undef SOLVE_PHASE
     LAUNCH_CHECK();
