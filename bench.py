@@ -277,6 +277,48 @@ def bench_c4(args, torch, KKTProblem):
     print(json.dumps(result), flush=True)
 
 
+def bench_c3(args, torch, KKTProblem):
+    """Reduced gradient through the solve at 801 x 281, 80 sources, 5 Hz: autograd
+    forward (factorisation + forward solves) and backward (adjoint solves + gradient
+    kernel), complex128 and complex64.  Each step perturbs gamma, so it refactorises."""
+    from synthetic.configs import make_problem_inputs
+    from paper_2204_06489_amd.autograd import HelmholtzSolve
+    inp = make_problem_inputs("c2", 0)
+    log(args, f"c3 timing on {inp['nx']}x{inp['nz']} K={inp['K']} {inp['freq']} Hz")
+    d = observed_data(inp, torch, KKTProblem)
+    p = KKTProblem.from_inputs(inp, reg_on_update=True)
+    g0 = torch.as_tensor(inp["gamma0"]).cuda()
+    riz = torch.as_tensor(inp["rec_iz"]).long().cuda()
+    rix = torch.as_tensor(inp["rec_ix"]).long().cuda()
+    res = {}
+    for prec in ("c128", "c64"):
+        def step(k):
+            x = (g0 * (1.0 + 1e-4 * k)).requires_grad_(True)
+            u = HelmholtzSolve.apply(x, p, prec)
+            loss = 0.5 * torch.sum(torch.abs(d.to(u.dtype) - u[:, riz, rix]) ** 2)
+            loss.backward()
+            return x.grad
+        for w in range(args.warmup):
+            step(w + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(100 + k)
+        torch.cuda.synchronize()
+        res[prec] = (time.perf_counter() - t0) / args.steps
+        log(args, f"{prec}: {res[prec] * 1e3:.1f} ms per gradient")
+    result = {
+        "metric": "reduced-gradient time (autograd forward + backward)", "value": res["c64"], "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["c64"] * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "c3: torch.autograd.Function around the batched Helmholtz solve on the 801x281 grid, "
+                               "80 sources, 5 Hz; one step = factorisation, forward solves, misfit, adjoint solves "
+                               "and the gradient kernel", "global_batch": inp["K"], "parallelism": "single GPU"},
+        "c128_s": res["c128"],
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -291,6 +333,8 @@ def main():
     torch.cuda.set_device(0)
     if args.config == "c4":
         return bench_c4(args, torch, KKTProblem)
+    if args.config == "c3":
+        return bench_c3(args, torch, KKTProblem)
     if args.copy_calib:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         b = torch.empty_like(a)
