@@ -258,7 +258,9 @@ def bench_c4(args, torch, KKTProblem):
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / args.steps
     log(args, f"one at a time: {t_seq*1e3:.0f} ms per step, iters {[s['outer_iters'] for s in seq]}, "
-              f"factor {[round(s['t_factor_ms']) for s in seq]} ms, total {[round(s['t_total_ms']) for s in seq]} ms")
+              f"factor {[round(s['t_factor_ms']) for s in seq]} ms, total {[round(s['t_total_ms']) for s in seq]} ms, "
+              f"precond {[round(s['t_precond_ms']) for s in seq]} ms, matvec {[round(s['t_matvec_ms']) for s in seq]} ms, "
+              f"orth {[round(s['t_orth_ms']) for s in seq]} ms")
     result = {
         "metric": "Newton-step time to KKT rel. res 1e-6", "value": t_batch, "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": False,

@@ -304,15 +304,18 @@ __device__ inline void col_matvec(const cplx<R> *__restrict__ Tt, int m, const c
 
 // ---------------------------------------------------------------------------
 // Work items.  One launch covers every item of every problem of a batch (a single
-// problem is a batch of one).  Workgroups are dealt to the 8 XCDs in turn; the item
-// of a workgroup is chosen so that each XCD receives one contiguous range of items,
-// and the items of one chunk (its source groups) share that XCD's L2 copy of the
-// chunk's factors.
+// problem is a batch of one).  Workgroups are dealt to the 8 XCDs in turn, so
+// workgroup b runs on XCD b mod 8; XCD x is given the contiguous item range
+// [xs[x], xs[x+1]), in launch order.  The host cuts the ranges at equal estimated cost
+// (all items of one problem and phase cost about the same), so the XCDs finish
+// together even when a batch mixes grids of very different size, and the items of
+// one chunk (its source groups) share one XCD's L2 copy of the chunk's factors.
+// Returns -1 for the workgroups past the end of their XCD's range.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int item_of_block(int total) {
-  const int bk = blockIdx.x, x = bk & 7, r = bk >> 3;
-  const int per = total >> 3, rem = total & 7;
-  return x * per + min(x, rem) + r;
+__device__ __forceinline__ int item_of_block(const int *xs) {
+  const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+  const int it = xs[x] + r;
+  return it < xs[x + 1] ? it : -1;
 }
 
 __device__ __forceinline__ int find_problem(const int *first, int nprob, int item) {
@@ -388,7 +391,8 @@ __device__ __forceinline__ void factor_mid_body(const Grid &g, Chunk ch, double2
 template <int NB, int RMAX, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_factor_chunks(FactorBatch bt) {
   extern __shared__ unsigned char smem[];
-  const int item = item_of_block(bt.total);
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
   const FactorProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
@@ -504,7 +508,8 @@ __device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, i
 template <int NSP>
 __global__ __launch_bounds__(512) void k_spikes(FactorBatch bt) {
   extern __shared__ unsigned char smem[];
-  const int item = item_of_block(bt.total);
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
   const FactorProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
@@ -867,7 +872,8 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
   using C = cplx<R>;
   __shared__ C As[CG_K][CG_R + 1];
   __shared__ C Bs[CG_K][CG_S + 1];
-  const int item = item_of_block(bt.total);
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
   const SweepProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
@@ -968,7 +974,8 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
 template <typename R, int NS, int PH>
 __global__ __launch_bounds__(512) void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
-  const int item = item_of_block(bt.total);
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
   const SweepProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
@@ -1053,6 +1060,35 @@ inline dim3 sweep_block(int m) {
   } while (0)
 
 // ---------------------------------------------------------------------------
+// the XCD ranges of a launch: items [first[q], first[q+1]) of problem q cost cost[q]
+// each; the 8 ranges are cut at equal cumulative cost.  Returns the grid size.
+// ---------------------------------------------------------------------------
+static unsigned xcd_split(const int *first, int n, const double *cost, int *xs) {
+  double total = 0.0;
+  for (int q = 0; q < n; ++q) total += (first[q + 1] - first[q]) * cost[q];
+  xs[0] = 0;
+  xs[8] = first[n];
+  for (int x = 1; x < 8; ++x) {
+    const double target = total * x / 8.0;
+    int idx = first[n];
+    double cum = 0.0;
+    for (int q = 0; q < n; ++q) {
+      const double c = (first[q + 1] - first[q]) * cost[q];
+      if (c > 0.0 && cum + c >= target) {
+        idx = first[q] + (int)std::ceil((target - cum) / cost[q]);
+        idx = std::min(std::max(idx, first[q]), first[q + 1]);
+        break;
+      }
+      cum += c;
+    }
+    xs[x] = std::max(xs[x - 1], std::min(idx, first[n]));
+  }
+  int most = 0;
+  for (int x = 0; x < 8; ++x) most = std::max(most, xs[x + 1] - xs[x]);
+  return 8u * (unsigned)most;
+}
+
+// ---------------------------------------------------------------------------
 // partition of the columns
 // ---------------------------------------------------------------------------
 int blu_auto_chunks(int nx, int nz, int K) {
@@ -1131,31 +1167,38 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
     bt.p[q] = FactorProblem{p->grid(), p->P, p->d_part, p->T64, p->V64, p->W64, p->fac_work};
   }
   // 1. chunks: both sides, then the middle columns
+  double cost[KF_BATCH_MAX];
   for (int mode = 0; mode < 2; ++mode) {
     int tot = 0;
     for (int q = 0; q < bt.n; ++q) {
+      const double m = ps[q]->nz, L = (double)ps[q]->nx / ps[q]->P;
       bt.first[q] = tot;
       tot += (mode == 0 ? 2 : 1) * ps[q]->P;
+      cost[q] = m * m * m * (mode == 0 ? 0.5 * L : 1.0);
     }
     bt.first[bt.n] = bt.total = tot;
-    if (mode == 0) hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 0>), dim3(tot), dim3(NT), smem, s, bt);
-    else hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 1>), dim3(tot), dim3(NT), smem, s, bt);
+    const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
+    if (mode == 0) hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 0>), dim3(grid), dim3(NT), smem, s, bt);
+    else hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 1>), dim3(grid), dim3(NT), smem, s, bt);
     LAUNCH_CHECK();
   }
   // 2. spikes
   constexpr int NSP = 2;
   int tot = 0, pmax = 1;
   for (int q = 0; q < bt.n; ++q) {
+    const double m = ps[q]->nz, L = (double)ps[q]->nx / ps[q]->P;
     bt.first[q] = tot;
     tot += 2 * (ps[q]->P - 1) * ((ps[q]->nz + NSP - 1) / NSP);
     pmax = std::max(pmax, ps[q]->P);
+    cost[q] = m * m * 1.5 * L;
   }
   bt.first[bt.n] = bt.total = tot;
   if (tot == 0) return KF_OK;
+  const unsigned grid_sp = xcd_split(bt.first, bt.n, cost, bt.xs);
   const dim3 blk = sweep_block(m_max);
   const size_t smem_sp = (1 + (blk.y - 1)) * NSP * (size_t)m_max * sizeof(double2);
   HIP_TRY(hipFuncSetAttribute((const void *)k_spikes<NSP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
-  hipLaunchKernelGGL((k_spikes<NSP>), dim3(tot), blk, smem_sp, s, bt);
+  hipLaunchKernelGGL((k_spikes<NSP>), dim3(grid_sp), blk, smem_sp, s, bt);
   LAUNCH_CHECK();
   // 3. the separators' block LU, one separator at a time
   for (int j = 1; j < pmax; ++j) {
@@ -1268,9 +1311,12 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
   for (int ph = 0; ph < 6; ++ph) {
     int tot = 0;
+    double cost[KF_BATCH_MAX];
     for (int q = 0; q < bt.n; ++q) {
       const kf_problem *p = ps[q];
       const int G = (p->K + NS - 1) / NS;
+      const double m = p->nz, L = (double)p->nx / p->P;
+      cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 4 ? m * m * 2.0 * (p->P - 2) : ph == 5 ? m : m * m;
       bt.first[q] = tot;
       tot += ph == 0 || ph == 2 ? 2 * p->P * G
            : ph == 1            ? p->P * G
@@ -1280,13 +1326,14 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
     }
     bt.first[bt.n] = bt.total = tot;
     if (tot == 0) continue;
+    const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
     ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
 #define SOLVE_PHASE(PH)                                                                                       \
   do {                                                                                                        \
     if (smem > 65536)                                                                                         \
       HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, PH>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                   (int)smem));                                                                \
-    hipLaunchKernelGGL((k_solve<R, NS, PH>), dim3(tot), blk, smem, s, bt);                                   \
+    hipLaunchKernelGGL((k_solve<R, NS, PH>), dim3(grid), blk, smem, s, bt);                                  \
   } while (0)
     switch (ph) {
       case 0: SOLVE_PHASE(0); break;
@@ -1295,7 +1342,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       case 3: SOLVE_PHASE(3); break;
       case 4: SOLVE_PHASE(4); break;
       default:
-        hipLaunchKernelGGL((k_correct<R>), dim3(tot), dim3(256), 0, s, bt);
+        hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
     }
 #undef SOLVE_PHASE
     LAUNCH_CHECK();
@@ -1336,10 +1383,13 @@ kf_status solve_dispatch(const std::vector<kf_problem *> &ps, int adjoint, const
                          hipStream_t s, kf_problem *prof) {
   if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
   const bool fp32 = sizeof(R) == sizeof(float);
-  int ns = 8;
+  // sources per workgroup: the choice of the problem with the most work
+  int ns = 1;
+  double most = -1.0;
   for (kf_problem *p : ps) {
     if (!(fp32 ? p->have_T32 : p->have_T64)) { set_error("block solve before factorisation"); return KF_ESTATE; }
-    ns = std::min(ns, p->ns);
+    const double w = (double)p->nx * p->nz * p->nz * p->K;
+    if (w > most) { most = w; ns = p->ns; }
   }
   ProfScope sw(prof, PROF_SWEEP);
   return adjoint ? solve_copies<R, IO, true>(ps, rhs, x, s, ns, prof) : solve_copies<R, IO, false>(ps, rhs, x, s, ns, prof);

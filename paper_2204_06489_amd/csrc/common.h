@@ -98,6 +98,7 @@ struct SweepProblem {
 struct SweepBatch {
   int n, total;
   int first[KF_BATCH_MAX + 1];   // first item of each problem (prefix sums)
+  int xs[9];                     // items [xs[x], xs[x+1]) run on XCD x
   SweepProblem p[KF_BATCH_MAX];
 };
 struct FactorProblem {
@@ -109,6 +110,7 @@ struct FactorProblem {
 struct FactorBatch {
   int n, total;
   int first[KF_BATCH_MAX + 1];
+  int xs[9];
   FactorProblem p[KF_BATCH_MAX];
 };
 
