@@ -842,7 +842,7 @@ __device__ __forceinline__ void red_chain_body(const Grid &g, int K, int P, cons
         }
       __syncthreads();
       C acc[NS];
-      col_matvec<R, NS, (sizeof(R) == 4 && NS <= 2) ? 16 : 8>((pass == 0 ? V : W) + (size_t)sc * mm, m, w, part, acc);
+      col_matvec<R, NS, (sizeof(R) == 4 && NS == 1) ? 16 : 8>((pass == 0 ? V : W) + (size_t)sc * mm, m, w, part, acc);
       if (owner)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -971,8 +971,10 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
   }
 }
 
+// up to 1024 threads (4 wave groups of 256 rows) where the register budget allows
+template <typename R, int NS> struct SolveThreads { static constexpr int N = sizeof(R) == 4 && NS <= 2 ? 1024 : 512; };
 template <typename R, int NS, int PH>
-__global__ __launch_bounds__(512) void k_solve(SweepBatch bt) {
+__global__ __launch_bounds__((SolveThreads<R, NS>::N)) void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
@@ -1039,11 +1041,11 @@ __global__ __launch_bounds__(256) void k_from_colmajor(Grid g, const cplx<R> *__
   }
 }
 
-// block shape of the sweeps: x covers the rows, y splits each dot product
-// (at most 512 threads, so a thread may hold up to 256 VGPRs)
-inline dim3 sweep_block(int m) {
+// block shape of the sweeps: x covers the rows, y splits each dot product (at most
+// `threads` threads)
+inline dim3 sweep_block(int m, int threads = 512) {
   int rj = ((m + 63) / 64) * 64;
-  int gy = 512 / rj;
+  int gy = threads / rj;
   gy = gy > 4 ? 4 : (gy < 1 ? 1 : gy);
   return dim3(rj, gy);
 }
@@ -1306,7 +1308,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                            fp32 ? (const void *)p->W32 : (const void *)p->W64,
                            fp32 ? (void *)p->sol32 : (void *)p->sol64};
   }
-  const dim3 blk = sweep_block(m_max);
+  const dim3 blk = sweep_block(m_max, SolveThreads<R, NS>::N);
   const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
   static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
   for (int ph = 0; ph < 6; ++ph) {
