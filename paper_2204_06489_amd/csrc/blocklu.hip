@@ -879,7 +879,8 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
   const int local = item - bt.first[q];
   const int stiles = (pp.K + CG_S - 1) / CG_S;
   const int st = local % stiles, rest = local / stiles;
-  const int c = rest / pp.ncb, rt = rest % pp.ncb;
+  const int rtiles = (pp.lmax * pp.g.nz + CG_R - 1) / CG_R;
+  const int c = rest / rtiles, rt = rest % rtiles;
   const Chunk ch = chunk_of(pp.part, c);
   const Grid &g = pp.g;
   const int m = g.nz, K = pp.K;
@@ -968,6 +969,116 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
           *d = csub(*d, acc[x][y]);
         }
       }
+  }
+}
+
+// The same product on the matrix cores (complex64 solves): a workgroup computes a
+// 128 x 32 tile (rows x sources), each of its four wavefronts a 32 x 32 block with
+// v_mfma_f32_32x32x2f32, a complex product being four real ones (Re += ar br - ai bi,
+// Im += ar bi + ai br).  Operand lanes: A[i][k] in lane i + 32 k, B[k][j] in lane
+// j + 32 k; result D[i][j] in lane j + 32 ((i / 4) mod 2), register (i mod 4) + 4 (i / 8).
+// k in slabs of 16 through LDS with the next slab prefetched into registers; the tile
+// goes back through LDS so the updates of the column-major copy are coalesced.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int CM_R = 128, CM_S = 32, CM_K = 16;
+__global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
+  using C = float2;
+  // the operand slabs and the output tile share one LDS buffer (the tile is written
+  // after the last slab is consumed)
+  constexpr int SLAB = CM_K * (CM_R + 2) + CM_K * (CM_S + 2), TILE = CM_S * (CM_R + 1);
+  __shared__ C lds[SLAB > TILE ? SLAB : TILE];
+  C(*As)[CM_R + 2] = (C(*)[CM_R + 2])lds;
+  C(*Bs)[CM_S + 2] = (C(*)[CM_S + 2])(lds + CM_K * (CM_R + 2));
+  C(*Out)[CM_R + 1] = (C(*)[CM_R + 1])lds;
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int stiles = (pp.K + CM_S - 1) / CM_S;
+  const int rtiles = (pp.lmax * pp.g.nz + CM_R - 1) / CM_R;
+  const int st = local % stiles, rest = local / stiles;
+  const int c = rest / rtiles, rt = rest % rtiles;
+  const Chunk ch = chunk_of(pp.part, c);
+  const Grid &g = pp.g;
+  const int m = g.nz, K = pp.K;
+  const int rows = (ch.b - ch.a + 1) * m;
+  const int R0 = rt * CM_R;
+  if (R0 >= rows) return;   // uniform over the workgroup
+  const size_t mm = (size_t)m * m;
+  const bool hl = c > 0, hr = c < pp.P - 1;
+  const int lk0 = hl ? 0 : m, lk1 = hr ? 2 * m : m;
+  const C *V = (const C *)pp.V, *W = (const C *)pp.W;
+  const int s0 = st * CM_S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // load slots: A element (row R0 + (e & 127), k e >> 7), B element (k e & 15, source e >> 4)
+  int a_col[8], a_j[8], a_kk[8];
+  bool a_ok[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = tid + 256 * u, rr = e & 127;
+    const int row = min(R0 + rr, rows - 1);
+    a_kk[u] = e >> 7;
+    a_ok[u] = R0 + rr < rows;
+    a_col[u] = ch.a + row / m;
+    a_j[u] = row % m;
+  }
+  auto load_slab = [&](int kb, C (&ra)[8], C (&rb)[2]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int l = kb + a_kk[u], lc = min(l, lk1 - 1);
+      const size_t base = (size_t)a_col[u] * mm + (size_t)(lc < m ? lc : lc - m) * m + a_j[u];
+      const C v = lc < m ? V[base] : W[base];
+      ra[u] = (a_ok[u] && l < lk1) ? v : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 256 * u, l = kb + (e & 15), sidx = s0 + (e >> 4);
+      const int lc = min(l, lk1 - 1), k = min(sidx, K - 1);
+      const C v = colp<float>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
+      rb[u] = (l < lk1 && sidx < K) ? v : make_float2(0.f, 0.f);
+    }
+  };
+  floatx16 accR = {0}, accI = {0};
+  C ra[8], rb[2];
+  load_slab(lk0, ra, rb);
+  for (int kb = lk0; kb < lk1; kb += CM_K) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) As[a_kk[u]][(tid + 256 * u) & 127] = ra[u];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e & 15][e >> 4] = rb[u];
+    }
+    __syncthreads();
+    if (kb + CM_K < lk1) load_slab(kb + CM_K, ra, rb);   // in flight during the products
+#pragma unroll
+    for (int kp = 0; kp < CM_K / 2; ++kp) {
+      const int kk = 2 * kp + (lane >> 5);
+      const C a = As[kk][wave * 32 + (lane & 31)];
+      const C b = Bs[kk][lane & 31];
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, accI, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // tile to LDS as [source][row], then column-contiguous updates
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+    Out[lane & 31][wave * 32 + i] = make_float2(accR[r], accI[r]);
+  }
+  __syncthreads();
+  for (int e = tid; e < CM_S * CM_R; e += 256) {
+    const int sidx = e / CM_R, rr = e - sidx * CM_R;
+    const int row = R0 + rr, k = s0 + sidx;
+    if (row < rows && k < K) {
+      C *d = colp<float>(pp.x, g, k, ch.a + row / m) + (row % m);
+      const C o = Out[sidx][rr];
+      *d = make_float2(d->x - o.x, d->y - o.y);
+    }
   }
 }
 
@@ -1147,7 +1258,7 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
   p->P = chunks;
   int lmax = 0;
   for (int c = 0; c < chunks; ++c) lmax = std::max(lmax, part[3 * c + 1] - part[3 * c] + 1);
-  p->ncb = (lmax * m + CG_R - 1) / CG_R;   // row tiles of the stacked interior correction
+  p->lmax = lmax;
   p->have_T64 = p->have_T32 = false;
   return KF_OK;
 }
@@ -1302,7 +1413,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   for (int q = 0; q < bt.n; ++q) {
     kf_problem *p = ps[q];
     m_max = std::max(m_max, p->nz);
-    bt.p[q] = SweepProblem{p->grid(), p->K, p->P, p->ncb, p->d_part,
+    bt.p[q] = SweepProblem{p->grid(), p->K, p->P, p->lmax, p->d_part,
                            fp32 ? (const void *)p->T32 : (const void *)p->T64,
                            fp32 ? (const void *)p->V32 : (const void *)p->V64,
                            fp32 ? (const void *)p->W32 : (const void *)p->W64,
@@ -1324,7 +1435,10 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
            : ph == 1            ? p->P * G
            : ph == 3            ? (p->P - 1) * G
            : ph == 4            ? (p->P > 2 ? G : 0)
-                                : (p->P > 1 ? p->P * p->ncb * ((p->K + CG_S - 1) / CG_S) : 0);
+                                : (p->P > 1 ? p->P *
+                                                    (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
+                                                          : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S))
+                                              : 0);
     }
     bt.first[bt.n] = bt.total = tot;
     if (tot == 0) continue;
@@ -1344,7 +1458,8 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       case 3: SOLVE_PHASE(3); break;
       case 4: SOLVE_PHASE(4); break;
       default:
-        hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
+        if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
+        else hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
     }
 #undef SOLVE_PHASE
     LAUNCH_CHECK();

@@ -90,7 +90,7 @@ constexpr int KF_BATCH_MAX = 8;
 constexpr int KF_MAX_CHUNKS = 64;   // column chunks of the partitioned factorisation
 struct SweepProblem {
   Grid g;
-  int K, P, ncb;       // sources, chunks, correction blocks per chunk
+  int K, P, lmax;      // sources, chunks, longest chunk (columns)
   const int *part;     // [P][3]: first, last and meeting column of each chunk (device)
   const void *T, *V, *W;   // factors and spikes (c128 or c64)
   void *x;             // right-hand sides in, solutions out: column-major [K][nx][nz] (compute type)
@@ -147,7 +147,7 @@ struct kf_problem {
   // partitioned block factorisation over grid columns
   int P = 0;                                   // chunks
   int ns = 1;                                  // sources per workgroup in the block solves
-  int ncb = 1;                                 // correction blocks per chunk
+  int lmax = 1;                                // longest chunk (columns)
   std::vector<int> part;                       // [P][3] first, last, meeting column of each chunk
   int *d_part = nullptr;                       // device copy (KF_MAX_CHUNKS * 3)
   double2 *T64 = nullptr;                      // [nx][nz][nz], T_i stored transposed
