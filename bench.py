@@ -379,7 +379,8 @@ def main():
     prof = {f: p.profile_read(f) for f in families}
     p.profile_enable(False)
     for k, st in enumerate(stats):
-        log(args, f"step {k}: iters={st['outer_iters']} rel={st['rel_res']:.2e} total={st['t_total_ms']:.1f} ms "
+        log(args, f"step {k}: iters={st['outer_iters']} (reorth {st['reorth_passes']}) rel={st['rel_res']:.2e} "
+                  f"total={st['t_total_ms']:.1f} ms "
                   f"factor={st['t_factor_ms']:.1f} fwd={st['t_forward_ms']:.1f} pc={st['t_precond_ms']:.1f} "
                   f"mv={st['t_matvec_ms']:.1f} orth={st['t_orth_ms']:.1f} misfit={st['misfit_before']:.4f}")
     ms_per_step = elapsed / args.steps * 1e3

@@ -95,6 +95,14 @@ typedef struct {
   int32_t fwd_prec;        /* kf_prec of the background forward solve u_n = A^-1 f (C128 or MIXED) */
   double fwd_rtol;         /* tolerance of that solve when fwd_prec = KF_MIXED */
   int32_t misfit_after;    /* 1: also solve A(gamma_{n+1}) u = f and report the new misfit */
+  double reorth_eta;       /* Gram-Schmidt of the Arnoldi steps: after the first classical pass
+                              w' = w - V V^* w a second pass runs when |w'| < reorth_eta |w|
+                              (0 <= reorth_eta <= 1; 1: always, i.e. CGS2; 1/sqrt 2: the
+                              Daniel-Gragg-Kaufman-Stewart test; 0: never).  One pass leaves the
+                              new vector orthogonal to about eps |w| / |w'|, so 0.1 keeps the
+                              basis orthogonal to ~1e-15 while skipping the pass whenever the
+                              cancellation is mild; FGMRES's true residual at each restart and
+                              at exit checks the result either way. */
 } kf_newton_opts;
 
 typedef struct {

@@ -33,6 +33,7 @@ class KfNewtonOpts(C.Structure):
     _fields_ = [
         ("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32), ("pc", C.c_int32),
         ("fwd_prec", C.c_int32), ("fwd_rtol", C.c_double), ("misfit_after", C.c_int32),
+        ("reorth_eta", C.c_double),
     ]
 
 

@@ -618,26 +618,26 @@ struct FgmresOut {
 };
 
 // Orthogonalise Vn = V_{j+1} against V_0..V_j in FP64 by classical Gram-Schmidt with
-// reorthogonalisation (CGS2) in three sweeps over the basis: the dot products h1, the
-// first update fused with the second pass's dot products h2 and |Vn'|, and the second
-// update fused with the final norm.  The second update runs only when the DGKS test
-// finds that the first pass cancelled most of Vn (|Vn'| < |Vn| / sqrt 2); the test runs
-// on the device and a declined update's launches do nothing, so the step needs no host
-// round trip.  scal[0] receives |Vn| after the last pass; scal[6] holds the flag.
-constexpr double DGKS_ETA = 0.70710678118654752;
-static kf_status gram_schmidt(kf_problem *p, int j, double2 *Vn, double2 *h1, double2 *h2, double *scal) {
+// selective reorthogonalisation, in up to three sweeps over the basis: the dot products
+// h1, the first update fused with the second pass's dot products h2 and |Vn'|, and the
+// second update fused with the final norm.  The second update runs only when the first
+// pass cancelled Vn below eta |Vn| (|Vn| recovered as sqrt(|Vn'|^2 + |h1|^2)); the test
+// runs on the device and a declined update's launches do nothing, so the step needs no
+// host round trip.  scal[0] receives |Vn| after the last pass; scal[6] holds the flag.
+static kf_status gram_schmidt(kf_problem *p, int j, double2 *Vn, double2 *h1, double2 *h2, double *scal,
+                              double eta) {
   const int64_t N = p->Nxi;
   int *flag = (int *)(scal + 6);
   CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
   // first update fused with the second pass's dot products and the norm
   CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h1, Vn, N, h2, scal + 0));
-  CHECK_ST(reorth_test(p, j + 1, h1, scal + 0, DGKS_ETA, h2, flag));
+  CHECK_ST(reorth_test(p, j + 1, h1, scal + 0, eta, h2, flag));
   // second update fused with the final norm (nothing when the test declines it)
   CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h2, Vn, N, nullptr, scal + 0, flag));
   return KF_OK;
 }
 
-static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, double tol, int m, int maxit,
+static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, double tol, int m, int maxit, double eta,
                         FgmresOut &o) {
   const int64_t N = p->Nxi;
   double2 *H = p->hess;
@@ -687,7 +687,7 @@ static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, dou
       CHECK_ST(launch_kkt_apply(p, Zj, Vn));
       pt.stop();
       pt.start(PH_ORTH);
-      CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal));
+      CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal, eta));
       CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
       CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
       pt.stop();
@@ -749,6 +749,7 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
   if (o->fwd_prec != KF_C128 && o->fwd_prec != KF_MIXED) return fail(KF_EINVAL, "fwd_prec must be C128 or MIXED");
   if (o->fwd_prec == KF_MIXED && !(o->fwd_rtol > 0.0)) return fail(KF_EINVAL, "fwd_rtol must be > 0");
+  if (!(o->reorth_eta >= 0.0 && o->reorth_eta <= 1.0)) return fail(KF_EINVAL, "reorth_eta must be in [0, 1]");
   kf_newton_stats S;
   std::memset(&S, 0, sizeof(S));
   S.misfit_after = -1.0;
@@ -786,7 +787,7 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   CHECK_ST(launch_rhs(p, p->d_r, p->d_rptr, p->d_rlist, p->xi_b, p->d.reg_on_update));
   // KKT solve
   FgmresOut fo;
-  kf_status fst = fgmres(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->restart, o->maxit, fo);
+  kf_status fst = fgmres(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->restart, o->maxit, o->reorth_eta, fo);
   if (fst != KF_OK && fst != KF_ENOCONV) return fst;
   S.outer_iters = fo.iters;
   S.reorth_passes = fo.reorth;
@@ -1035,6 +1036,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
     return fail(KF_EINVAL, "need rtol > 0, 1 <= restart <= 200, maxit >= 1");
   if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
   if (o->fwd_prec != KF_C128) return fail(KF_EINVAL, "batched steps use a complex128 background solve");
+  if (!(o->reorth_eta >= 0.0 && o->reorth_eta <= 1.0)) return fail(KF_EINVAL, "reorth_eta must be in [0, 1]");
   const int m = o->restart;
   auto T0 = std::chrono::steady_clock::now();
   auto ms_since = [](std::chrono::steady_clock::time_point t) {
@@ -1139,7 +1141,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
                 *y = h2 + (m + 1);
         double *scal = (double *)(y + m + 8);
         double2 *Vn = p->V + (size_t)(j + 1) * N;
-        CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal));
+        CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal, o->reorth_eta));
         CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
         CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
         HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 7 * sizeof(double), hipMemcpyDeviceToHost, b->stream));

@@ -210,11 +210,13 @@ class KKTProblem:
         return z
 
     def newton_step(self, d_obs, rtol=1e-6, restart=30, maxit=200, pc="exact", fwd_prec="c128",
-                    fwd_rtol=1e-10, misfit_after=False, update_in_place=True, want_xi=True):
-        """One full-space GN step; returns (xi or None, gamma_{n+1}, stats dict)."""
+                    fwd_rtol=1e-10, misfit_after=False, update_in_place=True, want_xi=True, reorth_eta=0.1):
+        """One full-space GN step; returns (xi or None, gamma_{n+1}, stats dict).
+        reorth_eta: second Gram-Schmidt pass when |w'| < reorth_eta |w| (1 = always)."""
         o = KfNewtonOpts()
         o.rtol, o.restart, o.maxit, o.pc = float(rtol), int(restart), int(maxit), _PC[pc]
         o.fwd_prec, o.fwd_rtol, o.misfit_after = _PREC[fwd_prec], float(fwd_rtol), int(bool(misfit_after))
+        o.reorth_eta = float(reorth_eta)
         xi = self.empty_xi() if want_xi else None
         g1 = torch.empty((self.nz, self.nx), dtype=torch.float64, device=self.device)
         st = KfNewtonStats()
@@ -293,12 +295,13 @@ class KKTBatch:
         return xs
 
     def newton_step(self, d_obs, rtol=1e-6, restart=30, maxit=200, pc="exact", update_in_place=True,
-                    use_graph=True, want_xi=True):
+                    use_graph=True, want_xi=True, reorth_eta=0.1):
         """Returns (list of xi or None, list of gamma_{n+1}, list of stats dicts)."""
         n = len(self.problems)
         o = KfNewtonOpts()
         o.rtol, o.restart, o.maxit, o.pc = float(rtol), int(restart), int(maxit), _PC[pc]
         o.fwd_prec, o.fwd_rtol, o.misfit_after = KF_C128, 1e-10, 0
+        o.reorth_eta = float(reorth_eta)
         xis = [q.empty_xi() for q in self.problems] if want_xi else [None] * n
         gs = [torch.empty((q.nz, q.nx), dtype=torch.float64, device=q.device) for q in self.problems]
         dp = (C.c_void_p * n)(*[_ptr(d, torch.complex128, q.K * q.nrec, "d_obs").value

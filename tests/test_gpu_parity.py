@@ -176,6 +176,31 @@ def test_newton_step_matches_exact_kkt_solution(pc):
     assert rel(to_np(gpu.get_background()), u_n) <= 1e-10
 
 
+@pytest.mark.parametrize("eta", [1.0, 0.7071067811865476, 0.0])
+def test_newton_step_for_every_reorthogonalisation_rule(eta):
+    """CGS2 (eta 1), the DGKS test (1/sqrt 2), the default 0.1 and a single classical pass
+    (eta 0) all reach the exact step: the basis loses no accuracy that the step sees."""
+    inp, d, orc, gpu, u_n = _newton_setup(reg=True, weights="random", nx=41, nz=19, npml=4)
+    xi_ref = orc.kkt_solve_schur(u_n, orc.residual(d, u_n))
+    xi, _, st = gpu.newton_step(to_dev(d), rtol=1e-11, restart=40, maxit=200, pc="exact", update_in_place=False,
+                                reorth_eta=eta)
+    assert st["converged"], st
+    print(f"eta {eta}: {st['outer_iters']} iterations, {st['reorth_passes']} second passes")
+    if eta == 1.0:
+        assert st["reorth_passes"] == st["outer_iters"]
+    if eta == 0.0:
+        assert st["reorth_passes"] == 0
+    assert rel(orc.unpack(to_np(xi))[1], orc.unpack(xi_ref)[1]) <= 1e-10
+
+
+def test_newton_step_rejects_bad_reorthogonalisation_threshold():
+    from paper_2204_06489_amd._lib import KFError
+    inp, d, orc, gpu, u_n = _newton_setup(reg=True, nx=21, nz=15, npml=4)
+    for eta in (-0.1, 1.5, float("nan")):
+        with pytest.raises(KFError):
+            gpu.newton_step(to_dev(d), rtol=1e-6, reorth_eta=eta)
+
+
 @pytest.mark.parametrize("pc", ["exact", "inexact"])
 def test_newton_step_with_regularisation_row(pc):
     """b_s = -eps s_n (eq. KKT as printed).  ||b|| is then dominated by the control row, so the
