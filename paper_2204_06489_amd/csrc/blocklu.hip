@@ -24,13 +24,15 @@
 //  3. the reduced (Schur complement) system on the separators,
 //       R_jj     = D_{s_j} - C_{s_j} W^{j-1}_{b} - C_{s_j+1} V^{j}_{a}
 //       R_{j,j-1} = -C_{s_j} V^{j-1}_{b},   R_{j,j+1} = -C_{s_j+1} W^{j}_{a},
-//     block LU with S_1 = R_11, S_j = R_jj - R_{j,j-1} U_{j-1}, T_j = S_j^-1,
-//     N_j = T_j R_{j,j-1}, U_j = T_j R_{j,j+1}; T_j, N_j, U_j sit in the separator
-//     column's slots of T, V and W.
+//     solved by block cyclic reduction: log2(P) levels, each eliminating every other
+//     remaining separator at once (the blocks of each level sit in the separator
+//     column's slots of T, V and W and in per-separator ML, MU arrays).
 // Solve A x = b:
 //  1. z = A_II^-1 b_I by the chunks' twisted sweeps (all chunks at once);
 //  2. reduced right-hand side g_j = b_{s_j} - C_{s_j} z_{b} - C_{s_j+1} z_{a}, then
-//     y_j = T_j g_j - N_j y_{j-1} and x_j = y_j - U_j x_{j+1} on the separators;
+//     the separators' values by the reduction's forward levels, the root and the
+//     back-substitution levels (one launch per level, all separators of a level and
+//     all sources in parallel);
 //  3. x_I = z - V x_{s_left} - W x_{s_right} (every interior column at once).
 // P = 1 is the plain twisted LU of the whole grid.  The adjoint uses
 // A^H = conj(A):  A^H x = b  <=>  A conj(x) = conj(b).
@@ -39,6 +41,10 @@
 // all K forward and adjoint block solves of the stacked system (Section 2) and
 // every preconditioner application (Section 5).
 #include "common.h"
+
+#include <map>
+#include <utility>
+#include <vector>
 
 
 namespace {
@@ -520,26 +526,63 @@ __global__ __launch_bounds__(512) void k_spikes(FactorBatch bt) {
   spike_body<NSP>(pp.g, chunk_of(pp.part, c), which, grp * NSP, pp.T, which == 0 ? pp.V : pp.W, smem);
 }
 
-// ---- reduced system on the separators (one step j for every problem that has it) ----
-// Z = alpha X diag(d) Y, column-major m x m (d_k = coupling weight of column dcol, or 1)
-struct GemmJob {
-  Grid g;
-  int dcol;
+// ---- the separators' system by block cyclic reduction ----
+// Separators j = 1..n (n = P - 1) carry the block-tridiagonal Schur complement
+//   B_j = D_s - C_s W^{j-1}_b - C_{s+1} V^j_a,  L_j = -C_s V^{j-1}_b,  U_j = -C_{s+1} W^j_a
+// (s = s_j; all m x m blocks column-major).  Level l eliminates the odd multiples of
+// 2^l among the remaining separators, all at once: for such a j,
+//   Binv_j = B_j^-1,  F_j = Binv_j L_j,  G_j = Binv_j U_j      (T, V, W slots of column s_j)
+// and every even multiple k (neighbours j1 = k - 2^l, j2 = k + 2^l) becomes
+//   B_k -= L_k G_j1 + U_k F_j2,  L_k <- -L_k F_j1,  U_k <- -U_k G_j2,
+// with ML_k = L_k Binv_j1 and MU_k = U_k Binv_j2 kept for the right-hand side.  The last
+// separator left, 2^top with top = floor(log2 n), is inverted at the end.
+// A solve reduces g_k -= ML_k g_j1 + MU_k g_j2 level by level, takes x_root = Binv g,
+// and substitutes back x_j = Binv_j g_j - F_j x_j1' - G_j x_j2' from the top level down:
+// 2 top + 1 launches whose work within a level is all parallel.
+constexpr int CR_LV = 6;   // levels: n <= 63
+
+// one job of the factorisation's batched steps (pointers into the problems' buffers)
+struct CrJob {
+  int m;
   double alpha;
-  const double2 *X, *Y;
+  const double2 *X, *Y, *Cin;
   double2 *Z;
 };
-constexpr int GEMM_JOBS_MAX = 2 * KF_BATCH_MAX;
-struct GemmBatch {
-  int n;
-  GemmJob j[GEMM_JOBS_MAX];
-};
 
-// 32 x 32 output tile per workgroup, k in slabs of 16 through LDS; each of the 256
-// threads owns a 2 x 2 block of the tile.
-__global__ __launch_bounds__(256) void k_gemm_cm(GemmBatch gb) {
-  const GemmJob &J = gb.j[blockIdx.y];
-  const int m = J.g.nz;
+// B_j, L_j, U_j of every separator of every problem; item = (problem, separator), the
+// m x m entries grid-strided over blockIdx.x.  L, U: [n][4][m][m] (L, U, and two
+// staging blocks for the next level's L, U).
+__global__ void k_cr_setup(FactorBatch bt) {
+  const int q = find_problem(bt.first, bt.n, blockIdx.y);
+  const FactorProblem &pp = bt.p[q];
+  const int j = blockIdx.y - bt.first[q] + 1, n = pp.P - 1;
+  const Grid &g = pp.g;
+  const int m = g.nz;
+  const size_t mm = (size_t)m * m;
+  const int s = separator(pp.part, j);
+  double2 *B = pp.T + (size_t)s * mm;
+  double2 *L = pp.lu + (size_t)(j - 1) * 4 * mm, *U = L + mm;
+  const double2 *Wb = pp.W + (size_t)(s - 1) * mm, *Va = pp.V + (size_t)(s + 1) * mm;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (size_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e / m), r = (int)(e % m);   // entry (r, l), column-major
+    const double2 cs = coupling_x(g, s, r), cs1 = coupling_x(g, s + 1, r);
+    double2 v = csub(csub(make_double2(0.0, 0.0), cmul(cs, Wb[e])), cmul(cs1, Va[e]));
+    if (l >= r - 1 && l <= r + 1) {
+      const Stencil5 st = stencil_at(g, s, r);
+      v = cadd(v, l == r ? st.cc : (l < r ? st.czm : st.czp));
+    }
+    B[e] = v;
+    L[e] = j >= 2 ? csub(make_double2(0.0, 0.0), cmul(cs, pp.V[(size_t)(s - 1) * mm + e])) : make_double2(0.0, 0.0);
+    U[e] = j <= n - 1 ? csub(make_double2(0.0, 0.0), cmul(cs1, pp.W[(size_t)(s + 1) * mm + e])) : make_double2(0.0, 0.0);
+  }
+}
+
+// Z = Cin + alpha X Y (Cin may be NULL; Z may be Cin), column-major m x m; blockIdx.y =
+// job.  32 x 32 output tile per workgroup, k in slabs of 16 through LDS; each of the
+// 256 threads owns a 2 x 2 block of the tile.
+__global__ __launch_bounds__(256) void k_cr_gemm(const CrJob *jobs) {
+  const CrJob J = jobs[blockIdx.y];
+  const int m = J.m;
   const int nt = (m + 31) / 32;
   if ((int)blockIdx.x >= nt * nt) return;
   const int r0 = (blockIdx.x % nt) * 32, c0 = (blockIdx.x / nt) * 32;
@@ -557,12 +600,7 @@ __global__ __launch_bounds__(256) void k_gemm_cm(GemmBatch gb) {
       {  // X[r0 + rr][k0 + kk] (column-major: contiguous in rr)
         const int kk = e >> 5, rr = e & 31;
         const int r = r0 + rr, k = k0 + kk;
-        double2 v = make_double2(0.0, 0.0);
-        if (r < m && k < m) {
-          v = J.X[(size_t)k * m + r];
-          if (J.dcol >= 0) v = cmul(v, coupling_x(J.g, J.dcol, k));
-        }
-        xs[kk][rr] = v;
+        xs[kk][rr] = (r < m && k < m) ? J.X[(size_t)k * m + r] : make_double2(0.0, 0.0);
       }
       {  // Y[k0 + kk][c0 + cc] (contiguous in kk)
         const int cc = e >> 4, kk = e & 15;
@@ -587,56 +625,45 @@ __global__ __launch_bounds__(256) void k_gemm_cm(GemmBatch gb) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int r = r0 + tr + 16 * a, c = c0 + tc + 16 * b;
-      if (r < m && c < m) J.Z[(size_t)c * m + r] = cscale(acc[a][b], J.alpha);
+      if (r < m && c < m) {
+        const size_t o = (size_t)c * m + r;
+        double2 v = cscale(acc[a][b], J.alpha);
+        if (J.Cin) v = cadd(J.Cin[o], v);
+        J.Z[o] = v;
+      }
     }
 }
 
-// S_j (row-major) = D_s - C_s (W^{j-1}_b - G1) - C_{s+1} V^j_a, s = s_j; G1 = V^{j-1}_b U_{j-1}
-// (absent for j = 1).  All m x m inputs column-major.
-struct ReducedJob {
-  Grid g;
-  int sep;
-  const double2 *Wb, *Va, *G1;
-  double2 *S;
-};
-struct ReducedBatch {
-  int n;
-  ReducedJob j[KF_BATCH_MAX];
-};
-
-__global__ void k_reduced_S(ReducedBatch rb) {
-  const ReducedJob &J = rb.j[blockIdx.y];
-  const int m = J.g.nz;
-  const size_t mm = (size_t)m * m;
+// Z = X (X NULL: zero), m x m blocks; with alpha != 0 Z is row-major X (X column-major),
+// the form the inversion kernel reads.  blockIdx.y = job.
+__global__ void k_cr_copy(const CrJob *jobs) {
+  const CrJob J = jobs[blockIdx.y];
+  const size_t mm = (size_t)J.m * J.m;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (size_t)gridDim.x * blockDim.x) {
-    const int l = (int)(e / m), r = (int)(e % m);
-    double2 wv = J.Wb[e];
-    if (J.G1) wv = csub(wv, J.G1[e]);
-    double2 v = csub(make_double2(0.0, 0.0), cmul(coupling_x(J.g, J.sep, r), wv));
-    v = csub(v, cmul(coupling_x(J.g, J.sep + 1, r), J.Va[e]));
-    if (l >= r - 1 && l <= r + 1) {
-      const Stencil5 s = stencil_at(J.g, J.sep, r);
-      v = cadd(v, l == r ? s.cc : (l < r ? s.czm : s.czp));
+    if (!J.X) { J.Z[e] = make_double2(0.0, 0.0); continue; }
+    if (J.alpha != 0.0) {
+      const int r = (int)(e / J.m), c = (int)(e % J.m);   // Z[r][c] = X[r][c] (X column-major)
+      J.Z[e] = J.X[(size_t)c * J.m + r];
+    } else {
+      J.Z[e] = J.X[e];
     }
-    J.S[(size_t)r * m + l] = v;
   }
 }
 
-struct InvertJob {
-  int m;
-  double2 *S, *Tout;   // S: m x m row-major followed by NB_MAX x m staging
-};
-struct InvertBatch {
-  int n;
-  InvertJob j[KF_BATCH_MAX];
-};
+// job: X = S (m x m row-major, followed by NB_MAX x m staging), Z = the transposed
+// inverse's destination
 template <int NB, int RMAX, int NT>
-__global__ __launch_bounds__(NT) void k_invert(InvertBatch ib) {
+__global__ __launch_bounds__(NT) void k_cr_invert(const CrJob *jobs) {
   extern __shared__ unsigned char smem[];
-  const InvertJob &J = ib.j[blockIdx.x];
+  const CrJob J = jobs[blockIdx.x];
   FacLds L = fac_lds<NB>(smem, J.m);
-  gj_invert_store<NB, RMAX>(J.S, J.m, J.Tout, L.pan, L.x1, L.prow, L.piv, L.perm, J.S + (size_t)J.m * J.m);
+  double2 *S = const_cast<double2 *>(J.X);
+  gj_invert_store<NB, RMAX>(S, J.m, J.Z, L.pan, L.x1, L.prow, L.piv, L.perm, S + (size_t)J.m * J.m);
 }
+
+// up to 1024 threads (4 wave groups of 256 rows) where the register budget allows
+template <typename R, int NS> struct SolveThreads { static constexpr int N = sizeof(R) == 4 && NS <= 2 ? 1024 : 512; };
+template <typename R, int NS> struct SolveThreadsCR { static constexpr int N = SolveThreads<R, NS>::N; };
 
 // ---------------------------------------------------------------------------
 // solve phases.  They work in place on a column-major copy X of the right-hand
@@ -777,11 +804,32 @@ __device__ __forceinline__ void bwd_body(const Grid &g, int K, Chunk ch, const c
   }
 }
 
-// 3: reduced right-hand side of separator j, t_j = T_j (b_s - C_s z_{s-1} - C_{s+1} z_{s+1}),
-//    stored at column s
+// 3: right-hand side of separator j, g_j = b_s - C_s z_{s-1} - C_{s+1} z_{s+1}, stored at
+//    column s
 template <typename R, int NS>
-__device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, const cplx<R> *__restrict__ T, void *X,
-                                             int group, unsigned char *smem) {
+__device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, void *X, int group) {
+  using C = cplx<R>;
+  const int m = g.nz;
+  const int j = threadIdx.x;
+  if (threadIdx.y != 0 || j >= m) return;
+  const int k0 = group * NS;
+  const C cl = ccast<R>(coupling_x(g, s_col, j)), cr = ccast<R>(coupling_x(g, s_col + 1, j));
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (k0 + s < K) {
+      C r = colp<R>(X, g, k0 + s, s_col)[j];
+      r = csub(r, cmul(cl, colp<R>(X, g, k0 + s, s_col - 1)[j]));
+      r = csub(r, cmul(cr, colp<R>(X, g, k0 + s, s_col + 1)[j]));
+      colp<R>(X, g, k0 + s, s_col)[j] = r;
+    }
+}
+
+// 4: one level of the separators' cyclic reduction for NS sources: the value at column
+//    out is set to (keep ? old value : 0) + M_0 x(col_0) - M_1 x(col_1) - M_2 x(col_2),
+//    absent terms (NULL M_t) skipped.
+template <typename R, int NS>
+__device__ __forceinline__ void cr_terms(const Grid &g, int K, void *X, int group, const cplx<R> *const *M,
+                                         const int *col, int out, bool keep, unsigned char *smem) {
   using C = cplx<R>;
   const int m = g.nz;
   C *w = (C *)smem;
@@ -789,69 +837,83 @@ __device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, co
   const int j = threadIdx.x;
   const bool owner = threadIdx.y == 0 && j < m;
   const int k0 = group * NS;
-  if (owner) {
-    const C cl = ccast<R>(coupling_x(g, s_col, j)), cr = ccast<R>(coupling_x(g, s_col + 1, j));
+  C tot[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      C r = mk<R>(0, 0);
-      if (k0 + s < K) {
-        r = colp<R>(X, g, k0 + s, s_col)[j];
-        r = csub(r, cmul(cl, colp<R>(X, g, k0 + s, s_col - 1)[j]));
-        r = csub(r, cmul(cr, colp<R>(X, g, k0 + s, s_col + 1)[j]));
-      }
-      w[s * m + j] = r;
-    }
+  for (int s = 0; s < NS; ++s)
+    tot[s] = (owner && keep && k0 + s < K) ? colp<R>(X, g, k0 + s, out)[j] : mk<R>(0, 0);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {   // term 0 adds, terms 1 and 2 subtract
+    if (!M[t]) continue;            // uniform over the workgroup
+    if (owner)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) w[s * m + j] = k0 + s < K ? colp<R>(X, g, k0 + s, col[t])[j] : mk<R>(0, 0);
+    __syncthreads();
+    C acc[NS];
+    col_matvec<R, NS>(M[t], m, w, part, acc);
+    if (owner)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) tot[s] = t == 0 ? cadd(tot[s], acc[s]) : csub(tot[s], acc[s]);
+    __syncthreads();
   }
-  __syncthreads();
-  C acc[NS];
-  col_matvec<R, NS>(T + (size_t)s_col * m * m, m, w, part, acc);
   if (owner)
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (k0 + s < K) colp<R>(X, g, k0 + s, s_col)[j] = acc[s];
+      if (k0 + s < K) colp<R>(X, g, k0 + s, out)[j] = tot[s];
 }
 
-// 4: the separators' block LU: y_j = t_j - N_j y_{j-1} (j = 2..P-1), then
-//    x_j = y_j - U_j x_{j+1} (j = P-2..1); N_j, U_j in the V, W slots of column s_j
-template <typename R, int NS>
-__device__ __forceinline__ void red_chain_body(const Grid &g, int K, int P, const int *part_cols,
-                                               const cplx<R> *__restrict__ V, const cplx<R> *__restrict__ W, void *X,
-                                               int group, unsigned char *smem) {
+__host__ __device__ inline int cr_top(int n) {   // floor(log2 n), n >= 1
+  int t = 0;
+  while ((2 << t) <= n) ++t;
+  return t;
+}
+
+// KIND 0: forward reduction at level bt.level (item k = (t + 1) 2^(l+1)):
+//           g_k -= ML_k g_{k-2^l} + MU_k g_{k+2^l};
+// KIND 1: root, x = Binv g at separator 2^top;
+// KIND 2: back-substitution at level bt.level (item j = (2t + 1) 2^l):
+//           x_j = Binv_j g_j - F_j x_{j-2^l} - G_j x_{j+2^l}.
+template <typename R, int NS, int KIND>
+__global__ __launch_bounds__((SolveThreadsCR<R, NS>::N)) void k_cr_solve(SweepBatch bt) {
+  extern __shared__ unsigned char smem[];
   using C = cplx<R>;
-  const int m = g.nz;
-  C *w = (C *)smem;
-  C *part = w + 2 * NS * m;
-  const int j = threadIdx.x;
-  const bool owner = threadIdx.y == 0 && j < m;
-  const int k0 = group * NS;
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int G = (pp.K + NS - 1) / NS;
+  const int grp = local % G, t = local / G;
+  const Grid &g = pp.g;
+  const int m = g.nz, n = pp.P - 1, lv = bt.level;
   const size_t mm = (size_t)m * m;
-  C cur[NS];
-  if (owner)
-#pragma unroll
-    for (int s = 0; s < NS; ++s) cur[s] = k0 + s < K ? colp<R>(X, g, k0 + s, separator(part_cols, 1))[j] : mk<R>(0, 0);
-  for (int pass = 0; pass < 2; ++pass) {   // forward over j = 2..P-1, then back over j = P-2..1
-    for (int step = 0; step < P - 2; ++step) {
-      const int jj = pass == 0 ? 2 + step : P - 2 - step;
-      const int sc = separator(part_cols, jj);
-      C t[NS];
-      if (owner)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          w[s * m + j] = cur[s];
-          t[s] = k0 + s < K ? colp<R>(X, g, k0 + s, sc)[j] : mk<R>(0, 0);
-        }
-      __syncthreads();
-      C acc[NS];
-      col_matvec<R, NS, (sizeof(R) == 4 && NS == 1) ? 16 : 8>((pass == 0 ? V : W) + (size_t)sc * mm, m, w, part, acc);
-      if (owner)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          cur[s] = csub(t[s], acc[s]);
-          if (k0 + s < K) colp<R>(X, g, k0 + s, sc)[j] = cur[s];
-        }
-      __syncthreads();
-    }
+  const C *T = (const C *)pp.T, *V = (const C *)pp.V, *W = (const C *)pp.W, *CR = (const C *)pp.CR;
+  // up to three terms at fixed slots (absent ones NULL)
+  const C *M[3] = {nullptr, nullptr, nullptr};
+  int col[3] = {0, 0, 0};
+  int out;
+  bool keep;
+  if (KIND == 0) {
+    const int st = 1 << lv, k = (t + 1) * 2 * st;
+    out = separator(pp.part, k);
+    keep = true;
+    M[1] = CR + ((size_t)(k - 1) * CR_LV + lv) * 2 * mm;
+    col[1] = separator(pp.part, k - st);
+    if (k + st <= n) { M[2] = M[1] + mm; col[2] = separator(pp.part, k + st); }
+  } else if (KIND == 1) {
+    out = separator(pp.part, 1 << cr_top(n));
+    keep = false;
+    M[0] = T + (size_t)out * mm;
+    col[0] = out;
+  } else {
+    const int st = 1 << lv, j = (2 * t + 1) * st;
+    out = separator(pp.part, j);
+    keep = false;
+    M[0] = T + (size_t)out * mm;
+    col[0] = out;
+    if (j - st >= 1) { M[1] = V + (size_t)out * mm; col[1] = separator(pp.part, j - st); }
+    if (j + st <= n) { M[2] = W + (size_t)out * mm; col[2] = separator(pp.part, j + st); }
   }
+  cr_terms<R, NS>(g, pp.K, pp.x, grp, M, col, out, keep, smem);
 }
 
 // 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}.  A workgroup
@@ -1082,8 +1144,6 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   }
 }
 
-// up to 1024 threads (4 wave groups of 256 rows) where the register budget allows
-template <typename R, int NS> struct SolveThreads { static constexpr int N = sizeof(R) == 4 && NS <= 2 ? 1024 : 512; };
 template <typename R, int NS, int PH>
 __global__ __launch_bounds__((SolveThreads<R, NS>::N)) void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
@@ -1101,10 +1161,8 @@ __global__ __launch_bounds__((SolveThreads<R, NS>::N)) void k_solve(SweepBatch b
     mid_body<R, NS>(pp.g, pp.K, chunk_of(pp.part, rest), T, pp.x, grp, smem);
   else if (PH == 2)
     bwd_body<R, NS>(pp.g, pp.K, chunk_of(pp.part, rest >> 1), T, pp.x, grp, rest & 1, smem);
-  else if (PH == 3)
-    red_rhs_body<R, NS>(pp.g, pp.K, separator(pp.part, rest + 1), T, pp.x, grp, smem);
   else
-    red_chain_body<R, NS>(pp.g, pp.K, pp.P, pp.part, (const cplx<R> *)pp.V, (const cplx<R> *)pp.W, pp.x, grp, smem);
+    red_rhs_body<R, NS>(pp.g, pp.K, separator(pp.part, rest + 1), pp.x, grp);
 }
 
 // Row-major fields [K][nz][nx] (IO type) to the column-major compute copy [K][nx][nz]
@@ -1254,6 +1312,17 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     HIP_TRY(hipMalloc((void **)&p->V32, sizeof(float2) * n));
     HIP_TRY(hipMalloc((void **)&p->W32, sizeof(float2) * n));
   }
+  // the separators' reduction blocks, sized by the separator count
+  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32})
+    if (q) HIP_TRY(hipFree(q));
+  p->CRL64 = p->CR64 = nullptr;
+  p->CR32 = nullptr;
+  if (chunks > 1) {
+    const size_t nsep = chunks - 1;
+    HIP_TRY(hipMalloc((void **)&p->CRL64, sizeof(double2) * nsep * 4 * mm));
+    HIP_TRY(hipMalloc((void **)&p->CR64, sizeof(double2) * nsep * CR_LV * 2 * mm));
+    HIP_TRY(hipMalloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
+  }
   p->part = part;
   p->P = chunks;
   int lmax = 0;
@@ -1272,7 +1341,7 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
   const size_t smem = (2 * (size_t)m_max * NB + 2 * (size_t)m_max + 2 * NB) * sizeof(double2) + 2 * (size_t)m_max * sizeof(int);
   HIP_TRY(hipFuncSetAttribute((const void *)k_factor_chunks<NB, RMAX, NT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   HIP_TRY(hipFuncSetAttribute((const void *)k_factor_chunks<NB, RMAX, NT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  HIP_TRY(hipFuncSetAttribute((const void *)k_invert<NB, RMAX, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  HIP_TRY(hipFuncSetAttribute((const void *)k_cr_invert<NB, RMAX, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   FactorBatch bt{};
   bt.n = (int)ps.size();
   for (int q = 0; q < bt.n; ++q) {
@@ -1313,43 +1382,132 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
   HIP_TRY(hipFuncSetAttribute((const void *)k_spikes<NSP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
   hipLaunchKernelGGL((k_spikes<NSP>), dim3(grid_sp), blk, smem_sp, s, bt);
   LAUNCH_CHECK();
-  // 3. the separators' block LU, one separator at a time
-  for (int j = 1; j < pmax; ++j) {
-    GemmBatch g1{}, nu{};
-    ReducedBatch rb{};
-    InvertBatch ib{};
-    int tiles = 0;
-    for (kf_problem *p : ps) {
-      if (p->P - 1 < j) continue;
-      const int m = p->nz;
-      const size_t mm = (size_t)m * m;
-      const size_t slot = mm + (size_t)NB_MAX * m;
-      const int sc = p->part[3 * (j - 1) + 1] + 1;   // s_j; b_{j-1} = sc - 1, a_j = sc + 1
-      double2 *S = p->fac_work, *G1 = p->fac_work + slot;
-      tiles = std::max(tiles, ((m + 31) / 32) * ((m + 31) / 32));
-      if (j >= 2) {
-        const int sp = p->part[3 * (j - 2) + 1] + 1;  // s_{j-1}
-        g1.j[g1.n++] = GemmJob{p->grid(), -1, 1.0, p->V64 + (size_t)(sc - 1) * mm, p->W64 + (size_t)sp * mm, G1};
-        nu.j[nu.n++] = GemmJob{p->grid(), sc, -1.0, p->T64 + (size_t)sc * mm, p->V64 + (size_t)(sc - 1) * mm,
-                               p->V64 + (size_t)sc * mm};
+  // 3. the separators' system by block cyclic reduction (all problems, level by level)
+  {
+    int ntot = 0, top_max = -1;
+    for (int q = 0; q < bt.n; ++q) {
+      bt.first[q] = ntot;
+      const int nsep = ps[q]->P - 1;
+      ntot += nsep;
+      if (nsep > 0) top_max = std::max(top_max, cr_top(nsep));
+      bt.p[q].lu = ps[q]->CRL64;
+    }
+    bt.first[bt.n] = bt.total = ntot;
+    if (ntot == 0) return KF_OK;
+    hipLaunchKernelGGL(k_cr_setup, dim3(std::min(256, (m_max * m_max + 255) / 256), ntot), dim3(256), 0, s, bt);
+    LAUNCH_CHECK();
+    // job table of every step of every level
+    std::vector<CrJob> jobs;
+    struct Step { int kind, off, cnt; };   // kind 0 copy, 1 invert, 2 gemm
+    std::vector<Step> steps;
+    auto sep = [](kf_problem *p, int j) { return p->part[3 * (j - 1) + 1] + 1; };
+    auto blk = [](kf_problem *p, double2 *base, int col) { return base + (size_t)col * p->nz * p->nz; };
+    auto lu = [](kf_problem *p, int j, int w) { return p->CRL64 + ((size_t)(j - 1) * 4 + w) * p->nz * p->nz; };
+    auto crb = [](kf_problem *p, int k, int lv, int w) {
+      return p->CR64 + (((size_t)(k - 1) * CR_LV + lv) * 2 + w) * p->nz * p->nz;
+    };
+    auto slot = [](kf_problem *p, int i) { return p->fac_work + (size_t)i * ((size_t)p->nz * p->nz + (size_t)NB_MAX * p->nz); };
+    auto begin = [&](int kind) { steps.push_back(Step{kind, (int)jobs.size(), 0}); };
+    auto add = [&](const CrJob &j) { jobs.push_back(j); steps.back().cnt++; };
+    for (int lv = 0; lv <= top_max; ++lv) {
+      // A: invert the separators eliminated at this level (and each problem's root at its top)
+      std::vector<std::pair<kf_problem *, int>> inv;
+      for (kf_problem *p : ps) {
+        const int n = p->P - 1;
+        if (n < 1) continue;
+        const int top = cr_top(n), st = 1 << lv;
+        if (lv < top)
+          for (int j = st; j <= n; j += 2 * st) inv.push_back({p, j});
+        else if (lv == top)
+          inv.push_back({p, 1 << top});
       }
-      if (j <= p->P - 2)
-        nu.j[nu.n++] = GemmJob{p->grid(), sc + 1, -1.0, p->T64 + (size_t)sc * mm, p->W64 + (size_t)(sc + 1) * mm,
-                               p->W64 + (size_t)sc * mm};
-      rb.j[rb.n++] = ReducedJob{p->grid(), sc, p->W64 + (size_t)(sc - 1) * mm, p->V64 + (size_t)(sc + 1) * mm,
-                                j >= 2 ? G1 : nullptr, S};
-      ib.j[ib.n++] = InvertJob{m, S, p->T64 + (size_t)sc * mm};
+      if (inv.empty()) continue;
+      std::map<kf_problem *, int> used;
+      begin(0);
+      for (auto &e : inv) {
+        const int i = used[e.first]++;
+        add(CrJob{e.first->nz, 1.0, blk(e.first, e.first->T64, sep(e.first, e.second)), nullptr, nullptr, slot(e.first, i)});
+      }
+      used.clear();
+      begin(1);
+      for (auto &e : inv) {
+        const int i = used[e.first]++;
+        add(CrJob{e.first->nz, 0.0, slot(e.first, i), nullptr, nullptr, blk(e.first, e.first->T64, sep(e.first, e.second))});
+      }
+      // B: F_j = Binv_j L_j, G_j = Binv_j U_j
+      begin(2);
+      for (kf_problem *p : ps) {
+        const int n = p->P - 1;
+        if (n < 1 || lv >= cr_top(n)) continue;
+        const int st = 1 << lv;
+        for (int j = st; j <= n; j += 2 * st) {
+          const int s_ = sep(p, j);
+          if (j - st >= 1) add(CrJob{p->nz, 1.0, blk(p, p->T64, s_), lu(p, j, 0), nullptr, blk(p, p->V64, s_)});
+          if (j + st <= n) add(CrJob{p->nz, 1.0, blk(p, p->T64, s_), lu(p, j, 1), nullptr, blk(p, p->W64, s_)});
+        }
+      }
+      // C: B_k -= L_k G_j1, ML, MU, and the next level's L, U (staging)
+      begin(2);
+      for (kf_problem *p : ps) {
+        const int n = p->P - 1;
+        if (n < 1 || lv >= cr_top(n)) continue;
+        const int st = 1 << lv;
+        for (int k = 2 * st; k <= n; k += 2 * st) {
+          const int sk = sep(p, k), s1 = sep(p, k - st), j2 = k + st;
+          add(CrJob{p->nz, -1.0, lu(p, k, 0), blk(p, p->W64, s1), blk(p, p->T64, sk), blk(p, p->T64, sk)});
+          add(CrJob{p->nz, 1.0, lu(p, k, 0), blk(p, p->T64, s1), nullptr, crb(p, k, lv, 0)});
+          if (k - 2 * st >= 1) add(CrJob{p->nz, -1.0, lu(p, k, 0), blk(p, p->V64, s1), nullptr, lu(p, k, 2)});
+          if (j2 <= n) {
+            const int s2 = sep(p, j2);
+            add(CrJob{p->nz, 1.0, lu(p, k, 1), blk(p, p->T64, s2), nullptr, crb(p, k, lv, 1)});
+            if (j2 + st <= n) add(CrJob{p->nz, -1.0, lu(p, k, 1), blk(p, p->W64, s2), nullptr, lu(p, k, 3)});
+          }
+        }
+      }
+      // D: B_k -= U_k F_j2
+      begin(2);
+      for (kf_problem *p : ps) {
+        const int n = p->P - 1;
+        if (n < 1 || lv >= cr_top(n)) continue;
+        const int st = 1 << lv;
+        for (int k = 2 * st; k + st <= n; k += 2 * st) {
+          const int sk = sep(p, k);
+          add(CrJob{p->nz, -1.0, lu(p, k, 1), blk(p, p->V64, sep(p, k + st)), blk(p, p->T64, sk), blk(p, p->T64, sk)});
+        }
+      }
+      // E: the next level's L_k, U_k (zero where the neighbour has none)
+      begin(0);
+      for (kf_problem *p : ps) {
+        const int n = p->P - 1;
+        if (n < 1 || lv >= cr_top(n)) continue;
+        const int st = 1 << lv;
+        for (int k = 2 * st; k <= n; k += 2 * st) {
+          add(CrJob{p->nz, 0.0, k - 2 * st >= 1 ? lu(p, k, 2) : nullptr, nullptr, nullptr, lu(p, k, 0)});
+          add(CrJob{p->nz, 0.0, (k + st <= n && k + 2 * st <= n) ? lu(p, k, 3) : nullptr, nullptr, nullptr, lu(p, k, 1)});
+        }
+      }
     }
-    if (g1.n) {
-      hipLaunchKernelGGL(k_gemm_cm, dim3(tiles, g1.n), dim3(256), 0, s, g1);
-      LAUNCH_CHECK();
+    // the table lives in the first problem's buffer; the previous factorisation's
+    // launches must be done with it before it is overwritten
+    kf_problem *p0 = ps[0];
+    if (jobs.size() > p0->cr_jobs_cap) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (p0->cr_jobs) HIP_TRY(hipFree(p0->cr_jobs));
+      p0->cr_jobs = nullptr;
+      p0->cr_jobs_cap = 0;
+      HIP_TRY(hipMalloc(&p0->cr_jobs, sizeof(CrJob) * jobs.size()));
+      p0->cr_jobs_cap = jobs.size();
     }
-    hipLaunchKernelGGL(k_reduced_S, dim3(std::min(1024, (m_max * m_max + 255) / 256), rb.n), dim3(256), 0, s, rb);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_invert<NB, RMAX, NT>), dim3(ib.n), dim3(NT), smem, s, ib);
-    LAUNCH_CHECK();
-    if (nu.n) {
-      hipLaunchKernelGGL(k_gemm_cm, dim3(tiles, nu.n), dim3(256), 0, s, nu);
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(p0->cr_jobs, jobs.data(), sizeof(CrJob) * jobs.size(), hipMemcpyHostToDevice));
+    const CrJob *dj = (const CrJob *)p0->cr_jobs;
+    const int tiles = ((m_max + 31) / 32) * ((m_max + 31) / 32);
+    const int cblocks = std::min(64, (m_max * m_max + 255) / 256);
+    for (const Step &stp : steps) {
+      if (stp.cnt == 0) continue;
+      if (stp.kind == 0) hipLaunchKernelGGL(k_cr_copy, dim3(cblocks, stp.cnt), dim3(256), 0, s, dj + stp.off);
+      else if (stp.kind == 1) hipLaunchKernelGGL((k_cr_invert<NB, RMAX, NT>), dim3(stp.cnt), dim3(NT), smem, s, dj + stp.off);
+      else hipLaunchKernelGGL(k_cr_gemm, dim3(tiles, stp.cnt), dim3(256), 0, s, dj + stp.off);
       LAUNCH_CHECK();
     }
   }
@@ -1381,6 +1539,8 @@ kf_status blu_factor_batch(const std::vector<kf_problem *> &all, int which, hipS
         kf_status st = launch_copy_c128_to_c64(p, n, p->T64, p->T32);
         if (st == KF_OK && p->P > 1) st = launch_copy_c128_to_c64(p, n, p->V64, p->V32);
         if (st == KF_OK && p->P > 1) st = launch_copy_c128_to_c64(p, n, p->W64, p->W32);
+        if (st == KF_OK && p->P > 1)
+          st = launch_copy_c128_to_c64(p, (int64_t)(p->P - 1) * CR_LV * 2 * p->nz * p->nz, p->CR64, p->CR32);
         if (st != KF_OK) return st;
         p->have_T32 = true;
       }
@@ -1417,51 +1577,78 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                            fp32 ? (const void *)p->T32 : (const void *)p->T64,
                            fp32 ? (const void *)p->V32 : (const void *)p->V64,
                            fp32 ? (const void *)p->W32 : (const void *)p->W64,
+                           fp32 ? (const void *)p->CR32 : (const void *)p->CR64,
                            fp32 ? (void *)p->sol32 : (void *)p->sol64};
   }
   const dim3 blk = sweep_block(m_max, SolveThreads<R, NS>::N);
   const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
+  if (smem > 65536) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NS, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  }
+  // launch order: 0 forward sweeps, 1 middle columns, 2 back-substitution, 3 separator
+  // right-hand sides, the separators' reduction (forward levels, root, back levels),
+  // then 5 the interior correction
+  int top_max = -1;
+  for (kf_problem *p : ps)
+    if (p->P > 1) top_max = std::max(top_max, cr_top(p->P - 1));
+  std::vector<std::pair<int, int>> seq;   // (phase, level); phase 4: 0 fwd, 1 root, 2 bwd in .second / 16
+  for (int ph = 0; ph < 4; ++ph) seq.push_back({ph, 0});
+  for (int lv = 0; lv < top_max; ++lv) seq.push_back({4, lv});
+  if (top_max >= 0) seq.push_back({4, 16});
+  for (int lv = top_max - 1; lv >= 0; --lv) seq.push_back({4, 32 + lv});
+  seq.push_back({5, 0});
   static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
-  for (int ph = 0; ph < 6; ++ph) {
+  for (const auto &e : seq) {
+    const int ph = e.first, kind = e.second >> 4, lv = e.second & 15;
     int tot = 0;
     double cost[KF_BATCH_MAX];
     for (int q = 0; q < bt.n; ++q) {
       const kf_problem *p = ps[q];
-      const int G = (p->K + NS - 1) / NS;
+      const int G = (p->K + NS - 1) / NS, n = p->P - 1;
       const double m = p->nz, L = (double)p->nx / p->P;
-      cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 4 ? m * m * 2.0 * (p->P - 2) : ph == 5 ? m : m * m;
+      cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 5 ? m : m * m;
       bt.first[q] = tot;
-      tot += ph == 0 || ph == 2 ? 2 * p->P * G
-           : ph == 1            ? p->P * G
-           : ph == 3            ? (p->P - 1) * G
-           : ph == 4            ? (p->P > 2 ? G : 0)
-                                : (p->P > 1 ? p->P *
-                                                    (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
-                                                          : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S))
-                                              : 0);
+      int items = 0;
+      if (ph == 0 || ph == 2) items = 2 * p->P * G;
+      else if (ph == 1) items = p->P * G;
+      else if (ph == 3) items = n * G;
+      else if (ph == 4) {
+        if (n >= 1) {
+          const int top = cr_top(n);
+          if (kind == 0 && lv < top) items = (n >> (lv + 1)) * G;
+          else if (kind == 1) items = G;
+          else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * G;
+        }
+      } else if (p->P > 1) {
+        items = p->P * (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
+                             : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S));
+      }
+      tot += items;
     }
     bt.first[bt.n] = bt.total = tot;
+    bt.level = lv;
     if (tot == 0) continue;
     const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
     ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
-#define SOLVE_PHASE(PH)                                                                                       \
-  do {                                                                                                        \
-    if (smem > 65536)                                                                                         \
-      HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, PH>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                  (int)smem));                                                                \
-    hipLaunchKernelGGL((k_solve<R, NS, PH>), dim3(grid), blk, smem, s, bt);                                  \
-  } while (0)
     switch (ph) {
-      case 0: SOLVE_PHASE(0); break;
-      case 1: SOLVE_PHASE(1); break;
-      case 2: SOLVE_PHASE(2); break;
-      case 3: SOLVE_PHASE(3); break;
-      case 4: SOLVE_PHASE(4); break;
+      case 0: hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt); break;
+      case 1: hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt); break;
+      case 2: hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt); break;
+      case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
+      case 4:
+        if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
+        else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
+        else hipLaunchKernelGGL((k_cr_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
+        break;
       default:
         if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
         else hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
     }
-#undef SOLVE_PHASE
     LAUNCH_CHECK();
   }
   return KF_OK;

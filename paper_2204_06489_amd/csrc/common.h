@@ -93,10 +93,11 @@ struct SweepProblem {
   int K, P, lmax;      // sources, chunks, longest chunk (columns)
   const int *part;     // [P][3]: first, last and meeting column of each chunk (device)
   const void *T, *V, *W;   // factors and spikes (c128 or c64)
+  const void *CR;      // separators' reduction blocks ML, MU: [n][levels][2][m][m]
   void *x;             // right-hand sides in, solutions out: column-major [K][nx][nz] (compute type)
 };
 struct SweepBatch {
-  int n, total;
+  int n, total, level;           // level: cyclic-reduction level of the launch
   int first[KF_BATCH_MAX + 1];   // first item of each problem (prefix sums)
   int xs[9];                     // items [xs[x], xs[x+1]) run on XCD x
   SweepProblem p[KF_BATCH_MAX];
@@ -106,6 +107,7 @@ struct FactorProblem {
   int P;
   const int *part;
   double2 *T, *V, *W, *work;
+  double2 *lu;         // separators' current L, U and staging: [n][4][m][m]
 };
 struct FactorBatch {
   int n, total;
@@ -157,6 +159,11 @@ struct kf_problem {
   bool have_T64 = false, have_T32 = false;
   double2 *fac_work = nullptr;                 // factorisation scratch, fac_slots work matrices
   size_t fac_slots = 0;
+  double2 *CRL64 = nullptr;                    // separators' L, U during the reduction [n][4][m][m]
+  double2 *CR64 = nullptr;                     // separators' ML, MU [n][levels][2][m][m]
+  float2 *CR32 = nullptr;
+  void *cr_jobs = nullptr;                     // device job table of the reduction
+  size_t cr_jobs_cap = 0;
   double2 *sol64 = nullptr;                    // [K][nx][nz] column-major solve copy (c128)
   float2 *sol32 = nullptr;                     // the same for complex64 sweeps
 
