@@ -157,7 +157,7 @@ kf_status kf_set_stream(kf_problem *p, void *hip_stream);
  * every piece is factorised and swept independently and a block-tridiagonal system on
  * the separators (their Schur complement) joins them, so more chunks means more parallel
  * work and shorter sequential sweeps, plus a longer separator chain.  1 <= chunks <=
- * min(64, (nx + 1) / 2); 0 picks round(sqrt(nx / 2)) (1 below nx = 32).
+ * min(64, (nx + 1) / 2); 0 picks round(1.6 sqrt(nx)) (1 below nx = 32).
  * sources_per_group: right-hand sides per workgroup in the block solves, 1, 2, 4 or 8
  * (0 = 1; FP64 solves use at most 4).  Results do not depend on either beyond rounding. */
 kf_status kf_set_solver_shape(kf_problem *p, int32_t chunks, int32_t sources_per_group);

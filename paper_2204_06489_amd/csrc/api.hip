@@ -407,9 +407,9 @@ extern "C" kf_status kf_autotune(kf_problem *p, int32_t prec, double solves_per_
   if (table_len < 0 || (table_len > 0 && !table)) return fail(KF_EINVAL, "table is NULL");
   HIP_TRY(hipStreamSynchronize(p->stream));
   const int pmax = std::min(KF_MAX_CHUNKS, (p->nx + 1) / 2);
-  const int a = std::max(1, (int)std::lround(std::sqrt(p->nx / 2.0)));
+  const int a = std::max(1, (int)std::lround(1.6 * std::sqrt((double)p->nx)));
   std::vector<int> cand;
-  for (double f : {0.0, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0}) {
+  for (double f : {0.0, 0.35, 0.5, 0.7, 1.0, 1.4, 2.0}) {
     int c = f == 0.0 ? 1 : std::max(1, std::min(pmax, (int)std::lround(f * a)));
     if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
   }

@@ -663,6 +663,8 @@ __global__ __launch_bounds__(NT) void k_cr_invert(const CrJob *jobs) {
 
 // up to 1024 threads (4 wave groups of 256 rows) where the register budget allows
 template <typename R, int NS> struct SolveThreads { static constexpr int N = sizeof(R) == 4 && NS <= 2 ? 1024 : 512; };
+// sources per workgroup in the separators' reduction, given the sweeps' NS
+template <typename R, int NS> struct CrSources { static constexpr int N = NS; };
 template <typename R, int NS> struct SolveThreadsCR { static constexpr int N = SolveThreads<R, NS>::N; };
 
 // ---------------------------------------------------------------------------
@@ -1265,7 +1267,8 @@ static unsigned xcd_split(const int *first, int n, const double *cost, int *xs) 
 int blu_auto_chunks(int nx, int nz, int K) {
   (void)nz; (void)K;
   if (nx < 32) return 1;
-  int P = (int)std::lround(std::sqrt(nx / 2.0));
+  // the separators cost log2(P) levels, so chunks of ~sqrt(nx) / 1.6 columns
+  int P = (int)std::lround(1.6 * std::sqrt((double)nx));
   return std::max(1, std::min({P, KF_MAX_CHUNKS, (nx + 1) / 2}));
 }
 
@@ -1586,9 +1589,14 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
     HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NS, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  }
+  constexpr int NSC = CrSources<R, NS>::N;
+  const dim3 blkc = sweep_block(m_max, SolveThreadsCR<R, NSC>::N);
+  const size_t smemc = (2 + (blkc.y - 1)) * NSC * (size_t)m_max * sizeof(cplx<R>);
+  if (smemc > 65536) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NSC, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemc));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NSC, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemc));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NSC, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemc));
   }
   // launch order: 0 forward sweeps, 1 middle columns, 2 back-substitution, 3 separator
   // right-hand sides, the separators' reduction (forward levels, root, back levels),
@@ -1609,7 +1617,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
     double cost[KF_BATCH_MAX];
     for (int q = 0; q < bt.n; ++q) {
       const kf_problem *p = ps[q];
-      const int G = (p->K + NS - 1) / NS, n = p->P - 1;
+      const int G = (p->K + (ph == 4 ? NSC : NS) - 1) / (ph == 4 ? NSC : NS), n = p->P - 1;
       const double m = p->nz, L = (double)p->nx / p->P;
       cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 5 ? m : m * m;
       bt.first[q] = tot;
@@ -1641,9 +1649,9 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       case 2: hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt); break;
       case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
       case 4:
-        if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
-        else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
-        else hipLaunchKernelGGL((k_cr_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
+        if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
+        else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
+        else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);
         break;
       default:
         if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
