@@ -246,7 +246,11 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   ALLOC(p->u_n, K * Nu);
   p->kkt_groups_max = (int)std::min<size_t>(K, 64);
   ALLOC(p->ys_part, (size_t)p->kkt_groups_max * p->Ng);
-  ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m);
+  // complex64 factors padded by four zero columns: the matrix-core sweeps read whole
+  // k-steps of four columns past a block's end
+  ALLOC(p->T64, (size_t)p->nx * m * m); ALLOC(p->T32, (size_t)p->nx * m * m + 4 * m);
+  if (st == KF_OK && hipMemset(p->T32 + (size_t)p->nx * m * m, 0, sizeof(float2) * 4 * m) != hipSuccess)
+    st = fail(KF_EHIP, "hipMemset failed");
   ALLOC(p->d_part, 3 * KF_MAX_CHUNKS);
   ALLOC(p->sol64, K * Nu); ALLOC(p->sol32, K * Nu);
   ALLOC(p->vec_a, K * Nu); ALLOC(p->vec_b, K * Nu); ALLOC(p->vec_c, K * Nu); ALLOC(p->vec_d, K * Nu);

@@ -1146,6 +1146,170 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   }
 }
 
+// Chunk sweeps of complex64 solves on the matrix cores (columns up to SW_M = 144 rows).
+// Item (chunk, side, tile of SW_S = 16 sources).  Each step is the product of the m x m
+// block T_i with an m x 16 right-hand side, as v_mfma_f32_16x16x4f32 tiles: wave w owns
+// rows 16 w .. 16 w + 15 and holds its A operand (T_i's rows, all columns) in registers,
+// fetched for the next column while the current one is multiplied (the blocks do not
+// depend on the chain).  A complex product is four real ones:
+//   Re += Ar Br + Ai (-Bi),  Im += Ar Bi + Ai Br.
+// Operand layout of the 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+// Per step: (a) all threads, coalesced over rows: store the previous column's result
+// from LDS, form the right-hand side in LDS (forward: b_i - C y_prev; back-substitution:
+// C x_prev, with y_i staged beside it); (b) each wave: its 16 x 16 tile of T_i times the
+// right-hand side, the result (forward: y_i; back-substitution: y_i - product) to LDS.
+constexpr int SW_M = 144, SW_S = 16, SW_KS = SW_M / 4, SW_T = 576;   // rows, sources, k-steps, threads
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+template <int PH>   // 0: forward sweep, 2: back-substitution
+__global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
+  using C = float2;
+  __shared__ C Bv[SW_M][SW_S + 1];    // right-hand side of the step (B operand)
+  __shared__ C Pv[SW_M][SW_S + 1];    // the previous column's result
+  __shared__ C Yv[PH == 2 ? SW_M : 1][SW_S + 1];   // y_i (back-substitution)
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int ST = (pp.K + SW_S - 1) / SW_S;
+  const int st = local % ST, rest = local / ST;
+  const Chunk ch = chunk_of(pp.part, rest >> 1);
+  const int side = rest & 1;
+  const Grid &g = pp.g;
+  const int m = g.nz, K = pp.K, s0 = st * SW_S;
+  const size_t mm = (size_t)m * m;
+  const C *T = (const C *)pp.T;
+  const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+  if (cnt <= 0) return;   // uniform over the workgroup
+  // column of step t and the coupling column to the previous one
+  auto col_of = [&](int t) {
+    return PH == 0 ? (side == 0 ? ch.a + t : ch.b - t) : (side == 0 ? ch.mid - 1 - t : ch.mid + 1 + t);
+  };
+  auto cc_of = [&](int i) { return PH == 0 ? (side == 0 ? i : i + 1) : (side == 0 ? i + 1 : i); };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = 16 * wave;
+  // phase (a) slots: e = tid + SW_T u -> (row e % SW_M, source e / SW_M)
+  constexpr int NA = SW_M * SW_S / SW_T;
+  // per slot: offset of (source, row) in the column-major copy (column 0), and the
+  // row's coupling factor zn[row] (-1 / h^2); the column's factor ixh[i] is uniform
+  size_t aoff[NA];
+  C zf[NA];
+  bool aok[NA];
+  const double ih2 = -1.0 / (g.h * g.h);
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int e = tid + SW_T * u, r = e % SW_M, j = e / SW_M;
+    aok[u] = r < m && s0 + j < K;
+    aoff[u] = (size_t)min(s0 + j, K - 1) * g.nx * m + min(r, m - 1);
+    const double2 z = g.zn[min(r, m - 1)];
+    zf[u] = make_float2((float)(z.x * ih2), (float)(z.y * ih2));
+  }
+  C *const Xb = (C *)pp.x;
+  auto xaddr = [&](int u, int i) { return Xb + aoff[u] + (size_t)i * m; };
+  auto slot_r = [&](int u) { return (tid + SW_T * u) % SW_M; };
+  auto slot_j = [&](int u) { return (tid + SW_T * u) / SW_M; };
+  // A operand of column i: lane (i', k') = (lane % 16, lane / 16) of k-step ks holds
+  // T_i[r0 + i'][4 ks + k'] (column-major block: rows contiguous).  Every wave runs all
+  // SW_KS k-steps (rows past m are clamped to row m - 1, k-steps past the last one
+  // repeat it: the right-hand side is zero there), so the loads are unconditional and
+  // the wait counts stay exact across the loop.  The last k-step reads up to three
+  // columns beyond the block: the next block, or the zero padding after the last one.
+  C areg[SW_KS];
+  const int arw = min(r0 + (lane & 15), m - 1), akq = lane >> 4;
+  const int ksl = (m - 1) / 4;
+  const size_t kstride = 4 * (size_t)m;
+  auto a_base = [&](int i) { return T + (size_t)i * mm + (size_t)akq * m + arw; };
+  // right-hand-side values of the next step, held in registers
+  C bnext[NA];
+  if (PH == 2) {   // x_mid into Pv
+    const int im = ch.mid;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const C v = *xaddr(u, im);
+      Pv[slot_r(u)][slot_j(u)] = aok[u] ? v : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+  }
+  // in the loop's order: right-hand side, coupling factor, then the block
+  {
+    const int i0 = col_of(0);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) bnext[u] = *xaddr(u, i0);
+  }
+  // coupling to the previous column: C_cc = zn[row] ixh[cc] (-1 / h^2); the column
+  // factor of the next step is fetched with the next right-hand side, ahead of the
+  // block's loads
+  double2 xh = g.ixh[PH == 2 ? cc_of(col_of(0)) : col_of(0)];
+  {
+    const C *ap = a_base(col_of(0));
+#pragma unroll
+    for (int ks = 0; ks < SW_KS; ++ks) areg[ks] = ap[min(ks, ksl) * kstride];
+  }
+  for (int t = 0; t < cnt; ++t) {
+    const int i = col_of(t);
+    const C xf = make_float2((float)xh.x, (float)xh.y);
+    // (a) store the previous result, form this step's right-hand side
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int r = slot_r(u), j = slot_j(u);
+      const C pv = Pv[r][j];
+      if (t > 0 && aok[u]) *xaddr(u, col_of(t - 1)) = pv;
+      const C cj = make_float2(zf[u].x * xf.x - zf[u].y * xf.y, zf[u].x * xf.y + zf[u].y * xf.x);
+      const C cp = make_float2(cj.x * pv.x - cj.y * pv.y, cj.x * pv.y + cj.y * pv.x);
+      const C bv = bnext[u];
+      C rhs;
+      if (PH == 0) rhs = t > 0 ? make_float2(bv.x - cp.x, bv.y - cp.y) : bv;
+      else {
+        rhs = cp;
+        Yv[PH == 2 ? r : 0][j] = aok[u] ? bv : make_float2(0.f, 0.f);
+      }
+      Bv[r][j] = aok[u] ? rhs : make_float2(0.f, 0.f);
+    }
+    if (t + 1 < cnt) {
+      const int in = col_of(t + 1);
+#pragma unroll
+      for (int u = 0; u < NA; ++u) bnext[u] = *xaddr(u, in);
+      xh = g.ixh[cc_of(in)];
+    }
+    __syncthreads();
+    // (b) the wave's 16 x 16 tile of T_i times the right-hand side (waves past the last
+    //     row tile compute copies of row m - 1 into rows >= m, which nothing reads),
+    //     the next column's block fetched as the current one is consumed (the last
+    //     step fetches its own block again)
+    {
+      floatx4 accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+      const C *an = a_base(t + 1 < cnt ? col_of(t + 1) : i);
+#pragma unroll
+      for (int ks = 0; ks < SW_KS; ++ks) {
+        const C a = areg[ks];
+        const C b = Bv[4 * ks + akq][lane & 15];
+        accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, -b.y, accR, 0, 0, 0);   // sign on the LDS operand
+        accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, accI, 0, 0, 0);
+        areg[ks] = an[min(ks, ksl) * kstride];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 4 * (lane >> 4) + r, j = lane & 15;   // row < SW_M
+        const C o = make_float2(accR[r], accI[r]);
+        if (PH == 0) Pv[row][j] = o;
+        else {
+          const C y = Yv[PH == 2 ? row : 0][j];
+          Pv[row][j] = make_float2(y.x - o.x, y.y - o.y);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the last column's result
+  const int il = col_of(cnt - 1);
+#pragma unroll
+  for (int u = 0; u < NA; ++u)
+    if (aok[u]) *xaddr(u, il) = Pv[slot_r(u)][slot_j(u)];
+}
+
 template <typename R, int NS, int PH>
 __global__ __launch_bounds__((SolveThreads<R, NS>::N)) void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
@@ -1611,6 +1775,8 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   for (int lv = top_max - 1; lv >= 0; --lv) seq.push_back({4, 32 + lv});
   seq.push_back({5, 0});
   static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
+  // complex64 chunk sweeps on the matrix cores where the columns fit the kernel
+  const bool mfma_sweeps = fp32 && m_max <= SW_M;
   for (const auto &e : seq) {
     const int ph = e.first, kind = e.second >> 4, lv = e.second & 15;
     int tot = 0;
@@ -1622,7 +1788,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 5 ? m : m * m;
       bt.first[q] = tot;
       int items = 0;
-      if (ph == 0 || ph == 2) items = 2 * p->P * G;
+      if (ph == 0 || ph == 2) items = 2 * p->P * (mfma_sweeps ? (p->K + SW_S - 1) / SW_S : G);
       else if (ph == 1) items = p->P * G;
       else if (ph == 3) items = n * G;
       else if (ph == 4) {
@@ -1644,9 +1810,15 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
     const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
     ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
     switch (ph) {
-      case 0: hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt); break;
+      case 0:
+        if (mfma_sweeps) hipLaunchKernelGGL(k_sweep_mfma<0>, dim3(grid), dim3(SW_T), 0, s, bt);
+        else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
+        break;
       case 1: hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt); break;
-      case 2: hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt); break;
+      case 2:
+        if (mfma_sweeps) hipLaunchKernelGGL(k_sweep_mfma<2>, dim3(grid), dim3(SW_T), 0, s, bt);
+        else hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
+        break;
       case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
       case 4:
         if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
