@@ -1037,14 +1037,15 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
 }
 
 // The same product on the matrix cores (complex64 solves): a workgroup computes a
-// 128 x 32 tile (rows x sources), each of its four wavefronts a 32 x 32 block with
-// v_mfma_f32_32x32x2f32, a complex product being four real ones (Re += ar br - ai bi,
-// Im += ar bi + ai br).  Operand lanes: A[i][k] in lane i + 32 k, B[k][j] in lane
-// j + 32 k; result D[i][j] in lane j + 32 ((i / 4) mod 2), register (i mod 4) + 4 (i / 8).
-// k in slabs of 16 through LDS with the next slab prefetched into registers; the tile
-// goes back through LDS so the updates of the column-major copy are coalesced.
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-constexpr int CM_R = 128, CM_S = 32, CM_K = 16;
+// 128 x 48 tile (rows x sources), each of its four wavefronts a 32 x 48 block as 2 x 3
+// tiles of v_mfma_f32_16x16x4f32, a complex product being four real ones
+// (Re += ar br + ai (-bi), Im += ar bi + ai br).  Operand lanes: A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k; result D[i][j] in lane j + 16 (i / 4), element
+// i mod 4.  Up to 48 sources share one pass over V and W; k in slabs of 16 through
+// LDS with the next slab prefetched into registers; the tile goes back through LDS
+// so the updates of the column-major copy are coalesced.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int CM_R = 128, CM_S = 48, CM_K = 16;
 __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   using C = float2;
   // the operand slabs and the output tile share one LDS buffer (the tile is written
@@ -1075,6 +1076,7 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   const C *V = (const C *)pp.V, *W = (const C *)pp.W;
   const int s0 = st * CM_S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NB = CM_K * CM_S / 256;   // B elements per thread and slab
   // load slots: A element (row R0 + (e & 127), k e >> 7), B element (k e & 15, source e >> 4)
   int a_col[8], a_j[8], a_kk[8];
   bool a_ok[8];
@@ -1087,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
     a_col[u] = ch.a + row / m;
     a_j[u] = row % m;
   }
-  auto load_slab = [&](int kb, C (&ra)[8], C (&rb)[2]) {
+  auto load_slab = [&](int kb, C (&ra)[8], C (&rb)[NB]) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int l = kb + a_kk[u], lc = min(l, lk1 - 1);
@@ -1096,44 +1098,58 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
       ra[u] = (a_ok[u] && l < lk1) ? v : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int e = tid + 256 * u, l = kb + (e & 15), sidx = s0 + (e >> 4);
       const int lc = min(l, lk1 - 1), k = min(sidx, K - 1);
       const C v = colp<float>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
       rb[u] = (l < lk1 && sidx < K) ? v : make_float2(0.f, 0.f);
     }
   };
-  floatx16 accR = {0}, accI = {0};
-  C ra[8], rb[2];
+  floatx4 accR[2][3], accI[2][3];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 3; ++y) accR[x][y] = accI[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+  C ra[8], rb[NB];
   load_slab(lk0, ra, rb);
   for (int kb = lk0; kb < lk1; kb += CM_K) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) As[a_kk[u]][(tid + 256 * u) & 127] = ra[u];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int e = tid + 256 * u;
       Bs[e & 15][e >> 4] = rb[u];
     }
     __syncthreads();
     if (kb + CM_K < lk1) load_slab(kb + CM_K, ra, rb);   // in flight during the products
 #pragma unroll
-    for (int kp = 0; kp < CM_K / 2; ++kp) {
-      const int kk = 2 * kp + (lane >> 5);
-      const C a = As[kk][wave * 32 + (lane & 31)];
-      const C b = Bs[kk][lane & 31];
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accR, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, accI, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, accI, 0, 0, 0);
+    for (int kq = 0; kq < CM_K / 4; ++kq) {
+      const int kk = 4 * kq + (lane >> 4);
+      C a[2], b[3];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[x] = As[kk][wave * 32 + 16 * x + (lane & 15)];
+#pragma unroll
+      for (int y = 0; y < 3; ++y) b[y] = Bs[kk][16 * y + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+          accR[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].x, accR[x][y], 0, 0, 0);
+          accR[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].y, -b[y].y, accR[x][y], 0, 0, 0);
+          accI[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].y, accI[x][y], 0, 0, 0);
+          accI[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].y, b[y].x, accI[x][y], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
   // tile to LDS as [source][row], then column-contiguous updates
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-    Out[lane & 31][wave * 32 + i] = make_float2(accR[r], accI[r]);
-  }
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Out[16 * y + (lane & 15)][wave * 32 + 16 * x + 4 * (lane >> 4) + r] = make_float2(accR[x][y][r], accI[x][y][r]);
   __syncthreads();
   for (int e = tid; e < CM_S * CM_R; e += 256) {
     const int sidx = e / CM_R, rr = e - sidx * CM_R;
@@ -1160,7 +1176,6 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
 // C x_prev, with y_i staged beside it); (b) each wave: its 16 x 16 tile of T_i times the
 // right-hand side, the result (forward: y_i; back-substitution: y_i - product) to LDS.
 constexpr int SW_M = 144, SW_S = 16, SW_KS = SW_M / 4, SW_T = 576;   // rows, sources, k-steps, threads
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 template <int PH>   // 0: forward sweep, 2: back-substitution
 __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   using C = float2;
