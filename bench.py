@@ -112,6 +112,9 @@ def kernel_work(name, p):
     raise KeyError(name)
 
 
+MFMA_KERNELS = ("blu_fwd_c64", "blu_bwd_c64", "blu_correct")
+
+
 def roofline_for(name, p, launches, total_ms):
     amount, unit, dt = kernel_work(name, p)
     avg_s = total_ms / launches * 1e-3
@@ -122,7 +125,11 @@ def roofline_for(name, p, launches, total_ms):
     else:
         achieved = amount / avg_s / 1e12
         peak = FP32_PEAK_TFLOPS if dt == "f32" else FP64_PEAK_TFLOPS
-        out = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+        # complex64 sweeps and the interior correction run on the matrix cores (dense
+        # FP32 MFMA peak); the FP64 sweeps on the vector units (FP64 vector peak)
+        # (the matrix-core sweeps take columns of up to 144 rows)
+        bound = "mfma" if name == "blu_correct" or (name in MFMA_KERNELS and p.nz <= 144) else "alu"
+        out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     out.update({"frac": achieved / peak, "traffic": None, "kernel": name, "launches": launches,
                 "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount, "work_unit": unit})
     return out
