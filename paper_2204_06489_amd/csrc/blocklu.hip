@@ -1038,8 +1038,8 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
 
 // The same product on the matrix cores (complex64 solves): a workgroup computes a
 // 128 x 48 tile (rows x sources), each of its four wavefronts a 32 x 48 block as 2 x 3
-// tiles of v_mfma_f32_16x16x4f32, a complex product being four real ones
-// (Re += ar br + ai (-bi), Im += ar bi + ai br).  Operand lanes: A[i][k] in lane
+// tiles of v_mfma_f32_16x16x4f32, a complex product being three real ones (Gauss:
+// P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); Re = P1 - P2, Im = P3 - P1 - P2).  Operand lanes: A[i][k] in lane
 // i + 16 k, B[k][j] in lane j + 16 k; result D[i][j] in lane j + 16 (i / 4), element
 // i mod 4.  Up to 48 sources share one pass over V and W; k in slabs of 16 through
 // LDS with the next slab prefetched into registers; the tile goes back through LDS
@@ -1105,11 +1105,11 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
       rb[u] = (l < lk1 && sidx < K) ? v : make_float2(0.f, 0.f);
     }
   };
-  floatx4 accR[2][3], accI[2][3];
+  floatx4 p1[2][3], p2[2][3], p3[2][3];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 3; ++y) accR[x][y] = accI[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int y = 0; y < 3; ++y) p1[x][y] = p2[x][y] = p3[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
   C ra[8], rb[NB];
   load_slab(lk0, ra, rb);
   for (int kb = lk0; kb < lk1; kb += CM_K) {
@@ -1130,14 +1130,18 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
       for (int x = 0; x < 2; ++x) a[x] = As[kk][wave * 32 + 16 * x + (lane & 15)];
 #pragma unroll
       for (int y = 0; y < 3; ++y) b[y] = Bs[kk][16 * y + (lane & 15)];
+      float as[2], bs[3];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) as[x] = a[x].x + a[x].y;
+#pragma unroll
+      for (int y = 0; y < 3; ++y) bs[y] = b[y].x + b[y].y;
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 3; ++y) {
-          accR[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].x, accR[x][y], 0, 0, 0);
-          accR[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].y, -b[y].y, accR[x][y], 0, 0, 0);
-          accI[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].y, accI[x][y], 0, 0, 0);
-          accI[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].y, b[y].x, accI[x][y], 0, 0, 0);
+          p1[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].x, p1[x][y], 0, 0, 0);
+          p2[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].y, b[y].y, p2[x][y], 0, 0, 0);
+          p3[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[x], bs[y], p3[x][y], 0, 0, 0);
         }
     }
     __syncthreads();
@@ -1149,7 +1153,8 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
     for (int y = 0; y < 3; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        Out[16 * y + (lane & 15)][wave * 32 + 16 * x + 4 * (lane >> 4) + r] = make_float2(accR[x][y][r], accI[x][y][r]);
+        Out[16 * y + (lane & 15)][wave * 32 + 16 * x + 4 * (lane >> 4) + r] =
+            make_float2(p1[x][y][r] - p2[x][y][r], p3[x][y][r] - p1[x][y][r] - p2[x][y][r]);
   __syncthreads();
   for (int e = tid; e < CM_S * CM_R; e += 256) {
     const int sidx = e / CM_R, rr = e - sidx * CM_R;
@@ -1167,8 +1172,8 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
 // block T_i with an m x 16 right-hand side, as v_mfma_f32_16x16x4f32 tiles: wave w owns
 // rows 16 w .. 16 w + 15 and holds its A operand (T_i's rows, all columns) in registers,
 // fetched for the next column while the current one is multiplied (the blocks do not
-// depend on the chain).  A complex product is four real ones:
-//   Re += Ar Br + Ai (-Bi),  Im += Ar Bi + Ai Br.
+// depend on the chain).  A complex product is three real ones (Gauss):
+//   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi);  Re = P1 - P2,  Im = P3 - P1 - P2.
 // Operand layout of the 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
 // j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
 // Per step: (a) all threads, coalesced over rows: store the previous column's result
@@ -1293,22 +1298,24 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
     //     the next column's block fetched as the current one is consumed (the last
     //     step fetches its own block again)
     {
-      floatx4 accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+      floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
       const C *an = a_base(t + 1 < cnt ? col_of(t + 1) : i);
 #pragma unroll
       for (int ks = 0; ks < SW_KS; ++ks) {
         const C a = areg[ks];
         const C b = Bv[4 * ks + akq][lane & 15];
-        accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accR, 0, 0, 0);
-        accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, -b.y, accR, 0, 0, 0);   // sign on the LDS operand
-        accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, accI, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, accI, 0, 0, 0);
+        p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1, 0, 0, 0);
+        p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2, 0, 0, 0);
+        p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, p3, 0, 0, 0);
         areg[ks] = an[min(ks, ksl) * kstride];
+        // keep each k-step's work in place: a sum of a later step's operands moved up
+        // would wait for that step's load
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + 4 * (lane >> 4) + r, j = lane & 15;   // row < SW_M
-        const C o = make_float2(accR[r], accI[r]);
+        const C o = make_float2(p1[r] - p2[r], p3[r] - p1[r] - p2[r]);
         if (PH == 0) Pv[row][j] = o;
         else {
           const C y = Yv[PH == 2 ? row : 0][j];
