@@ -635,10 +635,12 @@ static kf_status gram_schmidt(kf_problem *p, int j, double2 *Vn, double2 *h1, do
   const int64_t N = p->Nxi;
   int *flag = (int *)(scal + 6);
   CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
-  // first update fused with the second pass's dot products and the norm
+  // first update fused with the norm and the first dot products of a second pass
   CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h1, Vn, N, h2, scal + 0));
   CHECK_ST(reorth_test(p, j + 1, h1, scal + 0, eta, h2, flag));
-  // second update fused with the final norm (nothing when the test declines it)
+  // the second pass (nothing when the test declines it): its remaining dot products,
+  // then the update fused with the final norm
+  CHECK_ST(multidot_rest_c128(p, p->V, j + 1, Vn, N, h2, flag));
   CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h2, Vn, N, nullptr, scal + 0, flag));
   return KF_OK;
 }

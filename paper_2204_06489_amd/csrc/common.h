@@ -249,9 +249,12 @@ kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *
                         const int *active = nullptr);
 kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w,
                          int64_t n, const int *active = nullptr);
-// w <- w - V h, then h_out = V^H w (may be NULL) and nrm_out = |w|, in one sweep over V
+// w <- w - V h, then nrm_out = |w| and the first min(nv, 8) entries of h_out = V^H w
+// (h_out may be NULL), in one sweep over V; multidot_rest_c128 gives the other entries
 kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *h, double2 *w, int64_t n,
                         double2 *h_out, double *nrm_out, const int *active = nullptr);
+kf_status multidot_rest_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_out,
+                             const int *active = nullptr);
 // DGKS test after one Gram-Schmidt pass: *flag = 1 if a second pass is needed, else h2 = 0
 kf_status reorth_test(kf_problem *p, int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2,
                       int *flag);

@@ -77,12 +77,13 @@ __global__ __launch_bounds__(RB) void k_norm2_partial(const double2 *__restrict_
   if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
 }
 
-// sum the RG partials of nq quantities in fixed order; out[q] = sum (or sqrt for norms)
+// sum the RG partials of nq quantities in fixed order; out[q] = sum (or sqrt for norms).
+// One workgroup per quantity (grid-strided), so the order of each sum is fixed.
 __global__ __launch_bounds__(RB) void k_finish(const double *__restrict__ partial, int nq, int stride, int take_sqrt,
                                                double *out, const int *active) {
   if (active && *active == 0) return;
   __shared__ double lds[8 * RB + 1];
-  for (int q = 0; q < nq; ++q) {
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
     double v[1] = {0.0};
     for (int b = threadIdx.x; b < RG; b += RB) v[0] += partial[(size_t)b * stride + q];
     block_sum<1>(v, lds);
@@ -143,8 +144,17 @@ __global__ __launch_bounds__(RB) void k_axpy_dot_partial(const double2 *__restri
       x[q] = q < nd ? V[(size_t)q * n + t] : make_double2(0.0, 0.0);
       y = csub(y, cmul(x[q], hs[q]));
     }
+    // the remaining vectors eight at a time, their loads in flight together (the
+    // subtractions keep the ascending order)
 #pragma unroll 1
-    for (int q = NQ; q < nv; ++q) y = csub(y, cmul(V[(size_t)q * n + t], hs[q]));
+    for (int q0 = NQ; q0 < nv; q0 += 8) {
+      double2 xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = q0 + u < nv ? V[(size_t)(q0 + u) * n + t] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < nv) y = csub(y, cmul(xv[u], hs[q0 + u]));
+    }
     w[t] = y;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -164,10 +174,18 @@ __global__ __launch_bounds__(RB) void k_multiaxpy(const double2 *__restrict__ V,
   if (active && *active == 0) return;
   for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)gridDim.x * RB) {
     double2 acc = w[t];
-    for (int q = 0; q < nv; ++q) {
-      double2 hq = h[q];
-      hq.x *= sign; hq.y *= sign;
-      cfma(acc, V[(size_t)q * n + t], hq);
+#pragma unroll 1
+    for (int q0 = 0; q0 < nv; q0 += 8) {   // eight loads in flight, ascending order kept
+      double2 xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = q0 + u < nv ? V[(size_t)(q0 + u) * n + t] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < nv) {
+          double2 hq = h[q0 + u];
+          hq.x *= sign; hq.y *= sign;
+          cfma(acc, xv[u], hq);
+        }
     }
     w[t] = acc;
   }
@@ -225,7 +243,7 @@ kf_status dot_c128(kf_problem *p, const double2 *a, const double2 *b, int64_t n,
   ProfScope ps(p, PROF_REDUCE);
   hipLaunchKernelGGL(k_dot_partial, dim3(RG), dim3(RB), 0, p->stream, a, b, n, p->red);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2, 2, 0, (double *)out_dev, nullptr);
+  hipLaunchKernelGGL(k_finish, dim3(2), dim3(RB), 0, p->stream, p->red, 2, 2, 0, (double *)out_dev, nullptr);
   LAUNCH_CHECK();
   return KF_OK;
 }
@@ -248,7 +266,7 @@ kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *
                        active);
     LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev, active);
+  hipLaunchKernelGGL(k_finish, dim3(2 * nv), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev, active);
   LAUNCH_CHECK();
   return KF_OK;
 }
@@ -263,7 +281,8 @@ kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 
   return KF_OK;
 }
 
-// w <- w - V h (nv vectors); then h_out = V^H w and |w| (h_out may be NULL: norm only)
+// w <- w - V h (nv vectors); then |w| and, with h_out, the first min(nv, FDOT) entries
+// of V^H w from the same sweep (the rest: multidot_rest_c128)
 kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *h, double2 *w, int64_t n,
                         double2 *h_out, double *nrm_out, const int *active) {
   ProfScope ps(p, PROF_ORTH);
@@ -278,21 +297,27 @@ kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *
   LAUNCH_CHECK();
   if (h_out) {
     const int nd = nv < FDOT ? nv : FDOT;
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 2 * nd, stride, 0, (double *)h_out, active);
+    hipLaunchKernelGGL(k_finish, dim3(2 * nd), dim3(RB), 0, p->stream, p->red, 2 * nd, stride, 0, (double *)h_out, active);
     LAUNCH_CHECK();
-    if (nv > FDOT) {   // the remaining dot products against the updated w
-      double *red2 = p->red + (size_t)RG * stride;
-      const int stride2 = 2 * nv;
-      for (int q0 = FDOT; q0 < nv; q0 += MDOT) {
-        hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, red2, stride2,
-                           active);
-        LAUNCH_CHECK();
-      }
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, red2 + 2 * FDOT, 2 * (nv - FDOT), stride2, 0,
-                         (double *)(h_out + FDOT), active);
-      LAUNCH_CHECK();
-    }
   }
+  return KF_OK;
+}
+
+// h_out[q] = V_q^H w for FDOT <= q < nv (the entries the fused sweep does not carry)
+kf_status multidot_rest_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_out,
+                             const int *active) {
+  ProfScope ps(p, PROF_ORTH);
+  if (nv <= FDOT) return KF_OK;
+  double *red2 = p->red + (size_t)RG * (2 * FDOT + 1);
+  const int stride2 = 2 * nv;
+  for (int q0 = FDOT; q0 < nv; q0 += MDOT) {
+    hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, red2, stride2,
+                       active);
+    LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_finish, dim3(2 * (nv - FDOT)), dim3(RB), 0, p->stream, red2 + 2 * FDOT, 2 * (nv - FDOT), stride2,
+                     0, (double *)(h_out + FDOT), active);
+  LAUNCH_CHECK();
   return KF_OK;
 }
 
