@@ -1167,26 +1167,35 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   }
 }
 
-// Chunk sweeps of complex64 solves on the matrix cores (columns up to SW_M = 144 rows).
+// Chunk sweeps of complex64 solves on the matrix cores (columns up to 144 TPW rows).
 // Item (chunk, side, tile of SW_S = 16 sources).  Each step is the product of the m x m
 // block T_i with an m x 16 right-hand side, as v_mfma_f32_16x16x4f32 tiles: wave w owns
-// rows 16 w .. 16 w + 15 and holds its A operand (T_i's rows, all columns) in registers,
-// fetched for the next column while the current one is multiplied (the blocks do not
-// depend on the chain).  A complex product is three real ones (Gauss):
+// the row tiles w + 9 x (x < TPW).  With one tile per wave the wave holds its A operand
+// (T_i's rows, all columns) in registers, fetched for the next column while the current
+// one is multiplied (the blocks do not depend on the chain); with two, a ring of SW_D
+// k-steps per tile runs SW_D k-steps ahead, into the next column at the end of a step.
+// A complex product is three real ones (Gauss):
 //   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi);  Re = P1 - P2,  Im = P3 - P1 - P2.
 // Operand layout of the 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
 // j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
 // Per step: (a) all threads, coalesced over rows: store the previous column's result
 // from LDS, form the right-hand side in LDS (forward: b_i - C y_prev; back-substitution:
-// C x_prev, with y_i staged beside it); (b) each wave: its 16 x 16 tile of T_i times the
+// C x_prev, with y_i staged beside it); (b) each wave: its 16 x 16 tiles of T_i times the
 // right-hand side, the result (forward: y_i; back-substitution: y_i - product) to LDS.
-constexpr int SW_M = 144, SW_S = 16, SW_KS = SW_M / 4, SW_T = 576;   // rows, sources, k-steps, threads
-template <int PH>   // 0: forward sweep, 2: back-substitution
+constexpr int SW_S = 16, SW_T = 576, SW_D = 8;   // sources, threads, ring depth
+template <int TPW> struct SweepShape {
+  static constexpr int M = 144 * TPW, KS = M / 4, NA = M * SW_S / SW_T;   // rows, k-steps, slots per thread
+};
+template <int PH, int TPW>   // PH 0: forward sweep, 2: back-substitution
+size_t sweep_mfma_lds() { return (size_t)(PH == 2 ? 3 : 2) * SweepShape<TPW>::M * (SW_S + 1) * sizeof(float2); }
+template <int PH, int TPW>
 __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   using C = float2;
-  __shared__ C Bv[SW_M][SW_S + 1];    // right-hand side of the step (B operand)
-  __shared__ C Pv[SW_M][SW_S + 1];    // the previous column's result
-  __shared__ C Yv[PH == 2 ? SW_M : 1][SW_S + 1];   // y_i (back-substitution)
+  constexpr int SWM = SweepShape<TPW>::M, KS = SweepShape<TPW>::KS, NA = SweepShape<TPW>::NA;
+  extern __shared__ unsigned char smem_raw[];
+  C(*Bv)[SW_S + 1] = (C(*)[SW_S + 1])smem_raw;   // right-hand side of the step (B operand)
+  C(*Pv)[SW_S + 1] = Bv + SWM;                    // the previous column's result
+  C(*Yv)[SW_S + 1] = Pv + SWM;                    // y_i (back-substitution only)
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
@@ -1208,18 +1217,16 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   };
   auto cc_of = [&](int i) { return PH == 0 ? (side == 0 ? i : i + 1) : (side == 0 ? i + 1 : i); };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = 16 * wave;
-  // phase (a) slots: e = tid + SW_T u -> (row e % SW_M, source e / SW_M)
-  constexpr int NA = SW_M * SW_S / SW_T;
-  // per slot: offset of (source, row) in the column-major copy (column 0), and the
-  // row's coupling factor zn[row] (-1 / h^2); the column's factor ixh[i] is uniform
+  // phase (a) slots: e = tid + SW_T u -> (row e % SWM, source e / SWM); per slot the
+  // offset of (source, row) in the column-major copy (column 0), and the row's coupling
+  // factor zn[row] (-1 / h^2); the column's factor ixh[i] is uniform
   size_t aoff[NA];
   C zf[NA];
   bool aok[NA];
   const double ih2 = -1.0 / (g.h * g.h);
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
-    const int e = tid + SW_T * u, r = e % SW_M, j = e / SW_M;
+    const int e = tid + SW_T * u, r = e % SWM, j = e / SWM;
     aok[u] = r < m && s0 + j < K;
     aoff[u] = (size_t)min(s0 + j, K - 1) * g.nx * m + min(r, m - 1);
     const double2 z = g.zn[min(r, m - 1)];
@@ -1227,19 +1234,24 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   }
   C *const Xb = (C *)pp.x;
   auto xaddr = [&](int u, int i) { return Xb + aoff[u] + (size_t)i * m; };
-  auto slot_r = [&](int u) { return (tid + SW_T * u) % SW_M; };
-  auto slot_j = [&](int u) { return (tid + SW_T * u) / SW_M; };
-  // A operand of column i: lane (i', k') = (lane % 16, lane / 16) of k-step ks holds
-  // T_i[r0 + i'][4 ks + k'] (column-major block: rows contiguous).  Every wave runs all
-  // SW_KS k-steps (rows past m are clamped to row m - 1, k-steps past the last one
-  // repeat it: the right-hand side is zero there), so the loads are unconditional and
-  // the wait counts stay exact across the loop.  The last k-step reads up to three
-  // columns beyond the block: the next block, or the zero padding after the last one.
-  C areg[SW_KS];
-  const int arw = min(r0 + (lane & 15), m - 1), akq = lane >> 4;
+  auto slot_r = [&](int u) { return (tid + SW_T * u) % SWM; };
+  auto slot_j = [&](int u) { return (tid + SW_T * u) / SWM; };
+  // A operand of column i, tile x: lane (i', k') = (lane % 16, lane / 16) of k-step ks
+  // holds T_i[16 (wave + 9 x) + i'][4 ks + k'] (column-major block: rows contiguous).
+  // Every wave runs all KS k-steps (rows past m are clamped to row m - 1, k-steps past
+  // the last one repeat it: the right-hand side is zero there), so the loads are
+  // unconditional and the wait counts stay exact across the loop.  The last k-step reads
+  // up to three columns beyond the block: the next block, or the zero padding after the
+  // last one.
+  const int akq = lane >> 4;
+  int arw[TPW];
+#pragma unroll
+  for (int x = 0; x < TPW; ++x) arw[x] = min(16 * (wave + 9 * x) + (lane & 15), m - 1);
   const int ksl = (m - 1) / 4;
   const size_t kstride = 4 * (size_t)m;
-  auto a_base = [&](int i) { return T + (size_t)i * mm + (size_t)akq * m + arw; };
+  auto a_base = [&](int i, int x) { return T + (size_t)i * mm + (size_t)akq * m + arw[x]; };
+  constexpr int NREG = TPW == 1 ? KS : SW_D;   // k-steps held per tile
+  C areg[NREG][TPW];
   // right-hand-side values of the next step, held in registers
   C bnext[NA];
   if (PH == 2) {   // x_mid into Pv
@@ -1261,10 +1273,11 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   // factor of the next step is fetched with the next right-hand side, ahead of the
   // block's loads
   double2 xh = g.ixh[PH == 2 ? cc_of(col_of(0)) : col_of(0)];
-  {
-    const C *ap = a_base(col_of(0));
 #pragma unroll
-    for (int ks = 0; ks < SW_KS; ++ks) areg[ks] = ap[min(ks, ksl) * kstride];
+  for (int x = 0; x < TPW; ++x) {
+    const C *ap = a_base(col_of(0), x);
+#pragma unroll
+    for (int ks = 0; ks < NREG; ++ks) areg[ks][x] = ap[min(ks, ksl) * kstride];
   }
   for (int t = 0; t < cnt; ++t) {
     const int i = col_of(t);
@@ -1282,7 +1295,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
       if (PH == 0) rhs = t > 0 ? make_float2(bv.x - cp.x, bv.y - cp.y) : bv;
       else {
         rhs = cp;
-        Yv[PH == 2 ? r : 0][j] = aok[u] ? bv : make_float2(0.f, 0.f);
+        Yv[r][j] = aok[u] ? bv : make_float2(0.f, 0.f);
       }
       Bv[r][j] = aok[u] ? rhs : make_float2(0.f, 0.f);
     }
@@ -1293,35 +1306,60 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
       xh = g.ixh[cc_of(in)];
     }
     __syncthreads();
-    // (b) the wave's 16 x 16 tile of T_i times the right-hand side (waves past the last
-    //     row tile compute copies of row m - 1 into rows >= m, which nothing reads),
-    //     the next column's block fetched as the current one is consumed (the last
-    //     step fetches its own block again)
+    // (b) the wave's 16 x 16 tiles of T_i times the right-hand side (rows past m are
+    //     copies of row m - 1, which nothing reads), the blocks fetched ahead as they
+    //     are consumed (the last step fetches its own block again)
     {
-      floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
-      const C *an = a_base(t + 1 < cnt ? col_of(t + 1) : i);
+      floatx4 p1[TPW], p2[TPW], p3[TPW];
 #pragma unroll
-      for (int ks = 0; ks < SW_KS; ++ks) {
-        const C a = areg[ks];
-        const C b = Bv[4 * ks + akq][lane & 15];
-        p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1, 0, 0, 0);
-        p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2, 0, 0, 0);
-        p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, p3, 0, 0, 0);
-        areg[ks] = an[min(ks, ksl) * kstride];
-        // keep each k-step's work in place: a sum of a later step's operands moved up
-        // would wait for that step's load
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      for (int x = 0; x < TPW; ++x) p1[x] = p2[x] = p3[x] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int inext = t + 1 < cnt ? col_of(t + 1) : i;
+      const C *ac[TPW], *an[TPW];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + 4 * (lane >> 4) + r, j = lane & 15;   // row < SW_M
-        const C o = make_float2(p1[r] - p2[r], p3[r] - p1[r] - p2[r]);
-        if (PH == 0) Pv[row][j] = o;
-        else {
-          const C y = Yv[PH == 2 ? row : 0][j];
-          Pv[row][j] = make_float2(y.x - o.x, y.y - o.y);
+      for (int x = 0; x < TPW; ++x) { ac[x] = a_base(i, x); an[x] = a_base(inext, x); }
+      if constexpr (TPW == 1) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const C a = areg[ks][0];
+          const C b = Bv[4 * ks + akq][lane & 15];
+          p1[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1[0], 0, 0, 0);
+          p2[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2[0], 0, 0, 0);
+          p3[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, p3[0], 0, 0, 0);
+          areg[ks][0] = an[0][min(ks, ksl) * kstride];   // the next column's k-step
+          // keep each k-step's work in place: a sum of a later step's operands moved up
+          // would wait for that step's load
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const C b = Bv[4 * ks + akq][lane & 15];
+          const float bs = b.x + b.y;
+#pragma unroll
+          for (int x = 0; x < TPW; ++x) {
+            const C a = areg[ks % NREG][x];
+            p1[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1[x], 0, 0, 0);
+            p2[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2[x], 0, 0, 0);
+            p3[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, bs, p3[x], 0, 0, 0);
+            // refill: k-step ks + NREG of this column, else of the next one
+            const int kn = ks + NREG;
+            areg[ks % NREG][x] = kn < KS ? ac[x][min(kn, ksl) * kstride] : an[x][min(kn - KS, ksl) * kstride];
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
+#pragma unroll
+      for (int x = 0; x < TPW; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (wave + 9 * x) + 4 * (lane >> 4) + r, j = lane & 15;   // row < SWM
+          const C o = make_float2(p1[x][r] - p2[x][r], p3[x][r] - p1[x][r] - p2[x][r]);
+          if (PH == 0) Pv[row][j] = o;
+          else {
+            const C y = Yv[row][j];
+            Pv[row][j] = make_float2(y.x - o.x, y.y - o.y);
+          }
+        }
     }
     __syncthreads();
   }
@@ -1797,8 +1835,20 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   for (int lv = top_max - 1; lv >= 0; --lv) seq.push_back({4, 32 + lv});
   seq.push_back({5, 0});
   static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
-  // complex64 chunk sweeps on the matrix cores where the columns fit the kernel
-  const bool mfma_sweeps = fp32 && m_max <= SW_M;
+  // complex64 chunk sweeps on the matrix cores where the columns fit the kernel (one
+  // row tile per wave up to 144 rows, two up to 288)
+  const bool mfma_sweeps = fp32 && m_max <= SweepShape<2>::M;
+  const bool sweep_wide = m_max > SweepShape<1>::M;
+  if (mfma_sweeps) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<0, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_mfma_lds<0, 1>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_mfma_lds<2, 1>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<0, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_mfma_lds<0, 2>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<2, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_mfma_lds<2, 2>()));
+  }
   for (const auto &e : seq) {
     const int ph = e.first, kind = e.second >> 4, lv = e.second & 15;
     int tot = 0;
@@ -1833,12 +1883,18 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
     ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
     switch (ph) {
       case 0:
-        if (mfma_sweeps) hipLaunchKernelGGL(k_sweep_mfma<0>, dim3(grid), dim3(SW_T), 0, s, bt);
+        if (mfma_sweeps && sweep_wide)
+          hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 2>()), s, bt);
+        else if (mfma_sweeps)
+          hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 1>()), s, bt);
         else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
         break;
       case 1: hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt); break;
       case 2:
-        if (mfma_sweeps) hipLaunchKernelGGL(k_sweep_mfma<2>, dim3(grid), dim3(SW_T), 0, s, bt);
+        if (mfma_sweeps && sweep_wide)
+          hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 2>()), s, bt);
+        else if (mfma_sweeps)
+          hipLaunchKernelGGL((k_sweep_mfma<2, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 1>()), s, bt);
         else hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
         break;
       case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
