@@ -127,8 +127,8 @@ def roofline_for(name, p, launches, total_ms):
         peak = FP32_PEAK_TFLOPS if dt == "f32" else FP64_PEAK_TFLOPS
         # complex64 sweeps and the interior correction run on the matrix cores (dense
         # FP32 MFMA peak); the FP64 sweeps on the vector units (FP64 vector peak)
-        # (the matrix-core sweeps take columns of up to 144 rows)
-        bound = "mfma" if name == "blu_correct" or (name in MFMA_KERNELS and p.nz <= 144) else "alu"
+        # (the matrix-core sweeps take columns of up to 288 rows)
+        bound = "mfma" if name == "blu_correct" or (name in MFMA_KERNELS and p.nz <= 288) else "alu"
         out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     out.update({"frac": achieved / peak, "traffic": None, "kernel": name, "launches": launches,
                 "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount, "work_unit": unit})

@@ -7,7 +7,7 @@ namespace {
 
 constexpr int RB = 256;      // reduction block size (4 wavefronts)
 constexpr int RG = 1024;     // reduction grid size (fixed => fixed summation order)
-constexpr int MDOT = 8;      // vectors per multi-dot pass
+constexpr int MDOT = 16;     // vectors per multi-dot pass
 constexpr int FDOT = 8;      // dot products carried by the fused update-and-dot pass
 
 __device__ inline double wave_sum(double v) {
