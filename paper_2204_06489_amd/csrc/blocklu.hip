@@ -1076,12 +1076,12 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   const C *V = (const C *)pp.V, *W = (const C *)pp.W;
   const int s0 = st * CM_S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NB = CM_K * CM_S / 256;   // B elements per thread and slab
-  // load slots: A element (row R0 + (e & 127), k e >> 7), B element (k e & 15, source e >> 4)
-  int a_col[8], a_j[8], a_kk[8];
-  bool a_ok[8];
+  constexpr int NA = CM_K * CM_R / 256, NB = CM_K * CM_S / 256;   // A, B elements per thread and slab
+  // load slots: A element (row R0 + (e % CM_R), k e / CM_R), B element (k e % CM_K, source e / CM_K)
+  int a_col[NA], a_j[NA], a_kk[NA];
+  bool a_ok[NA];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < NA; ++u) {
     const int e = tid + 256 * u, rr = e & 127;
     const int row = min(R0 + rr, rows - 1);
     a_kk[u] = e >> 7;
@@ -1089,9 +1089,9 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
     a_col[u] = ch.a + row / m;
     a_j[u] = row % m;
   }
-  auto load_slab = [&](int kb, C (&ra)[8], C (&rb)[NB]) {
+  auto load_slab = [&](int kb, C (&ra)[NA], C (&rb)[NB]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < NA; ++u) {
       const int l = kb + a_kk[u], lc = min(l, lk1 - 1);
       const size_t base = (size_t)a_col[u] * mm + (size_t)(lc < m ? lc : lc - m) * m + a_j[u];
       const C v = lc < m ? V[base] : W[base];
@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int e = tid + 256 * u, l = kb + (e & 15), sidx = s0 + (e >> 4);
+      const int e = tid + 256 * u, l = kb + e % CM_K, sidx = s0 + e / CM_K;
       const int lc = min(l, lk1 - 1), k = min(sidx, K - 1);
       const C v = colp<float>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
       rb[u] = (l < lk1 && sidx < K) ? v : make_float2(0.f, 0.f);
@@ -1110,15 +1110,15 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 3; ++y) p1[x][y] = p2[x][y] = p3[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-  C ra[8], rb[NB];
+  C ra[NA], rb[NB];
   load_slab(lk0, ra, rb);
   for (int kb = lk0; kb < lk1; kb += CM_K) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) As[a_kk[u]][(tid + 256 * u) & 127] = ra[u];
+    for (int u = 0; u < NA; ++u) As[a_kk[u]][(tid + 256 * u) & 127] = ra[u];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int e = tid + 256 * u;
-      Bs[e & 15][e >> 4] = rb[u];
+      Bs[e % CM_K][e / CM_K] = rb[u];
     }
     __syncthreads();
     if (kb + CM_K < lk1) load_slab(kb + CM_K, ra, rb);   // in flight during the products
@@ -1156,13 +1156,30 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
         Out[16 * y + (lane & 15)][wave * 32 + 16 * x + 4 * (lane >> 4) + r] =
             make_float2(p1[x][y][r] - p2[x][y][r], p3[x][y][r] - p1[x][y][r] - p2[x][y][r]);
   __syncthreads();
-  for (int e = tid; e < CM_S * CM_R; e += 256) {
-    const int sidx = e / CM_R, rr = e - sidx * CM_R;
-    const int row = R0 + rr, k = s0 + sidx;
-    if (row < rows && k < K) {
-      C *d = colp<float>(pp.x, g, k, ch.a + row / m) + (row % m);
+  // eight updates at a time: their loads go out together (one latency per eight)
+  constexpr int EU = 8, NE = CM_S * CM_R / 256;
+  static_assert(NE % EU == 0, "epilogue batches");
+#pragma unroll 1
+  for (int e0 = 0; e0 < NE; e0 += EU) {
+    C *d[EU];
+    C old[EU];
+    bool ok[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int e = tid + 256 * (e0 + u);
+      const int sidx = e / CM_R, rr = e - sidx * CM_R;
+      const int row = R0 + rr, k = s0 + sidx;
+      ok[u] = row < rows && k < K;
+      const int rc = min(row, rows - 1);
+      d[u] = colp<float>(pp.x, g, min(k, K - 1), ch.a + rc / m) + (rc % m);
+      old[u] = *d[u];
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int e = tid + 256 * (e0 + u);
+      const int sidx = e / CM_R, rr = e - sidx * CM_R;
       const C o = Out[sidx][rr];
-      *d = make_float2(d->x - o.x, d->y - o.y);
+      if (ok[u]) *d[u] = make_float2(old[u].x - o.x, old[u].y - o.y);
     }
   }
 }
