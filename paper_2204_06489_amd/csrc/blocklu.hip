@@ -1203,7 +1203,7 @@ constexpr int SW_S = 16, SW_T = 576, SW_D = 8;   // sources, threads, ring depth
 template <int TPW> struct SweepShape {
   static constexpr int M = 144 * TPW, KS = M / 4, NA = M * SW_S / SW_T;   // rows, k-steps, slots per thread
 };
-template <int PH, int TPW>   // PH 0: forward sweep, 2: back-substitution
+template <int PH, int TPW>   // PH 0: forward sweep, 1: chunk middles, 2: back-substitution
 size_t sweep_mfma_lds() { return (size_t)(PH == 2 ? 3 : 2) * SweepShape<TPW>::M * (SW_S + 1) * sizeof(float2); }
 template <int PH, int TPW>
 __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
@@ -1220,17 +1220,19 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   const int local = item - bt.first[q];
   const int ST = (pp.K + SW_S - 1) / SW_S;
   const int st = local % ST, rest = local / ST;
-  const Chunk ch = chunk_of(pp.part, rest >> 1);
-  const int side = rest & 1;
+  // item: (chunk, side, source tile); the middles (PH 1) have no side
+  const Chunk ch = chunk_of(pp.part, PH == 1 ? rest : rest >> 1);
+  const int side = PH == 1 ? 0 : rest & 1;
   const Grid &g = pp.g;
   const int m = g.nz, K = pp.K, s0 = st * SW_S;
   const size_t mm = (size_t)m * m;
   const C *T = (const C *)pp.T;
-  const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+  const int cnt = PH == 1 ? 1 : side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
   if (cnt <= 0) return;   // uniform over the workgroup
   // column of step t and the coupling column to the previous one
   auto col_of = [&](int t) {
-    return PH == 0 ? (side == 0 ? ch.a + t : ch.b - t) : (side == 0 ? ch.mid - 1 - t : ch.mid + 1 + t);
+    return PH == 1 ? ch.mid
+                   : PH == 0 ? (side == 0 ? ch.a + t : ch.b - t) : (side == 0 ? ch.mid - 1 - t : ch.mid + 1 + t);
   };
   auto cc_of = [&](int i) { return PH == 0 ? (side == 0 ? i : i + 1) : (side == 0 ? i + 1 : i); };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1290,6 +1292,18 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   // factor of the next step is fetched with the next right-hand side, ahead of the
   // block's loads
   double2 xh = g.ixh[PH == 2 ? cc_of(col_of(0)) : col_of(0)];
+  // the middle's neighbours y_{mid-1}, y_{mid+1} (PH 1; zero where the chunk has none)
+  C ym[PH == 1 ? NA : 1], yp[PH == 1 ? NA : 1];
+  double2 xh2 = make_double2(0.0, 0.0);
+  if (PH == 1) {
+    const bool hl = ch.mid > ch.a, hr = ch.mid < ch.b;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      ym[u] = hl ? *xaddr(u, ch.mid - 1) : make_float2(0.f, 0.f);
+      yp[u] = hr ? *xaddr(u, ch.mid + 1) : make_float2(0.f, 0.f);
+    }
+    xh2 = g.ixh[ch.mid + 1];
+  }
 #pragma unroll
   for (int x = 0; x < TPW; ++x) {
     const C *ap = a_base(col_of(0), x);
@@ -1310,7 +1324,15 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
       const C bv = bnext[u];
       C rhs;
       if (PH == 0) rhs = t > 0 ? make_float2(bv.x - cp.x, bv.y - cp.y) : bv;
-      else {
+      else if (PH == 1) {
+        // b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}
+        const C xf2 = make_float2((float)xh2.x, (float)xh2.y);
+        const C cl = cj;
+        const C cr = make_float2(zf[u].x * xf2.x - zf[u].y * xf2.y, zf[u].x * xf2.y + zf[u].y * xf2.x);
+        const C tl = make_float2(cl.x * ym[u].x - cl.y * ym[u].y, cl.x * ym[u].y + cl.y * ym[u].x);
+        const C tr = make_float2(cr.x * yp[u].x - cr.y * yp[u].y, cr.x * yp[u].y + cr.y * yp[u].x);
+        rhs = make_float2(bv.x - tl.x - tr.x, bv.y - tl.y - tr.y);
+      } else {
         rhs = cp;
         Yv[r][j] = aok[u] ? bv : make_float2(0.f, 0.f);
       }
@@ -1371,7 +1393,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (wave + 9 * x) + 4 * (lane >> 4) + r, j = lane & 15;   // row < SWM
           const C o = make_float2(p1[x][r] - p2[x][r], p3[x][r] - p1[x][r] - p2[x][r]);
-          if (PH == 0) Pv[row][j] = o;
+          if (PH != 2) Pv[row][j] = o;
           else {
             const C y = Yv[row][j];
             Pv[row][j] = make_float2(y.x - o.x, y.y - o.y);
@@ -1865,6 +1887,10 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                                 (int)sweep_mfma_lds<0, 2>()));
     HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<2, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sweep_mfma_lds<2, 2>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_mfma_lds<1, 1>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_mfma_lds<1, 2>()));
   }
   for (const auto &e : seq) {
     const int ph = e.first, kind = e.second >> 4, lv = e.second & 15;
@@ -1878,7 +1904,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       bt.first[q] = tot;
       int items = 0;
       if (ph == 0 || ph == 2) items = 2 * p->P * (mfma_sweeps ? (p->K + SW_S - 1) / SW_S : G);
-      else if (ph == 1) items = p->P * G;
+      else if (ph == 1) items = p->P * (mfma_sweeps ? (p->K + SW_S - 1) / SW_S : G);
       else if (ph == 3) items = n * G;
       else if (ph == 4) {
         if (n >= 1) {
@@ -1906,7 +1932,13 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
           hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 1>()), s, bt);
         else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
         break;
-      case 1: hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt); break;
+      case 1:
+        if (mfma_sweeps && sweep_wide)
+          hipLaunchKernelGGL((k_sweep_mfma<1, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 2>()), s, bt);
+        else if (mfma_sweeps)
+          hipLaunchKernelGGL((k_sweep_mfma<1, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 1>()), s, bt);
+        else hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
+        break;
       case 2:
         if (mfma_sweeps && sweep_wide)
           hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 2>()), s, bt);
