@@ -828,39 +828,82 @@ __device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, vo
 
 // 4: one level of the separators' cyclic reduction for NS sources: the value at column
 //    out is set to (keep ? old value : 0) + M_0 x(col_0) - M_1 x(col_1) - M_2 x(col_2),
-//    absent terms (NULL M_t) skipped.
+//    absent terms (NULL M_t) skipped.  A level is a handful of matvecs per workgroup, so
+//    its cost is the depth of dependent loads: the workgroup is flat, thread t owning row
+//    t mod m of column group t / m (up to 16 groups, 7 at m = 141 with 1024 threads), each
+//    group walking a short range of every term's columns in blocks of 8 loads; the
+//    signed vectors of all terms are staged in one round, and the terms accumulate into
+//    one sum reduced once over the groups.
 template <typename R, int NS>
 __device__ __forceinline__ void cr_terms(const Grid &g, int K, void *X, int group, const cplx<R> *const *M,
                                          const int *col, int out, bool keep, unsigned char *smem) {
   using C = cplx<R>;
-  const int m = g.nz;
-  C *w = (C *)smem;
-  C *part = w + 2 * NS * m;
-  const int j = threadIdx.x;
-  const bool owner = threadIdx.y == 0 && j < m;
+  constexpr int MV_U = 8;
+  const int m = g.nz, nt = blockDim.x, tid = threadIdx.x;
+  const int G = min(nt / m, 16);
+  const int j = tid % m, gy = tid / m;
   const int k0 = group * NS;
-  C tot[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s)
-    tot[s] = (owner && keep && k0 + s < K) ? colp<R>(X, g, k0 + s, out)[j] : mk<R>(0, 0);
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {   // term 0 adds, terms 1 and 2 subtract
-    if (!M[t]) continue;            // uniform over the workgroup
-    if (owner)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) w[s * m + j] = k0 + s < K ? colp<R>(X, g, k0 + s, col[t])[j] : mk<R>(0, 0);
-    __syncthreads();
-    C acc[NS];
-    col_matvec<R, NS>(M[t], m, w, part, acc);
-    if (owner)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) tot[s] = t == 0 ? cadd(tot[s], acc[s]) : csub(tot[s], acc[s]);
-    __syncthreads();
+  C *w = (C *)smem;            // [nterm][NS][m] signed vectors of the present terms
+  C *part = w + 3 * NS * m;    // [G-1][NS][m] partial sums
+  const C *Mc0 = M[0] ? M[0] : (M[1] ? M[1] : M[2]);
+  const C *Mc1 = M[0] ? (M[1] ? M[1] : M[2]) : M[2];
+  const C *Mc2 = M[2];
+  const int cl0 = M[0] ? col[0] : (M[1] ? col[1] : col[2]);
+  const int cl1 = M[0] ? (M[1] ? col[1] : col[2]) : col[2];
+  const int cl2 = col[2];
+  const int nterm = (M[0] != nullptr) + (M[1] != nullptr) + (M[2] != nullptr);
+  const bool first_adds = M[0] != nullptr;   // term 0 adds, the others subtract
+  for (int e = tid; e < nterm * NS * m; e += nt) {
+    const int c = e / (NS * m), rem = e - c * NS * m, sidx = rem / m, r = rem - sidx * m;
+    const int cl = c == 0 ? cl0 : c == 1 ? cl1 : cl2;
+    const C v = k0 + sidx < K ? colp<R>(X, g, k0 + sidx, cl)[r] : mk<R>(0, 0);
+    w[e] = (c == 0 && first_adds) ? v : mk<R>(-v.x, -v.y);
   }
-  if (owner)
+  __syncthreads();
+  C acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = mk<R>(0, 0);
+  if (gy < G) {
+    const int chunk = (m + G - 1) / G;
+    const int l0 = gy * chunk, l1 = min(m, l0 + chunk);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c >= nterm) break;   // uniform
+      const C *Mt = c == 0 ? Mc0 : c == 1 ? Mc1 : Mc2;
+      const C *wt = w + c * NS * m;
+      for (int lb = l0; lb < l1; lb += MV_U) {
+        C t[MV_U];
+#pragma unroll
+        for (int u = 0; u < MV_U; ++u) t[u] = Mt[(size_t)min(lb + u, l1 - 1) * m + j];
+#pragma unroll
+        for (int u = 0; u < MV_U; ++u) {
+          const bool in = lb + u < l1;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const C wv = wt[s * m + min(lb + u, l1 - 1)];
+            cfma(acc[s], t[u], in ? wv : mk<R>(0, 0));
+          }
+        }
+      }
+    }
+  }
+  if (G > 1) {
+    if (gy > 0 && gy < G)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) part[((gy - 1) * NS + s) * m + j] = acc[s];
+    __syncthreads();
+    if (gy == 0)
+      for (int q = 1; q < G; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = cadd(acc[s], part[((q - 1) * NS + s) * m + j]);
+  }
+  if (gy == 0)
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (k0 + s < K) colp<R>(X, g, k0 + s, out)[j] = tot[s];
+      if (k0 + s < K) {
+        C *d = colp<R>(X, g, k0 + s, out) + j;
+        *d = keep ? cadd(*d, acc[s]) : acc[s];
+      }
 }
 
 __host__ __device__ inline int cr_top(int n) {   // floor(log2 n), n >= 1
@@ -1854,8 +1897,9 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
     HIP_TRY(hipFuncSetAttribute((const void *)k_solve<R, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   }
   constexpr int NSC = CrSources<R, NS>::N;
-  const dim3 blkc = sweep_block(m_max, SolveThreadsCR<R, NSC>::N);
-  const size_t smemc = (2 + (blkc.y - 1)) * NSC * (size_t)m_max * sizeof(cplx<R>);
+  // the reduction's levels: flat workgroups (row, column group), see cr_terms
+  const dim3 blkc(SolveThreadsCR<R, NSC>::N);
+  const size_t smemc = (3 * (size_t)m_max + SolveThreadsCR<R, NSC>::N) * NSC * sizeof(cplx<R>);
   if (smemc > 65536) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NSC, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemc));
     HIP_TRY(hipFuncSetAttribute((const void *)k_cr_solve<R, NSC, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smemc));
