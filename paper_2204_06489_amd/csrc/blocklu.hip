@@ -1918,11 +1918,13 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   for (int lv = top_max - 1; lv >= 0; --lv) seq.push_back({4, 32 + lv});
   seq.push_back({5, 0});
   static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
-  // complex64 chunk sweeps on the matrix cores where the columns fit the kernel (one
-  // row tile per wave up to 144 rows, two up to 288)
-  const bool mfma_sweeps = fp32 && m_max <= SweepShape<2>::M;
-  const bool sweep_wide = m_max > SweepShape<1>::M;
-  if (mfma_sweeps) {
+  // complex64 chunk sweeps and middles on the matrix cores where the columns fit the
+  // kernel (one row tile per wave up to 144 rows, two up to 288); in a batch each problem
+  // takes its own kind: sweep group 0 (one tile), 1 (two tiles), 2 (vector units)
+  auto sweep_group = [&](const kf_problem *p) {
+    return !fp32 ? 2 : p->nz <= SweepShape<1>::M ? 0 : p->nz <= SweepShape<2>::M ? 1 : 2;
+  };
+  if (fp32) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<0, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sweep_mfma_lds<0, 1>()));
     HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1938,69 +1940,71 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   }
   for (const auto &e : seq) {
     const int ph = e.first, kind = e.second >> 4, lv = e.second & 15;
-    int tot = 0;
-    double cost[KF_BATCH_MAX];
-    for (int q = 0; q < bt.n; ++q) {
-      const kf_problem *p = ps[q];
-      const int G = (p->K + (ph == 4 ? NSC : NS) - 1) / (ph == 4 ? NSC : NS), n = p->P - 1;
-      const double m = p->nz, L = (double)p->nx / p->P;
-      cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 5 ? m : m * m;
-      bt.first[q] = tot;
-      int items = 0;
-      if (ph == 0 || ph == 2) items = 2 * p->P * (mfma_sweeps ? (p->K + SW_S - 1) / SW_S : G);
-      else if (ph == 1) items = p->P * (mfma_sweeps ? (p->K + SW_S - 1) / SW_S : G);
-      else if (ph == 3) items = n * G;
-      else if (ph == 4) {
-        if (n >= 1) {
-          const int top = cr_top(n);
-          if (kind == 0 && lv < top) items = (n >> (lv + 1)) * G;
-          else if (kind == 1) items = G;
-          else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * G;
+    // phases 0-2 run once per sweep group (problems of other groups get no items)
+    for (int sg = (ph <= 2 ? 0 : -1); sg <= (ph <= 2 ? 2 : -1); ++sg) {
+      int tot = 0;
+      double cost[KF_BATCH_MAX];
+      for (int q = 0; q < bt.n; ++q) {
+        const kf_problem *p = ps[q];
+        const int G = (p->K + (ph == 4 ? NSC : NS) - 1) / (ph == 4 ? NSC : NS), n = p->P - 1;
+        const int STs = (p->K + SW_S - 1) / SW_S;
+        const double m = p->nz, L = (double)p->nx / p->P;
+        cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 5 ? m : m * m;
+        bt.first[q] = tot;
+        int items = 0;
+        if (ph <= 2 && sweep_group(p) != sg) items = 0;
+        else if (ph == 0 || ph == 2) items = 2 * p->P * (sg < 2 ? STs : G);
+        else if (ph == 1) items = p->P * (sg < 2 ? STs : G);
+        else if (ph == 3) items = n * G;
+        else if (ph == 4) {
+          if (n >= 1) {
+            const int top = cr_top(n);
+            if (kind == 0 && lv < top) items = (n >> (lv + 1)) * G;
+            else if (kind == 1) items = G;
+            else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * G;
+          }
+        } else if (p->P > 1) {
+          items = p->P * (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
+                               : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S));
         }
-      } else if (p->P > 1) {
-        items = p->P * (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
-                             : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S));
+        tot += items;
       }
-      tot += items;
+      bt.first[bt.n] = bt.total = tot;
+      bt.level = lv;
+      if (tot == 0) continue;
+      const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
+      ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
+      switch (ph) {
+        case 0:
+          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 2>()), s, bt);
+          else if (sg == 0)
+            hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 1>()), s, bt);
+          else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
+          break;
+        case 1:
+          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<1, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 2>()), s, bt);
+          else if (sg == 0)
+            hipLaunchKernelGGL((k_sweep_mfma<1, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 1>()), s, bt);
+          else hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
+          break;
+        case 2:
+          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 2>()), s, bt);
+          else if (sg == 0)
+            hipLaunchKernelGGL((k_sweep_mfma<2, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 1>()), s, bt);
+          else hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
+          break;
+        case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
+        case 4:
+          if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
+          else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
+          else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);
+          break;
+        default:
+          if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
+          else hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
+      }
+      LAUNCH_CHECK();
     }
-    bt.first[bt.n] = bt.total = tot;
-    bt.level = lv;
-    if (tot == 0) continue;
-    const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
-    ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
-    switch (ph) {
-      case 0:
-        if (mfma_sweeps && sweep_wide)
-          hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 2>()), s, bt);
-        else if (mfma_sweeps)
-          hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 1>()), s, bt);
-        else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
-        break;
-      case 1:
-        if (mfma_sweeps && sweep_wide)
-          hipLaunchKernelGGL((k_sweep_mfma<1, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 2>()), s, bt);
-        else if (mfma_sweeps)
-          hipLaunchKernelGGL((k_sweep_mfma<1, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 1>()), s, bt);
-        else hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
-        break;
-      case 2:
-        if (mfma_sweeps && sweep_wide)
-          hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 2>()), s, bt);
-        else if (mfma_sweeps)
-          hipLaunchKernelGGL((k_sweep_mfma<2, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 1>()), s, bt);
-        else hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
-        break;
-      case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
-      case 4:
-        if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
-        else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
-        else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);
-        break;
-      default:
-        if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
-        else hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
-    }
-    LAUNCH_CHECK();
   }
   return KF_OK;
 }

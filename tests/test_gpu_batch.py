@@ -100,3 +100,28 @@ def test_problems_work_alone_after_their_batch_is_destroyed():
         xi, _, st = g.newton_step(d, rtol=1e-11, restart=15, maxit=300, pc="exact", update_in_place=False)
         assert st["converged"]
         assert rel(to_np(xi), to_np(xb)) <= 1e-10
+
+
+def test_batch_mixing_sweep_kernels_matches_single_problem_solves():
+    """Members whose columns take different complex64 sweep kernels (matrix cores with one
+    or two row tiles per wavefront, vector units above 288 rows) share one batch."""
+    shapes = [dict(nx=21, nz=19, npml=4, K=3, freq=6.0), dict(nx=21, nz=150, npml=4, K=2, freq=6.0),
+              dict(nx=21, nz=300, npml=4, K=2, freq=6.0)]
+    gpus, rhs = [], []
+    for q, sh in enumerate(shapes):
+        print(f"[case] mixed-kernel batch member {q}: {sh}", flush=True)
+        g = KKTProblem.from_inputs(tiny_inputs(seed=q, **sh), eps=1.0)
+        gpus.append(g)
+        rhs.append(to_dev(complex_normal(g.field_shape, seed=40 + q), torch.complex64))
+    singles = [g.helmholtz_solve(r, prec="c64")[0] for g, r in zip(gpus, rhs)]
+    batch = KKTBatch(gpus)
+    xs = batch.helmholtz_solve(rhs, prec="c64")
+    for g, x, s1, r in zip(gpus, xs, singles, rhs):
+        x64, r64 = x.to(torch.complex128), r.to(torch.complex128)
+        xref = g.helmholtz_solve(r64, prec="c128")[0]
+        res = rel(to_np(g.stencil_apply(x64)), to_np(r64))
+        print(f"member nz={g.nz}: batch vs single {rel(to_np(x), to_np(s1)):.1e}, residual {res:.1e}, "
+              f"vs c128 solve {rel(to_np(x64), to_np(xref)):.1e}, |x| {float(x64.abs().max()):.2e}")
+        assert rel(to_np(x), to_np(s1)) <= 1e-5
+        assert rel(to_np(x64), to_np(xref)) <= 1e-3
+    batch.close()
