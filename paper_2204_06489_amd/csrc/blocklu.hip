@@ -112,7 +112,9 @@ __device__ __forceinline__ void gj_invert_store(double2 *S, int m, double2 *Tt, 
             int oi = __shfl_xor(bi, o, 64);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
           }
-          const int pr = bi;
+          // a column with no finite entry leaves bi = m: take no interchange, so that every
+          // index stays in range (the factors then carry the NaNs, the solve reports them)
+          const int pr = bi < m ? bi : k;
           // rows k and pr to LDS (pr first)
 #pragma unroll
           for (int t = 0; t < RMAX; ++t) {
