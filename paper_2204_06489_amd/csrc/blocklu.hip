@@ -916,7 +916,8 @@ __host__ __device__ inline int cr_top(int n) {   // floor(log2 n), n >= 1
 
 // KIND 0: forward reduction at level bt.level (item k = (t + 1) 2^(l+1)):
 //           g_k -= ML_k g_{k-2^l} + MU_k g_{k+2^l};
-// KIND 1: root, x = Binv g at separator 2^top;
+// KIND 1: root, x = Binv g at separator 2^top (only where there is no forward level:
+//         otherwise the last forward level's one item, the root, finishes with it);
 // KIND 2: back-substitution at level bt.level (item j = (2t + 1) 2^l):
 //           x_j = Binv_j g_j - F_j x_{j-2^l} - G_j x_{j+2^l}.
 template <typename R, int NS, int KIND>
@@ -961,6 +962,14 @@ __global__ __launch_bounds__((SolveThreadsCR<R, NS>::N)) void k_cr_solve(SweepBa
     if (j + st <= n) { M[2] = W + (size_t)out * mm; col[2] = separator(pp.part, j + st); }
   }
   cr_terms<R, NS>(g, pp.K, pp.x, grp, M, col, out, keep, smem);
+  if (KIND == 0 && lv == cr_top(n) - 1) {
+    // the last forward level has one item, the root 2^top: its value is final here, so
+    // the same workgroup takes x_root = Binv g_root (no launch of its own)
+    __syncthreads();   // this workgroup's g_root is written
+    const C *Mr[3] = {T + (size_t)out * mm, nullptr, nullptr};
+    const int cr[3] = {out, 0, 0};
+    cr_terms<R, NS>(g, pp.K, pp.x, grp, Mr, cr, out, false, smem);
+  }
 }
 
 // 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}.  A workgroup
@@ -1962,7 +1971,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
           if (n >= 1) {
             const int top = cr_top(n);
             if (kind == 0 && lv < top) items = (n >> (lv + 1)) * G;
-            else if (kind == 1) items = G;
+            else if (kind == 1) items = top == 0 ? G : 0;   // else taken by the last forward level
             else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * G;
           }
         } else if (p->P > 1) {
