@@ -1136,9 +1136,9 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   bool a_ok[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
-    const int e = tid + 256 * u, rr = e & 127;
+    const int e = tid + 256 * u, rr = e % CM_R;
     const int row = min(R0 + rr, rows - 1);
-    a_kk[u] = e >> 7;
+    a_kk[u] = e / CM_R;
     a_ok[u] = R0 + rr < rows;
     a_col[u] = ch.a + row / m;
     a_j[u] = row % m;
@@ -1159,16 +1159,17 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
       rb[u] = (l < lk1 && sidx < K) ? v : make_float2(0.f, 0.f);
     }
   };
-  floatx4 p1[2][3], p2[2][3], p3[2][3];
+  constexpr int RT = CM_R / 64;   // row tiles of 16 per wavefront
+  floatx4 p1[RT][3], p2[RT][3], p3[RT][3];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < RT; ++x)
 #pragma unroll
     for (int y = 0; y < 3; ++y) p1[x][y] = p2[x][y] = p3[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
   C ra[NA], rb[NB];
   load_slab(lk0, ra, rb);
   for (int kb = lk0; kb < lk1; kb += CM_K) {
 #pragma unroll
-    for (int u = 0; u < NA; ++u) As[a_kk[u]][(tid + 256 * u) & 127] = ra[u];
+    for (int u = 0; u < NA; ++u) As[a_kk[u]][(tid + 256 * u) % CM_R] = ra[u];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int e = tid + 256 * u;
@@ -1179,18 +1180,18 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
 #pragma unroll
     for (int kq = 0; kq < CM_K / 4; ++kq) {
       const int kk = 4 * kq + (lane >> 4);
-      C a[2], b[3];
+      C a[RT], b[3];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) a[x] = As[kk][wave * 32 + 16 * x + (lane & 15)];
+      for (int x = 0; x < RT; ++x) a[x] = As[kk][wave * 16 * RT + 16 * x + (lane & 15)];
 #pragma unroll
       for (int y = 0; y < 3; ++y) b[y] = Bs[kk][16 * y + (lane & 15)];
-      float as[2], bs[3];
+      float as[RT], bs[3];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) as[x] = a[x].x + a[x].y;
+      for (int x = 0; x < RT; ++x) as[x] = a[x].x + a[x].y;
 #pragma unroll
       for (int y = 0; y < 3; ++y) bs[y] = b[y].x + b[y].y;
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < RT; ++x)
 #pragma unroll
         for (int y = 0; y < 3; ++y) {
           p1[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].x, p1[x][y], 0, 0, 0);
@@ -1202,16 +1203,16 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   }
   // tile to LDS as [source][row], then column-contiguous updates
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < RT; ++x)
 #pragma unroll
     for (int y = 0; y < 3; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        Out[16 * y + (lane & 15)][wave * 32 + 16 * x + 4 * (lane >> 4) + r] =
+        Out[16 * y + (lane & 15)][wave * 16 * RT + 16 * x + 4 * (lane >> 4) + r] =
             make_float2(p1[x][y][r] - p2[x][y][r], p3[x][y][r] - p1[x][y][r] - p2[x][y][r]);
   __syncthreads();
   // eight updates at a time: their loads go out together (one latency per eight)
-  constexpr int EU = 8, NE = CM_S * CM_R / 256;
+  constexpr int NE = CM_S * CM_R / 256, EU = NE % 8 == 0 ? 8 : 4;
   static_assert(NE % EU == 0, "epilogue batches");
 #pragma unroll 1
   for (int e0 = 0; e0 < NE; e0 += EU) {
