@@ -255,7 +255,9 @@ class KKTBatch:
     ``newton_step`` runs the problems' FGMRES iterations in lockstep, optionally
     replaying each Krylov column's preconditioner and KKT matvec from a captured
     hipGraph.  The batch orders all work on one stream (the problems' streams are
-    set to it); destroy the batch before its problems."""
+    set to it, and given back when the batch is closed); destroy the batch before its
+    problems.  While the batch exists, a member's own calls run on the batch's stream:
+    close the batch (or synchronize) before reading their results on another stream."""
 
     def __init__(self, problems, stream=None):
         self.problems = list(problems)
