@@ -155,8 +155,9 @@ kf_status kf_set_stream(kf_problem *p, void *hip_stream);
 /* Shape of the block solver (any time; a change invalidates the factorisation).
  * chunks: the grid columns are cut into `chunks` pieces by chunks - 1 separator columns;
  * every piece is factorised and swept independently and a block-tridiagonal system on
- * the separators (their Schur complement) joins them, so more chunks means more parallel
- * work and shorter sequential sweeps, plus a longer separator chain.  1 <= chunks <=
+ * the separators (their Schur complement, solved by block cyclic reduction in about
+ * log2(chunks) levels) joins them, so more chunks means more parallel work and shorter
+ * sequential sweeps, plus more reduction levels and correction work.  1 <= chunks <=
  * min(64, (nx + 1) / 2); 0 picks round(1.6 sqrt(nx)) (1 below nx = 32).
  * sources_per_group: right-hand sides per workgroup in the block solves, 1, 2, 4 or 8
  * (0 = 1; FP64 solves use at most 4).  Results do not depend on either beyond rounding. */
@@ -243,7 +244,8 @@ kf_status kf_profile_enable(kf_problem *p, int32_t on);
  * block solve), "blu_fwd_c128", "blu_fwd_c64", "blu_bwd_c128", "blu_bwd_c64" (the chunks'
  * forward-sweep and back-substitution launches), "blu_mid", "blu_reduced_rhs",
  * "blu_chain", "blu_correct" (the middle columns, the separators' right-hand sides, the
- * separator chain and the interior correction), "precond_stage", "orth", "reduce".
+ * separator system's cyclic-reduction levels, one launch per level, and the interior
+ * correction), "precond_stage", "orth", "reduce".
  * Unknown names give KF_EINVAL. */
 kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
 
