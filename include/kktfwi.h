@@ -248,6 +248,10 @@ kf_status kf_profile_enable(kf_problem *p, int32_t on);
  * correction), "precond_stage", "orth", "reduce".
  * Unknown names give KF_EINVAL. */
 kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
+/* Restrict the recording to one kernel family (the names above), so that a timed run
+ * carries the events of that family only; NULL or "" records every family again.
+ * Counters are kept.  Unknown names give KF_EINVAL. */
+kf_status kf_profile_only(kf_problem *p, const char *name);
 
 /* ---- batches: several problems (e.g. frequencies on uneven grids) advanced together ----
  * The frequency sweep of Section 6 treats each frequency as its own Newton step; a batch

@@ -89,6 +89,7 @@ _SIGNATURES = {
                                       C.c_int32, C.c_int32, C.POINTER(KfNewtonStats)]),
     "kf_profile_enable": (C.c_int, [P, C.c_int32]),
     "kf_profile_read": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "kf_profile_only": (C.c_int, [P, C.c_char_p]),
 }
 
 _lib = None

@@ -41,7 +41,7 @@ static hipEvent_t take_event(kf_problem *p) {
   return e;
 }
 ProfScope::ProfScope(kf_problem *p_, int id_) : p(p_), id(id_) {
-  if (!p || id < 0 || !p->prof) return;
+  if (!p || id < 0 || !p->prof || !((p->prof_mask >> id) & 1u)) return;
   a = take_event(p);
   b = take_event(p);
   if (a) hipEventRecord(a, p->stream);
@@ -883,6 +883,21 @@ extern "C" kf_status kf_profile_enable(kf_problem *p, int32_t on) {
   p->prof = on != 0;
   for (int i = 0; i < PROF_N; ++i) p->counters[i] = ProfCounter();
   return KF_OK;
+}
+
+extern "C" kf_status kf_profile_only(kf_problem *p, const char *name) {
+  CHECK_ST(check_p(p));
+  prof_collect(p);
+  if (!name || !*name) {
+    p->prof_mask = ~0u;
+    return KF_OK;
+  }
+  for (int i = 0; i < PROF_N; ++i)
+    if (std::strcmp(name, prof_names[i]) == 0) {
+      p->prof_mask = 1u << i;
+      return KF_OK;
+    }
+  return fail(KF_EINVAL, std::string("unknown kernel family ") + name);
 }
 
 extern "C" kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms) {

@@ -183,6 +183,7 @@ struct kf_problem {
 
   // profiling
   bool prof = false;
+  uint32_t prof_mask = ~0u;                    // families recorded (bit = ProfId)
   std::vector<hipEvent_t> ev_free;             // event pool
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[16];
   ProfCounter counters[16];

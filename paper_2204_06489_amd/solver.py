@@ -247,6 +247,10 @@ class KKTProblem:
         check(lib().kf_profile_read(self._h, name.encode(), C.byref(n), C.byref(ms)))
         return int(n.value), float(ms.value)
 
+    def profile_only(self, name=None):
+        """Record one kernel family only (None: all families)."""
+        check(lib().kf_profile_only(self._h, (name or "").encode()))
+
 
 class KKTBatch:
     """Several problems (e.g. one per frequency, on uneven grids) advanced together.
