@@ -79,3 +79,22 @@ def test_autotune_picks_the_fastest_measured_shape_and_stays_exact():
     # a new problem of the same size starts from the tuned shape
     _, gpu2 = oracle_and_gpu(inp, eps=1.0)
     assert gpu2.solver_shape == gpu.solver_shape
+
+
+def test_profiling_records_the_selected_family_only():
+    inp = tiny_inputs(seed=2, **SHAPE)
+    _, gpu = oracle_and_gpu(inp, eps=1.0)
+    gpu.set_solver_shape(7, 1)
+    b = to_dev(complex_normal(gpu.field_shape, seed=9), torch.complex64)
+    gpu.profile_enable(True)
+    gpu.profile_only("blu_correct")
+    gpu.helmholtz_solve(b, prec="c64")
+    assert gpu.profile_read("blu_correct")[0] == 1
+    assert gpu.profile_read("blu_fwd_c64")[0] == 0
+    gpu.profile_only(None)
+    gpu.helmholtz_solve(b, prec="c64")
+    assert gpu.profile_read("blu_correct")[0] == 2
+    assert gpu.profile_read("blu_fwd_c64")[0] == 1
+    with pytest.raises(KFError):
+        gpu.profile_only("no_such_family")
+    gpu.profile_enable(False)
