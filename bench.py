@@ -135,9 +135,12 @@ def roofline_for(name, p, launches, total_ms):
     return out
 
 
-def measured_traffic(name):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None once the
-    kernel sources differ from the build the counters were taken on."""
+def measured_traffic(name, config):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (taken on the
+    401x141, 40-source workload, c1), or None for another workload or once the kernel
+    sources differ from the build the counters were taken on."""
+    if config != "c1":
+        return None
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -412,7 +415,7 @@ def main():
                   f"mv={st['t_matvec_ms']:.1f} orth={st['t_orth_ms']:.1f} misfit={st['misfit_before']:.4f}")
     ms_per_step = elapsed / args.steps * 1e3
     roof = roofline_for(dominant, p, *dom)
-    roof["traffic"] = measured_traffic(dominant)
+    roof["traffic"] = measured_traffic(dominant, args.config)
     roof["events"] = "HIP events around this family's launches only, over the timed steps"
     kkt_here = roofline_for("kkt_apply", p, *warm["kkt_apply"]) if warm and warm["kkt_apply"][0] else None
     per_kernel = ({f: {"launches": n, "total_ms": ms, "avg_us": (ms / n * 1e3 if n else None)}
