@@ -259,6 +259,14 @@ def bench_c4(args, torch, KKTProblem):
         log(args, f"batched step {k}: iters {[s['outer_iters'] for s in st]} factor {st[0]['t_factor_ms']:.0f} ms "
                   f"fwd {st[0]['t_forward_ms']:.0f} ms columns {st[0]['t_precond_ms']:.0f} ms "
                   f"orth {st[0]['t_orth_ms']:.0f} ms total {st[0]['t_total_ms']:.0f} ms")
+    # the same batch with every launch enqueued directly (no graph replay)
+    reset()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        batch.newton_step(ds, use_graph=False, **kw)
+    torch.cuda.synchronize()
+    t_batch_nograph = (time.perf_counter() - t0) / args.steps
+    log(args, f"batched without graphs: {t_batch_nograph * 1e3:.0f} ms per step")
     batch.close()
     # the same problems one at a time, each from gamma_0 again
     reset()
@@ -287,6 +295,7 @@ def bench_c4(args, torch, KKTProblem):
                                 "hipGraph replay of each FGMRES column, FGMRES(20) to " + f"{args.rtol:g}"),
                    "global_batch": 500, "parallelism": "single GPU"},
         "one_at_a_time_s": t_seq,
+        "batched_without_graphs_s": t_batch_nograph,
         "per_problem": [{"grid": f"{i['nx']}x{i['nz']}", "freq": i["freq"], "iters": s["outer_iters"],
                          "rel_res": s["rel_res"], "misfit": s["misfit_before"]} for i, s in zip(inps, sts[-1])],
     }
