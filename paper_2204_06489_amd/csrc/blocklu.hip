@@ -1252,8 +1252,10 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
 // j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
 // Per step: (a) all threads, coalesced over rows: store the previous column's result
 // from LDS, form the right-hand side in LDS (forward: b_i - C y_prev; back-substitution:
-// C x_prev, with y_i staged beside it); (b) each wave: its 16 x 16 tiles of T_i times the
-// right-hand side, the result (forward: y_i; back-substitution: y_i - product) to LDS.
+// C x_prev, with y_i staged beside it; a chunk's middle, one step:
+// b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}); (b) each wave: its 16 x 16 tiles of T_i
+// times the right-hand side, the result (forward and middle: the product;
+// back-substitution: y_i - product) to LDS.
 constexpr int SW_S = 16, SW_T = 576, SW_D = 8;   // sources, threads, ring depth
 template <int TPW> struct SweepShape {
   static constexpr int M = 144 * TPW, KS = M / 4, NA = M * SW_S / SW_T;   // rows, k-steps, slots per thread
