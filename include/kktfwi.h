@@ -239,7 +239,8 @@ kf_status kf_sizes(kf_problem *p, int64_t *out /*[host][6]*/);
  * family on the problem's stream: enable (1) / disable (0) and reset the counters. */
 kf_status kf_profile_enable(kf_problem *p, int32_t on);
 /* Read accumulated (launch count, total milliseconds) of a kernel family:
- * "kkt_apply" (the fused kernel, without the receiver term), "stencil", "blu_factor" (the
+ * "kkt_apply" (the fused kernel and, when it splits the sources into groups, the sum of
+ * the groups' parts of the control row; without the receiver term), "stencil", "blu_factor" (the
  * whole FP64 factorisation: chunks, spikes and separator system), "blu_sweep" (a whole
  * block solve), "blu_fwd_c128", "blu_fwd_c64", "blu_bwd_c128", "blu_bwd_c64" (the chunks'
  * forward-sweep and back-substitution launches), "blu_mid", "blu_reduced_rhs",

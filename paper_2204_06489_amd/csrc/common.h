@@ -144,6 +144,7 @@ struct kf_problem {
   double2 *u_n = nullptr;                      // [K][nz][nx]
   double2 *ys_part = nullptr;                  // [groups][Ng] per-source-group parts of sum_k P_k^* lambda_k
   int kkt_groups_max = 0;
+  int kkt_resident = 0;                        // resident k_kkt_apply workgroups on the device
   bool have_un = false;
 
   // partitioned block factorisation over grid columns

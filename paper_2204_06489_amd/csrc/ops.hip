@@ -60,20 +60,46 @@ __global__ __launch_bounds__(BX *BY) void k_stencil(Grid g, int K, const cplx<R>
   }
 }
 
-// Fused KKT matvec on 64 x (TY * RPT) tiles: thread (x, y) owns the RPT nodes
-// (i, j0 + y + TY r) and loops over the sources of its group (blockIdx.z).  The rows
-// of a tile share the vertical neighbours of their du / lambda rows through L1, so only
-// the two rows beyond the tile are fetched again by the neighbouring tile.  Each group
-// writes its part of the sum over k of P_k^* lambda_k into ys_part ([group][Ng]);
-// k_kkt_ys_finish adds the groups in fixed order.
-template <int TY, int RPT>
-__global__ __launch_bounds__(64 * TY) void k_kkt_tile(Grid g, int K, int kpg, int nxc,
-                                                       const double2 *__restrict__ xi,
-                                                       const double2 *__restrict__ un,
-                                                       double2 *__restrict__ y, double2 *__restrict__ ys_part) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= g.nx) return;
+// Stores that are not read again by the same kernel: the non-temporal hint keeps the
+// output lines from displacing the lambda / du rows that neighbouring workgroups still
+// read through L2.
+typedef double kf_dv2 __attribute__((ext_vector_type(2)));
+__device__ inline void store_stream(double2 *q, double2 v) {
+  const kf_dv2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, (kf_dv2 *)q);
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b mod 8).
+// Renumber them so that XCD x owns one contiguous run of logical workgroups.
+__device__ inline unsigned xcd_contiguous(unsigned b, unsigned n) {
+  const unsigned x = b & 7, s = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + s;
+}
+
+// Fused KKT matvec (eq. KKT with the blocks of eq. partitioned_system_matrix).
+// Logical workgroup L = chunk + chunks * group owns the KKT_WG consecutive nodes
+// [chunk * KKT_WG, ...) of the flattened grid, one per thread, and loops over the
+// sources of its group.  Each node reads lambda_k and du_k at itself and its four
+// neighbours (the x-neighbours share its cache lines, the z-neighbours are the rows
+// above and below, read by the workgroups of those rows too), u_k at itself, and
+// writes y_u,k = A^H lambda_k and y_lambda,k = A du_k - P_k ds.  Because each XCD
+// owns a contiguous run of chunks and all workgroups of a group walk the same sources
+// in the same order, the neighbour rows are mostly L2 hits.  The loop is unrolled by
+// two so that two sources' loads are in flight.  With one group the control row
+// y_s = eps ds - sum_k P_k^* lambda_k is written here; otherwise each group writes
+// its part of the sum over k into ys_part ([group][Ng]) and k_kkt_ys_finish adds the
+// groups in fixed order.
+constexpr int KKT_WG = 256;
+__global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, int nxc, unsigned chunks,
+                                                      double eps, const double2 *__restrict__ xi,
+                                                      const double2 *__restrict__ un,
+                                                      double2 *__restrict__ y, double2 *__restrict__ ys_part) {
+  const unsigned L = xcd_contiguous(blockIdx.x, gridDim.x);
+  const unsigned chunk = L % chunks, grp = L / chunks;
   const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t p = (size_t)chunk * KKT_WG + threadIdx.x;
+  if (p >= Nu) return;
+  const int j = (int)(p / g.nx), i = (int)(p - (size_t)j * g.nx);
   const int nzc = g.nz - 2 * g.npml;
   const size_t Ng = (size_t)nxc * nzc;
   const double2 *du = xi;
@@ -82,47 +108,33 @@ __global__ __launch_bounds__(64 * TY) void k_kkt_tile(Grid g, int K, int kpg, in
   double2 *yu = y;
   double2 *yl = y + (size_t)K * Nu + Ng;
   const double w2 = g.omega * g.omega;
-  const bool hxm = i > 0, hxp = i + 1 < g.nx;
-  Stencil5 st[RPT];
-  size_t pp[RPT], cc[RPT];
-  bool in[RPT], core[RPT], hzm[RPT], hzp[RPT];
-  double2 w2ds[RPT], acc[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int j = blockIdx.y * TY * RPT + threadIdx.y + TY * r;
-    in[r] = j < g.nz;
-    const int jj = in[r] ? j : 0;
-    st[r] = stencil_at(g, i, jj);
-    pp[r] = (size_t)jj * g.nx + i;
-    core[r] = in[r] && i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
-    cc[r] = core[r] ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
-    w2ds[r] = cscale(core[r] ? dsv[cc[r]] : make_double2(0.0, 0.0), w2);
-    hzm[r] = jj > 0;
-    hzp[r] = jj + 1 < g.nz;
-    acc[r] = make_double2(0.0, 0.0);
-  }
-  const int k0 = blockIdx.z * kpg, k1 = min(K, k0 + kpg);
+  const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
+  const Stencil5 s = stencil_at(g, i, j);
+  const bool core = i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
+  const size_t c = core ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
+  const double2 ds = core ? dsv[c] : make_double2(0.0, 0.0);
+  const double2 w2ds = cscale(ds, w2);
+  double2 acc = make_double2(0.0, 0.0);
+  const int k0 = grp * kpg, k1 = min(K, k0 + kpg);
+#pragma unroll 2
   for (int k = k0; k < k1; ++k) {
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      if (!in[r]) continue;
-      const Stencil5 &s = st[r];
-      const size_t o = (size_t)k * Nu + pp[r];
-      const double2 l0 = lam[o], d0 = du[o], u = un[o];
-      double2 ah = cmulc(s.cc, l0);     // conj(weight) * lambda: A^H lambda
-      double2 a = cmul(s.cc, d0);
-      if (hxm) { ah = cadd(ah, cmulc(s.cxm, lam[o - 1])); cfma(a, s.cxm, du[o - 1]); }
-      if (hxp) { ah = cadd(ah, cmulc(s.cxp, lam[o + 1])); cfma(a, s.cxp, du[o + 1]); }
-      if (hzm[r]) { ah = cadd(ah, cmulc(s.czm, lam[o - g.nx])); cfma(a, s.czm, du[o - g.nx]); }
-      if (hzp[r]) { ah = cadd(ah, cmulc(s.czp, lam[o + g.nx])); cfma(a, s.czp, du[o + g.nx]); }
-      yu[o] = ah;
-      yl[o] = csub(a, cmul(u, w2ds[r]));
-      acc[r] = cadd(acc[r], cmulc(u, l0));
-    }
+    const size_t o = (size_t)k * Nu + p;
+    const double2 l0 = lam[o], d0 = du[o], u = un[o];
+    double2 ah = cmulc(s.cc, l0);     // conj(weight) * lambda: A^H lambda
+    double2 a = cmul(s.cc, d0);
+    if (hxm) { ah = cadd(ah, cmulc(s.cxm, lam[o - 1])); cfma(a, s.cxm, du[o - 1]); }
+    if (hxp) { ah = cadd(ah, cmulc(s.cxp, lam[o + 1])); cfma(a, s.cxp, du[o + 1]); }
+    if (hzm) { ah = cadd(ah, cmulc(s.czm, lam[o - g.nx])); cfma(a, s.czm, du[o - g.nx]); }
+    if (hzp) { ah = cadd(ah, cmulc(s.czp, lam[o + g.nx])); cfma(a, s.czp, du[o + g.nx]); }
+    store_stream(yu + o, ah);
+    store_stream(yl + o, csub(a, cmul(u, w2ds)));
+    acc = cadd(acc, cmulc(u, l0));
   }
-#pragma unroll
-  for (int r = 0; r < RPT; ++r)
-    if (core[r]) ys_part[(size_t)blockIdx.z * Ng + cc[r]] = acc[r];
+  if (!core) return;
+  if (gridDim.x == chunks)
+    y[(size_t)K * Nu + c] = csub(cscale(ds, eps), cscale(acc, w2));
+  else
+    ys_part[(size_t)grp * Ng + c] = acc;
 }
 
 // y_s = eps ds - omega^2 sum over source groups (fixed order)
@@ -321,27 +333,38 @@ template kf_status launch_stencil<double>(kf_problem *, int, const double2 *, do
 template kf_status launch_stencil<float>(kf_problem *, int, const float2 *, float2 *);
 
 kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
-  constexpr int TY = 16, RPT = 1;
-  const int tx = (p->nx + 63) / 64, tz = (p->nz + TY * RPT - 1) / (TY * RPT);
-  // source groups: at least ~2 blocks of 16 waves per CU
-  int groups = (512 + tx * tz - 1) / (tx * tz);
-  groups = groups < 1 ? 1 : (groups > p->K ? p->K : groups);
+  if (!p->kkt_resident) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_kkt_apply, KKT_WG, 0) != hipSuccess) {
+      set_error("kkt_apply: device query failed");
+      return KF_EHIP;
+    }
+    p->kkt_resident = ncu * (per > 0 ? per : 1);
+  }
+  // Source groups.  When the operands fit the 256 MB Infinity Cache, one round of
+  // resident workgroups in lock step keeps the halo rows in L2.  When they stream from
+  // HBM, many short workgroups (about 5 sources each) keep more loads in flight, which
+  // pays for the larger per-group part of the control row.
+  const unsigned chunks = (unsigned)((p->Nu + KKT_WG - 1) / KKT_WG);
+  const double bytes = (double)p->Nu * (80.0 * p->K + 8.0);
+  int groups = bytes <= 192e6 ? (int)(p->kkt_resident / chunks) : (p->K + 4) / 5;
+  groups = groups < 1 ? 1 : (groups > p->kkt_groups_max ? p->kkt_groups_max : groups);
   const int kpg = (p->K + groups - 1) / groups;
   groups = (p->K + kpg - 1) / kpg;
-  if (groups > p->kkt_groups_max) {
-    set_error("kkt_apply: source-group scratch too small");
-    return KF_EINVAL;
-  }
   {
     ProfScope ps(p, PROF_KKT);
-    hipLaunchKernelGGL((k_kkt_tile<TY, RPT>), dim3(tx, tz, groups), dim3(64, TY), 0, p->stream, p->grid(), p->K, kpg,
-                       p->nxc, xi, p->u_n, y, p->ys_part);
+    hipLaunchKernelGGL(k_kkt_apply, dim3(chunks * groups), dim3(KKT_WG), 0, p->stream, p->grid(), p->K, kpg,
+                       p->nxc, chunks, p->eps, xi, p->u_n, y, p->ys_part);
     LAUNCH_CHECK();
+    if (groups > 1) {
+      hipLaunchKernelGGL(k_kkt_ys_finish, dim3((unsigned)((p->Ng + 255) / 256)), dim3(256), 0, p->stream,
+                         (size_t)p->Ng, groups, p->eps, p->omega * p->omega, xi + (size_t)p->K * p->Nu,
+                         p->ys_part, y + (size_t)p->K * p->Nu);
+      LAUNCH_CHECK();
+    }
   }
-  hipLaunchKernelGGL(k_kkt_ys_finish, dim3((unsigned)((p->Ng + 255) / 256)), dim3(256), 0, p->stream, (size_t)p->Ng,
-                     groups, p->eps, p->omega * p->omega, xi + (size_t)p->K * p->Nu, p->ys_part,
-                     y + (size_t)p->K * p->Nu);
-  LAUNCH_CHECK();
   int n = p->K * p->nru;
   hipLaunchKernelGGL(k_kkt_F, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->d_rnode, p->d_wsq,
                      (size_t)p->Nu, xi, y);
