@@ -187,8 +187,24 @@ def hbm_kkt(torch, KKTProblem, args):
     p.profile_enable(False)
     r = roofline_for("kkt_apply", p, n, ms)
     p.close()
+    del u, xi, y
+    # a plain 1 GiB device-to-device copy on torch's stream: the streaming rate this
+    # machine reaches for a read + write mix, next to the published HBM peak
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
     return {"grid": "801x281", "K": 80, "GB_per_call": r["work_per_launch"] / 1e9,
-            "avg_launch_us": r["avg_launch_us"], "GB_s": r["achieved"], "frac_of_hbm_peak": r["frac"]}
+            "avg_launch_us": r["avg_launch_us"], "GB_s": r["achieved"], "frac_of_hbm_peak": r["frac"],
+            "copy_GB_s": copy_gbs, "frac_of_copy": r["achieved"] / copy_gbs}
 
 
 def cpu_baseline(inp, gpu_iters, args):

@@ -98,6 +98,18 @@ def test_kkt_apply_matches_assembled_kkt_matrix(shape, weights):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+def test_kkt_apply_single_source_group():
+    """One source: the matvec kernel forms y_s itself instead of summing group parts."""
+    inp = _case(weights="random", nrec=7, nx=133, nz=37, npml=6, K=1)
+    orc, gpu = oracle_and_gpu(inp, eps=3.7e9)
+    u_n = _background(orc, gpu)
+    xi = complex_normal(orc.nxi, seed=11)
+    y = to_np(gpu.kkt_apply(to_dev(xi)))
+    ref = orc.kkt_apply(u_n, xi)
+    for a, b in zip(orc.unpack(y), orc.unpack(ref)):
+        assert rel(a, b) <= 1e-13
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_exact_preconditioner_matches_oracle_and_inverts(shape):
     inp = _case(nrec=5, **shape)
