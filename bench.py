@@ -299,6 +299,25 @@ def bench_c4(args, torch, KKTProblem):
               f"factor {[round(s['t_factor_ms']) for s in seq]} ms, total {[round(s['t_total_ms']) for s in seq]} ms, "
               f"precond {[round(s['t_precond_ms']) for s in seq]} ms, matvec {[round(s['t_matvec_ms']) for s in seq]} ms, "
               f"orth {[round(s['t_orth_ms']) for s in seq]} ms")
+    # the two smallest grids alone, where neither fills the chip: batched against one at a time
+    small = KKTBatch(probs[:2])
+    small.newton_step(ds[:2], use_graph=True, **kw)
+    reset()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        small.newton_step(ds[:2], use_graph=True, **kw)
+    torch.cuda.synchronize()
+    t_small_batch = (time.perf_counter() - t0) / args.steps
+    small.close()
+    reset()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for p, d in zip(probs[:2], ds[:2]):
+            p.newton_step(d, rtol=args.rtol, restart=20, maxit=600, pc=args.pc, fwd_prec="c128",
+                          update_in_place=True, want_xi=False)
+    torch.cuda.synchronize()
+    t_small_seq = (time.perf_counter() - t0) / args.steps
+    log(args, f"201x71 + 401x141 only: batched {t_small_batch*1e3:.0f} ms, one at a time {t_small_seq*1e3:.0f} ms per step")
     result = {
         "metric": "Newton-step time to KKT rel. res 1e-6", "value": t_batch, "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": False,
@@ -312,6 +331,8 @@ def bench_c4(args, torch, KKTProblem):
                    "global_batch": 500, "parallelism": "single GPU"},
         "one_at_a_time_s": t_seq,
         "batched_without_graphs_s": t_batch_nograph,
+        "two_smallest_grids": {"grids": ["201x71", "401x141"], "batched_s": t_small_batch,
+                               "one_at_a_time_s": t_small_seq},
         "per_problem": [{"grid": f"{i['nx']}x{i['nz']}", "freq": i["freq"], "iters": s["outer_iters"],
                          "rel_res": s["rel_res"], "misfit": s["misfit_before"]} for i, s in zip(inps, sts[-1])],
     }

@@ -1963,7 +1963,9 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         const int G = (p->K + (ph == 4 ? NSC : NS) - 1) / (ph == 4 ? NSC : NS), n = p->P - 1;
         const int STs = (p->K + SW_S - 1) / SW_S;
         const double m = p->nz, L = (double)p->nx / p->P;
-        cost[q] = ph == 0 || ph == 2 ? m * m * 0.5 * L : ph == 5 ? m : m * m;
+        // a matrix-core sweep step costs its fixed 144 TPW-row tile whatever m is
+        const double mt = ph <= 2 && sg < 2 ? 144.0 * (sg + 1) : m;
+        cost[q] = ph == 0 || ph == 2 ? mt * mt * 0.5 * L : ph == 5 ? m : mt * mt;
         bt.first[q] = tot;
         int items = 0;
         if (ph <= 2 && sweep_group(p) != sg) items = 0;

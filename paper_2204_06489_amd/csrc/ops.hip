@@ -161,7 +161,8 @@ __global__ void k_kkt_F(int K, int nru, const int32_t *__restrict__ rnode, const
 
 // ---------------------------------------------------------------------------
 // Preconditioner stage 2 (eq. precond, middle row) fused with the right-hand side
-// of stage 3:
+// of stage 3 (both source loops unrolled by four, so that four sources' loads are in
+// flight per thread):
 //   z_s   = (y_s + omega^2 sum_k E^T (conj(u_k) z_lam,k)) / eps
 //   rhs_k = y_lam,k + omega^2 u_k (E z_s)            -> written into z_u,k
 // ---------------------------------------------------------------------------
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(BX *BY) void k_precond_stage2(Grid g, int K, int nx
   double2 s = make_double2(0.0, 0.0);
   if (core) {
     double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
       size_t o = (size_t)k * Nu + p;
       acc = cadd(acc, cmulc(un[o], zl[o]));
@@ -195,6 +197,7 @@ __global__ __launch_bounds__(BX *BY) void k_precond_stage2(Grid g, int K, int nx
     zs[c] = s;
   }
   const double2 w2s = cscale(s, w2);
+#pragma unroll 4
   for (int k = 0; k < K; ++k) {
     size_t o = (size_t)k * Nu + p;
     zu[o] = cadd(yl[o], cmul(un[o], w2s));
