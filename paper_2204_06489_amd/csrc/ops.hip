@@ -161,23 +161,28 @@ __global__ void k_kkt_F(int K, int nru, const int32_t *__restrict__ rnode, const
 
 // ---------------------------------------------------------------------------
 // Preconditioner stage 2 (eq. precond, middle row) fused with the right-hand side
-// of stage 3 (both source loops unrolled by four, so that four sources' loads are in
-// flight per thread):
+// of stage 3:
 //   z_s   = (y_s + omega^2 sum_k E^T (conj(u_k) z_lam,k)) / eps
 //   rhs_k = y_lam,k + omega^2 u_k (E z_s)            -> written into z_u,k
+// A workgroup takes 64 consecutive nodes of the flattened grid; its S2_G rows of
+// threads split the sources (thread row r takes k = r, r + S2_G, ...), so S2_G times
+// as many loads are in flight as with one thread per node.  The rows' parts of the
+// sum over k are added in fixed order through LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BX *BY) void k_precond_stage2(Grid g, int K, int nxc, double eps,
-                                                            const double2 *__restrict__ y,
-                                                            const double2 *__restrict__ un,
-                                                            double2 *__restrict__ z) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  if (i >= g.nx || j >= g.nz) return;
+constexpr int S2_G = 4;
+__global__ __launch_bounds__(64 * S2_G) void k_precond_stage2(Grid g, int K, int nxc, double eps,
+                                                             const double2 *__restrict__ y,
+                                                             const double2 *__restrict__ un,
+                                                             double2 *__restrict__ z) {
+  __shared__ double2 part[S2_G][64];
   const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t p = (size_t)blockIdx.x * 64 + threadIdx.x;
+  const int r = threadIdx.y;
+  const bool valid = p < Nu;
+  const int j = valid ? (int)(p / g.nx) : 0, i = valid ? (int)(p - (size_t)j * g.nx) : 0;
   const int nzc = g.nz - 2 * g.npml;
   const size_t Ng = (size_t)nxc * nzc;
-  const size_t p = (size_t)j * g.nx + i;
-  const bool core = i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
+  const bool core = valid && i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
   const size_t c = core ? (size_t)(j - g.npml) * nxc + (i - g.npml) : 0;
   const double2 *ys = y + (size_t)K * Nu;
   const double2 *yl = ys + Ng;
@@ -185,24 +190,34 @@ __global__ __launch_bounds__(BX *BY) void k_precond_stage2(Grid g, int K, int nx
   double2 *zs = z + (size_t)K * Nu;
   const double2 *zl = zs + Ng;
   const double w2 = g.omega * g.omega;
-  double2 s = make_double2(0.0, 0.0);
+  double2 acc = make_double2(0.0, 0.0);
   if (core) {
-    double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-      size_t o = (size_t)k * Nu + p;
+    for (int k = r; k < K; k += S2_G) {
+      const size_t o = (size_t)k * Nu + p;
       acc = cadd(acc, cmulc(un[o], zl[o]));
     }
-    s = cscale(cadd(ys[c], cscale(acc, w2)), 1.0 / eps);
-    zs[c] = s;
   }
+  part[r][threadIdx.x] = acc;
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  if (core) {
+    double2 sum = part[0][threadIdx.x];
+#pragma unroll
+    for (int q = 1; q < S2_G; ++q) sum = cadd(sum, part[q][threadIdx.x]);
+    s = cscale(cadd(ys[c], cscale(sum, w2)), 1.0 / eps);
+    if (r == 0) zs[c] = s;
+  }
+  if (!valid) return;
   const double2 w2s = cscale(s, w2);
 #pragma unroll 4
-  for (int k = 0; k < K; ++k) {
-    size_t o = (size_t)k * Nu + p;
+  for (int k = r; k < K; k += S2_G) {
+    const size_t o = (size_t)k * Nu + p;
     zu[o] = cadd(yl[o], cmul(un[o], w2s));
   }
 }
+
+// ---------------------------------------------------------------------------
 
 // f_k = e_src_k / h^2
 __global__ void k_sources(int K, size_t Nu, const int32_t *__restrict__ src, double val, double2 *f) {
@@ -377,8 +392,8 @@ kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
 
 kf_status launch_precond_stage2(kf_problem *p, const double2 *y, double2 *z) {
   ProfScope ps(p, PROF_PRECOND);
-  hipLaunchKernelGGL(k_precond_stage2, field_grid(p), dim3(BX, BY), 0, p->stream, p->grid(), p->K, p->nxc,
-                     p->eps, y, p->u_n, z);
+  hipLaunchKernelGGL(k_precond_stage2, dim3((unsigned)((p->Nu + 63) / 64)), dim3(64, S2_G), 0, p->stream,
+                     p->grid(), p->K, p->nxc, p->eps, y, p->u_n, z);
   LAUNCH_CHECK();
   return KF_OK;
 }
