@@ -110,6 +110,27 @@ def test_kkt_apply_single_source_group():
         assert rel(a, b) <= 1e-13
 
 
+@pytest.mark.parametrize("cfg,fi", [("c1", 1), ("c2", 0)])
+def test_kkt_apply_full_size_matches_oracle(cfg, fi):
+    """The workloads bench.py times (401x141 x 40 sources; 801x281 x 80 sources), in the
+    launch configuration it times: every output against the oracle's sparse KKT matrix."""
+    from oracle.kkt import Problem
+    from paper_2204_06489_amd.solver import KKTProblem
+    inp = make_problem_inputs(cfg, fi)
+    print(f"[case] {cfg} {inp['nx']}x{inp['nz']} K={inp['K']}", flush=True)
+    eps = inp["eps"] or 1.0
+    orc = Problem.from_inputs(inp, eps=eps, factor=False)
+    gpu = KKTProblem.from_inputs(inp, eps=eps)
+    u_n = complex_normal((orc.K, orc.nz, orc.nx), seed=21)
+    gpu.set_background(to_dev(u_n))
+    xi = complex_normal(orc.nxi, seed=22)
+    y = to_np(gpu.kkt_apply(to_dev(xi)))
+    gpu.close()
+    ref = orc.kkt_apply(u_n, xi)
+    for a, b in zip(orc.unpack(y), orc.unpack(ref)):
+        assert rel(a, b) <= 1e-13
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_exact_preconditioner_matches_oracle_and_inverts(shape):
     inp = _case(nrec=5, **shape)
