@@ -131,6 +131,26 @@ def test_kkt_apply_full_size_matches_oracle(cfg, fi):
         assert rel(a, b) <= 1e-13
 
 
+def test_exact_preconditioner_full_size_matches_oracle():
+    """The preconditioner at the timed 401x141, 40-source workload (FP64 block solves and
+    the stage-2 kernel in the launch configuration bench.py times) against the oracle."""
+    from oracle.kkt import Problem
+    from paper_2204_06489_amd.solver import KKTProblem
+    inp = make_problem_inputs("c1", 1)
+    print(f"[case] c1 {inp['nx']}x{inp['nz']} K={inp['K']}", flush=True)
+    eps = inp["eps"] or 1.0
+    orc = Problem.from_inputs(inp, eps=eps)
+    gpu = KKTProblem.from_inputs(inp, eps=eps)
+    u_n = complex_normal((orc.K, orc.nz, orc.nx), seed=21)
+    gpu.set_background(to_dev(u_n))
+    y = complex_normal(orc.nxi, seed=23)
+    z = to_np(gpu.precond_apply(to_dev(y), pc="exact"))
+    gpu.close()
+    ref = orc.precond_apply(u_n, y)
+    for a, b in zip(orc.unpack(z), orc.unpack(ref)):
+        assert rel(a, b) <= 1e-10
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_exact_preconditioner_matches_oracle_and_inverts(shape):
     inp = _case(nrec=5, **shape)
