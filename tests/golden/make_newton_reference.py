@@ -1,14 +1,15 @@
-"""Write the FP64 oracle's Newton step on the 801 x 281, 80-source, 5 Hz workload.
+"""Write the FP64 oracle's Newton step on one of the timed workloads.
 
 Calls only the oracle (banded-LU forward solves, assembled KKT matrix, right-
 preconditioned GMRES with the exact banded-LU preconditioner of eq. precond) and
 stores what the mixed-precision GPU step is compared with: ds, gamma_{n+1}, the
 misfit before and after the step, and the KKT relative residual reached.
 
-Usage: python -m tests.golden.make_c2_reference [out.npz]   (about an hour of CPU)
+Usage: python -m tests.golden.make_newton_reference CONFIG FREQ_INDEX OUT.npz
+  c2 0 tests/golden/c2_newton_oracle.npz   801 x 281, 80 sources, 5 Hz (about an hour of CPU)
+  c1 1 tests/golden/c1_newton_oracle.npz   401 x 141, 40 sources, 5 Hz (a few minutes)
 """
 
-import os
 import sys
 import time
 
@@ -17,12 +18,11 @@ import numpy as np
 from oracle.kkt import Problem, gmres_right
 from synthetic.configs import make_problem_inputs
 
-HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def main(out):
+def main(config, freq_index, out):
     t0 = time.time()
-    inp = make_problem_inputs("c2", 0)
+    inp = make_problem_inputs(config, freq_index)
     pt = Problem.from_inputs(inp, gamma=inp["gamma_true"], eps=inp["eps"])
     d = pt.sample(pt.forward())
     del pt
@@ -59,4 +59,6 @@ def main(out):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "c2_newton_oracle.npz"))
+    if len(sys.argv) != 4:
+        sys.exit(__doc__)
+    main(sys.argv[1], int(sys.argv[2]), sys.argv[3])

@@ -1,9 +1,10 @@
-"""Mixed precision on the 801 x 281, 80-source, 5 Hz workload against the FP64 oracle.
+"""The Newton step on the timed workloads against the FP64 oracle, in every precision:
+801 x 281 with 80 sources and 401 x 141 with 40 sources, both at 5 Hz.
 
-The reference (tests/golden/c2_newton_oracle.npz, written by make_c2_reference.py from
-the oracle alone) is the oracle's Newton step: banded-LU forward solves, the assembled
-KKT matrix and GMRES with the exact block-triangular preconditioner to a relative
-residual of 1e-10.  The GPU step runs with complex64 block solves inside the inexact
+Each reference (tests/golden/c2_newton_oracle.npz and c1_newton_oracle.npz, written by
+make_newton_reference.py from the oracle alone) is the oracle's Newton step:
+banded-LU forward solves, the assembled KKT matrix and GMRES with the exact
+block-triangular preconditioner to a relative residual of 1e-10.  The GPU step runs with complex64 block solves inside the inexact
 preconditioner and complex64 sweeps with FP64 refinement for u_n, FP64 FGMRES,
 orthogonalisation, residuals and update.  Refined to the same 1e-10, its step, gamma
 update and misfits must agree with the oracle's to 1e-6 relative; the errors of the
@@ -26,7 +27,7 @@ from paper_2204_06489_amd.solver import KKTProblem  # noqa: E402
 from synthetic.configs import make_problem_inputs  # noqa: E402
 from tests.gpu_cases import rel, to_np  # noqa: E402
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_newton_oracle.npz")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "{}_newton_oracle.npz")
 
 FORMS = {   # name: (pc, fwd_prec, rtol)
     "mixed, refined to 1e-10": ("inexact", "mixed", 1e-10),
@@ -42,10 +43,11 @@ def _step(p, d, g0, pc, fwd, rtol):
     return to_np(p.unpack(xi)[1]), to_np(g1), st
 
 
-def test_c2_step_matches_oracle_in_every_precision():
-    ref = np.load(GOLDEN)
-    inp = make_problem_inputs("c2", 0)
-    print(f"[case] c2 {inp['nx']}x{inp['nz']} K={inp['K']} {inp['freq']} Hz", flush=True)
+@pytest.mark.parametrize("cfg,fi", [("c1", 1), ("c2", 0)])
+def test_step_matches_oracle_in_every_precision(cfg, fi):
+    ref = np.load(GOLDEN.format(cfg))
+    inp = make_problem_inputs(cfg, fi)
+    print(f"[case] {cfg} {inp['nx']}x{inp['nz']} K={inp['K']} {inp['freq']} Hz", flush=True)
     p = KKTProblem.from_inputs(inp, reg_on_update=True)
     d = torch.as_tensor(np.ascontiguousarray(ref["d"])).cuda()
     g0 = torch.as_tensor(inp["gamma0"]).cuda()
