@@ -33,33 +33,6 @@ __global__ void k_stretch(int n, double h, int npml, double omega, double r0, do
   ifh[t] = cdiv(make_double2(1.0, 0.0), f);
 }
 
-// ---------------------------------------------------------------------------
-// y_k = A x_k  (or A^H x_k = conj-coefficient stencil, A being complex symmetric)
-// ---------------------------------------------------------------------------
-template <typename R, bool ADJ>
-__global__ __launch_bounds__(BX *BY) void k_stencil(Grid g, int K, const cplx<R> *__restrict__ x,
-                                                     cplx<R> *__restrict__ y) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  if (i >= g.nx || j >= g.nz) return;
-  Stencil5 s = stencil_at(g, i, j);
-  if (ADJ) { s.cc = cconj(s.cc); s.cxm = cconj(s.cxm); s.cxp = cconj(s.cxp); s.czm = cconj(s.czm); s.czp = cconj(s.czp); }
-  const cplx<R> cc = ccast<R>(s.cc), cxm = ccast<R>(s.cxm), cxp = ccast<R>(s.cxp),
-                czm = ccast<R>(s.czm), czp = ccast<R>(s.czp);
-  const size_t Nu = (size_t)g.nx * g.nz;
-  const size_t p = (size_t)j * g.nx + i;
-  const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
-  for (int k = blockIdx.z; k < K; k += gridDim.z) {
-    const cplx<R> *xk = x + k * Nu;
-    cplx<R> acc = cmul(cc, xk[p]);
-    if (hxm) cfma(acc, cxm, xk[p - 1]);
-    if (hxp) cfma(acc, cxp, xk[p + 1]);
-    if (hzm) cfma(acc, czm, xk[p - g.nx]);
-    if (hzp) cfma(acc, czp, xk[p + g.nx]);
-    y[k * Nu + p] = acc;
-  }
-}
-
 // Stores that are not read again by the same kernel: the non-temporal hint keeps the
 // output lines from displacing the lambda / du rows that neighbouring workgroups still
 // read through L2.
@@ -135,6 +108,45 @@ __global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, in
     y[(size_t)K * Nu + c] = csub(cscale(ds, eps), cscale(acc, w2));
   else
     ys_part[(size_t)grp * Ng + c] = acc;
+}
+
+__device__ inline void store_stream(float2 *q, float2 v) {
+  typedef float kf_fv2 __attribute__((ext_vector_type(2)));
+  const kf_fv2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, (kf_fv2 *)q);
+}
+
+// y_k = A x_k, or A^H x_k (the conjugate weights: A is complex symmetric), for all
+// sources (eq. Au=f).  Laid out like k_kkt_apply: logical workgroup chunk + chunks *
+// group owns KKT_WG consecutive nodes of the flattened grid and the STEN_KPG sources
+// of its group, the XCDs each own a contiguous run of chunks (neighbour rows are L2
+// hits), the source loop is unrolled by two and the outputs are streamed.
+constexpr int STEN_KPG = 4;
+template <typename R, bool ADJ>
+__global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chunks, const cplx<R> *__restrict__ x,
+                                                    cplx<R> *__restrict__ y) {
+  const unsigned L = xcd_contiguous(blockIdx.x, gridDim.x);
+  const unsigned chunk = L % chunks, grp = L / chunks;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t p = (size_t)chunk * KKT_WG + threadIdx.x;
+  if (p >= Nu) return;
+  const int j = (int)(p / g.nx), i = (int)(p - (size_t)j * g.nx);
+  Stencil5 s = stencil_at(g, i, j);
+  if (ADJ) { s.cc = cconj(s.cc); s.cxm = cconj(s.cxm); s.cxp = cconj(s.cxp); s.czm = cconj(s.czm); s.czp = cconj(s.czp); }
+  const cplx<R> cc = ccast<R>(s.cc), cxm = ccast<R>(s.cxm), cxp = ccast<R>(s.cxp),
+                czm = ccast<R>(s.czm), czp = ccast<R>(s.czp);
+  const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
+  const int k0 = grp * STEN_KPG, k1 = min(K, k0 + STEN_KPG);
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k) {
+    const cplx<R> *xk = x + (size_t)k * Nu;
+    cplx<R> acc = cmul(cc, xk[p]);
+    if (hxm) cfma(acc, cxm, xk[p - 1]);
+    if (hxp) cfma(acc, cxp, xk[p + 1]);
+    if (hzm) cfma(acc, czm, xk[p - g.nx]);
+    if (hzp) cfma(acc, czp, xk[p + g.nx]);
+    store_stream(y + (size_t)k * Nu + p, acc);
+  }
 }
 
 // y_s = eps ds - omega^2 sum over source groups (fixed order)
@@ -339,11 +351,12 @@ kf_status launch_pml(kf_problem *p, const kf_desc &d) {
 template <typename R>
 kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *y) {
   ProfScope ps(p, PROF_STENCIL);
-  int zdim = p->K < 64 ? p->K : 64;
+  const unsigned chunks = (unsigned)((p->Nu + KKT_WG - 1) / KKT_WG);
+  const dim3 grid(chunks * (unsigned)((p->K + STEN_KPG - 1) / STEN_KPG));
   if (adjoint)
-    hipLaunchKernelGGL((k_stencil<R, true>), field_grid(p, zdim), dim3(BX, BY), 0, p->stream, p->grid(), p->K, x, y);
+    hipLaunchKernelGGL((k_stencil<R, true>), grid, dim3(KKT_WG), 0, p->stream, p->grid(), p->K, chunks, x, y);
   else
-    hipLaunchKernelGGL((k_stencil<R, false>), field_grid(p, zdim), dim3(BX, BY), 0, p->stream, p->grid(), p->K, x, y);
+    hipLaunchKernelGGL((k_stencil<R, false>), grid, dim3(KKT_WG), 0, p->stream, p->grid(), p->K, chunks, x, y);
   LAUNCH_CHECK();
   return KF_OK;
 }
