@@ -121,7 +121,7 @@ __device__ inline void store_stream(float2 *q, float2 v) {
 // group owns KKT_WG consecutive nodes of the flattened grid and the STEN_KPG sources
 // of its group, the XCDs each own a contiguous run of chunks (neighbour rows are L2
 // hits), the source loop is unrolled by two and the outputs are streamed.
-constexpr int STEN_KPG = 4;
+constexpr int STEN_KPG = 8;
 template <typename R, bool ADJ>
 __global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chunks, const cplx<R> *__restrict__ x,
                                                     cplx<R> *__restrict__ y) {
