@@ -7,18 +7,24 @@ KKT right-hand side, flexible GMRES with the block-triangular preconditioner to
 ||b - M xi|| <= 1e-6 ||b||, and the update gamma_{n+1} = gamma_n + Re(ds), which
 the next step continues from.
 
-Workload (default): the 401 x 141 grid (h = 10 m, 20-cell PML) of the seeded
-faulted-lens earth, 40 sources and 401 receivers on the first core row, 5 Hz,
-inexact preconditioner (complex64 block sweeps), FGMRES(30), b_s = 0.  Inputs
-are synthetic; the observed data are a forward solve of the true model.
+Workload (default): the 801 x 281 grid (h = 5 m, 40-cell PML) of the seeded
+faulted-lens earth, 80 sources and 801 receivers on the first core row, 5 Hz, in
+mixed precision: complex64 block factors and sweeps (FP32 arithmetic and
+accumulation) inside the inexact preconditioner and inside FP64 iterative
+refinement of the background solve; FGMRES(30), its orthogonalisation, the KKT
+matvec, the residuals and the update in FP64; b_s = 0.  `--config c1` runs the
+401 x 141, 40-source workload in plain FP64 (exact preconditioner, FP64 block
+solves) at 3, 5 or 7 Hz (`--freq-index 0|1|2`).  Inputs are synthetic; the
+observed data are a forward solve of the true model.
 
 Prints one JSON line.  Also reported:
-  roofline      the kernel with the most GPU time in the timed steps, timed live
-                with HIP events on the library's stream;
-  kkt_apply     the fused KKT matvec at this size and at 801 x 281 x 80 sources
-                (1.45 GB per call, larger than the 256 MB Infinity Cache);
+  roofline      the single kernel with the most GPU time in a profiled warm-up step,
+                re-timed live with HIP events on the library's stream over the timed
+                steps, against its algorithmic bytes or flops;
+  kkt_apply     the fused KKT matvec on this workload (20 calls), beside a plain device
+                copy;
   cpu_baseline  the FP64 oracle (banded LU, the paper's own CPU algorithm) timed on
-                a bounded sample of the same workload on the host.
+                a bounded sample of the same workload on all host cores (and on one).
 """
 
 import argparse
@@ -40,14 +46,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c1")
-    ap.add_argument("--freq-index", type=int, default=1)
-    ap.add_argument("--pc", default="inexact", choices=["exact", "inexact"])
+    ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--freq-index", type=int, default=None, help="default: 5 Hz of the workload")
+    ap.add_argument("--pc", default=None, choices=["exact", "inexact"],
+                    help="default: inexact for the mixed-precision workloads (c2, c4), exact for c0/c1")
+    ap.add_argument("--fwd-prec", default=None, choices=["c128", "mixed"],
+                    help="background solve: default mixed for c2, c128 otherwise")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-kkt", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the automatic solver shape")
+    ap.add_argument("--shape", default=None,
+                    help="CHUNKS,SOURCES_PER_GROUP: set the block solver's shape instead of autotuning "
+                         "(profiling runs: keeps the tuner's factorisations out of the trace)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -109,14 +121,38 @@ def kernel_work(name, p):
         # V_i and / or W_i (m x m) times the separator values, every interior column and source
         blocks = sum((b - a + 1) * ((1 if c > 0 else 0) + (1 if c < P - 1 else 0)) for c, (a, b, mid) in enumerate(part))
         return 8.0 * m * m * blocks * K, "flops", dt
+    if name == "blu_mid":
+        # the meeting column of every chunk: one m x m complex matvec per source
+        return 8.0 * m * m * P * K, "flops", "f32" if getattr(p, "inner_fp32", False) else "f64"
     raise KeyError(name)
 
 
 MFMA_KERNELS = ("blu_fwd_c64", "blu_bwd_c64", "blu_correct")
+# single-kernel families (one kernel per launch, apart from tiny fixed-order finish
+# kernels of the reductions) whose work the library counts per launch, in bytes
+LIB_COUNTED = ("kkt_apply", "gs_dot", "gs_update", "blu_chain")
+# every single-kernel family a Newton step launches: the roofline kernel is the one
+# of these with the most GPU time
+SINGLE = ("kkt_apply", "gs_dot", "gs_update", "blu_fwd_c64", "blu_bwd_c64", "blu_correct", "blu_chain",
+          "blu_mid", "blu_fwd_c128", "blu_bwd_c128")
+FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stage", "orth", "reduce")
+KERNEL_NAMES = {
+    "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial (+ k_finish)",
+    "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
+    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_mfma", "blu_chain": "k_cr_solve",
+    "blu_mid": "k_sweep_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
+    "blu_fwd_c128": "k_solve<double,*,0>", "blu_bwd_c128": "k_solve<double,*,2>",
+}
 
 
-def roofline_for(name, p, launches, total_ms):
-    amount, unit, dt = kernel_work(name, p)
+def roofline_for(name, p, launches, total_ms, lib_work=None):
+    """Roofline of a kernel family from its launches and time: work per launch (the
+    library's own count for LIB_COUNTED families, else kernel_work) over the average
+    launch duration."""
+    if name in LIB_COUNTED:
+        amount, unit, dt = lib_work / launches, "bytes", "f64"
+    else:
+        amount, unit, dt = kernel_work(name, p)
     avg_s = total_ms / launches * 1e-3
     if unit == "bytes":
         achieved = amount / avg_s / 1e9
@@ -128,25 +164,27 @@ def roofline_for(name, p, launches, total_ms):
         # complex64 sweeps and the interior correction run on the matrix cores (dense
         # FP32 MFMA peak); the FP64 sweeps on the vector units (FP64 vector peak)
         # (the matrix-core sweeps take columns of up to 288 rows)
-        bound = "mfma" if name == "blu_correct" or (name in MFMA_KERNELS and p.nz <= 288) else "alu"
+        bound = ("mfma" if name == "blu_correct" or (name in MFMA_KERNELS + ("blu_mid",) and dt == "f32" and p.nz <= 288)
+                 else "alu")
         out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
-    out.update({"frac": achieved / peak, "traffic": None, "kernel": name, "launches": launches,
-                "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount, "work_unit": unit})
+    out.update({"frac": achieved / peak, "traffic": None, "kernel": KERNEL_NAMES.get(name, name), "family": name,
+                "launches": launches, "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount,
+                "work_unit": unit})
     return out
 
 
-def measured_traffic(name, config):
-    """HBM bytes per launch from the committed rocprofv3 counter runs (taken on the
-    401x141, 40-source workload, c1), or None for another workload or once the kernel
-    sources differ from the build the counters were taken on."""
-    if config != "c1":
-        return None
+def measured_traffic(name, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None for a
+    workload the counters were not taken on, or once the kernel sources differ from
+    the build the counters were taken on."""
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     tab = json.load(open(path))
+    if tab.get("workload") != workload:
+        return None
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2204_06489_amd", "csrc", "*"))):
         h.update(open(f, "rb").read())
@@ -167,27 +205,22 @@ def observed_data(inp, torch, KKTProblem):
     return d
 
 
-def hbm_kkt(torch, KKTProblem, args):
-    """kkt_apply at 801 x 281, 80 sources (working set far above the Infinity Cache)."""
-    from synthetic.configs import make_problem_inputs
-    inp = make_problem_inputs("c2", 0)
-    p = KKTProblem.from_inputs(inp, eps=inp["eps"] or 1.0)
+def kkt_matvec_rate(p, torch, calls=20):
+    """kkt_apply on the workload's own problem and background (random xi), timed with
+    HIP events around each call, beside a plain 1 GiB device-to-device copy."""
     g = torch.Generator(device="cuda").manual_seed(1234)
-    u = torch.randn(p.field_shape, dtype=torch.complex128, device="cuda", generator=g)
-    p.set_background(u)
     xi = torch.randn(p.Nxi, dtype=torch.complex128, device="cuda", generator=g)
     y = p.empty_xi()
     for _ in range(3):
         p.kkt_apply(xi, out=y)
     torch.cuda.synchronize()
     p.profile_enable(True)
-    for _ in range(20):
+    for _ in range(calls):
         p.kkt_apply(xi, out=y)
     n, ms = p.profile_read("kkt_apply")
+    r = roofline_for("kkt_apply", p, n, ms, p.profile_work("kkt_apply"))
     p.profile_enable(False)
-    r = roofline_for("kkt_apply", p, n, ms)
-    p.close()
-    del u, xi, y
+    del xi, y
     # a plain 1 GiB device-to-device copy on torch's stream: the streaming rate this
     # machine reaches for a read + write mix, next to the published HBM peak
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -202,37 +235,72 @@ def hbm_kkt(torch, KKTProblem, args):
     torch.cuda.synchronize()
     copy_gbs = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
-    return {"grid": "801x281", "K": 80, "GB_per_call": r["work_per_launch"] / 1e9,
+    return {"grid": f"{p.nx}x{p.nz}", "K": p.K, "GB_per_call": r["work_per_launch"] / 1e9,
             "avg_launch_us": r["avg_launch_us"], "GB_s": r["achieved"], "frac_of_hbm_peak": r["frac"],
-            "copy_GB_s": copy_gbs, "frac_of_copy": r["achieved"] / copy_gbs}
+            "copy_GB_s": copy_gbs, "frac_of_copy": r["achieved"] / copy_gbs, "calls": n}
 
 
 def cpu_baseline(inp, gpu_iters, args):
-    """The oracle (numpy/scipy, banded LU) on a bounded sample of the same step."""
+    """The oracle (numpy/scipy, banded LU: the paper's own CPU algorithm) on a bounded
+    sample of the same Newton step, on all host cores and on one.
+
+    Timed: the full-size banded-LU factorisation, banded solves of a few sources (scaled
+    to the K forward solves of u_n and the 2 K solves of every preconditioner
+    application), one full-size assembled KKT matvec and one modified Gram-Schmidt
+    dot + axpy over a packed vector (scaled to the GPU step's iterations and mean Krylov
+    basis size).  The oracle is used as it stands: its BLAS threads are the only knob."""
     import numpy as np
     from threadpoolctl import threadpool_limits
-    from oracle.kkt import Problem, gmres_right
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        p = Problem.from_inputs(inp, gamma=inp["gamma0"], eps=inp["eps"], reg_on_update=True)
-        t_factor = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        u_n = p.forward()
-        t_fwd = time.perf_counter() - t0
-        rng = np.random.default_rng(0)
-        d = p.sample(u_n) * (1.0 + 0.1 * rng.standard_normal((p.K, p.nrec)))
-        b = p.rhs(p.residual(d, u_n))
-        n_it = 2
-        t0 = time.perf_counter()
-        gmres_right(lambda v: p.kkt_apply(u_n, v), lambda v: p.precond_apply(u_n, v), b, tol=1e-30,
-                    restart=args.restart, maxit=n_it)
-        t_it = (time.perf_counter() - t0) / n_it
-    est = t_factor + t_fwd + gpu_iters * t_it
-    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"full-size banded-LU factorisation ({t_factor:.1f} s), background solve ({t_fwd:.1f} s) "
-                       f"and {n_it} right-preconditioned GMRES iterations with the exact banded-LU "
-                       f"preconditioner ({t_it:.1f} s each), scaled to the GPU step's {gpu_iters:.1f} outer "
-                       f"iterations; one BLAS thread")}
+    from oracle.kkt import Problem
+    cores_all = len(os.sched_getaffinity(0))
+    out = {}
+    K = inp["K"]
+    ks = min(K, 4)
+    restart = args.restart
+    iters = max(1.0, gpu_iters)
+    # mean basis size over the iterations of restarted GMRES(restart)
+    js = [(i % restart) + 1 for i in range(int(round(iters)))]
+    mean_j = float(np.mean(js)) if js else 1.0
+    for cores in (cores_all, 1):
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            p = Problem.from_inputs(inp, gamma=inp["gamma0"], eps=inp["eps"], reg_on_update=True)
+            t_factor = time.perf_counter() - t0
+            f = p.sources()[:ks]
+            t0 = time.perf_counter()
+            u = p.lu.solve(f)
+            t_fwd_src = (time.perf_counter() - t0) / ks
+            t0 = time.perf_counter()
+            p.lu.solve(u, adjoint=True)
+            t_adj_src = (time.perf_counter() - t0) / ks
+            rng = np.random.default_rng(0)
+            u_n = np.zeros((p.K, p.nz, p.nx), np.complex128)
+            u_n[:ks] = u
+            M = p.assemble_M(u_n)
+            xi = rng.standard_normal(p.nxi) + 1j * rng.standard_normal(p.nxi)
+            t0 = time.perf_counter()
+            M @ xi
+            t_mv = time.perf_counter() - t0
+            v = rng.standard_normal(p.nxi) + 1j * rng.standard_normal(p.nxi)
+            t0 = time.perf_counter()
+            hq = np.vdot(v, xi)
+            xi -= hq * v
+            t_gs = time.perf_counter() - t0
+            del M, xi, v, u_n, p
+        est = t_factor + K * t_fwd_src + iters * (K * (t_fwd_src + t_adj_src) + t_mv + mean_j * t_gs)
+        out[cores] = dict(value=est, t_factor=t_factor, t_fwd_src=t_fwd_src, t_adj_src=t_adj_src, t_mv=t_mv,
+                          t_gs=t_gs)
+    a, one = out[cores_all], out[1]
+    return {"value": a["value"], "unit": "s", "cores": cores_all, "kind": "oracle",
+            "one_core_value": one["value"],
+            "sample": (f"oracle Newton step estimated from a bounded sample at full size: banded-LU "
+                       f"factorisation ({a['t_factor']:.1f} s), forward and adjoint banded solves of {ks} of the "
+                       f"{K} sources ({a['t_fwd_src']:.2f} / {a['t_adj_src']:.2f} s per source), one assembled "
+                       f"KKT matvec ({a['t_mv']:.2f} s) and one Gram-Schmidt dot + axpy ({a['t_gs']:.3f} s), scaled "
+                       f"to K forward solves for u_n plus {iters:.1f} GMRES iterations (the GPU step's count; "
+                       f"2 K solves, one matvec and {mean_j:.1f} dot + axpy each); numpy/scipy BLAS on "
+                       f"{cores_all} threads; on 1 thread: {one['value']:.0f} s (factorisation "
+                       f"{one['t_factor']:.1f} s, {one['t_fwd_src']:.2f} s per source solve)")}
 
 
 def bench_c4(args, torch, KKTProblem):
@@ -393,6 +461,13 @@ def main():
     from paper_2204_06489_amd.solver import KKTProblem
 
     torch.cuda.set_device(0)
+    mixed_cfg = args.config in ("c2", "c4")
+    if args.pc is None:
+        args.pc = "inexact" if mixed_cfg else "exact"
+    if args.fwd_prec is None:
+        args.fwd_prec = "mixed" if args.config == "c2" else "c128"
+    if args.freq_index is None:
+        args.freq_index = 1 if args.config == "c1" else 0
     if args.config == "c4":
         return bench_c4(args, torch, KKTProblem)
     if args.config == "c3":
@@ -408,21 +483,23 @@ def main():
     inp = make_problem_inputs(args.config, args.freq_index)
     if inp["eps"] is None:
         raise SystemExit("no eps for this workload in synthetic/eps_table.json")
-    log(args, f"workload {args.config} f={inp['freq']} Hz grid {inp['nx']}x{inp['nz']} K={inp['K']}")
+    mixed = args.pc == "inexact" or args.fwd_prec == "mixed"
+    log(args, f"workload {args.config} f={inp['freq']} Hz grid {inp['nx']}x{inp['nz']} K={inp['K']} "
+              f"pc={args.pc} fwd={args.fwd_prec}")
     d = observed_data(inp, torch, KKTProblem)
     p = KKTProblem.from_inputs(inp, reg_on_update=True)
-    if not args.no_autotune:
+    p.inner_fp32 = args.pc == "inexact"      # the block solves of the step run in complex64
+    if args.shape:
+        c, ns = (int(v) for v in args.shape.split(","))
+        p.set_solver_shape(c, ns)
+    elif not args.no_autotune:
         # shape of the block solver for this grid (setup, outside the timed region)
         table = p.autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)
         log(args, "autotune: " + ", ".join(f"P={r['chunks']} ns={r['sources_per_group']}: "
                                             f"{r['t_factor_ms']:.1f}+100x{r['t_solve_ms']:.3f} ms"
                                             for r in table[:4]))
-    opts = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec="c128",
-                update_in_place=True, want_xi=False)
-    families = ["kkt_apply", "blu_factor", "blu_fwd_c64", "blu_bwd_c64", "blu_correct", "blu_chain",
-                "blu_fwd_c128", "blu_bwd_c128"]
-    # (blu_chain is a family of launches of unequal work: the reduction's levels)
-    single = ["kkt_apply", "blu_fwd_c64", "blu_bwd_c64", "blu_correct", "blu_fwd_c128", "blu_bwd_c128"]
+    opts = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec=args.fwd_prec,
+                fwd_rtol=1e-10, update_in_place=True, want_xi=False)
     # The last warm-up step records every kernel family (HIP events around each launch):
     # it gives the per-family breakdown and picks the single-kernel family with the largest
     # total time.  The timed steps then record that family only, so the other families'
@@ -434,14 +511,15 @@ def main():
             p.profile_enable(True)
         _, _, st = p.newton_step(d, **opts)
         if last:
-            warm = {f: p.profile_read(f) for f in families}
+            warm = {f: p.profile_read(f) for f in FAMILIES}
+            warm_work = {f: p.profile_work(f) for f in LIB_COUNTED}
             p.profile_enable(False)
         log(args, f"warmup {w}: iters={st['outer_iters']} rel={st['rel_res']:.2e} {st['t_total_ms']:.1f} ms")
     torch.cuda.synchronize()
     if warm is not None:
-        dominant = max((f for f in single if warm[f][0] > 0), key=lambda f: warm[f][1])
-    else:   # no warm-up step: the family that dominates this workload in profiled runs
-        dominant = "blu_correct" if args.pc == "inexact" else "blu_fwd_c128"
+        dominant = max((f for f in SINGLE if warm[f][0] > 0), key=lambda f: warm[f][1])
+    else:   # no warm-up step: the family that dominates these workloads in profiled runs
+        dominant = "gs_update"
     p.profile_enable(True)
     p.profile_only(dominant)
     stats = []
@@ -452,6 +530,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dom = p.profile_read(dominant)
+    dom_work = p.profile_work(dominant) if dominant in LIB_COUNTED else None
     p.profile_only(None)
     p.profile_enable(False)
     for k, st in enumerate(stats):
@@ -460,13 +539,24 @@ def main():
                   f"factor={st['t_factor_ms']:.1f} fwd={st['t_forward_ms']:.1f} pc={st['t_precond_ms']:.1f} "
                   f"mv={st['t_matvec_ms']:.1f} orth={st['t_orth_ms']:.1f} misfit={st['misfit_before']:.4f}")
     ms_per_step = elapsed / args.steps * 1e3
-    roof = roofline_for(dominant, p, *dom)
-    roof["traffic"] = measured_traffic(dominant, args.config)
+    workload = f"{args.config}/{inp['nx']}x{inp['nz']}/K{inp['K']}/{inp['freq']:g}Hz/{args.pc}/{args.fwd_prec}"
+    roof = roofline_for(dominant, p, *dom, dom_work)
+    roof["traffic"] = measured_traffic(dominant, workload)
     roof["events"] = "HIP events around this family's launches only, over the timed steps"
-    kkt_here = roofline_for("kkt_apply", p, *warm["kkt_apply"]) if warm and warm["kkt_apply"][0] else None
-    per_kernel = ({f: {"launches": n, "total_ms": ms, "avg_us": (ms / n * 1e3 if n else None)}
-                   for f, (n, ms) in warm.items()} if warm else None)
+    per_kernel = None
+    if warm:
+        per_kernel = {}
+        for f, (n, ms) in warm.items():
+            row = {"launches": n, "total_ms": ms, "avg_us": (ms / n * 1e3 if n else None)}
+            if f in SINGLE and n:
+                r = roofline_for(f, p, n, ms, warm_work.get(f))
+                row.update({"achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"], "bound": r["bound"]})
+            per_kernel[f] = row
     mean = lambda key: float(np.mean([s[key] for s in stats]))
+    if mixed:
+        dtype = "c128 outer (FP64) + c64 inner block solves"
+    else:
+        dtype = "c128"
     result = {
         "metric": "Newton-step time to KKT rel. res 1e-6",
         "value": ms_per_step / 1e3,
@@ -478,13 +568,15 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128 outer (FP64) + c64 block sweeps" if args.pc == "inexact" else "c128",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": (f"{args.config}: {inp['nx']}x{inp['nz']} grid, h={inp['h']:g} m, "
                                 f"{inp['npml']}-cell PML, faulted-lens model, {inp['K']} sources, "
                                 f"{len(inp['rec_ix'])} receivers, {inp['freq']:g} Hz, "
-                                f"{'inexact' if args.pc == 'inexact' else 'exact'} block-triangular "
-                                f"preconditioner, FGMRES({args.restart}) to {args.rtol:g}, b_s = 0"),
+                                f"{'inexact (complex64 block factors)' if args.pc == 'inexact' else 'exact (FP64)'} "
+                                f"block-triangular preconditioner, background solve "
+                                f"{'complex64 + FP64 refinement to 1e-10' if args.fwd_prec == 'mixed' else 'FP64'}, "
+                                f"FGMRES({args.restart}) in FP64 to {args.rtol:g}, b_s = 0"),
                    "global_batch": inp["K"], "parallelism": "single GPU",
                    "solver_shape": dict(zip(("chunks", "sources_per_group"), p.solver_shape))},
         "roofline": roof,
@@ -494,12 +586,15 @@ def main():
                          "rel_res": max(s["rel_res"] for s in stats),
                          "misfit_first": stats[0]["misfit_before"], "misfit_last": stats[-1]["misfit_before"]},
         "per_kernel_warmup_step": per_kernel,
-        "kkt_apply": {"this_workload": kkt_here and {"GB_s": kkt_here["achieved"], "frac": kkt_here["frac"],
-                                                      "note": "183 MB per call: Infinity-Cache resident"}},
     }
     if not args.no_hbm_kkt:
-        p.close()
-        result["kkt_apply"]["hbm"] = hbm_kkt(torch, KKTProblem, args)
+        kk = kkt_matvec_rate(p, torch)
+        kk["note"] = ("cache-resident (working set below the 256 MB Infinity Cache)" if kk["GB_per_call"] < 0.25
+                      else "streams from HBM (working set above the 256 MB Infinity Cache)")
+        result["kkt_apply"] = kk
+        result["kkt_apply_GB_s"] = kk["GB_s"]
+        result["kkt_apply_frac_of_hbm_peak"] = kk["frac_of_hbm_peak"]
+    p.close()
     if not args.no_cpu_baseline:
         log(args, "timing the oracle on the host ...")
         result["cpu_baseline"] = cpu_baseline(inp, result["breakdown_ms"]["outer_iters"], args)

@@ -137,11 +137,16 @@ const char *kf_last_error(void);
 
 /* Create a problem: validates and copies the description and gamma ([nz][nx] FP64, host
  * or device: `gamma_on_device` says which), allocates device state and builds the PML
- * coefficients (Section 2).  `hip_stream` is a hipStream_t (NULL = default stream). */
+ * coefficients (Section 2).  `hip_stream` is a hipStream_t (NULL = default stream).
+ * Every gamma entry must be finite (checked on the host, or by a device reduction for a
+ * device gamma): otherwise KF_EINVAL and no problem is created. */
 kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t gamma_on_device,
                     void *hip_stream, kf_problem **out);
 kf_status kf_destroy(kf_problem *p);
-/* Replace gamma (device pointer, [nz][nx]); invalidates the factorisation and u_n. */
+/* Replace gamma (device pointer, [nz][nx]); invalidates the factorisation and u_n.
+ * The entries are checked by a device reduction first (the call synchronises the
+ * stream): a NaN or inf gives KF_EINVAL and leaves the problem's gamma, factors and
+ * u_n as they were, so no non-finite value reaches the factorisation. */
 kf_status kf_set_gamma(kf_problem *p, const double *gamma);
 /* Read gamma back into a device buffer [nz][nx]. */
 kf_status kf_get_gamma(kf_problem *p, double *gamma_out);
@@ -246,9 +251,19 @@ kf_status kf_profile_enable(kf_problem *p, int32_t on);
  * forward-sweep and back-substitution launches), "blu_mid", "blu_reduced_rhs",
  * "blu_chain", "blu_correct" (the middle columns, the separators' right-hand sides, the
  * separator system's cyclic-reduction levels, one launch per level, and the interior
- * correction), "precond_stage", "orth", "reduce".
+ * correction), "precond_stage", "gs_dot" (the first Gram-Schmidt pass's dot products of
+ * each Arnoldi step, with the norm of the new vector), "gs_update" (that pass's fused,
+ * normalising update), "orth" (the rest of the orthogonalisation: the occasional second
+ * pass, the Hessenberg and solution updates), "reduce".
  * Unknown names give KF_EINVAL. */
 kf_status kf_profile_read(kf_problem *p, const char *name, int64_t *launches, double *total_ms);
+/* Algorithmic work of the launches of a kernel family recorded since profiling was
+ * enabled, as the launchers count it: bytes that must cross HBM for "kkt_apply"
+ * (N_u (80 K + 8) + 32 N_g per call), "gs_dot" (the first Gram-Schmidt pass's dot
+ * products with |w|^2: nv + 1 packed vectors read) and "gs_update" (its update:
+ * nv + 1 vectors read, one written); block bytes plus vector bytes for "blu_chain"
+ * (the reduction levels); 0 for families that do not count it. */
+kf_status kf_profile_work(kf_problem *p, const char *name, double *work /*[host]*/);
 /* Restrict the recording to one kernel family (the names above), so that a timed run
  * carries the events of that family only; NULL or "" records every family again.
  * Counters are kept.  Unknown names give KF_EINVAL. */

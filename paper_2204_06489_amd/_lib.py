@@ -90,6 +90,7 @@ _SIGNATURES = {
     "kf_profile_enable": (C.c_int, [P, C.c_int32]),
     "kf_profile_read": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "kf_profile_only": (C.c_int, [P, C.c_char_p]),
+    "kf_profile_work": (C.c_int, [P, C.c_char_p, C.POINTER(C.c_double)]),
 }
 
 _lib = None

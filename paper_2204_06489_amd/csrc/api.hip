@@ -40,8 +40,9 @@ static hipEvent_t take_event(kf_problem *p) {
   p->ev_free.pop_back();
   return e;
 }
-ProfScope::ProfScope(kf_problem *p_, int id_) : p(p_), id(id_) {
+ProfScope::ProfScope(kf_problem *p_, int id_, double work) : p(p_), id(id_) {
   if (!p || id < 0 || !p->prof || !((p->prof_mask >> id) & 1u)) return;
+  p->counters[id].work += work;
   a = take_event(p);
   b = take_event(p);
   if (a) hipEventRecord(a, p->stream);
@@ -274,6 +275,11 @@ extern "C" kf_status kf_create(const kf_desc *desc, const double *gamma, int32_t
   if (st == KF_OK) st = h2d(p->d_rlist, rlist.data(), sizeof(int32_t) * p->nrec);
   if (st == KF_OK) st = h2d(p->d_wsq, wsq.data(), sizeof(double) * K * p->nru);
   if (st == KF_OK) st = h2d(p->d_w, p->w.data(), sizeof(double) * K * p->nrec);
+  if (st == KF_OK && gamma_on_device) {   // a device gamma is checked on the device before it is copied
+    int64_t bad = 0;
+    st = count_nonfinite(p, gamma, (int64_t)Nu, &bad);
+    if (st == KF_OK && bad) st = fail(KF_EINVAL, "gamma must be finite (" + std::to_string(bad) + " NaN/inf entries)");
+  }
   if (st == KF_OK) {
     hipError_t e = hipMemcpyAsync(p->gamma, gamma, sizeof(double) * Nu,
                                   gamma_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream);
@@ -320,6 +326,11 @@ extern "C" kf_status kf_get_solver_shape(kf_problem *p, int32_t *chunks, int32_t
 extern "C" kf_status kf_set_gamma(kf_problem *p, const double *gamma) {
   CHECK_ST(check_p(p));
   if (!gamma) return fail(KF_EINVAL, "gamma is NULL");
+  // checked before it replaces the problem's gamma: a NaN or inf must never reach the
+  // factorisation (the problem keeps its previous gamma and factors on failure)
+  int64_t bad = 0;
+  CHECK_ST(count_nonfinite(p, gamma, p->Nu, &bad));
+  if (bad) return fail(KF_EINVAL, "gamma must be finite (" + std::to_string(bad) + " NaN/inf entries)");
   HIP_TRY(hipMemcpyAsync(p->gamma, gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
   p->have_T64 = p->have_T32 = false;
   p->have_un = false;
@@ -624,24 +635,27 @@ struct FgmresOut {
 };
 
 // Orthogonalise Vn = V_{j+1} against V_0..V_j in FP64 by classical Gram-Schmidt with
-// selective reorthogonalisation, in up to three sweeps over the basis: the dot products
-// h1, the first update fused with the second pass's dot products h2 and |Vn'|, and the
-// second update fused with the final norm.  The second update runs only when the first
-// pass cancelled Vn below eta |Vn| (|Vn| recovered as sqrt(|Vn'|^2 + |h1|^2)); the test
-// runs on the device and a declined update's launches do nothing, so the step needs no
-// host round trip.  scal[0] receives |Vn| after the last pass; scal[6] holds the flag.
+// selective reorthogonalisation, and normalise it.  The usual step is two sweeps over
+// the basis: the dot products h1 = V^H Vn together with |Vn|^2, then the update
+// Vn <- (Vn - V h1) / |Vn - V h1| with the norm taken from |Vn|^2 - |h1|^2 (V is
+// orthonormal), decided on the device.  When the first pass cancels Vn below
+// max(eta, 0.1) |Vn| the norm is measured by the update's sweep instead; below
+// eta |Vn| a second pass (its dot products partly carried by the update's sweep, the
+// rest, and the second update fused with the final norm) follows, then a scaling
+// sweep.  Launches of a declined branch return at once, so the step needs no host
+// round trip.  scal: [0] |Vn| after the last pass (the Hessenberg entry), [4] |Vn|^2
+// before the first pass, [5] the first update's scale, [6] two int flags (second pass,
+// measured norm).
 static kf_status gram_schmidt(kf_problem *p, int j, double2 *Vn, double2 *h1, double2 *h2, double *scal,
                               double eta) {
   const int64_t N = p->Nxi;
-  int *flag = (int *)(scal + 6);
-  CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1));
-  // first update fused with the norm and the first dot products of a second pass
-  CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h1, Vn, N, h2, scal + 0));
-  CHECK_ST(reorth_test(p, j + 1, h1, scal + 0, eta, h2, flag));
-  // the second pass (nothing when the test declines it): its remaining dot products,
-  // then the update fused with the final norm
-  CHECK_ST(multidot_rest_c128(p, p->V, j + 1, Vn, N, h2, flag));
-  CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h2, Vn, N, nullptr, scal + 0, flag));
+  int *flags = (int *)(scal + 6);
+  CHECK_ST(multidot_c128(p, p->V, j + 1, Vn, N, h1, nullptr, scal + 4));
+  CHECK_ST(gs_decide(p, j + 1, h1, scal + 4, eta, h2, flags, scal + 0, scal + 5));
+  CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h1, Vn, N, h2, scal + 0, flags + 1, scal + 5, flags + 0));
+  CHECK_ST(multidot_rest_c128(p, p->V, j + 1, Vn, N, h2, flags));
+  CHECK_ST(axpy_dot_c128(p, p->V, j + 1, h2, Vn, N, nullptr, scal + 0, flags));
+  CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn, flags + 1));
   return KF_OK;
 }
 
@@ -697,7 +711,6 @@ static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, dou
       pt.start(PH_ORTH);
       CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal, eta));
       CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
-      CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
       pt.stop();
       HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 7 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
       HIP_TRY(hipStreamSynchronize(p->stream));
@@ -875,7 +888,8 @@ extern "C" kf_status helmholtz_adjoint_gradient(kf_problem *p, int32_t prec, con
 static const char *prof_names[PROF_N] = {"kkt_apply", "stencil",     "blu_factor",  "blu_sweep",
                                          "precond_stage", "orth",  "reduce",      "blu_fwd_c128",
                                          "blu_fwd_c64",   "blu_bwd_c128", "blu_bwd_c64", "blu_mid",
-                                         "blu_reduced_rhs", "blu_chain", "blu_correct"};
+                                         "blu_reduced_rhs", "blu_chain", "blu_correct", "gs_dot",
+                                         "gs_update"};
 
 extern "C" kf_status kf_profile_enable(kf_problem *p, int32_t on) {
   CHECK_ST(check_p(p));
@@ -895,6 +909,18 @@ extern "C" kf_status kf_profile_only(kf_problem *p, const char *name) {
   for (int i = 0; i < PROF_N; ++i)
     if (std::strcmp(name, prof_names[i]) == 0) {
       p->prof_mask = 1u << i;
+      return KF_OK;
+    }
+  return fail(KF_EINVAL, std::string("unknown kernel family ") + name);
+}
+
+extern "C" kf_status kf_profile_work(kf_problem *p, const char *name, double *work) {
+  CHECK_ST(check_p(p));
+  if (!name || !work) return fail(KF_EINVAL, "null pointer argument");
+  prof_collect(p);
+  for (int i = 0; i < PROF_N; ++i)
+    if (std::strcmp(name, prof_names[i]) == 0) {
+      *work = p->counters[i].work;
       return KF_OK;
     }
   return fail(KF_EINVAL, std::string("unknown kernel family ") + name);
@@ -1166,7 +1192,6 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
         double2 *Vn = p->V + (size_t)(j + 1) * N;
         CHECK_ST(gram_schmidt(p, j, Vn, h1, h2, scal, o->reorth_eta));
         CHECK_ST(arnoldi_finish(p, j, m, h1, h2, scal + 0, H, cs, sn, g, scal + 2));
-        CHECK_ST(scale_inv(p, N, scal + 0, Vn, Vn));
         HIP_TRY(hipMemcpyAsync(p->host_pinned, scal, 7 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
         const double hn = p->host_pinned[0], est = p->host_pinned[2] / bnorm[q];

@@ -1989,7 +1989,21 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
       bt.level = lv;
       if (tot == 0) continue;
       const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
-      ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph]);
+      // algorithmic bytes of a reduction level (single problem): its m x m blocks once,
+      // and per source the separators' vectors it reads and writes (edge separators,
+      // which have one term less, are counted with all terms)
+      double work = 0.0;
+      if (ph == 4 && prof && prof->P > 1) {
+        const int n = prof->P - 1, top = cr_top(n);
+        const double m = prof->nz, esz = 2.0 * sizeof(R);
+        int cnt = 0, terms = 0;
+        if (kind == 0 && lv < top) { cnt = n >> (lv + 1); terms = 2 * cnt; }
+        else if (kind == 1 && top == 0) { cnt = 1; terms = 1; }
+        else if (kind == 2 && lv < top) { cnt = ((n >> lv) + 1) / 2; terms = 3 * cnt; }
+        work = esz * (terms * m * m + (double)(terms + cnt) * prof->K * m);
+      }
+      ProfScope pf(prof, ph == 0 ? (fp32 ? PROF_FWD32 : PROF_FWD64) : ph == 2 ? (fp32 ? PROF_BWD32 : PROF_BWD64) : ids[ph],
+                   work);
       switch (ph) {
         case 0:
           if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 2>()), s, bt);

@@ -119,7 +119,10 @@ struct FactorBatch {
 // ---------------------------------------------------------------------------
 // problem state
 // ---------------------------------------------------------------------------
-struct ProfCounter { int64_t launches = 0; double ms = 0.0; };
+// per kernel family: launches, milliseconds and the algorithmic work of the recorded
+// launches (bytes for memory-bound families, flops for the block sweeps; 0 if the
+// family does not count it)
+struct ProfCounter { int64_t launches = 0; double ms = 0.0, work = 0.0; };
 
 struct kf_problem {
   kf_desc d;                      // copy; its host arrays point into the vectors below
@@ -186,13 +189,14 @@ struct kf_problem {
   bool prof = false;
   uint32_t prof_mask = ~0u;                    // families recorded (bit = ProfId)
   std::vector<hipEvent_t> ev_free;             // event pool
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[16];
-  ProfCounter counters[16];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[32];   // indexed by ProfId (< 32)
+  ProfCounter counters[32];
 };
 
 enum ProfId { PROF_KKT = 0, PROF_STENCIL, PROF_FACTOR, PROF_SWEEP, PROF_PRECOND, PROF_ORTH, PROF_REDUCE,
               PROF_FWD64, PROF_FWD32, PROF_BWD64, PROF_BWD32, PROF_MID, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT,
-              PROF_N };
+              PROF_GS_DOT, PROF_GS_UPDATE, PROF_N };
+static_assert(PROF_N <= 32, "profiling families are bits of a 32-bit mask");
 
 // error plumbing
 void set_error(const std::string &msg);
@@ -208,7 +212,7 @@ void set_error(const std::string &msg);
 // profiling helpers (no-ops unless enabled)
 struct ProfScope {
   kf_problem *p; int id; hipEvent_t a{}, b{};
-  ProfScope(kf_problem *p_, int id_);
+  ProfScope(kf_problem *p_, int id_, double work = 0.0);
   ~ProfScope();
 };
 
@@ -244,26 +248,33 @@ kf_status blu_solve_batch(const std::vector<kf_problem *> &ps, int adjoint, cons
 
 // reductions (deterministic, fixed order)
 kf_status per_source_norms(kf_problem *p, const double2 *x, int64_t n_per, int K, double *out_host);
+// number of NaN / inf entries of a real device array (synchronises the stream)
+kf_status count_nonfinite(kf_problem *p, const double *a, int64_t n, int64_t *count_host);
 kf_status dot_c128(kf_problem *p, const double2 *a, const double2 *b, int64_t n, double2 *out_dev);
 // `active` (device int, may be NULL): the launch does nothing when *active == 0
 kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev, const int *active = nullptr);
+// h_dev = V^H w (nv vectors); with nrm2_out also |w|^2 from the same sweep
 kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev,
-                        const int *active = nullptr);
+                        const int *active = nullptr, double *nrm2_out = nullptr);
 kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 *h_dev, double sign, double2 *w,
                          int64_t n, const int *active = nullptr);
-// w <- w - V h, then nrm_out = |w| and the first min(nv, 8) entries of h_out = V^H w
-// (h_out may be NULL), in one sweep over V; multidot_rest_c128 gives the other entries
+// w <- (w - V h) * scale[0] (scale NULL: 1), then nrm_out = |w| and the first
+// min(nv, 8) entries of h_out = V^H w (h_out may be NULL), in one sweep over V;
+// multidot_rest_c128 gives the other entries.  With scale the update itself always
+// runs and `active` gates only the norm; `active_dots` (if given) gates the dots.
 kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *h, double2 *w, int64_t n,
-                        double2 *h_out, double *nrm_out, const int *active = nullptr);
+                        double2 *h_out, double *nrm_out, const int *active = nullptr,
+                        const double *scale = nullptr, const int *active_dots = nullptr);
+// Gram-Schmidt decision from |w|^2 and h1 = V^H w before the first update (see krylov.hip)
+kf_status gs_decide(kf_problem *p, int nv, const double2 *h1, const double *wn2, double eta, double2 *h2, int *flags,
+                    double *nrm, double *scale);
 kf_status multidot_rest_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_out,
                              const int *active = nullptr);
-// DGKS test after one Gram-Schmidt pass: *flag = 1 if a second pass is needed, else h2 = 0
-kf_status reorth_test(kf_problem *p, int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2,
-                      int *flag);
 // FGMRES small dense algebra on the device (single-thread kernels)
 kf_status arnoldi_finish(kf_problem *p, int j, int m, const double2 *h1, const double2 *h2, const double *nrm,
                          double2 *H, double2 *cs, double2 *sn, double2 *g, double *resid);
-kf_status scale_inv(kf_problem *p, int64_t n, const double *nrm, const double2 *x, double2 *y);
+kf_status scale_inv(kf_problem *p, int64_t n, const double *nrm, const double2 *x, double2 *y,
+                    const int *active = nullptr);
 kf_status hess_backsolve(kf_problem *p, int nj, int m, const double2 *H, const double2 *g, double2 *y);
 kf_status set_g0(kf_problem *p, int m, const double *beta, double2 *g);
 kf_status imag_part(kf_problem *p, int64_t n, const double2 *x, double2 *y);

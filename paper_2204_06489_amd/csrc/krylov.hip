@@ -7,7 +7,7 @@ namespace {
 
 constexpr int RB = 256;      // reduction block size (4 wavefronts)
 constexpr int RG = 1024;     // reduction grid size (fixed => fixed summation order)
-constexpr int MDOT = 16;     // vectors per multi-dot pass
+constexpr int MDOT = 32;     // vectors per multi-dot sweep (at most)
 constexpr int FDOT = 8;      // dot products carried by the fused update-and-dot pass
 
 __device__ inline double wave_sum(double v) {
@@ -92,16 +92,27 @@ __global__ __launch_bounds__(RB) void k_finish(const double *__restrict__ partia
   }
 }
 
-// h[q] = V_q^H w for q in [q0, q0 + NQ): partial sums per block
+// number of non-finite entries (NaN or +-inf) of a real array: partial counts per block
+__global__ __launch_bounds__(RB) void k_nonfinite_partial(const double *__restrict__ a, int64_t n, double *partial) {
+  __shared__ double lds[8 * RB + 1];
+  double v[1] = {0.0};
+  for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB)
+    if (!isfinite(a[t])) v[0] += 1.0;
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// h[q] = V_q^H w for q in [q0, q0 + NQ): partial sums per block; with `norm` also
+// |w|^2 from the same sweep, stored after the 2 nv dot-product entries of the row
 template <int NQ>
 __global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restrict__ V, int q0, int nv,
                                                          const double2 *__restrict__ w, int64_t n, double *partial,
-                                                         int stride, const int *active) {
+                                                         int stride, int norm, const int *active) {
   if (active && *active == 0) return;
-  __shared__ double lds[8 * RB + 2 * NQ];
-  double v[2 * NQ];
+  __shared__ double lds[8 * RB + 2 * NQ + 1];
+  double v[2 * NQ + 1];
 #pragma unroll
-  for (int q = 0; q < 2 * NQ; ++q) v[q] = 0.0;
+  for (int q = 0; q < 2 * NQ + 1; ++q) v[q] = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x; t < n; t += (int64_t)RG * RB) {
     double2 y = w[t];
 #pragma unroll
@@ -112,21 +123,38 @@ __global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restri
         v[2 * q + 1] += x.x * y.y - x.y * y.x;
       }
     }
+    v[2 * NQ] += y.x * y.x + y.y * y.y;
   }
-  block_sum<2 * NQ>(v, lds);
-  if (threadIdx.x == 0)
+  block_sum<2 * NQ + 1>(v, lds);
+  if (threadIdx.x == 0) {
     for (int q = 0; q < 2 * NQ; ++q)
       if (q0 + q / 2 < nv) partial[(size_t)blockIdx.x * stride + 2 * q0 + q] = v[q];
+    if (norm) partial[(size_t)blockIdx.x * stride + 2 * nv] = v[2 * NQ];
+  }
 }
 
-// Fused Gram-Schmidt update: w <- w - sum_{q<nv} V_q h_q, written back, while the same
-// sweep accumulates the dot products V_q^H w (new w) for q < min(nv, FDOT) (WANT_DOTS)
-// and |w|^2 (new w).  partial row of a block: [2 * FDOT dots | norm^2].
+// One sweep of the multi-dot over vectors [q0, q0 + nq) with the smallest template
+// that holds them (8, 16 or 32 vectors per sweep).
+inline void launch_multidot(hipStream_t s, const double2 *V, int q0, int nq, int nv, const double2 *w, int64_t n,
+                            double *partial, int stride, int norm, const int *active) {
+  if (nq <= 8)
+    hipLaunchKernelGGL(k_multidot_partial<8>, dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride, norm, active);
+  else if (nq <= 16)
+    hipLaunchKernelGGL(k_multidot_partial<16>, dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride, norm, active);
+  else
+    hipLaunchKernelGGL(k_multidot_partial<32>, dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride, norm, active);
+}
+
+// Fused Gram-Schmidt update: w <- (w - sum_{q<nv} V_q h_q) * scale[0] (scale NULL: 1),
+// written back, while the same sweep accumulates the dot products V_q^H w (new w) for
+// q < min(nv, FDOT) (WANT_DOTS) and |w|^2 (new w).  partial row of a block:
+// [2 * FDOT dots | norm^2].
 template <bool WANT_DOTS>
 __global__ __launch_bounds__(RB) void k_axpy_dot_partial(const double2 *__restrict__ V, int nv,
                                                          const double2 *__restrict__ h, double2 *w, int64_t n,
-                                                         double *partial, const int *active) {
+                                                         double *partial, const double *scale, const int *active) {
   if (active && *active == 0) return;
+  const double sc = scale ? scale[0] : 1.0;
   constexpr int NQ = WANT_DOTS ? FDOT : 0;
   __shared__ double lds[8 * RB + 2 * FDOT + 1];
   // h is read with uniform indices (scalar loads): the coefficients sit in SGPRs
@@ -155,6 +183,7 @@ __global__ __launch_bounds__(RB) void k_axpy_dot_partial(const double2 *__restri
       for (int u = 0; u < 8; ++u)
         if (q0 + u < nv) y = csub(y, cmul(xv[u], hs[q0 + u]));
     }
+    y = cscale(y, sc);
     w[t] = y;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -191,17 +220,37 @@ __global__ __launch_bounds__(RB) void k_multiaxpy(const double2 *__restrict__ V,
   }
 }
 
-// Reorthogonalisation test of Daniel, Gragg, Kaufman and Stewart after one classical
-// Gram-Schmidt pass w' = w - V h: the norm of w before the pass is sqrt(|w'|^2 + |h|^2)
-// (V orthonormal); a second pass is needed only if |w'| < eta |w|.  flag = 1 asks for
-// it; otherwise the second pass's coefficients h2 are zero.
-__global__ void k_reorth_test(int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2, int *flag) {
+// Gram-Schmidt decision before the update w' = w - V h (V orthonormal, so
+// |w'|^2 = |w|^2 - |h|^2 up to rounding), from |w|^2 of the dot-product sweep:
+//   |w'| >= max(eta, 0.1) |w|: the cancellation is mild, |w'| is taken from that
+//     difference (relative error ~ nv eps |w|^2 / |w'|^2 <= 1e-13) and the update
+//     writes the normalised vector w' / |w'| directly: flags (0, 0);
+//   |w'| < eta |w| (test of Daniel, Gragg, Kaufman and Stewart): a second pass,
+//     flags (1, 1);
+//   otherwise (eta < 0.1 and strong cancellation): one pass, but |w'| is measured by
+//     the update's sweep and a scaling pass follows: flags (0, 1).
+// flags[0] asks for the second pass, flags[1] for the measured norm and the scaling;
+// h2 is zeroed unless flags[0].  nrm[0] receives |w'| in the first case, scale[0] the
+// factor the update applies (1 / |w'| or 1).
+__global__ void k_gs_decide(int nv, const double2 *h1, const double *wn2, double eta, double2 *h2, int *flags,
+                            double *nrm, double *scale) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = nrm_after[0] * nrm_after[0];
+  double s = 0.0;
   for (int i = 0; i < nv; ++i) s += cabs2(h1[i]);
-  const int f = nrm_after[0] < eta * sqrt(s) ? 1 : 0;
-  flag[0] = f;
-  if (!f)
+  const double w2 = wn2[0], nu2 = w2 - s;
+  const double thr = eta > 0.1 ? eta : 0.1;
+  int reorth = 0, measure = 0;
+  if (nu2 >= thr * thr * w2 && nu2 > 0.0) {
+    nrm[0] = sqrt(nu2);
+    scale[0] = 1.0 / nrm[0];
+  } else {
+    reorth = (eta > 0.0 && !(nu2 >= eta * eta * w2)) ? 1 : 0;
+    measure = 1;
+    scale[0] = 1.0;
+  }
+  flags[0] = reorth;
+  flags[1] = measure;
+  if (!reorth)
     for (int i = 0; i < nv; ++i) h2[i] = make_double2(0.0, 0.0);
 }
 
@@ -257,17 +306,32 @@ kf_status norm_c128(kf_problem *p, const double2 *a, int64_t n, double *out_dev,
   return KF_OK;
 }
 
+kf_status count_nonfinite(kf_problem *p, const double *a, int64_t n, int64_t *count_host) {
+  hipLaunchKernelGGL(k_nonfinite_partial, dim3(RG), dim3(RB), 0, p->stream, a, n, p->red);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red, 1, 1, 0, p->red_out, nullptr);
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(p->host_pinned, p->red_out, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  *count_host = (int64_t)p->host_pinned[0];
+  return KF_OK;
+}
+
 kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *w, int64_t n, double2 *h_dev,
-                        const int *active) {
-  ProfScope ps(p, PROF_ORTH);
-  int stride = 2 * nv;
+                        const int *active, double *nrm2_out) {
+  // algorithmic bytes: the nv basis vectors and w read once
+  ProfScope ps(p, nrm2_out ? PROF_GS_DOT : PROF_ORTH, 16.0 * (double)n * (nv + 1));
+  const int stride = 2 * nv + 1;
   for (int q0 = 0; q0 < nv; q0 += MDOT) {
-    hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, p->red, stride,
-                       active);
+    launch_multidot(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, p->red, stride, nrm2_out && q0 == 0, active);
     LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_finish, dim3(2 * nv), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev, active);
   LAUNCH_CHECK();
+  if (nrm2_out) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red + 2 * nv, 1, stride, 0, nrm2_out, active);
+    LAUNCH_CHECK();
+  }
   return KF_OK;
 }
 
@@ -284,12 +348,17 @@ kf_status multiaxpy_c128(kf_problem *p, const double2 *V, int nv, const double2 
 // w <- w - V h (nv vectors); then |w| and, with h_out, the first min(nv, FDOT) entries
 // of V^H w from the same sweep (the rest: multidot_rest_c128)
 kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *h, double2 *w, int64_t n,
-                        double2 *h_out, double *nrm_out, const int *active) {
-  ProfScope ps(p, PROF_ORTH);
+                        double2 *h_out, double *nrm_out, const int *active, const double *scale,
+                        const int *active_dots) {
+  // algorithmic bytes: the nv basis vectors and w read, w written
+  ProfScope ps(p, scale ? PROF_GS_UPDATE : PROF_ORTH, 16.0 * (double)n * (nv + 2));
   if (nv > 256) { set_error("too many Krylov vectors for the fused update"); return KF_EINVAL; }
   const int stride = 2 * FDOT + 1;
-  if (h_out) hipLaunchKernelGGL(k_axpy_dot_partial<true>, dim3(RG), dim3(RB), 0, p->stream, V, nv, h, w, n, p->red, active);
-  else hipLaunchKernelGGL(k_axpy_dot_partial<false>, dim3(RG), dim3(RB), 0, p->stream, V, nv, h, w, n, p->red, active);
+  const int *gate = scale ? nullptr : active;   // with a scale the update itself always runs
+  if (h_out)
+    hipLaunchKernelGGL(k_axpy_dot_partial<true>, dim3(RG), dim3(RB), 0, p->stream, V, nv, h, w, n, p->red, scale, gate);
+  else
+    hipLaunchKernelGGL(k_axpy_dot_partial<false>, dim3(RG), dim3(RB), 0, p->stream, V, nv, h, w, n, p->red, scale, gate);
   LAUNCH_CHECK();
   // norm: the last entry of each partial row
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, p->stream, p->red + (h_out ? 2 * FDOT : 0), 1, stride, 1, nrm_out,
@@ -297,9 +366,18 @@ kf_status axpy_dot_c128(kf_problem *p, const double2 *V, int nv, const double2 *
   LAUNCH_CHECK();
   if (h_out) {
     const int nd = nv < FDOT ? nv : FDOT;
-    hipLaunchKernelGGL(k_finish, dim3(2 * nd), dim3(RB), 0, p->stream, p->red, 2 * nd, stride, 0, (double *)h_out, active);
+    hipLaunchKernelGGL(k_finish, dim3(2 * nd), dim3(RB), 0, p->stream, p->red, 2 * nd, stride, 0, (double *)h_out,
+                       active_dots ? active_dots : active);
     LAUNCH_CHECK();
   }
+  return KF_OK;
+}
+
+kf_status gs_decide(kf_problem *p, int nv, const double2 *h1, const double *wn2, double eta, double2 *h2, int *flags,
+                    double *nrm, double *scale) {
+  ProfScope ps(p, PROF_ORTH);
+  hipLaunchKernelGGL(k_gs_decide, dim3(1), dim3(64), 0, p->stream, nv, h1, wn2, eta, h2, flags, nrm, scale);
+  LAUNCH_CHECK();
   return KF_OK;
 }
 
@@ -311,8 +389,7 @@ kf_status multidot_rest_c128(kf_problem *p, const double2 *V, int nv, const doub
   double *red2 = p->red + (size_t)RG * (2 * FDOT + 1);
   const int stride2 = 2 * nv;
   for (int q0 = FDOT; q0 < nv; q0 += MDOT) {
-    hipLaunchKernelGGL(k_multidot_partial<MDOT>, dim3(RG), dim3(RB), 0, p->stream, V, q0, nv, w, n, red2, stride2,
-                       active);
+    launch_multidot(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, red2, stride2, 0, active);
     LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_finish, dim3(2 * (nv - FDOT)), dim3(RB), 0, p->stream, red2 + 2 * FDOT, 2 * (nv - FDOT), stride2,
@@ -388,7 +465,8 @@ __global__ void k_set_g0(int m, const double *beta, double2 *g) {
   for (int i = t; i <= m; i += blockDim.x) g[i] = make_double2(i == 0 ? beta[0] : 0.0, 0.0);
 }
 
-__global__ void k_scale_inv(int64_t n, const double *nrm, const double2 *x, double2 *y) {
+__global__ void k_scale_inv(int64_t n, const double *nrm, const double2 *x, double2 *y, const int *active) {
+  if (active && *active == 0) return;
   double s = nrm[0] > 0.0 ? 1.0 / nrm[0] : 0.0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
     y[t] = cscale(x[t], s);
@@ -413,13 +491,6 @@ kf_status arnoldi_finish(kf_problem *p, int j, int m, const double2 *h1, const d
   LAUNCH_CHECK();
   return KF_OK;
 }
-kf_status reorth_test(kf_problem *p, int nv, const double2 *h1, const double *nrm_after, double eta, double2 *h2,
-                      int *flag) {
-  ProfScope ps(p, PROF_ORTH);
-  hipLaunchKernelGGL(k_reorth_test, dim3(1), dim3(64), 0, p->stream, nv, h1, nrm_after, eta, h2, flag);
-  LAUNCH_CHECK();
-  return KF_OK;
-}
 kf_status hess_backsolve(kf_problem *p, int nj, int m, const double2 *H, const double2 *g, double2 *y) {
   hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, p->stream, nj, m, H, g, y);
   LAUNCH_CHECK();
@@ -430,9 +501,9 @@ kf_status set_g0(kf_problem *p, int m, const double *beta, double2 *g) {
   LAUNCH_CHECK();
   return KF_OK;
 }
-kf_status scale_inv(kf_problem *p, int64_t n, const double *nrm, const double2 *x, double2 *y) {
+kf_status scale_inv(kf_problem *p, int64_t n, const double *nrm, const double2 *x, double2 *y, const int *active) {
   ProfScope ps(p, PROF_ORTH);
-  hipLaunchKernelGGL(k_scale_inv, dim3(grid_for(n)), dim3(256), 0, p->stream, n, nrm, x, y);
+  hipLaunchKernelGGL(k_scale_inv, dim3(grid_for(n)), dim3(256), 0, p->stream, n, nrm, x, y, active);
   LAUNCH_CHECK();
   return KF_OK;
 }

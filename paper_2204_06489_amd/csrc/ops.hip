@@ -363,7 +363,10 @@ kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *
 template kf_status launch_stencil<double>(kf_problem *, int, const double2 *, double2 *);
 template kf_status launch_stencil<float>(kf_problem *, int, const float2 *, float2 *);
 
-kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
+// y = M xi.  part / part_groups: buffer of the source groups' parts of the control
+// row ([groups][Ng] c128) and the most groups it holds.
+static kf_status launch_kkt_apply_into(kf_problem *p, const double2 *xi, double2 *y, double2 *part,
+                                       int part_groups) {
   if (!p->kkt_resident) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -381,18 +384,20 @@ kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
   const unsigned chunks = (unsigned)((p->Nu + KKT_WG - 1) / KKT_WG);
   const double bytes = (double)p->Nu * (80.0 * p->K + 8.0);
   int groups = bytes <= 192e6 ? (int)(p->kkt_resident / chunks) : (p->K + 4) / 5;
-  groups = groups < 1 ? 1 : (groups > p->kkt_groups_max ? p->kkt_groups_max : groups);
+  groups = groups < 1 ? 1 : (groups > part_groups ? part_groups : groups);
   const int kpg = (p->K + groups - 1) / groups;
   groups = (p->K + kpg - 1) / kpg;
   {
-    ProfScope ps(p, PROF_KKT);
+    // algorithmic bytes: du, lambda, u_n read and y_u, y_lambda written per node and
+    // source; gamma per node; ds read and y_s written per control node
+    ProfScope ps(p, PROF_KKT, bytes + 32.0 * (double)p->Ng);
     hipLaunchKernelGGL(k_kkt_apply, dim3(chunks * groups), dim3(KKT_WG), 0, p->stream, p->grid(), p->K, kpg,
-                       p->nxc, chunks, p->eps, xi, p->u_n, y, p->ys_part);
+                       p->nxc, chunks, p->eps, xi, p->u_n, y, part);
     LAUNCH_CHECK();
     if (groups > 1) {
       hipLaunchKernelGGL(k_kkt_ys_finish, dim3((unsigned)((p->Ng + 255) / 256)), dim3(256), 0, p->stream,
                          (size_t)p->Ng, groups, p->eps, p->omega * p->omega, xi + (size_t)p->K * p->Nu,
-                         p->ys_part, y + (size_t)p->K * p->Nu);
+                         part, y + (size_t)p->K * p->Nu);
       LAUNCH_CHECK();
     }
   }
@@ -401,6 +406,10 @@ kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
                      (size_t)p->Nu, xi, y);
   LAUNCH_CHECK();
   return KF_OK;
+}
+
+kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
+  return launch_kkt_apply_into(p, xi, y, p->ys_part, p->kkt_groups_max);
 }
 
 kf_status launch_precond_stage2(kf_problem *p, const double2 *y, double2 *z) {

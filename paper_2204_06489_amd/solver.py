@@ -247,6 +247,12 @@ class KKTProblem:
         check(lib().kf_profile_read(self._h, name.encode(), C.byref(n), C.byref(ms)))
         return int(n.value), float(ms.value)
 
+    def profile_work(self, name):
+        """Algorithmic work (bytes) the library counted for a kernel family's recorded launches."""
+        w = C.c_double()
+        check(lib().kf_profile_work(self._h, name.encode(), C.byref(w)))
+        return float(w.value)
+
     def profile_only(self, name=None):
         """Record one kernel family only (None: all families)."""
         check(lib().kf_profile_only(self._h, (name or "").encode()))

@@ -5,9 +5,11 @@ preconditioned GMRES with the exact banded-LU preconditioner of eq. precond) and
 stores what the mixed-precision GPU step is compared with: ds, gamma_{n+1}, the
 misfit before and after the step, and the KKT relative residual reached.
 
-Usage: python -m tests.golden.make_newton_reference CONFIG FREQ_INDEX OUT.npz
-  c2 0 tests/golden/c2_newton_oracle.npz   801 x 281, 80 sources, 5 Hz (about an hour of CPU)
-  c1 1 tests/golden/c1_newton_oracle.npz   401 x 141, 40 sources, 5 Hz (a few minutes)
+Usage: python -m tests.golden.make_newton_reference CONFIG FREQ_INDEX OUT.npz [TOL]
+  c2 0 tests/golden/c2_newton_oracle.npz 1e-10   801 x 281, 80 sources, 5 Hz (about an hour of CPU)
+  c1 1 tests/golden/c1_newton_oracle.npz 1e-12   401 x 141, 40 sources, 5 Hz (several minutes)
+TOL is the GMRES relative residual target (default 1e-12, near the FP64 floor of
+these systems, so that the stored step is the exact KKT solution to ~1e-12).
 """
 
 import sys
@@ -20,7 +22,7 @@ from synthetic.configs import make_problem_inputs
 
 
 
-def main(config, freq_index, out):
+def main(config, freq_index, out, tol=1e-12):
     t0 = time.time()
     inp = make_problem_inputs(config, freq_index)
     pt = Problem.from_inputs(inp, gamma=inp["gamma_true"], eps=inp["eps"])
@@ -44,7 +46,7 @@ def main(config, freq_index, out):
             print(f"  precond {it[0]} ({time.time() - t0:.0f}s)", flush=True)
         return p.precond_apply(u_n, v)
 
-    xi, hist, _ = gmres_right(apply_M, apply_P, b, tol=1e-10, restart=15, maxit=400)
+    xi, hist, _ = gmres_right(apply_M, apply_P, b, tol=tol, restart=15, maxit=600)
     rel = np.linalg.norm(b - M @ xi) / np.linalg.norm(b)
     ds = p.unpack(xi)[1]
     g1 = p.update(ds)
@@ -53,12 +55,12 @@ def main(config, freq_index, out):
     mis0 = np.linalg.norm(r) / np.linalg.norm(d)
     mis1 = np.linalg.norm(d - q.sample(u1)) / np.linalg.norm(d)
     np.savez_compressed(out, ds=ds, gamma_next=g1, misfit_before=mis0, misfit_after=mis1, rel_res=rel,
-                        iterations=len(hist) - 1, d=d)
+                        iterations=len(hist) - 1, d=d, tol=tol)
     print(f"done: {len(hist) - 1} iterations rel_res={rel:.2e} misfit {mis0:.4e} -> {mis1:.4e} "
           f"({time.time() - t0:.0f}s)", flush=True)
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 4:
+    if len(sys.argv) not in (4, 5):
         sys.exit(__doc__)
-    main(sys.argv[1], int(sys.argv[2]), sys.argv[3])
+    main(sys.argv[1], int(sys.argv[2]), sys.argv[3], *(float(a) for a in sys.argv[4:]))

@@ -1,15 +1,21 @@
 """The Newton step on the timed workloads against the FP64 oracle, in every precision:
-801 x 281 with 80 sources and 401 x 141 with 40 sources, both at 5 Hz.
+401 x 141 with 40 sources at 3, 5 and 7 Hz, and 801 x 281 with 80 sources at 5 Hz.
 
-Each reference (tests/golden/c2_newton_oracle.npz and c1_newton_oracle.npz, written by
-make_newton_reference.py from the oracle alone) is the oracle's Newton step:
-banded-LU forward solves, the assembled KKT matrix and GMRES with the exact
-block-triangular preconditioner to a relative residual of 1e-10.  The GPU step runs with complex64 block solves inside the inexact
-preconditioner and complex64 sweeps with FP64 refinement for u_n, FP64 FGMRES,
-orthogonalisation, residuals and update.  Refined to the same 1e-10, its step, gamma
-update and misfits must agree with the oracle's to 1e-6 relative; the errors of the
-other forms (FP64 throughout, and the 1e-6 tolerance of the timed workload) are
-printed beside it.
+Each reference (tests/golden/*_newton_oracle.npz, written by make_newton_reference.py
+from the oracle alone) is the oracle's Newton step: banded-LU forward solves, the
+assembled KKT matrix and GMRES with the exact block-triangular preconditioner.  The
+401 x 141 references are solved to the FP64 floor of their systems (a true relative
+residual of ~8e-12, asked 1e-12), so that they are the exact KKT step to ~1e-11; the
+801 x 281 reference is solved to 1e-10 (an hour of CPU).
+
+Forms of the GPU step:
+* FP64 throughout (exact preconditioner, FP64 block solves, FGMRES to 1e-11): its ds
+  and gamma update must match the 401 x 141 references to 1e-10 relative, the bar of
+  the FP64 path;
+* mixed precision refined to 1e-10 (complex64 block solves inside the inexact
+  preconditioner, complex64 sweeps with FP64 refinement for u_n, FP64 FGMRES,
+  orthogonalisation, residuals and update): within 1e-6 of the reference;
+* the timed form (mixed precision, FGMRES to 1e-6): its gamma within 1e-5.
 """
 
 import os
@@ -27,12 +33,14 @@ from paper_2204_06489_amd.solver import KKTProblem  # noqa: E402
 from synthetic.configs import make_problem_inputs  # noqa: E402
 from tests.gpu_cases import rel, to_np  # noqa: E402
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "{}_newton_oracle.npz")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GOLDEN = {("c1", 0): "c1_3Hz_newton_oracle.npz", ("c1", 1): "c1_newton_oracle.npz",
+          ("c1", 2): "c1_7Hz_newton_oracle.npz", ("c2", 0): "c2_newton_oracle.npz"}
 
 FORMS = {   # name: (pc, fwd_prec, rtol)
     "mixed, refined to 1e-10": ("inexact", "mixed", 1e-10),
     "mixed, 1e-6 (timed form)": ("inexact", "mixed", 1e-6),
-    "FP64, refined to 1e-10": ("exact", "c128", 1e-10),
+    "FP64, refined to 1e-11": ("exact", "c128", 1e-11),
 }
 
 
@@ -43,9 +51,12 @@ def _step(p, d, g0, pc, fwd, rtol):
     return to_np(p.unpack(xi)[1]), to_np(g1), st
 
 
-@pytest.mark.parametrize("cfg,fi", [("c1", 1), ("c2", 0)])
+@pytest.mark.parametrize("cfg,fi", [("c1", 1), ("c1", 0), ("c1", 2), ("c2", 0)])
 def test_step_matches_oracle_in_every_precision(cfg, fi):
-    ref = np.load(GOLDEN.format(cfg))
+    path = os.path.join(GOLDEN_DIR, GOLDEN[(cfg, fi)])
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    ref = np.load(path)
     inp = make_problem_inputs(cfg, fi)
     print(f"[case] {cfg} {inp['nx']}x{inp['nz']} K={inp['K']} {inp['freq']} Hz", flush=True)
     p = KKTProblem.from_inputs(inp, reg_on_update=True)
@@ -60,14 +71,17 @@ def test_step_matches_oracle_in_every_precision(cfg, fi):
             gamma=rel(g1, ref["gamma_next"]),
             misfit_before=abs(st["misfit_before"] - float(ref["misfit_before"])) / float(ref["misfit_before"]),
             misfit_after=abs(st["misfit_after"] - float(ref["misfit_after"])) / float(ref["misfit_after"]),
-            iters=st["outer_iters"], ms=st["t_total_ms"])
+            iters=st["outer_iters"], ms=st["t_total_ms"], rel_res=st["rel_res"])
     print(f"oracle: {int(ref['iterations'])} GMRES iterations, rel. res {float(ref['rel_res']):.1e}, "
           f"misfit {float(ref['misfit_before']):.6f} -> {float(ref['misfit_after']):.6f}")
     for name, r in rows.items():
         print(f"{name:28s} ds {r['ds']:.2e}  gamma {r['gamma']:.2e}  misfit before {r['misfit_before']:.2e}  "
-              f"after {r['misfit_after']:.2e}  ({r['iters']} iterations, {r['ms']:.0f} ms)")
+              f"after {r['misfit_after']:.2e}  ({r['iters']} iterations, rel. res {r['rel_res']:.1e}, "
+              f"{r['ms']:.0f} ms)")
     for key in ("ds", "gamma", "misfit_before", "misfit_after"):
         assert rows["mixed, refined to 1e-10"][key] <= 1e-6, key
-        assert rows["FP64, refined to 1e-10"][key] <= 1e-6, key
+    fp64_bar = 1e-10 if float(ref["rel_res"]) <= 1e-11 else 1e-6
+    for key in ("ds", "gamma", "misfit_before", "misfit_after"):
+        assert rows["FP64, refined to 1e-11"][key] <= fp64_bar, key
     # the timed tolerance: the step is accurate to what a 1e-6 residual allows
     assert rows["mixed, 1e-6 (timed form)"]["gamma"] <= 1e-5

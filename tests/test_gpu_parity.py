@@ -31,7 +31,11 @@ def _case(seed=0, **kw):
     return inp
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+# 17 sources: the stencil kernel's source groups 0, 1 and a ragged group 2
+STENCIL_SHAPES = SHAPES + [dict(nx=133, nz=37, npml=6, K=17)]
+
+
+@pytest.mark.parametrize("shape", STENCIL_SHAPES)
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_stencil_matches_assembled_matrix(shape, adjoint):
     inp = _case(**shape)
@@ -43,6 +47,58 @@ def test_stencil_matches_assembled_matrix(shape, adjoint):
     assert rel(y, ref) <= 1e-13
     y32 = to_np(gpu.stencil_apply(to_dev(x, torch.complex64), adjoint=adjoint))
     assert rel(y32, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_stencil_full_size_matches_assembled_matrix(adjoint):
+    """801 x 281 with 80 sources (ten source groups, XCD-contiguous chunks), c128 and c64,
+    every output against the oracle's assembled A."""
+    from oracle.helmholtz import assemble_A
+    from paper_2204_06489_amd.solver import KKTProblem
+    inp = make_problem_inputs("c2", 0)
+    print(f"[case] stencil 801x281 K=80 adjoint={adjoint}", flush=True)
+    gpu = KKTProblem.from_inputs(inp, eps=1.0)
+    A = assemble_A(inp["nx"], inp["nz"], inp["h"], inp["npml"], inp["omega"], inp["gamma0"],
+                   inp["pml_r0"], inp["pml_cref"])
+    M = (A.conj().T if adjoint else A).tocsr()
+    x = complex_normal(gpu.field_shape, seed=31)
+    ref = np.stack([M @ x[k].ravel() for k in range(gpu.K)]).reshape(x.shape)
+    y = to_np(gpu.stencil_apply(to_dev(x), adjoint=adjoint))
+    assert rel(y, ref) <= 1e-13
+    for k in (0, 7, 8, 40, 79):          # per source: no group lost or shifted
+        assert rel(y[k], ref[k]) <= 1e-13
+    y32 = to_np(gpu.stencil_apply(to_dev(x, torch.complex64), adjoint=adjoint))
+    assert rel(y32, ref) <= 2e-6
+    for k in (0, 7, 8, 40, 79):
+        assert rel(y32[k], ref[k]) <= 2e-6
+    gpu.close()
+
+
+def test_block_solve_largest_batched_grid_matches_banded_lu():
+    """The 1001 x 351 grid of the five-frequency batch (10 Hz, 100 sources, 351-row
+    columns on the vector units) in c128 and c64, sampled sources against the banded LU."""
+    from oracle.kkt import Problem
+    from paper_2204_06489_amd.solver import KKTProblem
+    inp = make_problem_inputs("c4", 4)
+    print(f"[case] block solve {inp['nx']}x{inp['nz']} K={inp['K']} {inp['freq']} Hz", flush=True)
+    gpu = KKTProblem.from_inputs(inp, eps=1.0)
+    b = complex_normal(gpu.field_shape, seed=41)
+    x, st = gpu.helmholtz_solve(to_dev(b), prec="c128", rtol=1e-30)
+    x = to_np(x)
+    assert st["rel_res_max"] <= 1e-11
+    x32, st32 = gpu.helmholtz_solve(to_dev(b, torch.complex64), prec="c64", rtol=1e-30)
+    x32 = to_np(x32)
+    assert st32["rel_res_max"] <= 1e-3
+    gpu.close()
+    print("[case] oracle banded LU of 1001x351 ...", flush=True)
+    orc = Problem.from_inputs(inp, eps=1.0)
+    pick = [0, 1, 37, 63, 99]
+    ref = orc.lu.solve(b[pick])
+    for i, k in enumerate(pick):
+        e64, e32 = rel(x[k], ref[i]), rel(x32[k], ref[i])
+        print(f"source {k}: c128 error {e64:.2e}, c64 error {e32:.2e} (c64 residual {st32['rel_res_max']:.1e})")
+        assert e64 <= 1e-10
+        assert e32 <= 1e-2      # FP32 factors: the residual bound above times the condition number
 
 
 @pytest.mark.parametrize("shape", SHAPES)
