@@ -206,6 +206,19 @@ kf_status helmholtz_solve(kf_problem *p, int32_t adjoint, int32_t prec, const vo
  * c128 (no aliasing).  Asynchronous. */
 kf_status kkt_apply(kf_problem *p, const void *xi, void *y);
 
+/* kkt_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * result as kkt_apply (up to the order of the sum over source groups), but the source
+ * groups' parts of the control row live in a file-scope device array of
+ * KF_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of the
+ * problem's buffer.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); the problem, xi and y are the caller's.  A control row of more than
+ * KF_NOALLOC_SCRATCH_BYTES / 16 nodes gives KF_ESHAPE; fewer source groups are used when
+ * the array holds fewer than kkt_apply would take.  Calls on one GPU share the array:
+ * calls that overlap (different streams or threads) race.  Asynchronous. */
+#define KF_NOALLOC_SCRATCH_BYTES (64u << 20)
+kf_status kkt_apply_noalloc(kf_problem *p, const void *xi, void *y);
+
 /* z = P^-1 y for the block-triangular preconditioner of eq. precond (pc = KF_PC_EXACT) or
  * eq. precond_approx (KF_PC_INEXACT):
  *   z_lam = A^-* y_u;  z_s = (y_s + P^* z_lam) / eps;  z_u = A^-1 (y_lam + P z_s).

@@ -76,6 +76,7 @@ _SIGNATURES = {
     "helmholtz_solve": (C.c_int, [P, C.c_int32, C.c_int32, P, P, C.c_double, C.c_int32,
                                   C.POINTER(KfSolveStats)]),
     "kkt_apply": (C.c_int, [P, P, P]),
+    "kkt_apply_noalloc": (C.c_int, [P, P, P]),
     "precond_apply": (C.c_int, [P, C.c_int32, P, P]),
     "newton_step": (C.c_int, [P, P, C.POINTER(KfNewtonOpts), P, P, C.c_int32, C.POINTER(KfNewtonStats)]),
     "helmholtz_adjoint_gradient": (C.c_int, [P, C.c_int32, P, P, P]),

@@ -585,6 +585,14 @@ extern "C" kf_status kkt_apply(kf_problem *p, const void *xi, void *y) {
   return launch_kkt_apply(p, (const double2 *)xi, (double2 *)y);
 }
 
+extern "C" kf_status kkt_apply_noalloc(kf_problem *p, const void *xi, void *y) {
+  CHECK_ST(check_p(p));
+  if (!xi || !y) return fail(KF_EINVAL, "xi or y is NULL");
+  if (xi == y) return fail(KF_EINVAL, "xi and y must not alias");
+  if (!p->have_un) return fail(KF_ESTATE, "no background field (kf_set_background or newton_step first)");
+  return launch_kkt_apply_noalloc(p, (const double2 *)xi, (double2 *)y);
+}
+
 static kf_status precond_impl(kf_problem *p, int pc, const double2 *y, double2 *z) {
   const size_t Ku = (size_t)p->K * p->Nu;
   const double2 *yu = y;

@@ -222,6 +222,7 @@ struct ProfScope {
 kf_status launch_pml(kf_problem *p, const kf_desc &d);
 template <typename R> kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *y);
 kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y);
+kf_status launch_kkt_apply_noalloc(kf_problem *p, const double2 *xi, double2 *y);   // scratch array, no allocation
 kf_status launch_precond_stage2(kf_problem *p, const double2 *y, double2 *z);
 kf_status launch_sources(kf_problem *p, double2 *f);
 kf_status launch_residual(kf_problem *p, const double2 *d_obs, const double2 *u, double2 *r, double2 *wr);

@@ -7,6 +7,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace {
 
@@ -410,6 +411,56 @@ static kf_status launch_kkt_apply_into(kf_problem *p, const double2 *xi, double2
 
 kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y) {
   return launch_kkt_apply_into(p, xi, y, p->ys_part, p->kkt_groups_max);
+}
+
+// ---------------------------------------------------------------------------
+// The KKT matvec for callers that cannot allocate (graph capture, serving loops):
+// the source groups' parts of the control row go to a file-scope device array
+// instead of the problem's own buffer.  Each GPU holds its copy of the array for the
+// life of the process; its device address is looked up once per device.  Every part
+// the finish kernel reads is written by the same launch first, so nothing needs
+// clearing; calls that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;   // KF_NOALLOC_SCRATCH_BYTES
+static __device__ __align__(256) double2 scratch[NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+static_assert(NOALLOC_SCRATCH_BYTES == KF_NOALLOC_SCRATCH_BYTES, "header and library agree on the scratch size");
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double2 *scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static kf_status scratch_address(double2 **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) { set_error("device index out of range"); return KF_EHIP; }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e));
+      return KF_EHIP;
+    }
+    scratch_ptr[dev] = (double2 *)ptr;
+  }
+  *out = scratch_ptr[dev];
+  return KF_OK;
+}
+
+kf_status launch_kkt_apply_noalloc(kf_problem *p, const double2 *xi, double2 *y) {
+  const size_t per_group = sizeof(double2) * (size_t)p->Ng;
+  if (per_group > NOALLOC_SCRATCH_BYTES) {
+    set_error("kkt_apply_noalloc: the control row (" + std::to_string(per_group) +
+              " bytes) exceeds the scratch array (" + std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes)");
+    return KF_ESHAPE;
+  }
+  double2 *part = nullptr;
+  kf_status st = scratch_address(&part);
+  if (st != KF_OK) return st;
+  const size_t fit = NOALLOC_SCRATCH_BYTES / per_group;
+  return launch_kkt_apply_into(p, xi, y, part, (int)std::min<size_t>(fit, (size_t)p->kkt_groups_max));
 }
 
 kf_status launch_precond_stage2(kf_problem *p, const double2 *y, double2 *z) {
