@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--fwd-prec", default=None, choices=["c128", "mixed"],
                     help="background solve: default mixed for c2, c128 otherwise")
     ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--solver", default="fgmres", choices=["fgmres", "rsgn"],
+                    help="rsgn: the reduced-space GN step by CG on the normal equations (Section 3), "
+                         "to E_cg <= rtol, block solves in FP64 (c128) or, with --fwd-prec mixed, complex64 + "
+                         "FP64 refinement")
+    ap.add_argument("--continuation", action="store_true",
+                    help="c1 only: 3 -> 5 -> 7 Hz, 5 Newton steps each, the model carried over")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-kkt", action="store_true")
@@ -137,7 +143,7 @@ SINGLE = ("kkt_apply", "gs_dot", "gs_update", "blu_fwd_c64", "blu_bwd_c64", "blu
           "blu_mid", "blu_fwd_c128", "blu_bwd_c128")
 FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stage", "orth", "reduce")
 KERNEL_NAMES = {
-    "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial (+ k_finish)",
+    "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial<8|16, true> (+ k_finish)",
     "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
     "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_mfma", "blu_chain": "k_cr_solve",
     "blu_mid": "k_sweep_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
@@ -407,6 +413,100 @@ def bench_c4(args, torch, KKTProblem):
     print(json.dumps(result), flush=True)
 
 
+def bench_continuation(args, torch, KKTProblem):
+    """The 401 x 141, 40-source workload as its configuration states it: 3, 5 and 7 Hz
+    solved one after another, 5 Newton steps each, the model carried from one frequency
+    to the next (newton_continuation); plain FP64 by default (exact preconditioner)."""
+    import numpy as np
+    from synthetic.configs import make_problem_inputs, CONFIGS
+    from paper_2204_06489_amd.solver import newton_continuation
+    cfg = CONFIGS["c1"]
+    inps = [make_problem_inputs("c1", fi) for fi in range(len(cfg["freqs"]))]
+    steps = [cfg["newton_steps"]] * len(inps)
+    ds, probs = [], []
+    for inp in inps:
+        log(args, f"c1 continuation problem {inp['nx']}x{inp['nz']} f={inp['freq']:g} Hz K={inp['K']}")
+        ds.append(observed_data(inp, torch, KKTProblem))
+        p = KKTProblem.from_inputs(inp, reg_on_update=True)
+        if args.shape:
+            c, ns = (int(v) for v in args.shape.split(","))
+            p.set_solver_shape(c, ns)
+        elif not args.no_autotune:
+            p.autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)
+        probs.append(p)
+    g0 = torch.as_tensor(inps[0]["gamma0"]).cuda()
+    kw = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec=args.fwd_prec, fwd_rtol=1e-10)
+    for w in range(args.warmup):     # one short pass (one step per frequency) as warm-up
+        probs[0].set_gamma(g0)
+        newton_continuation(probs, ds, [1] * len(probs), **kw)
+    probs[0].set_gamma(g0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, st = newton_continuation(probs, ds, steps, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n = sum(steps)
+    i = 0
+    per = []
+    for inp, k in zip(inps, steps):
+        sl = st[i:i + k]
+        i += k
+        per.append({"freq": inp["freq"], "steps": k, "ms": [round(s["t_total_ms"], 1) for s in sl],
+                    "outer_iters": [s["outer_iters"] for s in sl],
+                    "misfit": [round(s["misfit_before"], 5) for s in sl]})
+        log(args, f"{inp['freq']:g} Hz: iters {per[-1]['outer_iters']} ms {per[-1]['ms']} misfit {per[-1]['misfit']}")
+    result = {
+        "metric": "Newton-step time to KKT rel. res 1e-6", "value": elapsed / n, "unit": "s", "n_gpus": 1,
+        "steps": n, "warmup": args.warmup, "ms_per_step": elapsed / n * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if args.pc == "exact" and args.fwd_prec == "c128" else "c128 outer (FP64) + c64 inner block solves",
+        "data": "synthetic",
+        "config": {"workload": (f"c1 frequency continuation: 401x141 grid, h=10 m, 20-cell PML, faulted-lens model, "
+                                f"40 sources, 401 receivers, 3 -> 5 -> 7 Hz with {steps[0]} Newton steps each, the "
+                                f"model carried over, {args.pc} preconditioner, FGMRES({args.restart}) to {args.rtol:g}"),
+                   "global_batch": inps[0]["K"], "parallelism": "single GPU"},
+        "total_s": elapsed, "per_frequency": per,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def bench_rsgn(args, torch, p, d, inp):
+    """Reduced-space GN steps by CG (rsgn_cg_step) on the workload: the paper's baseline
+    method on the same problem, to E_cg <= rtol."""
+    import numpy as np
+    prec = "mixed" if args.fwd_prec == "mixed" else "c128"
+    kw = dict(rtol=args.rtol, maxit=2000, solve_prec=prec, solve_rtol=1e-10, fwd_prec=prec, fwd_rtol=1e-10,
+              update_in_place=True, want_ds=False)
+    for w in range(args.warmup):
+        _, _, st = p.rsgn_step(d, **kw)
+        log(args, f"warmup {w}: cg iters={st['iters']} E_cg={st['true_rel_res']:.2e} {st['t_total_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        _, _, st = p.rsgn_step(d, **kw)
+        sts.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for k, st in enumerate(sts):
+        log(args, f"rsgn step {k}: cg iters={st['iters']} solves={st['solves']} E_cg={st['true_rel_res']:.2e} "
+                  f"total={st['t_total_ms']:.1f} ms factor={st['t_factor_ms']:.1f} cg={st['t_cg_ms']:.1f} "
+                  f"misfit={st['misfit_before']:.4f}")
+    result = {
+        "metric": "Newton-step time (reduced-space GN by CG, E_cg <= rtol)", "value": elapsed / args.steps,
+        "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if prec == "c128" else "c128 CG + c64 block solves in FP64 refinement",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.config} RSGN-CG: {inp['nx']}x{inp['nz']}, {inp['K']} sources, "
+                                f"{inp['freq']:g} Hz, CG to E_cg {args.rtol:g}, block solves {prec}"),
+                   "global_batch": inp["K"], "parallelism": "single GPU"},
+        "cg_iters": [s["iters"] for s in sts], "solves": [s["solves"] for s in sts],
+        "E_cg": [s["true_rel_res"] for s in sts], "misfit": [s["misfit_before"] for s in sts],
+    }
+    print(json.dumps(result), flush=True)
+
+
 def bench_c3(args, torch, KKTProblem):
     """Reduced gradient through the solve at 801 x 281, 80 sources, 5 Hz: autograd
     forward (factorisation + forward solves) and backward (adjoint solves + gradient
@@ -472,6 +572,10 @@ def main():
         return bench_c4(args, torch, KKTProblem)
     if args.config == "c3":
         return bench_c3(args, torch, KKTProblem)
+    if args.continuation:
+        if args.config != "c1":
+            raise SystemExit("--continuation runs the c1 frequency sequence")
+        return bench_continuation(args, torch, KKTProblem)
     if args.copy_calib:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         b = torch.empty_like(a)
@@ -498,6 +602,8 @@ def main():
         log(args, "autotune: " + ", ".join(f"P={r['chunks']} ns={r['sources_per_group']}: "
                                             f"{r['t_factor_ms']:.1f}+100x{r['t_solve_ms']:.3f} ms"
                                             for r in table[:4]))
+    if args.solver == "rsgn":
+        return bench_rsgn(args, torch, p, d, inp)
     opts = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec=args.fwd_prec,
                 fwd_rtol=1e-10, update_in_place=True, want_xi=False)
     # The last warm-up step records every kernel family (HIP events around each launch):

@@ -239,6 +239,58 @@ kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newton_opts *op
                       void *xi_out, double *gamma_next, int32_t update_in_place,
                       kf_newton_stats *st /*[host], may be NULL*/);
 
+/* Frequency continuation (Section 6, the frequency sweep: the frequencies are
+ * inverted one after another from low to high, each starting from the model the
+ * previous one reached, with its own eps, i.e. the eps ramp).  problems[0..n) share
+ * the grid (nx, nz, h, npml; KF_ESHAPE otherwise) and are ordered by frequency;
+ * steps[q] >= 0 full Newton steps (newton_step with opts, gamma updated in place) run
+ * on problem q from the gamma problem q-1 ended with (problem 0 starts from its own).
+ * d_obs[q] is problem q's data ([K][nrec] c128 device).  gamma_out: device [nz][nx]
+ * receiving the final gamma, or NULL.  st: [host] array of sum(steps) entries, the
+ * statistics of every step in order, or NULL.  The first failing step's status is
+ * returned (its statistics filled); later problems are then not touched. */
+kf_status newton_continuation(kf_problem *const *problems /*[host][n]*/, int32_t n,
+                              const void *const *d_obs /*[host][n]*/, const int32_t *steps /*[host][n]*/,
+                              const kf_newton_opts *opts /*[host]*/, double *gamma_out,
+                              kf_newton_stats *st /*[host], may be NULL*/);
+
+/* ---- reduced-space Gauss-Newton by conjugate gradients (Section 3) ----
+ * The step the paper compares the full-space method with (Table 1 "CG"): with
+ * u_n = A(gamma_n)^-1 f and r_k = d_k - Q u_k, CG on the normal equations
+ *   H ds = g,  H = eps I + sum_k J_k^* W_k^2 J_k,  g = sum_k J_k^* W_k^2 r_k - eps s_n
+ * (eqs. normal_system_discrete2 and normal_system_discrete_sum; the -eps s_n term is
+ * dropped with reg_on_update, as in the KKT right-hand side), J_k = Q A^-1 P_k.  Every
+ * Hessian product is one forward and one adjoint block solve of all K sources (the
+ * solves the paper counts per CG iteration), P_k v and P^* lambda in between.  CG stops
+ * at ||H ds - g|| <= rtol ||g|| (E_cg of Section 6); the true E_cg is recomputed at
+ * exit.  real_constrained = 1 solves the real-constrained step instead: ds real with
+ * Re(H) ds = Re(g), the normal equations of the GN problem over real updates (the real
+ * model takes Re(ds) of the complex-linear step otherwise). */
+typedef struct {
+  double rtol;             /* CG stopping tolerance on ||H ds - g|| / ||g|| */
+  int32_t maxit;           /* CG iteration limit */
+  int32_t solve_prec;      /* the block solves of each Hessian product: KF_C128 (FP64 factors)
+                              or KF_MIXED (complex64 factors in FP64 refinement to solve_rtol) */
+  double solve_rtol;       /* refinement target when solve_prec = KF_MIXED */
+  int32_t real_constrained;/* 1: real ds with Re(H) ds = Re(g) */
+  int32_t fwd_prec;        /* background solve: KF_C128 or KF_MIXED (to fwd_rtol) */
+  double fwd_rtol;
+} kf_cg_opts;
+typedef struct {
+  int32_t iters;           /* CG iterations (Hessian products) */
+  int32_t solves;          /* batched block solves of all K sources, gradient and check included */
+  double rel_res;          /* ||H ds - g|| / ||g|| by the CG recurrence at exit */
+  double true_rel_res;     /* the same recomputed with one more Hessian product */
+  double rel_res_hist[512];/* recurrence residual per iteration (first 512) */
+  double misfit_before;    /* ||d - Q u_n|| / ||d|| */
+  double phi_before;       /* 1/2 sum_k ||W_k (d_k - Q u_k)||^2 */
+  double t_factor_ms, t_forward_ms, t_cg_ms, t_total_ms;
+} kf_cg_stats;
+/* ds_out: [Ng] c128 device or NULL; gamma_next / update_in_place as in newton_step.
+ * Returns KF_ENOCONV (outputs and stats filled) if maxit is reached first. */
+kf_status rsgn_cg_step(kf_problem *p, const void *d_obs, const kf_cg_opts *opts /*[host]*/, void *ds_out,
+                       double *gamma_next, int32_t update_in_place, kf_cg_stats *st /*[host], may be NULL*/);
+
 /* Reduced gradient through the forward solve (Section 3, gradient; Section 4, eq. tmp2):
  * for u = A(gamma)^-1 f and grad_u = dl/dRe(u) + i dl/dIm(u) (both [K][nz][nx], c128 or
  * c64 per prec), computes mu = A^-H grad_u and

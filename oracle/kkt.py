@@ -67,6 +67,12 @@ class Problem:
                    w=inp["w"][:K], eps=inp["eps"] if eps is None else eps,
                    pml_r0=inp["pml_r0"], pml_cref=inp["pml_cref"], **kw)
 
+    def with_gamma(self, gamma, omega=None):
+        """The same grid, acquisition, weights and eps with another gamma (and frequency)."""
+        return Problem(self.nx, self.nz, self.h, self.npml, self.omega if omega is None else omega, gamma,
+                       self.src_ix, self.src_iz, self.rec_ix, self.rec_iz, w=self.w, eps=self.eps,
+                       reg_on_update=self.reg_on_update, pml_r0=self.r0, pml_cref=self.cref)
+
     # --- sizes and packing -------------------------------------------------
     @property
     def nxi(self):
@@ -258,6 +264,71 @@ class Problem:
         H, g = self.normal_system(u_n, r) if H_g is None else H_g
         return np.linalg.norm(H @ ds - g) / np.linalg.norm(g)
 
+    # --- reduced-space Gauss-Newton by CG (Section 3, the RSGN-CG baseline) ------
+    def gn_gradient(self, u_n, r):
+        """g = sum_k J_k^* W_k^2 r_k - L s_n (Section 3; -L s_n dropped with reg_on_update),
+        from one adjoint solve per source: J_k^* y = omega^2 E^T conj(u_k) (A^-* Q^T y)."""
+        Q = self.Q()
+        r = np.asarray(r).reshape(self.K, self.nrec)
+        src = np.stack([Q.T @ (self.w[k] ** 2 * r[k]) for k in range(self.K)])
+        lam0 = self.lu.solve(src.reshape(self.K, self.nz, self.nx), adjoint=True)
+        u = np.asarray(u_n).reshape(self.K, -1)
+        g = self.omega ** 2 * np.sum(np.conj(u) * lam0.reshape(self.K, -1), axis=0)[self.core_idx]
+        if not self.reg_on_update:
+            g = g - self.eps * self.control()
+        return g
+
+    def hessian_apply(self, u_n, v):
+        """H v = L v + sum_k J_k^* W_k^2 J_k v with L = eps I, by two solves per source
+        (Section 3): du_k = A^-1 P_k v, lambda_k = A^-* Q^T W_k^2 Q du_k,
+        H v = eps v + omega^2 E^T sum_k conj(u_k) lambda_k."""
+        u = np.asarray(u_n).reshape(self.K, self.nz, self.nx)
+        ext = np.zeros(self.Nu, np.complex128)
+        ext[self.core_idx] = v
+        du = self.lu.solve(self.omega ** 2 * u * ext.reshape(self.nz, self.nx)[None])
+        Q = self.Q()
+        src = np.stack([Q.T @ (self.w[k] ** 2 * (Q @ du[k].ravel())) for k in range(self.K)])
+        lam = self.lu.solve(src.reshape(self.K, self.nz, self.nx), adjoint=True)
+        return self.eps * v + self.omega ** 2 * np.sum(np.conj(u) * lam, axis=0).ravel()[self.core_idx]
+
+    def rsgn_cg(self, u_n, r, tol=1e-8, maxit=500, real=False):
+        """Conjugate gradients on the normal equations H ds = g (Section 3, the reduced-space
+        Gauss-Newton step the paper compares with; Table 1 "CG").  The iteration stops
+        when ||H ds - g|| <= tol ||g|| (E_cg of Section 6).
+
+        real=True solves the real-constrained step instead: ds real with
+        Re(H) ds = Re(g), the normal equations of the GN problem over real updates
+        (for real v, Re(H v) = Re(H) v since L is real).
+        Returns (ds, history of ||H ds - g|| / ||g||)."""
+        g = self.gn_gradient(u_n, r)
+        if real:
+            g = g.real.astype(np.complex128)
+        apply = (lambda v: self.hessian_apply(u_n, v).real.astype(np.complex128)) if real else \
+            (lambda v: self.hessian_apply(u_n, v))
+        x = np.zeros_like(g)
+        res = g.copy()
+        d = res.copy()
+        rr = np.real(np.vdot(res, res))
+        gn = np.sqrt(rr)
+        hist = [1.0]
+        for _ in range(maxit):
+            if np.sqrt(rr) <= tol * gn:
+                break
+            Hd = apply(d)
+            alpha = rr / np.real(np.vdot(d, Hd))
+            x = x + alpha * d
+            res = res - alpha * Hd
+            rr_new = np.real(np.vdot(res, res))
+            d = res + (rr_new / rr) * d
+            rr = rr_new
+            hist.append(np.sqrt(rr) / gn)
+        return x, hist
+
+    def normal_system_real(self, u_n, r):
+        """(Re H, Re g): the normal equations of the GN step restricted to real ds."""
+        H, g = self.normal_system(u_n, r)
+        return H.real, g.real
+
     # --- reduced gradient and update ------------------------------------------
     def reduced_gradient(self, u_n, r):
         """grad Phi on the core: -omega^2 sum_k Re(conj(u_k) * lambda0_k),
@@ -275,6 +346,27 @@ class Problem:
         g = self.gamma.copy().ravel()
         g[self.core_idx] += np.real(ds)
         return g.reshape(self.nz, self.nx)
+
+
+def continuation(problems, data, steps):
+    """Frequency continuation (Section 6, the frequency sweep): the problems (same grid,
+    increasing frequency, each with its own eps) are inverted in order, steps[q] exact
+    Newton steps each (the Schur route of eqs. tmp1, tmp2, normal_system_discrete3 and
+    the update s_{n+1} = s_n + Re(ds)), every problem starting from the model the
+    previous one reached.  Returns (final gamma, misfits ||d - Q u_n|| / ||d|| before
+    every step)."""
+    gamma = problems[0].gamma
+    misfits = []
+    for prob, d, n in zip(problems, data, steps):
+        p = prob.with_gamma(gamma)
+        for _ in range(n):
+            u_n = p.forward()
+            r = p.residual(d, u_n)
+            misfits.append(np.linalg.norm(r) / np.linalg.norm(d))
+            xi = p.kkt_solve_schur(u_n, r)
+            gamma = p.update(p.unpack(xi)[1])
+            p = p.with_gamma(gamma)
+    return gamma, misfits
 
 
 def adjoint_gradient_full(A_solver, nx, nz, h, npml, omega, u, grad_u, r0, cref):

@@ -53,6 +53,18 @@ class KfTuneEntry(C.Structure):
                 ("t_solve_ms", C.c_double), ("score_ms", C.c_double)]
 
 
+class KfCgOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("solve_prec", C.c_int32), ("solve_rtol", C.c_double),
+                ("real_constrained", C.c_int32), ("fwd_prec", C.c_int32), ("fwd_rtol", C.c_double)]
+
+
+class KfCgStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("solves", C.c_int32), ("rel_res", C.c_double), ("true_rel_res", C.c_double),
+                ("rel_res_hist", C.c_double * 512), ("misfit_before", C.c_double), ("phi_before", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_forward_ms", C.c_double), ("t_cg_ms", C.c_double),
+                ("t_total_ms", C.c_double)]
+
+
 class KfSolveStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_res_max", C.c_double)]
 
@@ -80,6 +92,9 @@ _SIGNATURES = {
     "precond_apply": (C.c_int, [P, C.c_int32, P, P]),
     "newton_step": (C.c_int, [P, P, C.POINTER(KfNewtonOpts), P, P, C.c_int32, C.POINTER(KfNewtonStats)]),
     "helmholtz_adjoint_gradient": (C.c_int, [P, C.c_int32, P, P, P]),
+    "newton_continuation": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(P), C.POINTER(C.c_int32),
+                                      C.POINTER(KfNewtonOpts), P, C.POINTER(KfNewtonStats)]),
+    "rsgn_cg_step": (C.c_int, [P, P, C.POINTER(KfCgOpts), P, P, C.c_int32, C.POINTER(KfCgStats)]),
     "kf_sources": (C.c_int, [P, P]),
     "kf_sizes": (C.c_int, [P, C.POINTER(C.c_int64)]),
     "kf_batch_create": (C.c_int, [C.POINTER(P), C.c_int32, P, C.POINTER(P)]),

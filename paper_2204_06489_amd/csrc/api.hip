@@ -133,6 +133,7 @@ static void free_all(kf_problem *p) {
   dfree(p->V64); dfree(p->W64); dfree(p->V32); dfree(p->W32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
+  dfree(p->cg_vec); dfree(p->cg_field);
   if (p->host_pinned) hipHostFree(p->host_pinned);
   p->host_pinned = nullptr;
   for (int i = 0; i < PROF_N; ++i) {
@@ -862,6 +863,184 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   if (st) *st = S;
   prof_collect(p);
   return fst;
+}
+
+// ---------------------------------------------------------------------------
+// frequency continuation (Section 6, the frequency sweep)
+// ---------------------------------------------------------------------------
+extern "C" kf_status newton_continuation(kf_problem *const *problems, int32_t n, const void *const *d_obs,
+                                         const int32_t *steps, const kf_newton_opts *opts, double *gamma_out,
+                                         kf_newton_stats *st) {
+  if (!problems || !d_obs || !steps || !opts) return fail(KF_EINVAL, "null pointer argument");
+  if (n < 1) return fail(KF_EINVAL, "need at least one problem");
+  for (int q = 0; q < n; ++q) {
+    if (!problems[q] || !d_obs[q]) return fail(KF_EINVAL, "problem or data " + std::to_string(q) + " is NULL");
+    if (steps[q] < 0) return fail(KF_EINVAL, "steps must be >= 0");
+    const kf_problem *a = problems[0], *b = problems[q];
+    if (a->nx != b->nx || a->nz != b->nz || a->npml != b->npml || a->h != b->h)
+      return fail(KF_ESHAPE, "continuation problems must share the grid (nx, nz, h, npml)");
+  }
+  int i = 0;
+  for (int q = 0; q < n; ++q) {
+    kf_problem *p = problems[q];
+    if (q > 0) {   // the previous frequency's model starts this one
+      HIP_TRY(hipStreamSynchronize(problems[q - 1]->stream));
+      CHECK_ST(kf_set_gamma(p, problems[q - 1]->gamma));
+    }
+    for (int s = 0; s < steps[q]; ++s) {
+      kf_newton_stats S;
+      kf_status r = newton_step(p, d_obs[q], opts, nullptr, nullptr, 1, &S);
+      if (st) st[i] = S;
+      ++i;
+      if (r != KF_OK) return r;
+    }
+  }
+  kf_problem *last = problems[n - 1];
+  if (gamma_out) HIP_TRY(hipMemcpyAsync(gamma_out, last->gamma, sizeof(double) * last->Nu, hipMemcpyDeviceToDevice,
+                                        last->stream));
+  HIP_TRY(hipStreamSynchronize(last->stream));
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reduced-space Gauss-Newton step by conjugate gradients (Section 3; Table 1 "CG")
+// ---------------------------------------------------------------------------
+static kf_status cg_solve_field(kf_problem *p, int adjoint, int prec, double rtol, const double2 *rhs, double2 *x,
+                                int *solves) {
+  *solves += 1;
+  if (prec == KF_MIXED) {
+    int it = 0;
+    double rm = 0.0;
+    return solve_mixed(p, adjoint, rhs, x, rtol, 30, &it, &rm);
+  }
+  return blu_solve<double>(p, adjoint, rhs, x);
+}
+
+// out = H v (real part only when real_only), by one forward and one adjoint block solve
+// of all sources; uses vec_d and cg_field
+static kf_status hessian_apply(kf_problem *p, const kf_cg_opts *o, const double2 *v, double2 *out, int *solves) {
+  CHECK_ST(launch_scatter_P(p, v, p->vec_d));
+  CHECK_ST(cg_solve_field(p, 0, o->solve_prec, o->solve_rtol, p->vec_d, p->cg_field, solves));
+  CHECK_ST(launch_apply_F(p, p->cg_field, p->vec_d));
+  CHECK_ST(cg_solve_field(p, 1, o->solve_prec, o->solve_rtol, p->vec_d, p->cg_field, solves));
+  return launch_gather_PH(p, p->eps, v, 0.0, p->cg_field, o->real_constrained, out);
+}
+
+static kf_status read_scalar(kf_problem *p, const double *dev, double *host) {
+  HIP_TRY(hipMemcpyAsync(p->host_pinned, dev, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  *host = p->host_pinned[0];
+  return KF_OK;
+}
+
+// Re(a^H b) read back to the host
+static kf_status host_dot_re(kf_problem *p, const double2 *a, const double2 *b, int64_t n, double *out) {
+  CHECK_ST(dot_c128(p, a, b, n, (double2 *)p->red_out));
+  return read_scalar(p, p->red_out, out);
+}
+
+extern "C" kf_status rsgn_cg_step(kf_problem *p, const void *d_obs, const kf_cg_opts *o, void *ds_out,
+                                  double *gamma_next, int32_t update_in_place, kf_cg_stats *st) {
+  CHECK_ST(check_p(p));
+  if (!d_obs || !o) return fail(KF_EINVAL, "d_obs or opts is NULL");
+  if (!(o->rtol > 0.0) || o->maxit < 1) return fail(KF_EINVAL, "need rtol > 0 and maxit >= 1");
+  if (o->solve_prec != KF_C128 && o->solve_prec != KF_MIXED) return fail(KF_EINVAL, "solve_prec must be C128 or MIXED");
+  if (o->solve_prec == KF_MIXED && !(o->solve_rtol > 0.0)) return fail(KF_EINVAL, "solve_rtol must be > 0");
+  if (o->fwd_prec != KF_C128 && o->fwd_prec != KF_MIXED) return fail(KF_EINVAL, "fwd_prec must be C128 or MIXED");
+  if (o->fwd_prec == KF_MIXED && !(o->fwd_rtol > 0.0)) return fail(KF_EINVAL, "fwd_rtol must be > 0");
+  kf_cg_stats S;
+  std::memset(&S, 0, sizeof(S));
+  auto T0 = std::chrono::steady_clock::now();
+  auto ms_since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+  };
+  const int64_t Ng = p->Ng;
+  if (!p->cg_vec) CHECK_ST(dalloc(&p->cg_vec, (size_t)5 * Ng));
+  if (!p->cg_field) CHECK_ST(dalloc(&p->cg_field, (size_t)p->K * p->Nu));
+  double2 *x = p->cg_vec, *r = x + Ng, *d = r + Ng, *Hd = d + Ng, *g = Hd + Ng;
+  // factorisation and background field u_n = A^-1 f
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  auto t = std::chrono::steady_clock::now();
+  const bool need32 = o->fwd_prec == KF_MIXED || o->solve_prec == KF_MIXED;
+  CHECK_ST(blu_factor(p, 1 | (need32 ? 2 : 0)));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_factor_ms = ms_since(t);
+  t = std::chrono::steady_clock::now();
+  int fit = 0;
+  CHECK_ST(forward_solve(p, o->fwd_prec, o->fwd_rtol, p->u_n, &fit));
+  p->have_un = true;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_forward_ms = ms_since(t);
+  // data residual, misfit and the gradient g = sum_k J_k^* W_k^2 r_k (- eps s_n)
+  kf_status e = KF_OK;
+  CHECK_ST(launch_residual(p, (const double2 *)d_obs, p->u_n, p->d_r, p->d_wr));
+  const int64_t nd = (int64_t)p->K * p->nrec;
+  double rn = host_norm(p, p->d_r, nd, &e); CHECK_ST(e);
+  double dn = host_norm(p, (const double2 *)d_obs, nd, &e); CHECK_ST(e);
+  double wn = host_norm(p, p->d_wr, nd, &e); CHECK_ST(e);
+  S.misfit_before = dn > 0 ? rn / dn : rn;
+  S.phi_before = 0.5 * wn * wn;
+  t = std::chrono::steady_clock::now();
+  int solves = 0;
+  CHECK_ST(launch_rhs_u_field(p, p->d_r, p->vec_d));
+  CHECK_ST(cg_solve_field(p, 1, o->solve_prec, o->solve_rtol, p->vec_d, p->cg_field, &solves));
+  CHECK_ST(launch_gather_PH(p, 0.0, nullptr, p->d.reg_on_update ? 0.0 : -p->eps, p->cg_field, o->real_constrained, g));
+  // CG on H ds = g from ds = 0
+  HIP_TRY(hipMemsetAsync(x, 0, sizeof(double2) * Ng, p->stream));
+  HIP_TRY(hipMemcpyAsync(r, g, sizeof(double2) * Ng, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(d, g, sizeof(double2) * Ng, hipMemcpyDeviceToDevice, p->stream));
+  double rr = 0.0;
+  CHECK_ST(host_dot_re(p, r, r, Ng, &rr));
+  const double gn = std::sqrt(rr);
+  if (!std::isfinite(gn)) return fail(KF_ENAN, "non-finite gradient");
+  kf_status status = KF_OK;
+  int it = 0;
+  double rel = gn > 0.0 ? 1.0 : 0.0;
+  while (gn > 0.0 && rel > o->rtol) {
+    if (it >= o->maxit) { status = fail(KF_ENOCONV, "RSGN-CG reached maxit"); break; }
+    CHECK_ST(hessian_apply(p, o, d, Hd, &solves));
+    double dHd = 0.0;
+    CHECK_ST(host_dot_re(p, d, Hd, Ng, &dHd));
+    if (!(dHd > 0.0)) { status = fail(dHd == dHd ? KF_EBREAKDOWN : KF_ENAN, "RSGN-CG: d^H H d is not positive"); break; }
+    const double alpha = rr / dHd;
+    CHECK_ST(launch_axpy_field(p, Ng, make_double2(alpha, 0.0), d, x));
+    CHECK_ST(launch_axpy_field(p, Ng, make_double2(-alpha, 0.0), Hd, r));
+    double rr_new = 0.0;
+    CHECK_ST(host_dot_re(p, r, r, Ng, &rr_new));
+    if (!std::isfinite(rr_new)) { status = fail(KF_ENAN, "non-finite CG residual"); break; }
+    CHECK_ST(launch_axpby_field(p, Ng, make_double2(1.0, 0.0), r, make_double2(rr_new / rr, 0.0), d));
+    rr = rr_new;
+    ++it;
+    rel = std::sqrt(rr) / gn;
+    if (it <= 512) S.rel_res_hist[it - 1] = rel;
+  }
+  S.iters = it;
+  S.rel_res = rel;
+  // the true E_cg = ||H ds - g|| / ||g|| at exit (one more Hessian product)
+  if (status == KF_OK && gn > 0.0) {
+    CHECK_ST(hessian_apply(p, o, x, Hd, &solves));
+    CHECK_ST(launch_axpy_field(p, Ng, make_double2(-1.0, 0.0), g, Hd));
+    double t2 = 0.0;
+    CHECK_ST(host_dot_re(p, Hd, Hd, Ng, &t2));
+    S.true_rel_res = std::sqrt(t2) / gn;
+  }
+  S.solves = solves;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_cg_ms = ms_since(t);
+  if (ds_out) HIP_TRY(hipMemcpyAsync(ds_out, x, sizeof(double2) * Ng, hipMemcpyDeviceToDevice, p->stream));
+  if (update_in_place) {
+    CHECK_ST(launch_update_gamma(p, x, p->gamma));
+    p->have_T64 = p->have_T32 = false;
+    p->have_un = false;
+    if (gamma_next) HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+  } else if (gamma_next) {
+    HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
+    CHECK_ST(launch_update_gamma(p, x, gamma_next));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.t_total_ms = ms_since(T0);
+  if (st) *st = S;
+  return status;
 }
 
 // ---------------------------------------------------------------------------

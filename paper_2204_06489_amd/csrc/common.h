@@ -182,6 +182,9 @@ struct kf_problem {
   double2 *V = nullptr, *Z = nullptr;          // (m+1) and m packed vectors
   double2 *xi_w = nullptr, *xi_b = nullptr, *xi_x = nullptr;
   double2 *hess = nullptr;                     // (m+1) x m Hessenberg + rotations etc.
+  // reduced-space CG (allocated on first use): five control vectors and one field
+  double2 *cg_vec = nullptr;                   // [5][Ng]: ds, residual, direction, H direction, g
+  double2 *cg_field = nullptr;                 // [K][nz][nx]
 
   Grid grid() const { return Grid{nx, nz, npml, h, omega, gamma, xn, ixh, zn, izh}; }
 
@@ -232,6 +235,15 @@ kf_status launch_update_gamma(kf_problem *p, const double2 *ds, double *target);
 kf_status launch_grad_gamma(kf_problem *p, const void *u, const void *mu, int c64, double *grad);
 kf_status launch_axpy_field(kf_problem *p, int64_t n, double2 a, const double2 *x, double2 *y);
 kf_status launch_copy_c128_to_c64(kf_problem *p, int64_t n, const double2 *x, float2 *y);
+// y = a x + b y
+kf_status launch_axpby_field(kf_problem *p, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
+// reduced Hessian pieces (Section 3): out_k = P_k v; out = Q^T W^2 Q x; out = Q^T W^2 r;
+// out = alpha v + P^* lambda + gcoef gamma_core (real part only with real_only)
+kf_status launch_scatter_P(kf_problem *p, const double2 *v, double2 *out);
+kf_status launch_apply_F(kf_problem *p, const double2 *x, double2 *out);
+kf_status launch_rhs_u_field(kf_problem *p, const double2 *r, double2 *out);
+kf_status launch_gather_PH(kf_problem *p, double alpha, const double2 *v, double gcoef, const double2 *lam,
+                           int real_only, double2 *out);
 kf_status launch_copy_c64_to_c128(kf_problem *p, int64_t n, const float2 *x, double2 *y);
 
 // block factorisation and sweeps

@@ -7,7 +7,7 @@ namespace {
 
 constexpr int RB = 256;      // reduction block size (4 wavefronts)
 constexpr int RG = 1024;     // reduction grid size (fixed => fixed summation order)
-constexpr int MDOT = 32;     // vectors per multi-dot sweep (at most)
+constexpr int MDOT = 16;     // vectors per multi-dot sweep (at most): 32 accumulators cost occupancy (4.0 vs 6.1 TB/s)
 constexpr int FDOT = 8;      // dot products carried by the fused update-and-dot pass
 
 __device__ inline double wave_sum(double v) {
@@ -103,8 +103,11 @@ __global__ __launch_bounds__(RB) void k_nonfinite_partial(const double *__restri
 }
 
 // h[q] = V_q^H w for q in [q0, q0 + NQ): partial sums per block; with `norm` also
-// |w|^2 from the same sweep, stored after the 2 nv dot-product entries of the row
-template <int NQ>
+// |w|^2 from the same sweep, stored after the 2 nv dot-product entries of the row.
+// FIRST marks the first Gram-Schmidt pass's launches (always real work) apart from the
+// second pass's (which return at once unless the step needs them), so that kernel
+// traces time the two separately.
+template <int NQ, bool FIRST>
 __global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restrict__ V, int q0, int nv,
                                                          const double2 *__restrict__ w, int64_t n, double *partial,
                                                          int stride, int norm, const int *active) {
@@ -133,16 +136,17 @@ __global__ __launch_bounds__(RB) void k_multidot_partial(const double2 *__restri
   }
 }
 
-// One sweep of the multi-dot over vectors [q0, q0 + nq) with the smallest template
-// that holds them (8, 16 or 32 vectors per sweep).
+// One sweep of the multi-dot over vectors [q0, q0 + nq), nq <= MDOT, with the smaller
+// template that holds them (8 or 16 vectors per sweep).
+template <bool FIRST>
 inline void launch_multidot(hipStream_t s, const double2 *V, int q0, int nq, int nv, const double2 *w, int64_t n,
                             double *partial, int stride, int norm, const int *active) {
   if (nq <= 8)
-    hipLaunchKernelGGL(k_multidot_partial<8>, dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride, norm, active);
-  else if (nq <= 16)
-    hipLaunchKernelGGL(k_multidot_partial<16>, dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride, norm, active);
+    hipLaunchKernelGGL((k_multidot_partial<8, FIRST>), dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride,
+                       norm, active);
   else
-    hipLaunchKernelGGL(k_multidot_partial<32>, dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride, norm, active);
+    hipLaunchKernelGGL((k_multidot_partial<16, FIRST>), dim3(RG), dim3(RB), 0, s, V, q0, nv, w, n, partial, stride,
+                       norm, active);
 }
 
 // Fused Gram-Schmidt update: w <- (w - sum_{q<nv} V_q h_q) * scale[0] (scale NULL: 1),
@@ -323,7 +327,10 @@ kf_status multidot_c128(kf_problem *p, const double2 *V, int nv, const double2 *
   ProfScope ps(p, nrm2_out ? PROF_GS_DOT : PROF_ORTH, 16.0 * (double)n * (nv + 1));
   const int stride = 2 * nv + 1;
   for (int q0 = 0; q0 < nv; q0 += MDOT) {
-    launch_multidot(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, p->red, stride, nrm2_out && q0 == 0, active);
+    if (nrm2_out)
+      launch_multidot<true>(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, p->red, stride, q0 == 0, active);
+    else
+      launch_multidot<false>(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, p->red, stride, 0, active);
     LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_finish, dim3(2 * nv), dim3(RB), 0, p->stream, p->red, 2 * nv, stride, 0, (double *)h_dev, active);
@@ -389,7 +396,7 @@ kf_status multidot_rest_c128(kf_problem *p, const double2 *V, int nv, const doub
   double *red2 = p->red + (size_t)RG * (2 * FDOT + 1);
   const int stride2 = 2 * nv;
   for (int q0 = FDOT; q0 < nv; q0 += MDOT) {
-    launch_multidot(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, red2, stride2, 0, active);
+    launch_multidot<false>(p->stream, V, q0, std::min(MDOT, nv - q0), nv, w, n, red2, stride2, 0, active);
     LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_finish, dim3(2 * (nv - FDOT)), dim3(RB), 0, p->stream, red2 + 2 * FDOT, 2 * (nv - FDOT), stride2,

@@ -311,6 +311,52 @@ __global__ void k_axpy(int64_t n, double2 a, const double2 *__restrict__ x, doub
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; t < n; t += (int64_t)gridDim.x * blockDim.x) y[t] = cadd(y[t], cmul(a, x[t]));
 }
+// y = a x + b y
+__global__ void k_axpby(int64_t n, double2 a, const double2 *__restrict__ x, double2 b, double2 *y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t < n; t += (int64_t)gridDim.x * blockDim.x) y[t] = cadd(cmul(a, x[t]), cmul(b, y[t]));
+}
+
+// ---------------------------------------------------------------------------
+// Pieces of the reduced Hessian product of Section 3,
+//   H v = eps v + sum_k J_k^* W_k^2 J_k v,   J_k = Q A^-1 P_k,  P_k = omega^2 diag(u_k) E:
+// P v for every source (the right-hand sides of the forward solves), Q^T W^2 Q on the
+// solved fields, and eps v + P^* lambda (the sum over sources of the adjoint fields).
+// ---------------------------------------------------------------------------
+// out_k(node) = omega^2 u_k(node) v(core index of node), 0 in the PML
+__global__ void k_scatter_P(Grid g, int K, int nxc, const double2 *__restrict__ un, const double2 *__restrict__ v,
+                            double2 *__restrict__ out) {
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)K * Nu) return;
+  const size_t p = t % Nu;
+  const int j = (int)(p / g.nx), i = (int)(p - (size_t)j * g.nx);
+  const bool core = i >= g.npml && i < g.nx - g.npml && j >= g.npml && j < g.nz - g.npml;
+  double2 r = make_double2(0.0, 0.0);
+  if (core) r = cscale(cmul(un[t], v[(size_t)(j - g.npml) * nxc + (i - g.npml)]), g.omega * g.omega);
+  out[t] = r;
+}
+
+// out(c) = alpha v(c) + omega^2 sum_k conj(u_k) lambda_k (node of c) + gcoef gamma(node of c);
+// real_only keeps the real part (the real-constrained step).  v may be NULL when alpha = 0.
+__global__ void k_gather_PH(Grid g, int K, int nxc, double alpha, const double2 *__restrict__ v, double gcoef,
+                            const double2 *__restrict__ un, const double2 *__restrict__ lam, int real_only,
+                            double2 *__restrict__ out) {
+  const int nzc = g.nz - 2 * g.npml;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (size_t)nxc * nzc) return;
+  const size_t Nu = (size_t)g.nx * g.nz;
+  const int ic = (int)(c % nxc), jc = (int)(c / nxc);
+  const size_t p = (size_t)(jc + g.npml) * g.nx + ic + g.npml;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < K; ++k) acc = cadd(acc, cmulc(un[(size_t)k * Nu + p], lam[(size_t)k * Nu + p]));
+  double2 r = cscale(acc, g.omega * g.omega);
+  if (v) r = cadd(r, cscale(v[c], alpha));
+  r.x += gcoef * g.gamma[p];
+  if (real_only) r.y = 0.0;
+  out[c] = r;
+}
+
 __global__ void k_c128_to_c64(int64_t n, const double2 *__restrict__ x, float2 *y) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; t < n; t += (int64_t)gridDim.x * blockDim.x) y[t] = make_float2((float)x[t].x, (float)x[t].y);
@@ -528,6 +574,48 @@ kf_status launch_axpy_field(kf_problem *p, int64_t n, double2 a, const double2 *
   LAUNCH_CHECK();
   return KF_OK;
 }
+kf_status launch_axpby_field(kf_problem *p, int64_t n, double2 a, const double2 *x, double2 b, double2 *y) {
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(256), 0, p->stream, n, a, x, b, y);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_scatter_P(kf_problem *p, const double2 *v, double2 *out) {
+  const int64_t n = (int64_t)p->K * p->Nu;
+  hipLaunchKernelGGL(k_scatter_P, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p->stream, p->grid(), p->K,
+                     p->nxc, p->u_n, v, out);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+// out = Q^T W^2 Q x for every source (zero away from the receivers)
+kf_status launch_apply_F(kf_problem *p, const double2 *x, double2 *out) {
+  HIP_TRY(hipMemsetAsync(out, 0, sizeof(double2) * p->K * p->Nu, p->stream));
+  int n = p->K * p->nru;
+  hipLaunchKernelGGL(k_kkt_F, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->d_rnode, p->d_wsq,
+                     (size_t)p->Nu, x, out);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+// out = Q^T W^2 r for every source, r the data residual [K][nrec]
+kf_status launch_rhs_u_field(kf_problem *p, const double2 *r, double2 *out) {
+  HIP_TRY(hipMemsetAsync(out, 0, sizeof(double2) * p->K * p->Nu, p->stream));
+  int n = p->K * p->nru;
+  hipLaunchKernelGGL(k_rhs_u, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->K, p->nru, p->nrec,
+                     (size_t)p->Nu, p->d_rnode, p->d_rptr, p->d_rlist, p->d_w, r, out);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
+kf_status launch_gather_PH(kf_problem *p, double alpha, const double2 *v, double gcoef, const double2 *lam,
+                           int real_only, double2 *out) {
+  hipLaunchKernelGGL(k_gather_PH, dim3((unsigned)((p->Ng + 255) / 256)), dim3(256), 0, p->stream, p->grid(), p->K,
+                     p->nxc, alpha, v, gcoef, p->u_n, lam, real_only, out);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
 kf_status launch_copy_c128_to_c64(kf_problem *p, int64_t n, const double2 *x, float2 *y) {
   hipLaunchKernelGGL(k_c128_to_c64, dim3(blocks_for(n)), dim3(256), 0, p->stream, n, x, y);
   LAUNCH_CHECK();

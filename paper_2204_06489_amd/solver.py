@@ -12,8 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (KF_C128, KF_C64, KF_MIXED, KF_PC_EXACT, KF_PC_INEXACT, KF_ENOCONV, KfDesc, KfNewtonOpts,
-                   KfNewtonStats, KfSolveStats, check, lib)
+from ._lib import (KF_C128, KF_C64, KF_MIXED, KF_PC_EXACT, KF_PC_INEXACT, KF_ENOCONV, KfCgOpts, KfCgStats, KfDesc,
+                   KfNewtonOpts, KfNewtonStats, KfSolveStats, check, lib)
 
 _PREC = {"c128": KF_C128, "c64": KF_C64, "mixed": KF_MIXED}
 _PC = {"exact": KF_PC_EXACT, "inexact": KF_PC_INEXACT}
@@ -230,6 +230,26 @@ class KKTProblem:
         stats["converged"] = s != KF_ENOCONV
         return xi, g1, stats
 
+    def rsgn_step(self, d_obs, rtol=1e-6, maxit=500, solve_prec="c128", solve_rtol=1e-10, real_constrained=False,
+                  fwd_prec="c128", fwd_rtol=1e-10, update_in_place=True, want_ds=True):
+        """Reduced-space GN step by CG on the normal equations (rsgn_cg_step); returns
+        (ds or None, gamma_{n+1}, stats dict)."""
+        o = KfCgOpts()
+        o.rtol, o.maxit, o.solve_prec, o.solve_rtol = float(rtol), int(maxit), _PREC[solve_prec], float(solve_rtol)
+        o.real_constrained, o.fwd_prec, o.fwd_rtol = int(bool(real_constrained)), _PREC[fwd_prec], float(fwd_rtol)
+        ds = torch.empty(self.Ng, dtype=torch.complex128, device=self.device) if want_ds else None
+        g1 = torch.empty((self.nz, self.nx), dtype=torch.float64, device=self.device)
+        st = KfCgStats()
+        s = check(lib().rsgn_cg_step(self._h, _ptr(d_obs, torch.complex128, self.K * self.nrec, "d_obs"),
+                                     C.byref(o), _ptr(ds) if ds is not None else None, _ptr(g1),
+                                     int(bool(update_in_place)), C.byref(st)), allow=(KF_ENOCONV,))
+        if update_in_place:
+            self.gamma_token = getattr(self, "gamma_token", 0) + 1
+        stats = {f: getattr(st, f) for f, _ in KfCgStats._fields_ if f != "rel_res_hist"}
+        stats["rel_res_hist"] = list(st.rel_res_hist[:max(0, min(st.iters, 512))])
+        stats["converged"] = s != KF_ENOCONV
+        return ds, g1, stats
+
     def adjoint_gradient(self, u, grad_u, prec="c128"):
         pv = _PREC[prec]
         dt = torch.complex64 if pv == KF_C64 else torch.complex128
@@ -256,6 +276,35 @@ class KKTProblem:
     def profile_only(self, name=None):
         """Record one kernel family only (None: all families)."""
         check(lib().kf_profile_only(self._h, (name or "").encode()))
+
+
+def newton_continuation(problems, d_obs, steps, rtol=1e-6, restart=30, maxit=200, pc="exact", fwd_prec="c128",
+                        fwd_rtol=1e-10, reorth_eta=0.1):
+    """Frequency continuation (newton_continuation): steps[q] Newton steps on problems[q],
+    each problem starting from the model the previous one reached.  Returns (final gamma,
+    list of per-step stats dicts)."""
+    n = len(problems)
+    o = KfNewtonOpts()
+    o.rtol, o.restart, o.maxit, o.pc = float(rtol), int(restart), int(maxit), _PC[pc]
+    o.fwd_prec, o.fwd_rtol, o.misfit_after = _PREC[fwd_prec], float(fwd_rtol), 0
+    o.reorth_eta = float(reorth_eta)
+    last = problems[-1]
+    g = torch.empty((last.nz, last.nx), dtype=torch.float64, device=last.device)
+    arr = (C.c_void_p * n)(*[q._h.value for q in problems])
+    dp = (C.c_void_p * n)(*[_ptr(d, torch.complex128, q.K * q.nrec, "d_obs").value for d, q in zip(d_obs, problems)])
+    sp = (C.c_int32 * n)(*[int(s) for s in steps])
+    total = sum(int(s) for s in steps)
+    st = (KfNewtonStats * max(total, 1))()
+    torch.cuda.current_stream().synchronize()
+    check(lib().newton_continuation(arr, n, dp, sp, C.byref(o), _ptr(g), st))
+    out = []
+    for k in range(total):
+        d = {f: getattr(st[k], f) for f, _ in KfNewtonStats._fields_ if f != "rel_res_hist"}
+        d["rel_res_hist"] = list(st[k].rel_res_hist[:max(0, st[k].outer_iters)])
+        out.append(d)
+    for q in problems:
+        q.gamma_token = getattr(q, "gamma_token", 0) + 1
+    return g, out
 
 
 class KKTBatch:

@@ -199,3 +199,60 @@ def test_update_changes_core_only():
     g1 = p.update(p.unpack(xi)[1])
     assert np.all(g1[~p.core] == p.gamma[~p.core])
     assert np.allclose(g1[p.core], p.gamma[p.core] + np.real(p.unpack(xi)[1]))
+
+
+@pytest.mark.parametrize("reg", [False, True])
+def test_rsgn_cg_converges_to_the_normal_equation_solution(reg):
+    """CG on H ds = g (Section 3, Table 1 "CG") reaches the Cholesky solution of the
+    normal equations, which numpy's least squares pins; E_cg falls to the tolerance."""
+    p, u_n, r, _ = _setup(weights="random", reg_on_update=reg)
+    H, g = p.normal_system(u_n, r)
+    assert np.linalg.norm(p.gn_gradient(u_n, r) - g) <= 1e-12 * np.linalg.norm(g)
+    v = np.random.default_rng(4).standard_normal(p.Ng) + 0j
+    assert np.linalg.norm(p.hessian_apply(u_n, v) - H @ v) <= 1e-12 * np.linalg.norm(H @ v)
+    ds, hist = p.rsgn_cg(u_n, r, tol=1e-12, maxit=400)
+    ref = np.linalg.solve(H, g)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(ds - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_real_constrained_step_is_the_real_least_squares_minimiser():
+    """The real-constrained GN step minimises 1/2 ||W (r - J ds)||^2 + eps/2 ||ds||^2 over
+    real ds (b_s = 0): numpy's least squares on the stacked real and imaginary parts."""
+    p, u_n, r, _ = _setup(weights="random", reg_on_update=True)
+    J = p.jacobians(u_n)
+    WJ = np.vstack([p.w[k][:, None] * J[k] for k in range(p.K)])
+    Wr = np.concatenate([p.w[k] * r[k] for k in range(p.K)])
+    A_ls = np.vstack([WJ.real, WJ.imag, np.sqrt(p.eps) * np.eye(p.Ng)])
+    b_ls = np.concatenate([Wr.real, Wr.imag, np.zeros(p.Ng)])
+    ref, *_ = np.linalg.lstsq(A_ls, b_ls, rcond=None)
+    ds, hist = p.rsgn_cg(u_n, r, tol=1e-12, maxit=400, real=True)
+    assert np.abs(ds.imag).max() == 0.0
+    assert np.linalg.norm(ds.real - ref) <= 1e-9 * np.linalg.norm(ref)
+    Hr, gr = p.normal_system_real(u_n, r)
+    assert np.linalg.norm(np.linalg.solve(Hr, gr) - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_continuation_composes_single_steps():
+    """The frequency sweep is the composition of exact single steps, each frequency
+    starting from the previous one's model; one step at one frequency is the step itself."""
+    from oracle.kkt import continuation
+    inp = tiny_inputs(weights="random")
+    probs, data = [], []
+    for f in (4.0, 6.0):
+        q = dict(inp, freq=f, omega=2 * np.pi * f)
+        pt = Problem.from_inputs(q, gamma=q["gamma_true"], eps=1.0)
+        data.append(pt.sample(pt.forward()))
+        probs.append(Problem.from_inputs(q, eps=1e3, reg_on_update=True))
+    g1, mis = continuation(probs[:1], data[:1], [1])
+    p = probs[0]
+    u_n = p.forward()
+    xi = p.kkt_solve_schur(u_n, p.residual(data[0], u_n))
+    assert np.array_equal(g1, p.update(p.unpack(xi)[1]))
+    g2, mis2 = continuation(probs, data, [1, 2])
+    q = probs[1].with_gamma(g1)
+    for _ in range(2):
+        u = q.forward()
+        q = q.with_gamma(q.update(q.unpack(q.kkt_solve_schur(u, q.residual(data[1], u)))[1]))
+    assert np.array_equal(g2, q.gamma)
+    assert len(mis2) == 3
