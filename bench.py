@@ -48,8 +48,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--freq-index", type=int, default=None, help="default: 5 Hz of the workload")
-    ap.add_argument("--pc", default=None, choices=["exact", "inexact"],
-                    help="default: inexact for the mixed-precision workloads (c2, c4), exact for c0/c1")
+    ap.add_argument("--pc", default=None, choices=["exact", "inexact", "multigrid"],
+                    help="default: inexact for the mixed-precision workloads (c2, c4), exact for c0/c1; "
+                         "multigrid: BiCGStab block solves with shifted-Laplacian V-cycles to --inner-rtol "
+                         "(complex128 with --fwd-prec c128, else complex64)")
+    ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--fwd-prec", default=None, choices=["c128", "mixed"],
                     help="background solve: default mixed for c2, c128 otherwise")
     ap.add_argument("--rtol", type=float, default=1e-6)
@@ -141,7 +144,7 @@ LIB_COUNTED = ("kkt_apply", "gs_dot", "gs_update", "blu_chain")
 # of these with the most GPU time
 SINGLE = ("kkt_apply", "gs_dot", "gs_update", "blu_fwd_c64", "blu_bwd_c64", "blu_correct", "blu_chain",
           "blu_mid", "blu_fwd_c128", "blu_bwd_c128")
-FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stage", "orth", "reduce")
+FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stage", "orth", "reduce", "mg_solve")
 KERNEL_NAMES = {
     "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial<8|16, true> (+ k_finish)",
     "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
@@ -428,6 +431,8 @@ def bench_continuation(args, torch, KKTProblem):
         log(args, f"c1 continuation problem {inp['nx']}x{inp['nz']} f={inp['freq']:g} Hz K={inp['K']}")
         ds.append(observed_data(inp, torch, KKTProblem))
         p = KKTProblem.from_inputs(inp, reg_on_update=True)
+        if args.pc == "multigrid":
+            p.set_multigrid(prec="c128" if args.fwd_prec == "c128" else "c64", inner_rtol=args.inner_rtol)
         if args.shape:
             c, ns = (int(v) for v in args.shape.split(","))
             p.set_solver_shape(c, ns)
@@ -587,12 +592,14 @@ def main():
     inp = make_problem_inputs(args.config, args.freq_index)
     if inp["eps"] is None:
         raise SystemExit("no eps for this workload in synthetic/eps_table.json")
-    mixed = args.pc == "inexact" or args.fwd_prec == "mixed"
+    mixed = args.pc == "inexact" or args.fwd_prec == "mixed"   # multigrid with c128 fwd: complex128 throughout
     log(args, f"workload {args.config} f={inp['freq']} Hz grid {inp['nx']}x{inp['nz']} K={inp['K']} "
               f"pc={args.pc} fwd={args.fwd_prec}")
     d = observed_data(inp, torch, KKTProblem)
     p = KKTProblem.from_inputs(inp, reg_on_update=True)
     p.inner_fp32 = args.pc == "inexact"      # the block solves of the step run in complex64
+    if args.pc == "multigrid":
+        p.set_multigrid(prec="c128" if args.fwd_prec == "c128" else "c64", inner_rtol=args.inner_rtol)
     if args.shape:
         c, ns = (int(v) for v in args.shape.split(","))
         p.set_solver_shape(c, ns)
@@ -679,7 +686,7 @@ def main():
         "config": {"workload": (f"{args.config}: {inp['nx']}x{inp['nz']} grid, h={inp['h']:g} m, "
                                 f"{inp['npml']}-cell PML, faulted-lens model, {inp['K']} sources, "
                                 f"{len(inp['rec_ix'])} receivers, {inp['freq']:g} Hz, "
-                                f"{'inexact (complex64 block factors)' if args.pc == 'inexact' else 'exact (FP64)'} "
+                                f"{ {'inexact': 'inexact (complex64 block factors)', 'exact': 'exact (FP64)', 'multigrid': 'inexact (multigrid-preconditioned BiCGStab block solves to ' + format(args.inner_rtol, 'g') + ')'}[args.pc]} "
                                 f"block-triangular preconditioner, background solve "
                                 f"{'complex64 + FP64 refinement to 1e-10' if args.fwd_prec == 'mixed' else 'FP64'}, "
                                 f"FGMRES({args.restart}) in FP64 to {args.rtol:g}, b_s = 0"),

@@ -62,9 +62,12 @@ typedef enum {
 
 /* Preconditioner of the KKT system (Section 5). */
 typedef enum {
-  KF_PC_EXACT = 0,   /* eq. precond: A and A^* solved exactly (FP64 factors) */
-  KF_PC_INEXACT = 1  /* eq. precond_approx: A replaced by A~ = the complex64
-                        factorisation of A (one sweep per block solve) */
+  KF_PC_EXACT = 0,     /* eq. precond: A and A^* solved exactly (FP64 factors) */
+  KF_PC_INEXACT = 1,   /* eq. precond_approx: A replaced by A~ = the complex64
+                          factorisation of A (one sweep per block solve) */
+  KF_PC_MULTIGRID = 2  /* eq. precond_approx with A~^-1 = BiCGStab on A preconditioned by
+                          one shifted-Laplacian multigrid V-cycle, stopped at the inner
+                          tolerance of kf_set_multigrid (Section 5's suggested A~) */
 } kf_pc;
 
 /* Problem description (Sections 2-4).  Arrays marked [host] are copied. */
@@ -103,7 +106,13 @@ typedef struct {
                               basis orthogonal to ~1e-15 while skipping the pass whenever the
                               cancellation is mild; FGMRES's true residual at each restart and
                               at exit checks the result either way. */
+  int32_t outer;           /* KF_OUTER_FGMRES (restarted flexible GMRES, 2 restart + 1 packed
+                              vectors) or KF_OUTER_BICGSTAB (right-preconditioned BiCGStab, the
+                              Conclusions' memory-lean alternative: nine packed vectors, two
+                              preconditioner applications and KKT matvecs per iteration, a
+                              fixed preconditioner assumed; restart and reorth_eta unused) */
 } kf_newton_opts;
+typedef enum { KF_OUTER_FGMRES = 0, KF_OUTER_BICGSTAB = 1 } kf_outer;
 
 typedef struct {
   int32_t outer_iters;     /* FGMRES iterations taken */
@@ -299,6 +308,44 @@ kf_status rsgn_cg_step(kf_problem *p, const void *d_obs, const kf_cg_opts *opts 
 kf_status helmholtz_adjoint_gradient(kf_problem *p, int32_t prec, const void *u, const void *grad_u,
                                      double *grad_gamma);
 
+/* ---- shifted-Laplacian multigrid: the inexact block solver of KF_PC_MULTIGRID ----
+ * Section 5 names the shifted-Laplacian preconditioner, inverted approximately by
+ * multigrid, as the better A~ for eq. precond_approx; the paper gives no details.  The
+ * library takes: the shifted operator M = A(gamma (1 + i beta)); levels by standard
+ * coarsening of the vertex grid (n -> (n + 1) / 2 while both sizes are odd and the
+ * smaller one is at least n_min; spacing doubled, PML width halved, gamma injected), M
+ * rediscretised on every level; one z-line then one x-line Jacobi sweep before the
+ * coarse-grid correction and the reverse after it; full-weighting restriction, bilinear
+ * prolongation; the coarsest level solved exactly by the block factorisation of its M.
+ * Each block solve is BiCGStab on A for all K sources in lock step (own scalars per
+ * source), right-preconditioned by one V-cycle, stopped when every source meets
+ * ||b_k - A x_k|| <= rtol ||b_k|| (by the recurrence).  A^H x = b is solved as
+ * A conj(x) = conj(b).  The hierarchy is rebuilt when gamma changes. */
+typedef struct {
+  int32_t iters;           /* BiCGStab iterations (all sources in lock step) */
+  int32_t vcycles;         /* V-cycles applied (two per iteration) */
+  int32_t levels;          /* multigrid levels, the coarsest included */
+  double rel_res_max;      /* true max_k ||b_k - op(A) x_k|| / ||b_k|| in FP64 (-1 when b and x alias) */
+} kf_mg_stats;
+/* prec: KF_C64 (complex64 fields, FP32 arithmetic, FP64 inner products) or KF_C128;
+ * beta > 0 the shift (0.5 is the usual choice); 0 < inner_rtol < 1 and inner_maxit >= 1
+ * for the block solves of KF_PC_MULTIGRID; n_min >= 3.  Defaults before any call:
+ * KF_C64, 0.5, 1e-3, 200, 20. */
+kf_status kf_set_multigrid(kf_problem *p, int32_t prec, double beta, double inner_rtol, int32_t inner_maxit,
+                           int32_t n_min);
+/* A x = rhs (adjoint = 0) or A^H x = rhs (1) for all K sources by the multigrid-
+ * preconditioned BiCGStab to rtol (c128 rhs, x; they may alias).  KF_ENOCONV (x and stats
+ * filled) if maxit iterations do not reach rtol; KF_ESHAPE if the grid has no coarser level.
+ * Synchronous. */
+kf_status helmholtz_solve_mg(kf_problem *p, int32_t adjoint, const void *rhs, void *x, double rtol, int32_t maxit,
+                             kf_mg_stats *st /*[host], may be NULL*/);
+/* x = V(b): one V-cycle of the shifted operator for every source from x = 0 (c128 b, x,
+ * distinct), in the configured precision.  Asynchronous. */
+kf_status kf_mg_vcycle(kf_problem *p, const void *b, void *x);
+/* The hierarchy built so far: nlev levels, dims[2 l], dims[2 l + 1] = nx, nz of level l
+ * (dims [host][16]). */
+kf_status kf_mg_levels(kf_problem *p, int32_t *dims /*[host][16]*/, int32_t *nlev /*[host]*/);
+
 /* Build the point sources f_k = e_src / h^2 of the problem into f ([K][nz][nx], c128). */
 kf_status kf_sources(kf_problem *p, void *f);
 
@@ -316,7 +363,7 @@ kf_status kf_profile_enable(kf_problem *p, int32_t on);
  * forward-sweep and back-substitution launches), "blu_mid", "blu_reduced_rhs",
  * "blu_chain", "blu_correct" (the middle columns, the separators' right-hand sides, the
  * separator system's cyclic-reduction levels, one launch per level, and the interior
- * correction), "precond_stage", "gs_dot" (the first Gram-Schmidt pass's dot products of
+ * correction), "precond_stage", "mg_solve" (a whole multigrid-preconditioned block solve), "gs_dot" (the first Gram-Schmidt pass's dot products of
  * each Arnoldi step, with the norm of the new vector), "gs_update" (that pass's fused,
  * normalising update), "orth" (the rest of the orthogonalisation: the occasional second
  * pass, the Hessenberg and solution updates), "reduce".

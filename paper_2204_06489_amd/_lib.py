@@ -16,7 +16,8 @@ KF_OK, KF_EINVAL, KF_ESHAPE, KF_ENOMEM, KF_EHIP, KF_ENOCONV, KF_EBREAKDOWN, KF_E
 STATUS_NAMES = {0: "KF_OK", 1: "KF_EINVAL", 2: "KF_ESHAPE", 3: "KF_ENOMEM", 4: "KF_EHIP", 5: "KF_ENOCONV",
                 6: "KF_EBREAKDOWN", 7: "KF_ENAN", 8: "KF_ESTATE"}
 KF_C128, KF_C64, KF_MIXED = 0, 1, 2
-KF_PC_EXACT, KF_PC_INEXACT = 0, 1
+KF_PC_EXACT, KF_PC_INEXACT, KF_PC_MULTIGRID = 0, 1, 2
+KF_OUTER_FGMRES, KF_OUTER_BICGSTAB = 0, 1
 
 
 class KfDesc(C.Structure):
@@ -33,7 +34,7 @@ class KfNewtonOpts(C.Structure):
     _fields_ = [
         ("rtol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32), ("pc", C.c_int32),
         ("fwd_prec", C.c_int32), ("fwd_rtol", C.c_double), ("misfit_after", C.c_int32),
-        ("reorth_eta", C.c_double),
+        ("reorth_eta", C.c_double), ("outer", C.c_int32),
     ]
 
 
@@ -63,6 +64,10 @@ class KfCgStats(C.Structure):
                 ("rel_res_hist", C.c_double * 512), ("misfit_before", C.c_double), ("phi_before", C.c_double),
                 ("t_factor_ms", C.c_double), ("t_forward_ms", C.c_double), ("t_cg_ms", C.c_double),
                 ("t_total_ms", C.c_double)]
+
+
+class KfMgStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("vcycles", C.c_int32), ("levels", C.c_int32), ("rel_res_max", C.c_double)]
 
 
 class KfSolveStats(C.Structure):
@@ -96,6 +101,10 @@ _SIGNATURES = {
                                       C.POINTER(KfNewtonOpts), P, C.POINTER(KfNewtonStats)]),
     "rsgn_cg_step": (C.c_int, [P, P, C.POINTER(KfCgOpts), P, P, C.c_int32, C.POINTER(KfCgStats)]),
     "kf_sources": (C.c_int, [P, P]),
+    "kf_set_multigrid": (C.c_int, [P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32]),
+    "helmholtz_solve_mg": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.c_int32, C.POINTER(KfMgStats)]),
+    "kf_mg_vcycle": (C.c_int, [P, P, P]),
+    "kf_mg_levels": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "kf_sizes": (C.c_int, [P, C.POINTER(C.c_int64)]),
     "kf_batch_create": (C.c_int, [C.POINTER(P), C.c_int32, P, C.POINTER(P)]),
     "kf_batch_destroy": (C.c_int, [P]),

@@ -11,7 +11,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "ops.hip", "blocklu.hip", "krylov.hip"]
+SOURCES = ["api.hip", "ops.hip", "blocklu.hip", "krylov.hip", "multigrid.hip"]
 LIB = os.path.join(HERE, "libkktfwi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -133,7 +133,8 @@ static void free_all(kf_problem *p) {
   dfree(p->V64); dfree(p->W64); dfree(p->V32); dfree(p->W32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
-  dfree(p->cg_vec); dfree(p->cg_field);
+  dfree(p->cg_vec); dfree(p->cg_field); dfree(p->bicg);
+  mg_destroy(p);
   if (p->host_pinned) hipHostFree(p->host_pinned);
   p->host_pinned = nullptr;
   for (int i = 0; i < PROF_N; ++i) {
@@ -334,6 +335,7 @@ extern "C" kf_status kf_set_gamma(kf_problem *p, const double *gamma) {
   if (bad) return fail(KF_EINVAL, "gamma must be finite (" + std::to_string(bad) + " NaN/inf entries)");
   HIP_TRY(hipMemcpyAsync(p->gamma, gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
   p->have_T64 = p->have_T32 = false;
+  ++p->gamma_version;
   p->have_un = false;
   return KF_OK;
 }
@@ -594,18 +596,70 @@ extern "C" kf_status kkt_apply_noalloc(kf_problem *p, const void *xi, void *y) {
   return launch_kkt_apply_noalloc(p, (const double2 *)xi, (double2 *)y);
 }
 
+// A~ of the multigrid variant: an inner iteration that stops at its tolerance or its
+// iteration limit; the flexible outer Krylov method accepts either
+static kf_status mg_inexact(kf_problem *p, int adjoint, const double2 *b, double2 *x) {
+  kf_status st = mg_solve(p, adjoint, b, x, 0.0, 0, nullptr);
+  return st == KF_ENOCONV ? KF_OK : st;
+}
+
 static kf_status precond_impl(kf_problem *p, int pc, const double2 *y, double2 *z) {
   const size_t Ku = (size_t)p->K * p->Nu;
   const double2 *yu = y;
   double2 *zu = z, *zl = z + Ku + p->Ng;
   // stage 1: z_lam = A^-* y_u
   if (pc == KF_PC_EXACT) CHECK_ST(blu_solve<double>(p, 1, yu, zl));
-  else CHECK_ST(blu_solve_mixed_io(p, 1, yu, zl));
+  else if (pc == KF_PC_INEXACT) CHECK_ST(blu_solve_mixed_io(p, 1, yu, zl));
+  else CHECK_ST(mg_inexact(p, 1, yu, zl));
   // stage 2: z_s = (y_s + P^* z_lam) / eps, and z_u := y_lam + P z_s
   CHECK_ST(launch_precond_stage2(p, y, z));
   // stage 3: z_u = A^-1 (y_lam + P z_s)
   if (pc == KF_PC_EXACT) CHECK_ST(blu_solve<double>(p, 0, zu, zu));
-  else CHECK_ST(blu_solve_mixed_io(p, 0, zu, zu));
+  else if (pc == KF_PC_INEXACT) CHECK_ST(blu_solve_mixed_io(p, 0, zu, zu));
+  else CHECK_ST(mg_inexact(p, 0, zu, zu));
+  return KF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// shifted-Laplacian multigrid (the inexact block solver of the third variant)
+// ---------------------------------------------------------------------------
+extern "C" kf_status kf_set_multigrid(kf_problem *p, int32_t prec, double beta, double inner_rtol, int32_t inner_maxit,
+                                      int32_t n_min) {
+  CHECK_ST(check_p(p));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return mg_configure(p, prec, beta, inner_rtol, inner_maxit, n_min);
+}
+
+extern "C" kf_status helmholtz_solve_mg(kf_problem *p, int32_t adjoint, const void *rhs, void *x, double rtol,
+                                        int32_t maxit, kf_mg_stats *st) {
+  CHECK_ST(check_p(p));
+  if (!rhs || !x) return fail(KF_EINVAL, "rhs or x is NULL");
+  if (!(rtol > 0.0 && rtol < 1.0) || maxit < 1) return fail(KF_EINVAL, "need 0 < rtol < 1 and maxit >= 1");
+  kf_mg_stats S{};
+  kf_status r = mg_solve(p, adjoint != 0, (const double2 *)rhs, (double2 *)x, rtol, maxit, &S);
+  if (r != KF_OK && r != KF_ENOCONV) return r;
+  // the true residual max_k ||rhs_k - op(A) x_k|| / ||rhs_k|| in FP64
+  double rm = -1.0;
+  if (rhs != x) CHECK_ST(residual_max(p, adjoint != 0, (const double2 *)rhs, (const double2 *)x, &rm, nullptr));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  S.rel_res_max = rm;
+  S.levels = mg_levels(p, nullptr);
+  if (st) *st = S;
+  return r;
+}
+
+extern "C" kf_status kf_mg_vcycle(kf_problem *p, const void *b, void *x) {
+  CHECK_ST(check_p(p));
+  if (!b || !x || b == x) return fail(KF_EINVAL, "b and x must be distinct non-NULL fields");
+  return mg_vcycle_apply(p, (const double2 *)b, (double2 *)x);
+}
+
+extern "C" kf_status kf_mg_levels(kf_problem *p, int32_t *dims, int32_t *nlev) {
+  CHECK_ST(check_p(p));
+  if (!dims || !nlev) return fail(KF_EINVAL, "null pointer argument");
+  int d[16] = {0};
+  *nlev = mg_levels(p, d);
+  for (int q = 0; q < 16; ++q) dims[q] = d[q];
   return KF_OK;
 }
 
@@ -613,7 +667,7 @@ extern "C" kf_status precond_apply(kf_problem *p, int32_t pc, const void *y, voi
   CHECK_ST(check_p(p));
   if (!y || !z) return fail(KF_EINVAL, "y or z is NULL");
   if (y == z) return fail(KF_EINVAL, "y and z must not alias");
-  if (pc != KF_PC_EXACT && pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
+  if (pc != KF_PC_EXACT && pc != KF_PC_INEXACT && pc != KF_PC_MULTIGRID) return fail(KF_EINVAL, "invalid preconditioner");
   if (!p->have_un) return fail(KF_ESTATE, "no background field (kf_set_background or newton_step first)");
   return precond_impl(p, pc, (const double2 *)y, (double2 *)z);
 }
@@ -621,16 +675,24 @@ extern "C" kf_status precond_apply(kf_problem *p, int32_t pc, const void *y, voi
 // ---------------------------------------------------------------------------
 // flexible GMRES (right preconditioned, CGS2, Givens on the device)
 // ---------------------------------------------------------------------------
+// the packed right-hand side, solution and work vector of a KKT solve
+static kf_status ensure_xi(kf_problem *p) {
+  const size_t N = p->Nxi;
+  if (!p->xi_w) CHECK_ST(dalloc(&p->xi_w, N));
+  if (!p->xi_b) CHECK_ST(dalloc(&p->xi_b, N));
+  if (!p->xi_x) CHECK_ST(dalloc(&p->xi_x, N));
+  return KF_OK;
+}
+
+// the FGMRES(m) basis (m + 1 vectors), its preconditioned vectors (m) and Hessenberg data
 static kf_status ensure_krylov(kf_problem *p, int m) {
+  CHECK_ST(ensure_xi(p));
   if (p->krylov_m >= m) return KF_OK;
-  dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
+  dfree(p->V); dfree(p->Z); dfree(p->hess);
   p->krylov_m = 0;
   const size_t N = p->Nxi;
   CHECK_ST(dalloc(&p->V, (size_t)(m + 1) * N));
   CHECK_ST(dalloc(&p->Z, (size_t)m * N));
-  CHECK_ST(dalloc(&p->xi_w, N));
-  CHECK_ST(dalloc(&p->xi_b, N));
-  CHECK_ST(dalloc(&p->xi_x, N));
   CHECK_ST(dalloc(&p->hess, (size_t)(m + 1) * m + 6 * (size_t)(m + 1) + 16));
   p->krylov_m = m;
   return KF_OK;
@@ -746,6 +808,122 @@ static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, dou
 }
 
 // ---------------------------------------------------------------------------
+// outer BiCGStab (the Conclusions' memory-lean alternative to GMRES): right-
+// preconditioned, nine packed vectors whatever the iteration count
+// ---------------------------------------------------------------------------
+static double host_norm(kf_problem *p, const double2 *x, int64_t n, kf_status *st);
+
+static kf_status read_c(kf_problem *p, const double2 *dev, double2 *host) {
+  HIP_TRY(hipMemcpyAsync(p->host_pinned, dev, sizeof(double2), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  host->x = p->host_pinned[0];
+  host->y = p->host_pinned[1];
+  return KF_OK;
+}
+
+static inline double2 cdiv_h(double2 a, double2 b) { return cdiv(a, b); }
+
+static kf_status bicgstab_outer(kf_problem *p, int pc, const double2 *b, double2 *x, double tol, int maxit,
+                                FgmresOut &o) {
+  const int64_t N = p->Nxi;
+  if (!p->bicg) CHECK_ST(dalloc(&p->bicg, (size_t)8 * N));
+  double2 *r = p->bicg, *rh = r + N, *pv = rh + N, *v = pv + N, *sv = v + N, *t = sv + N, *ph = t + N, *sh = ph + N;
+  double2 *dot = (double2 *)p->red_out;
+  PhaseTimer pt(p);
+  kf_status e = KF_OK;
+  const double bnorm = host_norm(p, b, N, &e);
+  CHECK_ST(e);
+  HIP_TRY(hipMemsetAsync(x, 0, sizeof(double2) * N, p->stream));
+  o.hist.assign(1, 1.0);
+  if (!std::isfinite(bnorm)) return fail(KF_ENAN, "non-finite right-hand side");
+  if (bnorm == 0.0) { o.rel_res = 0.0; return KF_OK; }
+  HIP_TRY(hipMemcpyAsync(r, b, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(rh, b, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemsetAsync(pv, 0, sizeof(double2) * N, p->stream));
+  HIP_TRY(hipMemsetAsync(v, 0, sizeof(double2) * N, p->stream));
+  double2 rho = make_double2(1.0, 0.0), alpha = rho, omega = rho;
+  const double2 one = make_double2(1.0, 0.0);
+  kf_status status = KF_OK;
+  int it = 0;
+  double rel = 1.0;
+  for (;;) {
+    if (it >= maxit) { status = fail(KF_ENOCONV, "outer BiCGStab reached maxit"); break; }
+    double2 rho_new;
+    pt.start(PH_ORTH);
+    CHECK_ST(dot_c128(p, rh, r, N, dot));
+    CHECK_ST(read_c(p, dot, &rho_new));
+    if (cabs2(rho_new) == 0.0 || cabs2(omega) == 0.0) { status = fail(KF_EBREAKDOWN, "outer BiCGStab breakdown"); break; }
+    const double2 beta = cmul(cdiv_h(rho_new, rho), cdiv_h(alpha, omega));
+    // p = r + beta (p - omega v)
+    CHECK_ST(launch_axpy_field(p, N, csub(make_double2(0.0, 0.0), omega), v, pv));
+    CHECK_ST(launch_axpby_field(p, N, one, r, beta, pv));
+    pt.stop();
+    pt.start(PH_PRECOND);
+    CHECK_ST(precond_impl(p, pc, pv, ph));
+    pt.stop();
+    pt.start(PH_MATVEC);
+    CHECK_ST(launch_kkt_apply(p, ph, v));
+    pt.stop();
+    pt.start(PH_ORTH);
+    double2 rv;
+    CHECK_ST(dot_c128(p, rh, v, N, dot));
+    CHECK_ST(read_c(p, dot, &rv));
+    if (cabs2(rv) == 0.0) { status = fail(KF_EBREAKDOWN, "outer BiCGStab breakdown"); pt.stop(); break; }
+    alpha = cdiv_h(rho_new, rv);
+    // s = r - alpha v
+    HIP_TRY(hipMemcpyAsync(sv, r, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+    CHECK_ST(launch_axpy_field(p, N, csub(make_double2(0.0, 0.0), alpha), v, sv));
+    pt.stop();
+    pt.start(PH_PRECOND);
+    CHECK_ST(precond_impl(p, pc, sv, sh));
+    pt.stop();
+    pt.start(PH_MATVEC);
+    CHECK_ST(launch_kkt_apply(p, sh, t));
+    pt.stop();
+    pt.start(PH_ORTH);
+    double2 ts, tt;
+    CHECK_ST(dot_c128(p, t, sv, N, dot));
+    CHECK_ST(read_c(p, dot, &ts));
+    CHECK_ST(dot_c128(p, t, t, N, dot));
+    CHECK_ST(read_c(p, dot, &tt));
+    omega = tt.x > 0.0 ? cdiv_h(ts, tt) : make_double2(0.0, 0.0);
+    // x += alpha ph + omega sh;  r = s - omega t
+    CHECK_ST(launch_axpy_field(p, N, alpha, ph, x));
+    CHECK_ST(launch_axpy_field(p, N, omega, sh, x));
+    CHECK_ST(launch_axpby_field(p, N, csub(make_double2(0.0, 0.0), omega), t, one, sv));
+    HIP_TRY(hipMemcpyAsync(r, sv, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+    rho = rho_new;
+    const double rn = host_norm(p, r, N, &e);
+    CHECK_ST(e);
+    pt.stop();
+    ++it;
+    rel = rn / bnorm;
+    o.hist.push_back(rel);
+    if (!std::isfinite(rel)) { status = fail(KF_ENAN, "non-finite residual in outer BiCGStab"); break; }
+    if (rel <= tol) {
+      // the true residual decides: b - M x
+      CHECK_ST(launch_kkt_apply(p, x, p->xi_w));
+      HIP_TRY(hipMemcpyAsync(t, b, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+      CHECK_ST(launch_axpy_field(p, N, make_double2(-1.0, 0.0), p->xi_w, t));
+      const double tn = host_norm(p, t, N, &e);
+      CHECK_ST(e);
+      rel = tn / bnorm;
+      if (rel <= tol) break;
+      // the recurrence drifted: restart from the true residual
+      HIP_TRY(hipMemcpyAsync(r, t, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+      HIP_TRY(hipMemcpyAsync(rh, t, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+      HIP_TRY(hipMemsetAsync(pv, 0, sizeof(double2) * N, p->stream));
+      HIP_TRY(hipMemsetAsync(v, 0, sizeof(double2) * N, p->stream));
+      rho = alpha = omega = one;
+    }
+  }
+  o.iters = it;
+  o.rel_res = rel;
+  pt.sum(o.ph, PH_N);
+  return status;
+}
+
+// ---------------------------------------------------------------------------
 // one Gauss-Newton step in the full space (Sections 3-5)
 // ---------------------------------------------------------------------------
 static double host_norm(kf_problem *p, const double2 *x, int64_t n, kf_status *st) {
@@ -776,10 +954,12 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   if (!d_obs || !o) return fail(KF_EINVAL, "d_obs or opts is NULL");
   if (!(o->rtol > 0.0) || o->restart < 1 || o->restart > 200 || o->maxit < 1)
     return fail(KF_EINVAL, "need rtol > 0, 1 <= restart <= 200, maxit >= 1");
-  if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
+  if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT && o->pc != KF_PC_MULTIGRID)
+    return fail(KF_EINVAL, "invalid preconditioner");
   if (o->fwd_prec != KF_C128 && o->fwd_prec != KF_MIXED) return fail(KF_EINVAL, "fwd_prec must be C128 or MIXED");
   if (o->fwd_prec == KF_MIXED && !(o->fwd_rtol > 0.0)) return fail(KF_EINVAL, "fwd_rtol must be > 0");
   if (!(o->reorth_eta >= 0.0 && o->reorth_eta <= 1.0)) return fail(KF_EINVAL, "reorth_eta must be in [0, 1]");
+  if (o->outer != KF_OUTER_FGMRES && o->outer != KF_OUTER_BICGSTAB) return fail(KF_EINVAL, "invalid outer solver");
   kf_newton_stats S;
   std::memset(&S, 0, sizeof(S));
   S.misfit_after = -1.0;
@@ -787,7 +967,8 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   auto ms_since = [](std::chrono::steady_clock::time_point t) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
   };
-  CHECK_ST(ensure_krylov(p, o->restart));
+  if (o->outer == KF_OUTER_BICGSTAB) CHECK_ST(ensure_xi(p));
+  else CHECK_ST(ensure_krylov(p, o->restart));
   const int64_t N = p->Nxi;
   const size_t Ku = (size_t)p->K * p->Nu;
   // factorisation of A(gamma_n)
@@ -817,7 +998,9 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   CHECK_ST(launch_rhs(p, p->d_r, p->d_rptr, p->d_rlist, p->xi_b, p->d.reg_on_update));
   // KKT solve
   FgmresOut fo;
-  kf_status fst = fgmres(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->restart, o->maxit, o->reorth_eta, fo);
+  kf_status fst = o->outer == KF_OUTER_BICGSTAB
+                      ? bicgstab_outer(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->maxit, fo)
+                      : fgmres(p, o->pc, p->xi_b, p->xi_x, o->rtol, o->restart, o->maxit, o->reorth_eta, fo);
   if (fst != KF_OK && fst != KF_ENOCONV) return fst;
   S.outer_iters = fo.iters;
   S.reorth_passes = fo.reorth;
@@ -839,11 +1022,13 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
     if (!update_in_place) HIP_TRY(hipMemcpyAsync(p->vec_d, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
     CHECK_ST(launch_update_gamma(p, ds, p->gamma));
     p->have_T64 = p->have_T32 = false;
+    ++p->gamma_version;
     if (gamma_next) HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
     if (o->misfit_after) {
       CHECK_ST(blu_factor(p, o->fwd_prec == KF_MIXED ? 3 : 1));
       int it2;
-      double2 *u1 = p->V;  // Krylov space is free after the solve: m+1 >= 2 packed vectors > K*Nu
+      // the outer solver's vectors are free after the solve: at least 2 packed vectors > K*Nu
+      double2 *u1 = o->outer == KF_OUTER_BICGSTAB ? p->bicg : p->V;
       CHECK_ST(forward_solve(p, o->fwd_prec, o->fwd_rtol, u1, &it2));
       CHECK_ST(launch_residual(p, (const double2 *)d_obs, u1, p->d_r, p->d_wr));
       double rn1 = host_norm(p, p->d_r, nd, &e); CHECK_ST(e);
@@ -853,6 +1038,7 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
       // restore gamma_n (kept in vec_d, which no step above overwrote)
       HIP_TRY(hipMemcpyAsync(p->gamma, p->vec_d, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
       p->have_T64 = p->have_T32 = false;
+      ++p->gamma_version;
     }
   } else if (gamma_next) {
     HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
@@ -1031,6 +1217,7 @@ extern "C" kf_status rsgn_cg_step(kf_problem *p, const void *d_obs, const kf_cg_
   if (update_in_place) {
     CHECK_ST(launch_update_gamma(p, x, p->gamma));
     p->have_T64 = p->have_T32 = false;
+    ++p->gamma_version;
     p->have_un = false;
     if (gamma_next) HIP_TRY(hipMemcpyAsync(gamma_next, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));
   } else if (gamma_next) {
@@ -1076,7 +1263,7 @@ static const char *prof_names[PROF_N] = {"kkt_apply", "stencil",     "blu_factor
                                          "precond_stage", "orth",  "reduce",      "blu_fwd_c128",
                                          "blu_fwd_c64",   "blu_bwd_c128", "blu_bwd_c64", "blu_mid",
                                          "blu_reduced_rhs", "blu_chain", "blu_correct", "gs_dot",
-                                         "gs_update"};
+                                         "gs_update", "mg_solve"};
 
 extern "C" kf_status kf_profile_enable(kf_problem *p, int32_t on) {
   CHECK_ST(check_p(p));
@@ -1272,6 +1459,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
     return fail(KF_EINVAL, "need rtol > 0, 1 <= restart <= 200, maxit >= 1");
   if (o->pc != KF_PC_EXACT && o->pc != KF_PC_INEXACT) return fail(KF_EINVAL, "invalid preconditioner");
   if (o->fwd_prec != KF_C128) return fail(KF_EINVAL, "batched steps use a complex128 background solve");
+  if (o->outer != KF_OUTER_FGMRES) return fail(KF_EINVAL, "batched steps use flexible GMRES");
   if (!(o->reorth_eta >= 0.0 && o->reorth_eta <= 1.0)) return fail(KF_EINVAL, "reorth_eta must be in [0, 1]");
   const int m = o->restart;
   auto T0 = std::chrono::steady_clock::now();
@@ -1426,6 +1614,7 @@ extern "C" kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, 
     if (update_in_place) {
       CHECK_ST(launch_update_gamma(p, ds, p->gamma));
       p->have_T64 = p->have_T32 = false;
+      ++p->gamma_version;
     }
     S[q].t_precond_ms = t_cols;    // columns (preconditioner + matvec) of all problems together
     S[q].t_orth_ms = t_orth;

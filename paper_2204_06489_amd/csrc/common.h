@@ -56,6 +56,7 @@ struct Grid {
   double h, omega;
   const double *gamma;      // [nz][nx]
   const double2 *xn, *ixh, *zn, *izh;
+  double beta;              // 0 for A; beta != 0 gives the shifted operator A(gamma (1 + i beta))
 };
 
 // The five stencil weights of node (i, j) of A (Section 2, 5-point PML scheme):
@@ -72,6 +73,7 @@ __device__ inline Stencil5 stencil_at(const Grid &g, int i, int j) {
   s.czp = cscale(cmul(X, g.izh[j + 1]), -ih2);
   const double w2g = g.omega * g.omega * g.gamma[(size_t)j * g.nx + i];
   double2 m = cscale(cmul(X, Z), w2g);
+  if (g.beta != 0.0) m = cmul(m, make_double2(1.0, g.beta));   // shifted mass term (multigrid levels)
   s.cc = csub(make_double2(0.0, 0.0), cadd(cadd(s.cxm, s.cxp), cadd(s.czm, s.czp)));
   s.cc = csub(s.cc, m);
   return s;
@@ -185,8 +187,14 @@ struct kf_problem {
   // reduced-space CG (allocated on first use): five control vectors and one field
   double2 *cg_vec = nullptr;                   // [5][Ng]: ds, residual, direction, H direction, g
   double2 *cg_field = nullptr;                 // [K][nz][nx]
+  double2 *bicg = nullptr;                     // outer BiCGStab: 8 packed vectors (allocated on first use)
 
-  Grid grid() const { return Grid{nx, nz, npml, h, omega, gamma, xn, ixh, zn, izh}; }
+  double beta = 0.0;                           // mass-term shift (multigrid levels only)
+  uint64_t gamma_version = 0;                  // bumped whenever gamma changes
+  Grid grid() const { return Grid{nx, nz, npml, h, omega, gamma, xn, ixh, zn, izh, beta}; }
+
+  // shifted-Laplacian multigrid (the third preconditioner variant), built on first use
+  struct MgState *mg = nullptr;
 
   // profiling
   bool prof = false;
@@ -198,7 +206,7 @@ struct kf_problem {
 
 enum ProfId { PROF_KKT = 0, PROF_STENCIL, PROF_FACTOR, PROF_SWEEP, PROF_PRECOND, PROF_ORTH, PROF_REDUCE,
               PROF_FWD64, PROF_FWD32, PROF_BWD64, PROF_BWD32, PROF_MID, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT,
-              PROF_GS_DOT, PROF_GS_UPDATE, PROF_N };
+              PROF_GS_DOT, PROF_GS_UPDATE, PROF_MG, PROF_N };
 static_assert(PROF_N <= 32, "profiling families are bits of a 32-bit mask");
 
 // error plumbing
@@ -223,6 +231,9 @@ struct ProfScope {
 // launchers (all enqueue on p->stream)
 // ---------------------------------------------------------------------------
 kf_status launch_pml(kf_problem *p, const kf_desc &d);
+// X (nodes) and 1/X (faces) of one axis of n nodes (the PML stretch of Section 2)
+kf_status launch_stretch(hipStream_t s, int n, double h, int npml, double omega, double r0, double cref, double2 *fn,
+                         double2 *ifh);
 template <typename R> kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *y);
 kf_status launch_kkt_apply(kf_problem *p, const double2 *xi, double2 *y);
 kf_status launch_kkt_apply_noalloc(kf_problem *p, const double2 *xi, double2 *y);   // scratch array, no allocation
@@ -245,6 +256,15 @@ kf_status launch_rhs_u_field(kf_problem *p, const double2 *r, double2 *out);
 kf_status launch_gather_PH(kf_problem *p, double alpha, const double2 *v, double gcoef, const double2 *lam,
                            int real_only, double2 *out);
 kf_status launch_copy_c64_to_c128(kf_problem *p, int64_t n, const float2 *x, double2 *y);
+
+// shifted-Laplacian multigrid (multigrid.hip)
+kf_status mg_configure(kf_problem *p, int prec, double beta, double rtol, int maxit, int n_min);
+// BiCGStab with one V-cycle per preconditioning step; b and x (c128) may alias; rtol / maxit
+// <= 0 take the configured values
+kf_status mg_solve(kf_problem *p, int adjoint, const double2 *b, double2 *x, double rtol, int maxit, kf_mg_stats *st);
+kf_status mg_vcycle_apply(kf_problem *p, const double2 *b, double2 *x);
+int mg_levels(kf_problem *p, int *dims);
+void mg_destroy(kf_problem *p);
 
 // block factorisation and sweeps
 int blu_auto_chunks(int nx, int nz, int K);

@@ -395,6 +395,13 @@ kf_status launch_pml(kf_problem *p, const kf_desc &d) {
   return KF_OK;
 }
 
+kf_status launch_stretch(hipStream_t s, int n, double h, int npml, double omega, double r0, double cref, double2 *fn,
+                         double2 *ifh) {
+  hipLaunchKernelGGL(k_stretch, dim3((n + 256) / 256), dim3(256), 0, s, n, h, npml, omega, r0, cref, fn, ifh);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
 template <typename R>
 kf_status launch_stencil(kf_problem *p, int adjoint, const cplx<R> *x, cplx<R> *y) {
   ProfScope ps(p, PROF_STENCIL);

@@ -12,11 +12,12 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (KF_C128, KF_C64, KF_MIXED, KF_PC_EXACT, KF_PC_INEXACT, KF_ENOCONV, KfCgOpts, KfCgStats, KfDesc,
-                   KfNewtonOpts, KfNewtonStats, KfSolveStats, check, lib)
+from ._lib import (KF_C128, KF_C64, KF_MIXED, KF_PC_EXACT, KF_PC_INEXACT, KF_PC_MULTIGRID, KF_ENOCONV, KfCgOpts,
+                   KfCgStats, KfDesc, KfMgStats, KfNewtonOpts, KfNewtonStats, KfSolveStats, check, lib)
 
 _PREC = {"c128": KF_C128, "c64": KF_C64, "mixed": KF_MIXED}
-_PC = {"exact": KF_PC_EXACT, "inexact": KF_PC_INEXACT}
+_PC = {"exact": KF_PC_EXACT, "inexact": KF_PC_INEXACT, "multigrid": KF_PC_MULTIGRID}
+_OUTER = {"fgmres": 0, "bicgstab": 1}
 
 
 def _ptr(t, dtype=None, numel=None, name="tensor"):
@@ -180,6 +181,32 @@ class KKTProblem:
         check(lib().kf_sources(self._h, _ptr(f)))
         return f
 
+    # ---- shifted-Laplacian multigrid -----------------------------------------------
+    def set_multigrid(self, prec="c64", beta=0.5, inner_rtol=1e-3, inner_maxit=200, n_min=20):
+        check(lib().kf_set_multigrid(self._h, _PREC[prec], float(beta), float(inner_rtol), int(inner_maxit),
+                                     int(n_min)))
+
+    def helmholtz_solve_mg(self, rhs, adjoint=False, rtol=1e-3, maxit=200, out=None):
+        """x with A x = rhs (A^H x = rhs) by multigrid-preconditioned BiCGStab; (x, stats)."""
+        x = torch.empty_like(rhs) if out is None else out
+        st = KfMgStats()
+        s = check(lib().helmholtz_solve_mg(self._h, int(adjoint), _ptr(rhs, torch.complex128, self.K * self.Nu, "rhs"),
+                                           _ptr(x, torch.complex128, self.K * self.Nu, "x"), float(rtol), int(maxit),
+                                           C.byref(st)), allow=(KF_ENOCONV,))
+        return x, {"iters": st.iters, "vcycles": st.vcycles, "levels": st.levels, "rel_res_max": st.rel_res_max,
+                   "converged": s != KF_ENOCONV}
+
+    def mg_vcycle(self, b):
+        x = torch.empty_like(b)
+        check(lib().kf_mg_vcycle(self._h, _ptr(b, torch.complex128, self.K * self.Nu, "b"), _ptr(x)))
+        return x
+
+    def mg_levels(self):
+        dims = (C.c_int32 * 16)()
+        n = C.c_int32()
+        check(lib().kf_mg_levels(self._h, dims, C.byref(n)))
+        return [(dims[2 * l], dims[2 * l + 1]) for l in range(n.value)]
+
     # ---- operators --------------------------------------------------------------
     def stencil_apply(self, x, adjoint=False):
         prec = KF_C128 if x.dtype == torch.complex128 else KF_C64
@@ -210,13 +237,16 @@ class KKTProblem:
         return z
 
     def newton_step(self, d_obs, rtol=1e-6, restart=30, maxit=200, pc="exact", fwd_prec="c128",
-                    fwd_rtol=1e-10, misfit_after=False, update_in_place=True, want_xi=True, reorth_eta=0.1):
+                    fwd_rtol=1e-10, misfit_after=False, update_in_place=True, want_xi=True, reorth_eta=0.1,
+                    outer="fgmres"):
         """One full-space GN step; returns (xi or None, gamma_{n+1}, stats dict).
-        reorth_eta: second Gram-Schmidt pass when |w'| < reorth_eta |w| (1 = always)."""
+        reorth_eta: second Gram-Schmidt pass when |w'| < reorth_eta |w| (1 = always).
+        outer: "fgmres" or "bicgstab" (the KKT solver)."""
         o = KfNewtonOpts()
         o.rtol, o.restart, o.maxit, o.pc = float(rtol), int(restart), int(maxit), _PC[pc]
         o.fwd_prec, o.fwd_rtol, o.misfit_after = _PREC[fwd_prec], float(fwd_rtol), int(bool(misfit_after))
         o.reorth_eta = float(reorth_eta)
+        o.outer = _OUTER[outer]
         xi = self.empty_xi() if want_xi else None
         g1 = torch.empty((self.nz, self.nx), dtype=torch.float64, device=self.device)
         st = KfNewtonStats()

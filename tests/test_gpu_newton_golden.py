@@ -4,14 +4,14 @@
 Each reference (tests/golden/*_newton_oracle.npz, written by make_newton_reference.py
 from the oracle alone) is the oracle's Newton step: banded-LU forward solves, the
 assembled KKT matrix and GMRES with the exact block-triangular preconditioner.  The
-401 x 141 references are solved to the FP64 floor of their systems (a true relative
-residual of ~8e-12, asked 1e-12), so that they are the exact KKT step to ~1e-11; the
+401 x 141 references are solved to the FP64 floor of their systems (true relative
+residuals 5e-12 to 1.1e-11, asked 1e-12), so that they are the exact KKT step to ~1e-11; the
 801 x 281 reference is solved to 1e-10 (an hour of CPU).
 
 Forms of the GPU step:
-* FP64 throughout (exact preconditioner, FP64 block solves, FGMRES to 1e-11): its ds
-  and gamma update must match the 401 x 141 references to 1e-10 relative, the bar of
-  the FP64 path;
+* FP64 throughout (exact preconditioner, FP64 block solves, FGMRES to 1e-11, or twice
+  the reference's floor where that is higher): its ds and gamma update must match the
+  401 x 141 references to 1e-10 relative, the bar of the FP64 path;
 * mixed precision refined to 1e-10 (complex64 block solves inside the inexact
   preconditioner, complex64 sweeps with FP64 refinement for u_n, FP64 FGMRES,
   orthogonalisation, residuals and update): within 1e-6 of the reference;
@@ -64,6 +64,8 @@ def test_step_matches_oracle_in_every_precision(cfg, fi):
     g0 = torch.as_tensor(inp["gamma0"]).cuda()
     rows = {}
     for name, (pc, fwd, rtol) in FORMS.items():
+        if fwd == "c128":   # the FP64 form: as tight as the reference's own floor allows
+            rtol = max(rtol, 2.0 * float(ref["rel_res"]))
         ds, g1, st = _step(p, d, g0, pc, fwd, rtol)
         assert st["converged"], (name, st["rel_res"])
         rows[name] = dict(
@@ -80,7 +82,7 @@ def test_step_matches_oracle_in_every_precision(cfg, fi):
               f"{r['ms']:.0f} ms)")
     for key in ("ds", "gamma", "misfit_before", "misfit_after"):
         assert rows["mixed, refined to 1e-10"][key] <= 1e-6, key
-    fp64_bar = 1e-10 if float(ref["rel_res"]) <= 1e-11 else 1e-6
+    fp64_bar = 1e-10 if float(ref["rel_res"]) <= 2e-11 else 1e-6
     for key in ("ds", "gamma", "misfit_before", "misfit_after"):
         assert rows["FP64, refined to 1e-11"][key] <= fp64_bar, key
     # the timed tolerance: the step is accurate to what a 1e-6 residual allows
