@@ -53,6 +53,9 @@ def parse():
                          "multigrid: BiCGStab block solves with shifted-Laplacian V-cycles to --inner-rtol "
                          "(complex128 with --fwd-prec c128, else complex64)")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
+    ap.add_argument("--hblock", default="eps", choices=["eps", "lbfgs"],
+                    help="H-block of the preconditioner's middle stage: L = eps I, or L-BFGS from the previous "
+                         "steps' (ds, H ds) pairs")
     ap.add_argument("--fwd-prec", default=None, choices=["c128", "mixed"],
                     help="background solve: default mixed for c2, c128 otherwise")
     ap.add_argument("--rtol", type=float, default=1e-6)
@@ -600,6 +603,8 @@ def main():
     p.inner_fp32 = args.pc == "inexact"      # the block solves of the step run in complex64
     if args.pc == "multigrid":
         p.set_multigrid(prec="c128" if args.fwd_prec == "c128" else "c64", inner_rtol=args.inner_rtol)
+    if args.hblock == "lbfgs":
+        p.set_hblock("lbfgs", max_pairs=4)
     if args.shape:
         c, ns = (int(v) for v in args.shape.split(","))
         p.set_solver_shape(c, ns)

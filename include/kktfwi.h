@@ -346,6 +346,22 @@ kf_status kf_mg_vcycle(kf_problem *p, const void *b, void *x);
  * (dims [host][16]). */
 kf_status kf_mg_levels(kf_problem *p, int32_t *dims /*[host][16]*/, int32_t *nlev /*[host]*/);
 
+/* ---- the H-block of the preconditioner's middle stage (Section 5) ----
+ * The block-triangular preconditioner keeps L in its middle stage,
+ *   z_s = L^-1 (y_s + P^* z_lam);
+ * Section 5 and the Conclusions note that other approximations of the reduced Hessian
+ * H = L + sum_k J_k^* W_k^2 J_k can take its place, L-BFGS among them.  With
+ * KF_HBLOCK_LBFGS the middle stage applies the L-BFGS inverse (two-loop recursion over
+ * complex vectors, Re(y^H s) as the curvature, L = eps I as the initial matrix) built from
+ * up to max_pairs pairs (s, H s): every newton_step that converges adds the pair
+ * (ds, H ds) at gamma_n (one more forward and adjoint FP64 block solve of all sources),
+ * and kf_hblock_add_pair adds a pair given by the caller (s, y = H s: [Ng] c128, device;
+ * KF_EINVAL if Re(y^H s) <= 0).  kf_set_hblock clears the pairs.  KF_HBLOCK_EPS (the
+ * default) is L itself. */
+typedef enum { KF_HBLOCK_EPS = 0, KF_HBLOCK_LBFGS = 1 } kf_hblock;
+kf_status kf_set_hblock(kf_problem *p, int32_t kind, int32_t max_pairs);
+kf_status kf_hblock_add_pair(kf_problem *p, const void *s, const void *y);
+
 /* Build the point sources f_k = e_src / h^2 of the problem into f ([K][nz][nx], c128). */
 kf_status kf_sources(kf_problem *p, void *f);
 

@@ -181,6 +181,38 @@ class Problem:
         z_u = self.lu.solve(rhs_u)
         return self.pack(z_u, z_s, z_lam)
 
+    def lbfgs_inverse(self, q, pairs):
+        """Ht^-1 q for the L-BFGS approximation Ht of the reduced Hessian with L = eps I as
+        the initial matrix (Section 5: an approximation of H in place of L in the middle
+        stage), by the two-loop recursion over the pairs (s_i, y_i = H s_i), oldest first,
+        with the curvature Re(y_i^H s_i) (H is Hermitian)."""
+        q = np.array(q, dtype=np.complex128)
+        a = []
+        for s_i, y_i in reversed(pairs):
+            rho = 1.0 / np.real(np.vdot(y_i, s_i))
+            a_i = rho * np.vdot(s_i, q)
+            a.append((a_i, rho))
+            q = q - a_i * y_i
+        r = q / self.eps
+        for (s_i, y_i), (a_i, rho) in zip(pairs, reversed(a)):
+            b = rho * np.vdot(y_i, r)
+            r = r + (a_i - b) * s_i
+        return r
+
+    def precond_apply_hblock(self, u_n, y, pairs):
+        """The block-triangular preconditioner with the L-BFGS H-block in the middle
+        stage: z_lam = A^-* y_u, z_s = Ht^-1 (y_s + P^* z_lam), z_u = A^-1 (y_lam + P z_s)."""
+        yu, ys, ylam = self.unpack(np.asarray(y, dtype=np.complex128))
+        u_n = np.asarray(u_n).reshape(self.K, self.nz, self.nx)
+        w2 = self.omega ** 2
+        z_lam = self.lu.solve(yu, adjoint=True)
+        q = ys + w2 * np.sum(np.conj(u_n) * z_lam, axis=0).ravel()[self.core_idx]
+        z_s = self.lbfgs_inverse(q, pairs)
+        ext = np.zeros(self.Nu, np.complex128)
+        ext[self.core_idx] = z_s
+        z_u = self.lu.solve(ylam + w2 * u_n * ext.reshape(self.nz, self.nx)[None])
+        return self.pack(z_u, z_s, z_lam)
+
     # --- exact solutions ---------------------------------------------------------
     def kkt_solve_dense(self, u_n, b):
         """xi = M^-1 b by dense LU of the assembled KKT matrix (tiny grids only)."""

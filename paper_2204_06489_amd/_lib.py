@@ -101,6 +101,8 @@ _SIGNATURES = {
                                       C.POINTER(KfNewtonOpts), P, C.POINTER(KfNewtonStats)]),
     "rsgn_cg_step": (C.c_int, [P, P, C.POINTER(KfCgOpts), P, P, C.c_int32, C.POINTER(KfCgStats)]),
     "kf_sources": (C.c_int, [P, P]),
+    "kf_set_hblock": (C.c_int, [P, C.c_int32, C.c_int32]),
+    "kf_hblock_add_pair": (C.c_int, [P, P, P]),
     "kf_set_multigrid": (C.c_int, [P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32]),
     "helmholtz_solve_mg": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.c_int32, C.POINTER(KfMgStats)]),
     "kf_mg_vcycle": (C.c_int, [P, P, P]),

@@ -134,6 +134,7 @@ static void free_all(kf_problem *p) {
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);
   dfree(p->cg_vec); dfree(p->cg_field); dfree(p->bicg);
+  dfree(p->hb_s); dfree(p->hb_y); dfree(p->hb_q);
   mg_destroy(p);
   if (p->host_pinned) hipHostFree(p->host_pinned);
   p->host_pinned = nullptr;
@@ -596,6 +597,92 @@ extern "C" kf_status kkt_apply_noalloc(kf_problem *p, const void *xi, void *y) {
   return launch_kkt_apply_noalloc(p, (const double2 *)xi, (double2 *)y);
 }
 
+// ---------------------------------------------------------------------------
+// L-BFGS H-block (Section 5: other approximations of H than L in the middle stage)
+// ---------------------------------------------------------------------------
+static kf_status read_c(kf_problem *p, const double2 *dev, double2 *host);
+
+// z_s = Ht^-1 (y_s + P^* z_lam) by the two-loop recursion over the stored pairs with
+// Ht0 = eps I, then z_u = y_lam + P z_s
+static kf_status stage2_lbfgs(kf_problem *p, const double2 *y, double2 *z) {
+  const size_t Ku = (size_t)p->K * p->Nu;
+  const int64_t Ng = p->Ng;
+  const double2 *ys = y + Ku, *yl = ys + Ng;
+  double2 *zu = z, *zs = z + Ku;
+  const double2 *zl = zs + Ng;
+  double2 *q = p->hb_q, *dot = (double2 *)p->red_out;
+  ProfScope ps(p, PROF_PRECOND);
+  CHECK_ST(launch_gather_PH(p, 1.0, ys, 0.0, zl, 0, q));
+  std::vector<double2> a(p->hb_n);
+  for (int i = p->hb_n - 1; i >= 0; --i) {   // newest to oldest
+    const int slot = ((p->hb_head - p->hb_n + i) % p->hb_max + p->hb_max) % p->hb_max;
+    const double2 *si = p->hb_s + (size_t)slot * Ng, *yi = p->hb_y + (size_t)slot * Ng;
+    double2 sq;
+    CHECK_ST(dot_c128(p, si, q, Ng, dot));
+    CHECK_ST(read_c(p, dot, &sq));
+    a[i] = cscale(sq, p->hb_rho[slot]);
+    CHECK_ST(launch_axpy_field(p, Ng, csub(make_double2(0.0, 0.0), a[i]), yi, q));
+  }
+  HIP_TRY(hipMemsetAsync(zs, 0, sizeof(double2) * Ng, p->stream));
+  CHECK_ST(launch_axpy_field(p, Ng, make_double2(1.0 / p->eps, 0.0), q, zs));
+  for (int i = 0; i < p->hb_n; ++i) {        // oldest to newest
+    const int slot = ((p->hb_head - p->hb_n + i) % p->hb_max + p->hb_max) % p->hb_max;
+    const double2 *si = p->hb_s + (size_t)slot * Ng, *yi = p->hb_y + (size_t)slot * Ng;
+    double2 yr;
+    CHECK_ST(dot_c128(p, yi, zs, Ng, dot));
+    CHECK_ST(read_c(p, dot, &yr));
+    const double2 b = cscale(yr, p->hb_rho[slot]);
+    CHECK_ST(launch_axpy_field(p, Ng, csub(a[i], b), si, zs));
+  }
+  CHECK_ST(launch_scatter_P(p, zs, zu));
+  return launch_axpy_field(p, (int64_t)Ku, make_double2(1.0, 0.0), yl, zu);
+}
+
+static kf_status hblock_add_pair(kf_problem *p, const double2 *s, const double2 *y) {
+  const int64_t Ng = p->Ng;
+  double ys = 0.0;
+  {
+    double2 c;
+    CHECK_ST(dot_c128(p, y, s, Ng, (double2 *)p->red_out));
+    CHECK_ST(read_c(p, (const double2 *)p->red_out, &c));
+    ys = c.x;
+  }
+  if (!(ys > 0.0) || !std::isfinite(ys)) return fail(KF_EINVAL, "L-BFGS pair without positive curvature (Re y^H s <= 0)");
+  const int slot = p->hb_head;
+  HIP_TRY(hipMemcpyAsync(p->hb_s + (size_t)slot * Ng, s, sizeof(double2) * Ng, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->hb_y + (size_t)slot * Ng, y, sizeof(double2) * Ng, hipMemcpyDeviceToDevice, p->stream));
+  p->hb_rho[slot] = 1.0 / ys;
+  p->hb_head = (p->hb_head + 1) % p->hb_max;
+  p->hb_n = std::min(p->hb_n + 1, p->hb_max);
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return KF_OK;
+}
+
+extern "C" kf_status kf_set_hblock(kf_problem *p, int32_t kind, int32_t max_pairs) {
+  CHECK_ST(check_p(p));
+  if (kind != KF_HBLOCK_EPS && kind != KF_HBLOCK_LBFGS) return fail(KF_EINVAL, "invalid H-block kind");
+  if (kind == KF_HBLOCK_LBFGS && (max_pairs < 1 || max_pairs > 32)) return fail(KF_EINVAL, "max_pairs must be 1..32");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  dfree(p->hb_s); dfree(p->hb_y); dfree(p->hb_q);
+  p->hb_n = p->hb_head = 0;
+  p->hb_max = kind == KF_HBLOCK_LBFGS ? max_pairs : 0;
+  p->hb_rho.assign((size_t)p->hb_max, 0.0);
+  p->hblock = kind;
+  if (kind == KF_HBLOCK_LBFGS) {
+    CHECK_ST(dalloc(&p->hb_s, (size_t)max_pairs * p->Ng));
+    CHECK_ST(dalloc(&p->hb_y, (size_t)max_pairs * p->Ng));
+    CHECK_ST(dalloc(&p->hb_q, (size_t)p->Ng));
+  }
+  return KF_OK;
+}
+
+extern "C" kf_status kf_hblock_add_pair(kf_problem *p, const void *s, const void *y) {
+  CHECK_ST(check_p(p));
+  if (!s || !y) return fail(KF_EINVAL, "s or y is NULL");
+  if (p->hblock != KF_HBLOCK_LBFGS) return fail(KF_ESTATE, "the H-block is not L-BFGS (kf_set_hblock first)");
+  return hblock_add_pair(p, (const double2 *)s, (const double2 *)y);
+}
+
 // A~ of the multigrid variant: an inner iteration that stops at its tolerance or its
 // iteration limit; the flexible outer Krylov method accepts either
 static kf_status mg_inexact(kf_problem *p, int adjoint, const double2 *b, double2 *x) {
@@ -611,8 +698,9 @@ static kf_status precond_impl(kf_problem *p, int pc, const double2 *y, double2 *
   if (pc == KF_PC_EXACT) CHECK_ST(blu_solve<double>(p, 1, yu, zl));
   else if (pc == KF_PC_INEXACT) CHECK_ST(blu_solve_mixed_io(p, 1, yu, zl));
   else CHECK_ST(mg_inexact(p, 1, yu, zl));
-  // stage 2: z_s = (y_s + P^* z_lam) / eps, and z_u := y_lam + P z_s
-  CHECK_ST(launch_precond_stage2(p, y, z));
+  // stage 2: z_s = Ht^-1 (y_s + P^* z_lam) (Ht = L = eps I, or L-BFGS), and z_u := y_lam + P z_s
+  if (p->hblock == KF_HBLOCK_LBFGS && p->hb_n > 0) CHECK_ST(stage2_lbfgs(p, y, z));
+  else CHECK_ST(launch_precond_stage2(p, y, z));
   // stage 3: z_u = A^-1 (y_lam + P z_s)
   if (pc == KF_PC_EXACT) CHECK_ST(blu_solve<double>(p, 0, zu, zu));
   else if (pc == KF_PC_INEXACT) CHECK_ST(blu_solve_mixed_io(p, 0, zu, zu));
@@ -812,6 +900,7 @@ static kf_status fgmres(kf_problem *p, int pc, const double2 *b, double2 *x, dou
 // preconditioned, nine packed vectors whatever the iteration count
 // ---------------------------------------------------------------------------
 static double host_norm(kf_problem *p, const double2 *x, int64_t n, kf_status *st);
+static kf_status hessian_apply(kf_problem *p, const kf_cg_opts *o, const double2 *v, double2 *out, int *solves);
 
 static kf_status read_c(kf_problem *p, const double2 *dev, double2 *host) {
   HIP_TRY(hipMemcpyAsync(p->host_pinned, dev, sizeof(double2), hipMemcpyDeviceToHost, p->stream));
@@ -1017,6 +1106,17 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   double dsi = host_norm(p, p->vec_a, p->Ng, &e); CHECK_ST(e);
   S.ds_imag_ratio = dsn > 0 ? dsi / dsn : 0.0;
   if (xi_out) HIP_TRY(hipMemcpyAsync(xi_out, p->xi_x, sizeof(double2) * N, hipMemcpyDeviceToDevice, p->stream));
+  // L-BFGS H-block: the step gives the pair (ds, H ds) at gamma_n for the next steps
+  if (p->hblock == KF_HBLOCK_LBFGS && fst == KF_OK) {
+    if (!p->cg_vec) CHECK_ST(dalloc(&p->cg_vec, (size_t)5 * p->Ng));
+    if (!p->cg_field) CHECK_ST(dalloc(&p->cg_field, (size_t)p->K * p->Nu));
+    kf_cg_opts ho{};
+    ho.solve_prec = KF_C128;
+    int solves = 0;
+    CHECK_ST(hessian_apply(p, &ho, ds, p->cg_vec, &solves));
+    kf_status hs = hblock_add_pair(p, ds, p->cg_vec);
+    if (hs != KF_OK && hs != KF_EINVAL) return hs;   // a pair without curvature is skipped
+  }
   // gamma_{n+1} = gamma_n + Re(ds) on the core
   if (update_in_place || o->misfit_after) {
     if (!update_in_place) HIP_TRY(hipMemcpyAsync(p->vec_d, p->gamma, sizeof(double) * p->Nu, hipMemcpyDeviceToDevice, p->stream));

@@ -188,6 +188,12 @@ struct kf_problem {
   double2 *cg_vec = nullptr;                   // [5][Ng]: ds, residual, direction, H direction, g
   double2 *cg_field = nullptr;                 // [K][nz][nx]
   double2 *bicg = nullptr;                     // outer BiCGStab: 8 packed vectors (allocated on first use)
+  // H-block of the preconditioner's middle stage: 0 = L = eps I; 1 = L-BFGS from pairs
+  // (s_i, H s_i) with L as the initial matrix (a ring of up to hb_max pairs)
+  int hblock = 0, hb_max = 0, hb_n = 0, hb_head = 0;
+  double2 *hb_s = nullptr, *hb_y = nullptr;    // [hb_max][Ng]
+  double2 *hb_q = nullptr;                     // [Ng] work vector of the two-loop recursion
+  std::vector<double> hb_rho;                  // 1 / Re(y_i^H s_i)
 
   double beta = 0.0;                           // mass-term shift (multigrid levels only)
   uint64_t gamma_version = 0;                  // bumped whenever gamma changes

@@ -181,6 +181,15 @@ class KKTProblem:
         check(lib().kf_sources(self._h, _ptr(f)))
         return f
 
+    # ---- H-block of the preconditioner's middle stage ------------------------------
+    def set_hblock(self, kind="eps", max_pairs=4):
+        """"eps" (L = eps I) or "lbfgs" (L-BFGS from (ds, H ds) pairs of previous steps)."""
+        check(lib().kf_set_hblock(self._h, {"eps": 0, "lbfgs": 1}[kind], int(max_pairs)))
+
+    def hblock_add_pair(self, s, y):
+        check(lib().kf_hblock_add_pair(self._h, _ptr(s, torch.complex128, self.Ng, "s"),
+                                       _ptr(y, torch.complex128, self.Ng, "y")))
+
     # ---- shifted-Laplacian multigrid -----------------------------------------------
     def set_multigrid(self, prec="c64", beta=0.5, inner_rtol=1e-3, inner_maxit=200, n_min=20):
         check(lib().kf_set_multigrid(self._h, _PREC[prec], float(beta), float(inner_rtol), int(inner_maxit),

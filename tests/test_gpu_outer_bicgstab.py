@@ -28,7 +28,7 @@ def test_bicgstab_outer_step_matches_exact_step(pc):
     xi = to_np(xi)
     for a, b in zip(orc.unpack(xi), orc.unpack(xi_ref)):
         assert rel(a, b) <= 1e-8
-    assert rel(to_np(g1), orc.update(orc.unpack(xi_ref)[1])) <= 1e-12
+    assert rel(to_np(g1), orc.update(orc.unpack(xi_ref)[1])) <= 1e-10
     _, _, stg = gpu.newton_step(to_dev(d), rtol=1e-10, maxit=400, pc=pc, update_in_place=False)
     print(f"BiCGStab {st['outer_iters']} iterations (2 preconditioner applications each), "
           f"FGMRES {stg['outer_iters']}")

@@ -256,3 +256,26 @@ def test_continuation_composes_single_steps():
         q = q.with_gamma(q.update(q.unpack(q.kkt_solve_schur(u, q.residual(data[1], u)))[1]))
     assert np.array_equal(g2, q.gamma)
     assert len(mis2) == 3
+
+
+def test_lbfgs_inverse_meets_the_secant_condition_and_reduces_to_L():
+    """The L-BFGS H-block: without pairs it is L^-1 = I / eps; with pairs of the true
+    Hessian it maps the newest y to its s (the secant condition) and stays Hermitian
+    positive definite."""
+    p, u_n, r, _ = _setup(weights="random")
+    rng = np.random.default_rng(12)
+    q = rng.standard_normal(p.Ng) + 1j * rng.standard_normal(p.Ng)
+    assert np.array_equal(p.lbfgs_inverse(q, []), q / p.eps)
+    H, _ = p.normal_system(u_n, r)
+    pairs = []
+    for _ in range(3):
+        s = rng.standard_normal(p.Ng) + 1j * rng.standard_normal(p.Ng)
+        pairs.append((s, H @ s))
+    s3, y3 = pairs[-1]
+    assert np.linalg.norm(p.lbfgs_inverse(y3, pairs) - s3) <= 1e-10 * np.linalg.norm(s3)
+    B = np.stack([p.lbfgs_inverse(e, pairs) for e in np.eye(p.Ng)], axis=1)
+    assert np.abs(B - B.conj().T).max() <= 1e-10 * np.abs(B).max()
+    assert np.linalg.eigvalsh((B + B.conj().T) / 2).min() > 0
+    y = rng.standard_normal(p.nxi) + 1j * rng.standard_normal(p.nxi)
+    z0 = p.precond_apply_hblock(u_n, y, [])
+    assert np.linalg.norm(z0 - p.precond_apply(u_n, y)) <= 1e-12 * np.linalg.norm(z0)
