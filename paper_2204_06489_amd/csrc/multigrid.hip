@@ -143,6 +143,69 @@ __global__ __launch_bounds__(TB) void k_mg_xline(Grid g, int K, const cplx<R> *_
   }
 }
 
+// The same x-line sweep with one workgroup per grid row and source: the row's
+// tridiagonal system is held in LDS and solved by parallel cyclic reduction (every
+// equation eliminates its neighbours at distance s = 1, 2, 4, ... in log2 nx steps), so
+// K nz workgroups share the chip instead of K nz threads.  Rows of up to PCR_MAX nodes.
+constexpr int PCR_T = 256, PCR_E = 4, PCR_MAX = PCR_T * PCR_E;
+template <typename R>
+__global__ __launch_bounds__(PCR_T) void k_mg_xline_pcr(Grid g, int K, const cplx<R> *__restrict__ x,
+                                                        const cplx<R> *__restrict__ b, cplx<R> *__restrict__ y) {
+  using C = cplx<R>;
+  extern __shared__ unsigned char smem_pcr[];
+  const int nx = g.nx;
+  C *A = (C *)smem_pcr, *B = A + nx, *Cu = B + nx, *D = Cu + nx;
+  const int line = blockIdx.x;
+  if (line >= K * g.nz) return;   // uniform
+  const int k = line / g.nz, j = line - k * g.nz;
+  const size_t Nu = (size_t)nx * g.nz, base = (size_t)k * Nu + (size_t)j * nx;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nx; i += PCR_T) {
+    C cc, cxm, cxp, czm, czp;
+    stencil_R<R>(g, i, j, cc, cxm, cxp, czm, czp);
+    const size_t o = base + i;
+    C rhs = b[o];
+    if (j > 0) rhs = csub(rhs, cmul(czm, x[o - nx]));
+    if (j + 1 < g.nz) rhs = csub(rhs, cmul(czp, x[o + nx]));
+    A[i] = i > 0 ? cxm : mk<R>(0, 0);
+    B[i] = cc;
+    Cu[i] = i + 1 < nx ? cxp : mk<R>(0, 0);
+    D[i] = rhs;
+  }
+  __syncthreads();
+  for (int s = 1; s < nx; s <<= 1) {
+    C na[PCR_E], nb[PCR_E], nc[PCR_E], nd[PCR_E];
+#pragma unroll
+    for (int u = 0; u < PCR_E; ++u) {
+      const int i = tid + u * PCR_T;
+      if (i < nx) {
+        C bi = B[i], di = D[i], an = mk<R>(0, 0), cn = mk<R>(0, 0);
+        if (i - s >= 0) {
+          const C al = csub(mk<R>(0, 0), cdivR<R>(A[i], B[i - s]));
+          an = cmul(al, A[i - s]);
+          bi = cadd(bi, cmul(al, Cu[i - s]));
+          di = cadd(di, cmul(al, D[i - s]));
+        }
+        if (i + s < nx) {
+          const C ga = csub(mk<R>(0, 0), cdivR<R>(Cu[i], B[i + s]));
+          cn = cmul(ga, Cu[i + s]);
+          bi = cadd(bi, cmul(ga, A[i + s]));
+          di = cadd(di, cmul(ga, D[i + s]));
+        }
+        na[u] = an; nb[u] = bi; nc[u] = cn; nd[u] = di;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PCR_E; ++u) {
+      const int i = tid + u * PCR_T;
+      if (i < nx) { A[i] = na[u]; B[i] = nb[u]; Cu[i] = nc[u]; D[i] = nd[u]; }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < nx; i += PCR_T) y[base + i] = cdivR<R>(D[i], B[i]);
+}
+
 // full weighting: bc(I, J) = sum_{a, b in -1..1} w_a w_b r(2I + a, 2J + b) / 4, w = (1/2, 1, 1/2)
 template <typename R>
 __global__ __launch_bounds__(TB) void k_mg_restrict(int K, int nx, int nz, int ncx, int ncz,
@@ -482,6 +545,27 @@ static kf_status mg_build(kf_problem *p) {
   return KF_OK;
 }
 
+// x-line sweep: parallel cyclic reduction in LDS for rows of up to PCR_MAX nodes, the
+// thread-per-row Thomas kernel for longer ones
+template <typename R>
+static kf_status xline(hipStream_t s, const Grid &g, int K, const cplx<R> *x, const cplx<R> *b, cplx<R> *y,
+                       cplx<R> *cp) {
+  if (g.nx <= PCR_MAX) {
+    const size_t lds = 4 * sizeof(cplx<R>) * (size_t)g.nx;
+    static bool attr_set = false;
+    if (!attr_set) {
+      HIP_TRY(hipFuncSetAttribute((const void *)k_mg_xline_pcr<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(4 * sizeof(cplx<R>) * PCR_MAX)));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_mg_xline_pcr<R>, dim3((unsigned)(K * g.nz)), dim3(PCR_T), lds, s, g, K, x, b, y);
+  } else {
+    hipLaunchKernelGGL(k_mg_xline<R>, dim3(nblk((size_t)K * g.nz)), dim3(TB), 0, s, g, K, x, b, y, cp);
+  }
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle: x = V(b) on level l (b and x are that level's R fields)
 // ---------------------------------------------------------------------------
@@ -499,8 +583,7 @@ static kf_status vcycle(kf_problem *p, size_t l, const cplx<R> *b, cplx<R> *x) {
   // pre-smoothing from x = 0: z-lines (into xb), x-lines (into xa)
   hipLaunchKernelGGL(k_mg_zline<R>, dim3(gz), dim3(TB), 0, s, g, K, (const cplx<R> *)nullptr, b, xb, cp);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_mg_xline<R>, dim3(gx), dim3(TB), 0, s, g, K, (const cplx<R> *)xb, b, xa, cp);
-  LAUNCH_CHECK();
+  CHECK_ST(xline<R>(s, g, K, xb, b, xa, cp));
   // coarse-grid correction
   hipLaunchKernelGGL(k_mg_residual<R>, dim3(nblk(n)), dim3(TB), 0, s, g, K, (const cplx<R> *)xa, b, r);
   LAUNCH_CHECK();
@@ -513,8 +596,7 @@ static kf_status vcycle(kf_problem *p, size_t l, const cplx<R> *b, cplx<R> *x) {
                      (const cplx<R> *)C.xa, xa);
   LAUNCH_CHECK();
   // post-smoothing: x-lines (into xb), z-lines (into xa)
-  hipLaunchKernelGGL(k_mg_xline<R>, dim3(gx), dim3(TB), 0, s, g, K, (const cplx<R> *)xa, b, xb, cp);
-  LAUNCH_CHECK();
+  CHECK_ST(xline<R>(s, g, K, xa, b, xb, cp));
   hipLaunchKernelGGL(k_mg_zline<R>, dim3(gz), dim3(TB), 0, s, g, K, (const cplx<R> *)xb, b, xa, cp);
   LAUNCH_CHECK();
   return KF_OK;
