@@ -2,6 +2,8 @@
 // operator and preconditioner, flexible GMRES and the Gauss-Newton step.
 #include "common.h"
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -14,6 +16,18 @@
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+hipError_t kf_malloc(void **ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e == hipSuccess && std::getenv("KF_POISON_ALLOC")) {
+    e = hipMemset(*ptr, 0xFF, bytes);
+    if (e != hipSuccess) {
+      (void)hipFree(*ptr);
+      *ptr = nullptr;
+    }
+  }
+  return e;
+}
 static kf_status fail(kf_status st, const std::string &msg) {
   set_error(msg);
   return st;
@@ -110,7 +124,7 @@ enum { PH_PRECOND = 0, PH_MATVEC, PH_ORTH, PH_N };
 template <typename T> static kf_status dalloc(T **ptr, size_t count) {
   *ptr = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+  hipError_t e = kf_malloc((void **)ptr, count * sizeof(T));
   if (e != hipSuccess) {
     *ptr = nullptr;
     return fail(KF_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes failed: " +
@@ -129,7 +143,7 @@ static void free_all(kf_problem *p) {
   dfree(p->d_rptr); dfree(p->d_rlist); dfree(p->d_r); dfree(p->d_wr);
   dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->d_part); dfree(p->sol64); dfree(p->sol32);
   dfree(p->CRL64); dfree(p->CR64); dfree(p->CR32);
-  if (p->cr_jobs) hipFree(p->cr_jobs);
+  if (p->fac_jobs) hipFree(p->fac_jobs);
   dfree(p->V64); dfree(p->W64); dfree(p->V32); dfree(p->W32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);
   dfree(p->V); dfree(p->Z); dfree(p->xi_w); dfree(p->xi_b); dfree(p->xi_x); dfree(p->hess);

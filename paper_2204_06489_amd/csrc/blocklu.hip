@@ -42,6 +42,7 @@
 // every preconditioner application (Section 5).
 #include "common.h"
 
+#include <cstring>
 #include <map>
 #include <utility>
 #include <vector>
@@ -49,219 +50,205 @@
 
 namespace {
 
-// In-place Gauss-Jordan inversion of the row-major m x m matrix S (global memory),
-// blocked by NB-column panels, then the inverse written transposed into Tt.  Called
-// by a whole workgroup.
+// Inversion of a batch of dense m x m blocks (the Schur complements of the chunk sweeps
+// and the separators' pivot blocks) by Gauss-Jordan elimination with partial pivoting,
+// in place on a row-major work matrix S, the inverse then written transposed.
 //
-// For each panel the classical in-place Gauss-Jordan steps (partial pivoting over
-// all rows, pivot row scaled, pivot column eliminated from every other row, the
-// eliminated column replaced by the accumulated transform) run on the m x NB panel
-// in LDS.  Their combined effect on every other column x is
+// The columns are cut into blocks of GJ_NB; each elimination panel is one block.  The
+// classical in-place steps on a panel (pivot row chosen over the rows not yet pivoted,
+// interchanged, scaled; the pivot column eliminated from every other row and replaced
+// by the accumulated transform) act on every other column x as
 //     x  <-  (P x with the panel's pivot rows zeroed) + Pan (P x)[pivot rows],
-// P the panel's row interchanges and Pan the finished panel, which is one rank-NB
-// update of the matrix (register tiles of TR x TC entries per thread).  After the
-// last panel the row interchanges are undone as column interchanges.
-constexpr int TR = 4, TC = 4;   // update tile per thread
-constexpr int NB_MAX = 16;
+// P the panel's row interchanges and Pan the finished panel: a rank-GJ_NB update.  One
+// launch per panel, a workgroup per (column block, matrix): launch t applies panel t - 1
+// to every other block, and the workgroup of block t, once its block is updated,
+// eliminates panel t (its block) for the next launch.  So every column block of every
+// matrix of the batch is updated in parallel, and the sequential pivot steps run on one
+// workgroup per matrix, one panel per launch.  After the last panel the interchanges,
+// composed into one row permutation, are undone on the columns.
+//
+// Behind each S (m x m double2) its integer staging: perm[2][m], the row permutation of
+// the last two panels (perm[r] = the row whose content moved to r), and sig[2][m], the
+// composition of every panel's interchanges so far.
+constexpr int GJ_NB = 16;
+constexpr int NB_MAX = 16;   // staging rows (double2) behind each work matrix
 
-// orders the LDS accesses of the lanes of one wavefront (no workgroup barrier)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+struct GjJob {
+  int m;
+  double2 *S;    // m x m row-major, followed by the integer staging
+  double2 *Tt;   // destination: the inverse, transposed (T stored column-major)
+};
+
+__device__ __forceinline__ bool gj_better(double ob, int oi, double best, int bi) {
+  return ob > best || (ob == best && oi < bi);
 }
 
-template <int NB, int RMAX>
-__device__ __forceinline__ void gj_invert_store(double2 *S, int m, double2 *Tt, double2 *pan /*[m][NB]*/,
-                                                double2 *x1 /*[NB][m]*/, double2 *rowbuf /*[2][NB]*/, int *piv,
-                                                int *perm /*[m]*/, double2 *tmp /*[NB][m] global*/) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int K0 = 0; K0 < m; K0 += NB) {
-    const int nb = min(NB, m - K0);
-    for (int r = tid; r < m; r += nt) perm[r] = r;
-    __syncthreads();
-    // Gauss-Jordan on the panel by wavefront 0, the panel held in registers: lane l
-    // owns rows l, l + 64, ...  A pivot step is a shuffle reduction for the pivot, a
-    // two-row exchange through LDS and register arithmetic; no workgroup barrier.
-    if (wave == 0) {
-      double2 v[RMAX][NB];
+// launch t of a batch inversion; grid (column blocks, matrices), one thread per row
+// (blockDim.x >= m)
+template <int NB>
+__global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
+  const GjJob J = jobs[blockIdx.y];
+  const int m = J.m, npan = (m + NB - 1) / NB, b = blockIdx.x;
+  const int pp = t - 1;                  // the panel this launch applies
+  const bool fac = b == t;               // this block is the next panel
+  if (b >= npan || !(fac || (pp >= 0 && pp < npan && b != pp))) return;   // uniform
+  __shared__ double2 x1[NB][NB];
+  __shared__ double2 rowbuf[2][NB];
+  __shared__ double cbest[8];
+  __shared__ int cidx[8];
+  __shared__ int lperm[512];
+  int *perm = (int *)(J.S + (size_t)m * m), *sig = perm + 2 * m;
+  const int r = threadIdx.x, nt = blockDim.x;
+  const bool row = r < m;
+  const int cb0 = b * NB, ncol = min(NB, m - cb0);
+  double2 acc[NB];
+  if (pp >= 0 && b != pp) {
+    // the previous panel's interchanges and rank-nb update on this block
+    const int K0 = pp * NB, nb = min(NB, m - K0);
+    const int *pm = perm + (pp & 1) * m;
+    for (int e = r; e < nb * NB; e += nt) {
+      const int q = e / NB, c = e - q * NB;
+      x1[q][c] = c < ncol ? J.S[(size_t)pm[K0 + q] * m + cb0 + c] : make_double2(0.0, 0.0);
+    }
+    if (row) {
+      const bool piv_row = r >= K0 && r < K0 + nb;
+      const double2 *src = J.S + (size_t)pm[r] * m + cb0;
 #pragma unroll
-      for (int t = 0; t < RMAX; ++t) {
-        const int r = lane + 64 * t;
+      for (int c = 0; c < NB; ++c) acc[c] = (!piv_row && c < ncol) ? src[c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();   // every read of the block's old rows before any write
+    if (row) {
+      const double2 *pan = J.S + (size_t)r * m + K0;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) v[t][c] = (r < m && c < nb) ? S[(size_t)r * m + K0 + c] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < NB; ++q)
         if (q < nb) {
-          const int k = K0 + q;
-          double best = -1.0;
-          int bi = m;
+          const double2 pq = pan[q];
 #pragma unroll
-          for (int t = 0; t < RMAX; ++t) {
-            const int r = lane + 64 * t;
-            if (r >= k && r < m) {
-              double a = cabs2(v[t][q]);
-              if (a > best) { best = a; bi = r; }
-            }
-          }
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) {
-            double ob = __shfl_xor(best, o, 64);
-            int oi = __shfl_xor(bi, o, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-          }
-          // a column with no finite entry leaves bi = m: take no interchange, so that every
-          // index stays in range (the factors then carry the NaNs, the solve reports them)
-          const int pr = bi < m ? bi : k;
-          // rows k and pr to LDS (pr first)
-#pragma unroll
-          for (int t = 0; t < RMAX; ++t) {
-            const int r = lane + 64 * t;
-            if (r == pr)
-#pragma unroll
-              for (int c = 0; c < NB; ++c) rowbuf[c] = v[t][c];
-            if (r == k)
-#pragma unroll
-              for (int c = 0; c < NB; ++c) rowbuf[NB + c] = v[t][c];
-          }
-          if (lane == 0) {
-            piv[k] = pr;
-            int a = perm[k]; perm[k] = perm[pr]; perm[pr] = a;
-          }
-          wave_sync();
-          double2 prow[NB];
-#pragma unroll
-          for (int c = 0; c < NB; ++c) prow[c] = rowbuf[c];
-          // the new row k is the old row pr, scaled; the pivot entry becomes 1 / pivot
-          const double2 d = cdiv(make_double2(1.0, 0.0), prow[q]);
-#pragma unroll
-          for (int c = 0; c < NB; ++c) prow[c] = (c == q) ? d : cmul(prow[c], d);
-#pragma unroll
-          for (int t = 0; t < RMAX; ++t) {
-            const int r = lane + 64 * t;
-            if (r == k) {
-#pragma unroll
-              for (int c = 0; c < NB; ++c) v[t][c] = prow[c];
-            } else {
-              if (r == pr)   // the old row k moves to pr, then is eliminated like every other row
-#pragma unroll
-                for (int c = 0; c < NB; ++c) v[t][c] = rowbuf[NB + c];
-              const double2 f = v[t][q];
-#pragma unroll
-              for (int c = 0; c < NB; ++c)
-                v[t][c] = csub(c == q ? make_double2(0.0, 0.0) : v[t][c], cmul(f, prow[c]));
-            }
-          }
-          wave_sync();   // rowbuf is rewritten by the next pivot step
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < RMAX; ++t) {
-        const int r = lane + 64 * t;
-        if (r < m)
-#pragma unroll
-          for (int c = 0; c < NB; ++c) pan[r * NB + c] = v[t][c];
-      }
-    }
-    __syncthreads();
-    // The panel's row interchanges on the other columns, as one permutation: the new
-    // pivot-block rows go to x1, the old pivot-block rows are staged in tmp, and every
-    // row outside the block that took part in an interchange receives the old
-    // pivot-block row the interchanges moved there (perm[r] is its origin).
-    for (int e = tid; e < nb * m; e += nt) {
-      const int q = e / m, c = e % m;
-      x1[e] = S[(size_t)perm[K0 + q] * m + c];
-      tmp[e] = S[(size_t)(K0 + q) * m + c];
-    }
-    __syncthreads();
-    for (int e = tid; e < nb * m; e += nt) {
-      const int q = e / m, c = e % m;
-      const int r = piv[K0 + q];
-      if (r >= K0 + nb && perm[r] != r && !(c >= K0 && c < K0 + nb)) S[(size_t)r * m + c] = tmp[(size_t)(perm[r] - K0) * m + c];
-    }
-    __syncthreads();
-    // rank-nb update of every column outside the panel (register tiles TR x TC)
-    const int ntr = (m + TR - 1) / TR, ntc = (m + TC - 1) / TC;
-    for (int t = tid; t < ntr * ntc; t += nt) {
-      const int r0 = (t / ntc) * TR, c0 = (t % ntc) * TC;
-      double2 acc[TR][TC];
-#pragma unroll
-      for (int a = 0; a < TR; ++a)
-#pragma unroll
-        for (int b = 0; b < TC; ++b) {
-          int r = r0 + a, c = c0 + b;
-          bool in = r < m && c < m && !(r >= K0 && r < K0 + nb) && !(c >= K0 && c < K0 + nb);
-          acc[a][b] = in ? S[(size_t)r * m + c] : make_double2(0.0, 0.0);
-        }
-      for (int q = 0; q < nb; ++q) {
-        double2 pr[TR], xc[TC];
-#pragma unroll
-        for (int a = 0; a < TR; ++a) pr[a] = (r0 + a < m) ? pan[(r0 + a) * NB + q] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int b = 0; b < TC; ++b) xc[b] = (c0 + b < m) ? x1[q * m + c0 + b] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int a = 0; a < TR; ++a)
-#pragma unroll
-          for (int b = 0; b < TC; ++b) cfma(acc[a][b], pr[a], xc[b]);
-      }
-#pragma unroll
-      for (int a = 0; a < TR; ++a)
-#pragma unroll
-        for (int b = 0; b < TC; ++b) {
-          int r = r0 + a, c = c0 + b;
-          if (r < m && c < m && !(c >= K0 && c < K0 + nb)) S[(size_t)r * m + c] = acc[a][b];
+          for (int c = 0; c < NB; ++c) cfma(acc[c], pq, x1[q][c]);
         }
     }
-    for (int e = tid; e < m * nb; e += nt) {
-      int r = e / nb, q = e % nb;
-      S[(size_t)r * m + K0 + q] = pan[r * NB + q];
+    if (!fac) {
+      if (row)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < ncol) J.S[(size_t)r * m + cb0 + c] = acc[c];
+      return;
+    }
+  } else if (row) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[c] = c < ncol ? J.S[(size_t)r * m + cb0 + c] : make_double2(0.0, 0.0);
+  }
+  // elimination of panel t (this block).  The pivot loop is not unrolled (it holds
+  // barriers), so the register arrays are only ever indexed by unrolled constants:
+  // entry q is picked out by a chain of selects.
+  for (int e = r; e < m; e += nt) lperm[e] = e;
+  const int lane = r & 63, wave = r >> 6, nw = (nt + 63) >> 6;
+  for (int q = 0; q < ncol; ++q) {
+    const int k = cb0 + q;
+    double best = -1.0;
+    int bi = m;
+    double2 aq = acc[0];
+#pragma unroll
+    for (int c = 1; c < NB; ++c)
+      if (c == q) aq = acc[c];
+    if (row && r >= k) {
+      const double a = cabs2(aq);
+      if (a > best) { best = a; bi = r; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (gj_better(ob, oi, best, bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { cbest[wave] = best; cidx[wave] = bi; }
+    __syncthreads();
+    best = cbest[0];
+    bi = cidx[0];
+    for (int w = 1; w < nw; ++w)
+      if (gj_better(cbest[w], cidx[w], best, bi)) { best = cbest[w]; bi = cidx[w]; }
+    // a column with no finite entry leaves bi = m: no interchange, every index stays in
+    // range (the factors then carry the NaNs and the solves report them)
+    const int pr = bi < m ? bi : k;
+    if (r == pr)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) rowbuf[0][c] = acc[c];
+    if (r == k)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) rowbuf[1][c] = acc[c];
+    if (r == 0) {
+      const int tmp = lperm[k];
+      lperm[k] = lperm[pr];
+      lperm[pr] = tmp;
     }
     __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, in reverse order
-  if (tid == 0) {
-    for (int c = 0; c < m; ++c) perm[c] = c;
-    for (int k = m - 1; k >= 0; --k) {
-      int a = perm[k]; perm[k] = perm[piv[k]]; perm[piv[k]] = a;
+    double2 prow[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) prow[c] = rowbuf[0][c];
+    // the new row k is the old row pr, scaled; the pivot entry becomes 1 / pivot
+    double2 pq = prow[0];
+#pragma unroll
+    for (int c = 1; c < NB; ++c)
+      if (c == q) pq = prow[c];
+    const double2 d = cdiv(make_double2(1.0, 0.0), pq);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) prow[c] = (c == q) ? d : cmul(prow[c], d);
+    if (r == k) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = prow[c];
+    } else if (row) {
+      if (r == pr)   // the old row k moves to pr, then is eliminated like every other row
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = rowbuf[1][c];
+      double2 f = acc[0];
+#pragma unroll
+      for (int c = 1; c < NB; ++c)
+        if (c == q) f = acc[c];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = csub(c == q ? make_double2(0.0, 0.0) : acc[c], cmul(f, prow[c]));
     }
   }
-  __syncthreads();
-  // Tt[c][j] = Sinv[j][c] = S[j][colsrc[c]]
-  for (size_t e = tid; e < (size_t)m * m; e += nt) {
-    int c = (int)(e / m), j = (int)(e % m);
-    Tt[e] = S[(size_t)j * m + perm[c]];
+  __syncthreads();   // lperm complete
+  if (row)
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < ncol) J.S[(size_t)r * m + cb0 + c] = acc[c];
+  int *pn = perm + (t & 1) * m;
+  const int *sp = sig + ((t + 1) & 1) * m;
+  int *sn = sig + (t & 1) * m;
+  for (int e = r; e < m; e += nt) {
+    const int o = lperm[e];
+    pn[e] = o;
+    sn[e] = t == 0 ? o : sp[o];   // content now at e came from original row sn[e]
   }
-  __syncthreads();
 }
 
-// S = D_i - C_a Tprev C_a (- C_b Tnext C_b), row-major.  ca/cb: column index whose
-// coupling weights scale the correction, or -1 for none.  cw: LDS scratch [2][m].
-__device__ __forceinline__ void build_schur(const Grid &g, int m, int i, const double2 *Tprev, int ca, const double2 *Tnext, int cb,
-                            double2 *S, double2 *cw) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int j = tid; j < m; j += nt) {
-    cw[j] = ca >= 0 ? coupling_x(g, ca, j) : make_double2(0.0, 0.0);
-    cw[m + j] = cb >= 0 ? coupling_x(g, cb, j) : make_double2(0.0, 0.0);
+// after the last panel: Tt[c][j] = Sinv[j][c] = S[j][col(c)], col the inverse of the
+// composed row permutation; 32 x 32 tiles through LDS, grid (tiles, matrices)
+__global__ __launch_bounds__(256) void k_gj_store(const GjJob *jobs) {
+  const GjJob J = jobs[blockIdx.y];
+  const int m = J.m, nt32 = (m + 31) / 32;
+  if ((int)blockIdx.x >= nt32 * nt32) return;
+  const int npan = (m + GJ_NB - 1) / GJ_NB;
+  const int *sg = (const int *)(J.S + (size_t)m * m) + 2 * m + ((npan - 1) & 1) * m;
+  __shared__ int col[512];
+  __shared__ double2 tile[32][33];
+  const int tid = threadIdx.x;
+  for (int r = tid; r < m; r += 256) col[sg[r]] = r;
+  __syncthreads();
+  const int c0 = (blockIdx.x % nt32) * 32, j0 = (blockIdx.x / nt32) * 32;
+  const int lo = tid & 31, hi = tid >> 5;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {   // read S[j][col(c)] with lanes along c
+    const int j = j0 + hi + 8 * p, c = c0 + lo;
+    if (j < m && c < m) tile[lo][hi + 8 * p] = J.S[(size_t)j * m + col[c]];
   }
   __syncthreads();
-  for (size_t e = tid; e < (size_t)m * m; e += nt) {
-    int j = (int)(e / m), l = (int)(e % m);
-    double2 v = make_double2(0.0, 0.0);
-    if (ca >= 0) v = csub(v, cmul(cmul(cw[j], Tprev[(size_t)l * m + j]), cw[l]));   // Tprev[j][l] = Tt[l][j]
-    if (cb >= 0) v = csub(v, cmul(cmul(cw[m + j], Tnext[(size_t)l * m + j]), cw[m + l]));
-    S[e] = v;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {   // write Tt[c][j] with lanes along j
+    const int c = c0 + hi + 8 * p, j = j0 + lo;
+    if (j < m && c < m) J.Tt[(size_t)c * m + j] = tile[hi + 8 * p][lo];
   }
-  __syncthreads();
-  for (int j = tid; j < m; j += nt) {
-    Stencil5 s = stencil_at(g, i, j);
-    size_t d = (size_t)j * m + j;
-    S[d] = cadd(S[d], s.cc);
-    if (j > 0) S[d - 1] = cadd(S[d - 1], s.czm);
-    if (j + 1 < m) S[d + 1] = cadd(S[d + 1], s.czp);
-  }
-  __syncthreads();
 }
 
 // y[s][j] = sum_l T[j][l] w[s][l] for the rows j = threadIdx.x < m.  The l-range is
@@ -340,74 +327,47 @@ __device__ __forceinline__ int separator(const int *part, int j) { return part[3
 // ---------------------------------------------------------------------------
 // factorisation kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 *work_slot(const FactorProblem &pp, int slot) {
-  const size_t m = pp.g.nz;
-  return pp.work + (size_t)slot * (m * m + (size_t)NB_MAX * m);
-}
-
-struct FacLds {
-  double2 *pan, *x1, *cw, *prow;
-  int *piv, *perm;
+// One Schur complement of the chunk sweeps, row-major into a work matrix:
+//   S = D_i - C_a Tprev C_a (- C_b Tnext C_b)
+// (ca, cb: the column whose coupling weights scale a correction, -1 for none; Tprev,
+// Tnext stored transposed).
+struct SchurJob {
+  int q, i, ca, cb;            // problem of the batch, column, coupling columns
+  const double2 *Tprev, *Tnext;
+  double2 *S;
 };
-template <int NB> __device__ __forceinline__ FacLds fac_lds(unsigned char *smem, int m) {
-  FacLds L;
-  L.pan = (double2 *)smem;                 // [m][NB]
-  L.x1 = L.pan + (size_t)m * NB;           // [NB][m]
-  L.cw = L.x1 + (size_t)m * NB;            // [2][m]
-  L.prow = L.cw + 2 * (size_t)m;           // [2][NB] row exchange buffer
-  L.piv = (int *)(L.prow + 2 * NB);        // [m]
-  L.perm = L.piv + m;                      // [m]
-  return L;
-}
 
-// side 0: left sweep over a..mid-1; side 1: right sweep over b..mid+1.  S: an m x m
-// work matrix followed by an NB_MAX x m staging area.
-template <int NB, int RMAX>
-__device__ __forceinline__ void factor_side_body(const Grid &g, Chunk ch, int side, double2 *T, double2 *S,
-                                                 unsigned char *smem) {
-  const int m = g.nz;
-  const size_t mm = (size_t)m * m;
-  FacLds L = fac_lds<NB>(smem, m);
-  double2 *tmp = S + mm;
-  if (side == 0) {
-    for (int i = ch.a; i < ch.mid; ++i) {
-      const bool has = i > ch.a;
-      build_schur(g, m, i, has ? T + (size_t)(i - 1) * mm : nullptr, has ? i : -1, nullptr, -1, S, L.cw);
-      gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, L.pan, L.x1, L.prow, L.piv, L.perm, tmp);
-    }
-  } else {
-    for (int i = ch.b; i > ch.mid; --i) {
-      const bool has = i < ch.b;
-      build_schur(g, m, i, has ? T + (size_t)(i + 1) * mm : nullptr, has ? i + 1 : -1, nullptr, -1, S, L.cw);
-      gj_invert_store<NB, RMAX>(S, m, T + (size_t)i * mm, L.pan, L.x1, L.prow, L.piv, L.perm, tmp);
+// grid (32 x 32 tiles, jobs); the transposed reads of T go through LDS
+__global__ __launch_bounds__(256) void k_schur(FactorBatch bt, const SchurJob *jobs) {
+  const SchurJob J = jobs[blockIdx.y];
+  const Grid &g = bt.p[J.q].g;
+  const int m = g.nz, nt32 = (m + 31) / 32;
+  if ((int)blockIdx.x >= nt32 * nt32) return;
+  const int l0 = (blockIdx.x % nt32) * 32, j0 = (blockIdx.x / nt32) * 32;
+  __shared__ double2 ta[32][33], tb[32][33];
+  const int tid = threadIdx.x, lo = tid & 31, hi = tid >> 5;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {   // Tprev[j][l] = Tt[l][j], lanes along j
+    const int l = l0 + hi + 8 * p, j = j0 + lo;
+    if (l < m && j < m) {
+      if (J.ca >= 0) ta[hi + 8 * p][lo] = J.Tprev[(size_t)l * m + j];
+      if (J.cb >= 0) tb[hi + 8 * p][lo] = J.Tnext[(size_t)l * m + j];
     }
   }
-}
-
-template <int NB, int RMAX>
-__device__ __forceinline__ void factor_mid_body(const Grid &g, Chunk ch, double2 *T, double2 *S, unsigned char *smem) {
-  const int m = g.nz;
-  const size_t mm = (size_t)m * m;
-  FacLds L = fac_lds<NB>(smem, m);
-  const bool hl = ch.mid > ch.a, hr = ch.mid < ch.b;
-  build_schur(g, m, ch.mid, hl ? T + (size_t)(ch.mid - 1) * mm : nullptr, hl ? ch.mid : -1,
-              hr ? T + (size_t)(ch.mid + 1) * mm : nullptr, hr ? ch.mid + 1 : -1, S, L.cw);
-  gj_invert_store<NB, RMAX>(S, m, T + (size_t)ch.mid * mm, L.pan, L.x1, L.prow, L.piv, L.perm, S + mm);
-}
-
-// MODE 0: item = (chunk, side); MODE 1: item = chunk (its middle column)
-template <int NB, int RMAX, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_factor_chunks(FactorBatch bt) {
-  extern __shared__ unsigned char smem[];
-  const int item = item_of_block(bt.xs);
-  if (item < 0) return;
-  const int q = find_problem(bt.first, bt.n, item);
-  const FactorProblem &pp = bt.p[q];
-  const int local = item - bt.first[q];
-  if (MODE == 0)
-    factor_side_body<NB, RMAX>(pp.g, chunk_of(pp.part, local >> 1), local & 1, pp.T, work_slot(pp, local), smem);
-  else
-    factor_mid_body<NB, RMAX>(pp.g, chunk_of(pp.part, local), pp.T, work_slot(pp, 2 * local), smem);
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {   // S[j][l], lanes along l
+    const int j = j0 + hi + 8 * p, l = l0 + lo;
+    if (j >= m || l >= m) continue;
+    double2 v = make_double2(0.0, 0.0);
+    if (J.ca >= 0) v = csub(v, cmul(cmul(coupling_x(g, J.ca, j), ta[lo][hi + 8 * p]), coupling_x(g, J.ca, l)));
+    if (J.cb >= 0) v = csub(v, cmul(cmul(coupling_x(g, J.cb, j), tb[lo][hi + 8 * p]), coupling_x(g, J.cb, l)));
+    if (l >= j - 1 && l <= j + 1) {
+      const Stencil5 st = stencil_at(g, J.i, j);
+      v = cadd(v, l == j ? st.cc : (l < j ? st.czm : st.czp));
+    }
+    J.S[(size_t)j * m + l] = v;
+  }
 }
 
 // Spike of chunk ch for the right-hand-side columns s0 .. s0+NSP-1:
@@ -650,17 +610,6 @@ __global__ void k_cr_copy(const CrJob *jobs) {
       J.Z[e] = J.X[e];
     }
   }
-}
-
-// job: X = S (m x m row-major, followed by NB_MAX x m staging), Z = the transposed
-// inverse's destination
-template <int NB, int RMAX, int NT>
-__global__ __launch_bounds__(NT) void k_cr_invert(const CrJob *jobs) {
-  extern __shared__ unsigned char smem[];
-  const CrJob J = jobs[blockIdx.x];
-  FacLds L = fac_lds<NB>(smem, J.m);
-  double2 *S = const_cast<double2 *>(J.X);
-  gj_invert_store<NB, RMAX>(S, J.m, J.Z, L.pan, L.x1, L.prow, L.piv, L.perm, S + (size_t)J.m * J.m);
 }
 
 // up to 1024 threads (4 wave groups of 256 rows) where the register budget allows
@@ -1625,15 +1574,15 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     if (p->fac_work) HIP_TRY(hipFree(p->fac_work));
     p->fac_work = nullptr;
     p->fac_slots = 0;
-    HIP_TRY(hipMalloc((void **)&p->fac_work, sizeof(double2) * slots * (mm + (size_t)NB_MAX * m)));
+    HIP_TRY(kf_malloc((void **)&p->fac_work, sizeof(double2) * slots * (mm + (size_t)NB_MAX * m)));
     p->fac_slots = slots;
   }
   if (chunks > 1 && !p->V64) {
     const size_t n = (size_t)p->nx * mm;
-    HIP_TRY(hipMalloc((void **)&p->V64, sizeof(double2) * n));
-    HIP_TRY(hipMalloc((void **)&p->W64, sizeof(double2) * n));
-    HIP_TRY(hipMalloc((void **)&p->V32, sizeof(float2) * n));
-    HIP_TRY(hipMalloc((void **)&p->W32, sizeof(float2) * n));
+    HIP_TRY(kf_malloc((void **)&p->V64, sizeof(double2) * n));
+    HIP_TRY(kf_malloc((void **)&p->W64, sizeof(double2) * n));
+    HIP_TRY(kf_malloc((void **)&p->V32, sizeof(float2) * n));
+    HIP_TRY(kf_malloc((void **)&p->W32, sizeof(float2) * n));
   }
   // the separators' reduction blocks, sized by the separator count
   for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32})
@@ -1642,9 +1591,9 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
   p->CR32 = nullptr;
   if (chunks > 1) {
     const size_t nsep = chunks - 1;
-    HIP_TRY(hipMalloc((void **)&p->CRL64, sizeof(double2) * nsep * 4 * mm));
-    HIP_TRY(hipMalloc((void **)&p->CR64, sizeof(double2) * nsep * CR_LV * 2 * mm));
-    HIP_TRY(hipMalloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
+    HIP_TRY(kf_malloc((void **)&p->CRL64, sizeof(double2) * nsep * 4 * mm));
+    HIP_TRY(kf_malloc((void **)&p->CR64, sizeof(double2) * nsep * CR_LV * 2 * mm));
+    HIP_TRY(kf_malloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
   }
   p->part = part;
   p->P = chunks;
@@ -1659,77 +1608,92 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
 // factorisation of a batch of problems (a single problem is a batch of one)
 // ---------------------------------------------------------------------------
 namespace {
-template <int NB, int RMAX, int NT>
+// every matrix of the job range inverted: GJ_NB-column panels, one launch each, then
+// the transposed store
+kf_status gj_invert(const GjJob *dj, int cnt, int m_max, hipStream_t s) {
+  if (cnt == 0) return KF_OK;
+  const int npan = (m_max + GJ_NB - 1) / GJ_NB, nt = 64 * ((m_max + 63) / 64);
+  for (int t = 0; t <= npan; ++t) {
+    hipLaunchKernelGGL((k_gj_step<GJ_NB>), dim3(npan, cnt), dim3(nt), 0, s, dj, t);
+    LAUNCH_CHECK();
+  }
+  const int t32 = (m_max + 31) / 32;
+  hipLaunchKernelGGL(k_gj_store, dim3(t32 * t32, cnt), dim3(256), 0, s, dj);
+  LAUNCH_CHECK();
+  return KF_OK;
+}
+
 kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, int m_max) {
-  const size_t smem = (2 * (size_t)m_max * NB + 2 * (size_t)m_max + 2 * NB) * sizeof(double2) + 2 * (size_t)m_max * sizeof(int);
-  HIP_TRY(hipFuncSetAttribute((const void *)k_factor_chunks<NB, RMAX, NT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  HIP_TRY(hipFuncSetAttribute((const void *)k_factor_chunks<NB, RMAX, NT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  HIP_TRY(hipFuncSetAttribute((const void *)k_cr_invert<NB, RMAX, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  if (m_max > 512) { set_error("column height above 512"); return KF_EINVAL; }
   FactorBatch bt{};
   bt.n = (int)ps.size();
   for (int q = 0; q < bt.n; ++q) {
     kf_problem *p = ps[q];
     bt.p[q] = FactorProblem{p->grid(), p->P, p->d_part, p->T64, p->V64, p->W64, p->fac_work};
   }
-  // 1. chunks: both sides, then the middle columns
-  double cost[KF_BATCH_MAX];
-  for (int mode = 0; mode < 2; ++mode) {
-    int tot = 0;
+  auto slot = [](kf_problem *p, int i) { return p->fac_work + (size_t)i * ((size_t)p->nz * p->nz + (size_t)NB_MAX * p->nz); };
+  auto tblk = [](kf_problem *p, int col) { return p->T64 + (size_t)col * p->nz * p->nz; };
+  // 1. job tables of the chunks' twisted factorisations: step st of every (chunk,
+  //    side) chain that has one (side 0 walks a..mid-1, side 1 b..mid+1), then the
+  //    middle columns.  A step is a Schur complement and an inversion per chain.
+  std::vector<SchurJob> sjobs;
+  std::vector<GjJob> gjobs;
+  struct ChainStep { int off, cnt; };
+  std::vector<ChainStep> chain;
+  int maxcnt = 0;
+  for (kf_problem *p : ps)
+    for (int c = 0; c < p->P; ++c)
+      maxcnt = std::max(maxcnt, std::max(p->part[3 * c + 2] - p->part[3 * c], p->part[3 * c + 1] - p->part[3 * c + 2]));
+  for (int st = 0; st <= maxcnt; ++st) {
+    ChainStep cs{(int)sjobs.size(), 0};
     for (int q = 0; q < bt.n; ++q) {
-      const double m = ps[q]->nz, L = (double)ps[q]->nx / ps[q]->P;
-      bt.first[q] = tot;
-      tot += (mode == 0 ? 2 : 1) * ps[q]->P;
-      cost[q] = m * m * m * (mode == 0 ? 0.5 * L : 1.0);
+      kf_problem *p = ps[q];
+      const int m = p->nz;
+      for (int c = 0; c < p->P; ++c) {
+        const int a = p->part[3 * c], b = p->part[3 * c + 1], mid = p->part[3 * c + 2];
+        if (st == maxcnt) {   // the middle columns
+          const bool hl = mid > a, hr = mid < b;
+          double2 *S = slot(p, 2 * c);
+          sjobs.push_back(SchurJob{q, mid, hl ? mid : -1, hr ? mid + 1 : -1, hl ? tblk(p, mid - 1) : nullptr,
+                                   hr ? tblk(p, mid + 1) : nullptr, S});
+          gjobs.push_back(GjJob{m, S, tblk(p, mid)});
+          cs.cnt++;
+          continue;
+        }
+        for (int side = 0; side < 2; ++side) {
+          const int cnt = side == 0 ? mid - a : b - mid;
+          if (st >= cnt) continue;
+          const int i = side == 0 ? a + st : b - st;
+          const bool has = st > 0;
+          const int prev = side == 0 ? i - 1 : i + 1, cc = side == 0 ? i : i + 1;
+          double2 *S = slot(p, 2 * c + side);
+          sjobs.push_back(SchurJob{q, i, has ? cc : -1, -1, has ? tblk(p, prev) : nullptr, nullptr, S});
+          gjobs.push_back(GjJob{m, S, tblk(p, i)});
+          cs.cnt++;
+        }
+      }
     }
-    bt.first[bt.n] = bt.total = tot;
-    const unsigned grid = xcd_split(bt.first, bt.n, cost, bt.xs);
-    if (mode == 0) hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 0>), dim3(grid), dim3(NT), smem, s, bt);
-    else hipLaunchKernelGGL((k_factor_chunks<NB, RMAX, NT, 1>), dim3(grid), dim3(NT), smem, s, bt);
-    LAUNCH_CHECK();
+    chain.push_back(cs);
   }
-  // 2. spikes
-  constexpr int NSP = 2;
-  int tot = 0, pmax = 1;
+  // 2. job tables of the separators' reduction (all problems, level by level)
+  int ntot = 0, top_max = -1;
+  int sep_first[KF_BATCH_MAX];
   for (int q = 0; q < bt.n; ++q) {
-    const double m = ps[q]->nz, L = (double)ps[q]->nx / ps[q]->P;
-    bt.first[q] = tot;
-    tot += 2 * (ps[q]->P - 1) * ((ps[q]->nz + NSP - 1) / NSP);
-    pmax = std::max(pmax, ps[q]->P);
-    cost[q] = m * m * 1.5 * L;
+    sep_first[q] = ntot;
+    const int nsep = ps[q]->P - 1;
+    ntot += nsep;
+    if (nsep > 0) top_max = std::max(top_max, cr_top(nsep));
   }
-  bt.first[bt.n] = bt.total = tot;
-  if (tot == 0) return KF_OK;
-  const unsigned grid_sp = xcd_split(bt.first, bt.n, cost, bt.xs);
-  const dim3 blk = sweep_block(m_max);
-  const size_t smem_sp = (1 + (blk.y - 1)) * NSP * (size_t)m_max * sizeof(double2);
-  HIP_TRY(hipFuncSetAttribute((const void *)k_spikes<NSP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
-  hipLaunchKernelGGL((k_spikes<NSP>), dim3(grid_sp), blk, smem_sp, s, bt);
-  LAUNCH_CHECK();
-  // 3. the separators' system by block cyclic reduction (all problems, level by level)
+  std::vector<CrJob> jobs;
+  struct Step { int kind, off, cnt; };   // kind 0 copy, 1 invert (GjJob range), 2 gemm
+  std::vector<Step> steps;
   {
-    int ntot = 0, top_max = -1;
-    for (int q = 0; q < bt.n; ++q) {
-      bt.first[q] = ntot;
-      const int nsep = ps[q]->P - 1;
-      ntot += nsep;
-      if (nsep > 0) top_max = std::max(top_max, cr_top(nsep));
-      bt.p[q].lu = ps[q]->CRL64;
-    }
-    bt.first[bt.n] = bt.total = ntot;
-    if (ntot == 0) return KF_OK;
-    hipLaunchKernelGGL(k_cr_setup, dim3(std::min(256, (m_max * m_max + 255) / 256), ntot), dim3(256), 0, s, bt);
-    LAUNCH_CHECK();
-    // job table of every step of every level
-    std::vector<CrJob> jobs;
-    struct Step { int kind, off, cnt; };   // kind 0 copy, 1 invert, 2 gemm
-    std::vector<Step> steps;
     auto sep = [](kf_problem *p, int j) { return p->part[3 * (j - 1) + 1] + 1; };
     auto blk = [](kf_problem *p, double2 *base, int col) { return base + (size_t)col * p->nz * p->nz; };
     auto lu = [](kf_problem *p, int j, int w) { return p->CRL64 + ((size_t)(j - 1) * 4 + w) * p->nz * p->nz; };
     auto crb = [](kf_problem *p, int k, int lv, int w) {
       return p->CR64 + (((size_t)(k - 1) * CR_LV + lv) * 2 + w) * p->nz * p->nz;
     };
-    auto slot = [](kf_problem *p, int i) { return p->fac_work + (size_t)i * ((size_t)p->nz * p->nz + (size_t)NB_MAX * p->nz); };
     auto begin = [&](int kind) { steps.push_back(Step{kind, (int)jobs.size(), 0}); };
     auto add = [&](const CrJob &j) { jobs.push_back(j); steps.back().cnt++; };
     for (int lv = 0; lv <= top_max; ++lv) {
@@ -1752,10 +1716,11 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
         add(CrJob{e.first->nz, 1.0, blk(e.first, e.first->T64, sep(e.first, e.second)), nullptr, nullptr, slot(e.first, i)});
       }
       used.clear();
-      begin(1);
+      steps.push_back(Step{1, (int)gjobs.size(), 0});
       for (auto &e : inv) {
         const int i = used[e.first]++;
-        add(CrJob{e.first->nz, 0.0, slot(e.first, i), nullptr, nullptr, blk(e.first, e.first->T64, sep(e.first, e.second))});
+        gjobs.push_back(GjJob{e.first->nz, slot(e.first, i), blk(e.first, e.first->T64, sep(e.first, e.second))});
+        steps.back().cnt++;
       }
       // B: F_j = Binv_j L_j, G_j = Binv_j U_j
       begin(2);
@@ -1810,29 +1775,74 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
         }
       }
     }
-    // the table lives in the first problem's buffer; the previous factorisation's
-    // launches must be done with it before it is overwritten
-    kf_problem *p0 = ps[0];
-    if (jobs.size() > p0->cr_jobs_cap) {
-      HIP_TRY(hipStreamSynchronize(s));
-      if (p0->cr_jobs) HIP_TRY(hipFree(p0->cr_jobs));
-      p0->cr_jobs = nullptr;
-      p0->cr_jobs_cap = 0;
-      HIP_TRY(hipMalloc(&p0->cr_jobs, sizeof(CrJob) * jobs.size()));
-      p0->cr_jobs_cap = jobs.size();
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemcpy(p0->cr_jobs, jobs.data(), sizeof(CrJob) * jobs.size(), hipMemcpyHostToDevice));
-    const CrJob *dj = (const CrJob *)p0->cr_jobs;
-    const int tiles = ((m_max + 31) / 32) * ((m_max + 31) / 32);
-    const int cblocks = std::min(64, (m_max * m_max + 255) / 256);
-    for (const Step &stp : steps) {
-      if (stp.cnt == 0) continue;
-      if (stp.kind == 0) hipLaunchKernelGGL(k_cr_copy, dim3(cblocks, stp.cnt), dim3(256), 0, s, dj + stp.off);
-      else if (stp.kind == 1) hipLaunchKernelGGL((k_cr_invert<NB, RMAX, NT>), dim3(stp.cnt), dim3(NT), smem, s, dj + stp.off);
-      else hipLaunchKernelGGL(k_cr_gemm, dim3(tiles, stp.cnt), dim3(256), 0, s, dj + stp.off);
-      LAUNCH_CHECK();
-    }
+  }
+  // 3. one upload of every table (the previous factorisation's launches must be done
+  //    with the buffer first: it lives in the first problem)
+  const size_t sz_s = sizeof(SchurJob) * sjobs.size(), sz_g = sizeof(GjJob) * gjobs.size();
+  const size_t off_g = (sz_s + 255) & ~(size_t)255, off_c = (off_g + sz_g + 255) & ~(size_t)255;
+  const size_t bytes = off_c + sizeof(CrJob) * jobs.size();
+  kf_problem *p0 = ps[0];
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bytes > p0->fac_jobs_cap) {
+    if (p0->fac_jobs) HIP_TRY(hipFree(p0->fac_jobs));
+    p0->fac_jobs = nullptr;
+    p0->fac_jobs_cap = 0;
+    HIP_TRY(kf_malloc(&p0->fac_jobs, bytes));
+    p0->fac_jobs_cap = bytes;
+  }
+  std::vector<unsigned char> host(bytes, 0);
+  if (sz_s) std::memcpy(host.data(), sjobs.data(), sz_s);
+  if (sz_g) std::memcpy(host.data() + off_g, gjobs.data(), sz_g);
+  if (!jobs.empty()) std::memcpy(host.data() + off_c, jobs.data(), sizeof(CrJob) * jobs.size());
+  HIP_TRY(hipMemcpy(p0->fac_jobs, host.data(), bytes, hipMemcpyHostToDevice));
+  const SchurJob *dsj = (const SchurJob *)p0->fac_jobs;
+  const GjJob *dgj = (const GjJob *)((unsigned char *)p0->fac_jobs + off_g);
+  const CrJob *dj = (const CrJob *)((unsigned char *)p0->fac_jobs + off_c);
+  // 4. the chunks: Schur complement and inversion, chain step by chain step
+  const int t32 = (m_max + 31) / 32;
+  for (const ChainStep &cs : chain) {
+    if (cs.cnt == 0) continue;
+    hipLaunchKernelGGL(k_schur, dim3(t32 * t32, cs.cnt), dim3(256), 0, s, bt, dsj + cs.off);
+    LAUNCH_CHECK();
+    kf_status st = gj_invert(dgj + cs.off, cs.cnt, m_max, s);
+    if (st != KF_OK) return st;
+  }
+  // 5. spikes
+  constexpr int NSP = 2;
+  double cost[KF_BATCH_MAX];
+  int tot = 0, pmax = 1;
+  for (int q = 0; q < bt.n; ++q) {
+    const double m = ps[q]->nz, L = (double)ps[q]->nx / ps[q]->P;
+    bt.first[q] = tot;
+    tot += 2 * (ps[q]->P - 1) * ((ps[q]->nz + NSP - 1) / NSP);
+    pmax = std::max(pmax, ps[q]->P);
+    cost[q] = m * m * 1.5 * L;
+  }
+  bt.first[bt.n] = bt.total = tot;
+  if (tot == 0) return KF_OK;   // one chunk: no separators
+  const unsigned grid_sp = xcd_split(bt.first, bt.n, cost, bt.xs);
+  const dim3 blk = sweep_block(m_max);
+  const size_t smem_sp = (1 + (blk.y - 1)) * NSP * (size_t)m_max * sizeof(double2);
+  HIP_TRY(hipFuncSetAttribute((const void *)k_spikes<NSP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
+  hipLaunchKernelGGL((k_spikes<NSP>), dim3(grid_sp), blk, smem_sp, s, bt);
+  LAUNCH_CHECK();
+  // 6. the separators' system by block cyclic reduction
+  if (ntot == 0) return KF_OK;
+  for (int q = 0; q < bt.n; ++q) bt.first[q] = sep_first[q];
+  bt.first[bt.n] = bt.total = ntot;
+  for (int q = 0; q < bt.n; ++q) bt.p[q].lu = ps[q]->CRL64;
+  hipLaunchKernelGGL(k_cr_setup, dim3(std::min(256, (m_max * m_max + 255) / 256), ntot), dim3(256), 0, s, bt);
+  LAUNCH_CHECK();
+  const int tiles = t32 * t32;
+  const int cblocks = std::min(64, (m_max * m_max + 255) / 256);
+  for (const Step &stp : steps) {
+    if (stp.cnt == 0) continue;
+    if (stp.kind == 0) hipLaunchKernelGGL(k_cr_copy, dim3(cblocks, stp.cnt), dim3(256), 0, s, dj + stp.off);
+    else if (stp.kind == 1) {
+      kf_status st = gj_invert(dgj + stp.off, stp.cnt, m_max, s);
+      if (st != KF_OK) return st;
+    } else hipLaunchKernelGGL(k_cr_gemm, dim3(tiles, stp.cnt), dim3(256), 0, s, dj + stp.off);
+    LAUNCH_CHECK();
   }
   return KF_OK;
 }
@@ -1845,13 +1855,7 @@ kf_status blu_factor_batch(const std::vector<kf_problem *> &all, int which, hipS
     if ((which & 3) && !p->have_T64) { ps.push_back(p); m_max = std::max(m_max, p->nz); }
   if ((int)ps.size() > KF_BATCH_MAX) { set_error("batch too large"); return KF_EINVAL; }
   if (!ps.empty()) {
-    // panel width and rows per lane of the register-resident panel, by column height
-    // (the register-resident panel needs the larger VGPR budget of 256-thread groups
-    //  once a lane owns five or more rows)
-    kf_status st = m_max <= 128 ? factor64_launch<8, 2, 512>(ps, s, m_max)
-                 : m_max <= 192 ? factor64_launch<8, 3, 512>(ps, s, m_max)
-                 : m_max <= 320 ? factor64_launch<8, 5, 256>(ps, s, m_max)
-                                : factor64_launch<8, 8, 256>(ps, s, m_max);
+    kf_status st = factor64_launch(ps, s, m_max);
     if (st != KF_OK) return st;
     for (kf_problem *p : ps) p->have_T64 = true;
   }

@@ -168,8 +168,8 @@ struct kf_problem {
   double2 *CRL64 = nullptr;                    // separators' L, U during the reduction [n][4][m][m]
   double2 *CR64 = nullptr;                     // separators' ML, MU [n][levels][2][m][m]
   float2 *CR32 = nullptr;
-  void *cr_jobs = nullptr;                     // device job table of the reduction
-  size_t cr_jobs_cap = 0;
+  void *fac_jobs = nullptr;                    // device job tables of the factorisation
+  size_t fac_jobs_cap = 0;                     // bytes
   double2 *sol64 = nullptr;                    // [K][nx][nz] column-major solve copy (c128)
   float2 *sol32 = nullptr;                     // the same for complex64 sweeps
 
@@ -217,6 +217,11 @@ static_assert(PROF_N <= 32, "profiling families are bits of a 32-bit mask");
 
 // error plumbing
 void set_error(const std::string &msg);
+// hipMalloc of the library's device buffers.  With KF_POISON_ALLOC set in the
+// environment every new buffer is filled with 0xFF bytes (NaN in FP32 and FP64), so
+// that a read of memory no kernel has written shows up as a NaN instead of depending
+// on what the memory held before.
+hipError_t kf_malloc(void **ptr, size_t bytes);
 #define HIP_TRY(expr)                                                                    \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(RB) void k_axpy_dot_partial(const double2 *__restri
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       x[q] = q < nd ? V[(size_t)q * n + t] : make_double2(0.0, 0.0);
-      y = csub(y, cmul(x[q], hs[q]));
+      if (q < nd) y = csub(y, cmul(x[q], hs[q]));   // h holds nv entries only
     }
     // the remaining vectors eight at a time, their loads in flight together (the
     // subtractions keep the ascending order)

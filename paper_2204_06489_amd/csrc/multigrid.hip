@@ -462,7 +462,7 @@ void mg_destroy(kf_problem *p) {
 }
 
 template <typename T> static kf_status mg_alloc(T **q, size_t bytes) {
-  if (hipMalloc((void **)q, bytes ? bytes : 1) != hipSuccess) {
+  if (kf_malloc((void **)q, bytes ? bytes : 1) != hipSuccess) {
     *q = nullptr;
     set_error("multigrid: hipMalloc of " + std::to_string(bytes) + " bytes failed");
     return KF_ENOMEM;
