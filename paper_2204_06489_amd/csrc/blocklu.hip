@@ -83,6 +83,85 @@ __device__ __forceinline__ bool gj_better(double ob, int oi, double best, int bi
   return ob > best || (ob == best && oi < bi);
 }
 
+// One elimination step of a panel held one row per thread (acc: the row's NB panel
+// entries): the pivot row chosen over the rows not yet pivoted (largest modulus, the
+// lowest row on ties), exchanged with row k, scaled, and its column eliminated from
+// every other row.  Q is a compile-time column, so acc stays in registers.
+struct GjPanel {
+  int r, m, k0, nw, lane, wave;
+  bool row;
+  double2 *rowbuf;   // LDS [2][NB]: the pivot row, the old row k
+  double *cbest;     // LDS [8]: per-wavefront candidates
+  int *cidx;
+  int *lperm;        // LDS [m]: the panel's row permutation
+};
+
+template <int NB, int Q>
+__device__ __forceinline__ void gj_pivot(const GjPanel &P, double2 (&acc)[NB]) {
+  const int k = P.k0 + Q;
+  double best = -1.0;
+  int bi = P.m;
+  if (P.row && P.r >= k) {
+    const double a = cabs2(acc[Q]);
+    if (a > best) { best = a; bi = P.r; }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (gj_better(ob, oi, best, bi)) { best = ob; bi = oi; }
+  }
+  if (P.lane == 0) { P.cbest[P.wave] = best; P.cidx[P.wave] = bi; }
+  __syncthreads();
+  best = P.cbest[0];
+  bi = P.cidx[0];
+  for (int w = 1; w < P.nw; ++w)
+    if (gj_better(P.cbest[w], P.cidx[w], best, bi)) { best = P.cbest[w]; bi = P.cidx[w]; }
+  // a column with no finite entry leaves bi = m: no interchange, every index stays in
+  // range (the factors then carry the NaNs and the solves report them)
+  const int pr = bi < P.m ? bi : k;
+  if (P.r == pr)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) P.rowbuf[c] = acc[c];
+  if (P.r == k)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) P.rowbuf[NB + c] = acc[c];
+  if (P.r == 0) {
+    const int tmp = P.lperm[k];
+    P.lperm[k] = P.lperm[pr];
+    P.lperm[pr] = tmp;
+  }
+  __syncthreads();
+  // the new row k is the old row pr, scaled; the pivot entry becomes 1 / pivot
+  const double2 d = cdiv(make_double2(1.0, 0.0), P.rowbuf[Q]);
+  if (P.r == k) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[c] = (c == Q) ? d : cmul(P.rowbuf[c], d);
+  } else if (P.row) {
+    if (P.r == pr)   // the old row k moves to pr, then is eliminated like every other row
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = P.rowbuf[NB + c];
+    const double2 f = acc[Q];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double2 pc = (c == Q) ? d : cmul(P.rowbuf[c], d);
+      acc[c] = csub(c == Q ? make_double2(0.0, 0.0) : acc[c], cmul(f, pc));
+    }
+  }
+}
+
+template <int NB, int Q> struct GjPivots {
+  __device__ static __forceinline__ void run(const GjPanel &P, int ncol, double2 (&acc)[NB]) {
+    if (Q < ncol) {   // uniform
+      gj_pivot<NB, Q>(P, acc);
+      GjPivots<NB, Q + 1>::run(P, ncol, acc);
+    }
+  }
+};
+template <int NB> struct GjPivots<NB, NB> {
+  __device__ static __forceinline__ void run(const GjPanel &, int, double2 (&)[NB]) {}
+};
+
 // launch t of a batch inversion; grid (column blocks, matrices), one thread per row
 // (blockDim.x >= m)
 template <int NB>
@@ -138,76 +217,10 @@ __global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[c] = c < ncol ? J.S[(size_t)r * m + cb0 + c] : make_double2(0.0, 0.0);
   }
-  // elimination of panel t (this block).  The pivot loop is not unrolled (it holds
-  // barriers), so the register arrays are only ever indexed by unrolled constants:
-  // entry q is picked out by a chain of selects.
+  // elimination of panel t (this block)
   for (int e = r; e < m; e += nt) lperm[e] = e;
-  const int lane = r & 63, wave = r >> 6, nw = (nt + 63) >> 6;
-  for (int q = 0; q < ncol; ++q) {
-    const int k = cb0 + q;
-    double best = -1.0;
-    int bi = m;
-    double2 aq = acc[0];
-#pragma unroll
-    for (int c = 1; c < NB; ++c)
-      if (c == q) aq = acc[c];
-    if (row && r >= k) {
-      const double a = cabs2(aq);
-      if (a > best) { best = a; bi = r; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (gj_better(ob, oi, best, bi)) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { cbest[wave] = best; cidx[wave] = bi; }
-    __syncthreads();
-    best = cbest[0];
-    bi = cidx[0];
-    for (int w = 1; w < nw; ++w)
-      if (gj_better(cbest[w], cidx[w], best, bi)) { best = cbest[w]; bi = cidx[w]; }
-    // a column with no finite entry leaves bi = m: no interchange, every index stays in
-    // range (the factors then carry the NaNs and the solves report them)
-    const int pr = bi < m ? bi : k;
-    if (r == pr)
-#pragma unroll
-      for (int c = 0; c < NB; ++c) rowbuf[0][c] = acc[c];
-    if (r == k)
-#pragma unroll
-      for (int c = 0; c < NB; ++c) rowbuf[1][c] = acc[c];
-    if (r == 0) {
-      const int tmp = lperm[k];
-      lperm[k] = lperm[pr];
-      lperm[pr] = tmp;
-    }
-    __syncthreads();
-    double2 prow[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) prow[c] = rowbuf[0][c];
-    // the new row k is the old row pr, scaled; the pivot entry becomes 1 / pivot
-    double2 pq = prow[0];
-#pragma unroll
-    for (int c = 1; c < NB; ++c)
-      if (c == q) pq = prow[c];
-    const double2 d = cdiv(make_double2(1.0, 0.0), pq);
-#pragma unroll
-    for (int c = 0; c < NB; ++c) prow[c] = (c == q) ? d : cmul(prow[c], d);
-    if (r == k) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) acc[c] = prow[c];
-    } else if (row) {
-      if (r == pr)   // the old row k moves to pr, then is eliminated like every other row
-#pragma unroll
-        for (int c = 0; c < NB; ++c) acc[c] = rowbuf[1][c];
-      double2 f = acc[0];
-#pragma unroll
-      for (int c = 1; c < NB; ++c)
-        if (c == q) f = acc[c];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) acc[c] = csub(c == q ? make_double2(0.0, 0.0) : acc[c], cmul(f, prow[c]));
-    }
-  }
+  const GjPanel P{r, m, cb0, (nt + 63) >> 6, r & 63, r >> 6, row, &rowbuf[0][0], cbest, cidx, lperm};
+  GjPivots<NB, 0>::run(P, ncol, acc);
   __syncthreads();   // lperm complete
   if (row)
 #pragma unroll
@@ -225,11 +238,12 @@ __global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
 
 // after the last panel: Tt[c][j] = Sinv[j][c] = S[j][col(c)], col the inverse of the
 // composed row permutation; 32 x 32 tiles through LDS, grid (tiles, matrices)
+template <int NB>
 __global__ __launch_bounds__(256) void k_gj_store(const GjJob *jobs) {
   const GjJob J = jobs[blockIdx.y];
   const int m = J.m, nt32 = (m + 31) / 32;
   if ((int)blockIdx.x >= nt32 * nt32) return;
-  const int npan = (m + GJ_NB - 1) / GJ_NB;
+  const int npan = (m + NB - 1) / NB;
   const int *sg = (const int *)(J.S + (size_t)m * m) + 2 * m + ((npan - 1) & 1) * m;
   __shared__ int col[512];
   __shared__ double2 tile[32][33];
@@ -1188,6 +1202,183 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
   }
 }
 
+// The separators' reduction of complex64 solves on the matrix cores.  A level is, for
+// each separator it writes, one product of its blocks [M_0 | M_1 | M_2] (m x nterm m,
+// column-major) with the stacked vectors of the terms (nterm m x K) over every source,
+// so a workgroup computes a 64 x 16 tile (rows x sources) of it with
+// v_mfma_f32_16x16x4f32 (Gauss: three real products per complex one), each wavefront
+// 16 rows, k in slabs of 64 through LDS with the next slab prefetched.  A level has
+// few separators, so its time is the latency of one workgroup's chain of slabs: small
+// tiles (many workgroups, few products each) beat wide ones here (64 x 48 tiles: 1.25x
+// the time; 128- or 144-deep slabs: 1.07x and 1.2x).
+// Each block is read once per 16 sources instead of once per source group of the
+// vector-unit levels, and all rows of a level's separators run in parallel.  Tiles split a separator's rows over
+// workgroups, so a back-substitution level (x_j = Binv_j g_j - F_j x_j1 - G_j x_j2,
+// written over g_j) and the root take g_j from the copy staged by k_cr_stage instead
+// of from the column they overwrite.  item = (separator, row tile, source tile).
+constexpr int CRM_R = 64, CRM_S = 16, CRM_K = 64, CRM_ST = CRM_S / 16;
+
+// gsep[(j - 1) K + k][l] = the separator j column of source k, every separator
+__global__ __launch_bounds__(256) void k_cr_stage(SweepBatch bt) {
+  const int q = find_problem(bt.first, bt.n, blockIdx.y);
+  const SweepProblem &pp = bt.p[q];
+  const int col = blockIdx.y - bt.first[q];   // (separator - 1) K + source
+  const int K = pp.K, j = col / K + 1, k = col - (j - 1) * K;
+  const int m = pp.g.nz;
+  const float2 *src = colp<float>(pp.x, pp.g, k, separator(pp.part, j));
+  float2 *dst = (float2 *)pp.gsep + (size_t)col * m;
+  for (int l = threadIdx.x; l < m; l += 256) dst[l] = src[l];
+}
+
+// slab loader of k_cr_mfma: a slab (CRM_K values of k from l0) lies in one term, whose
+// block, source column (-1: the staged g_j) and sign the caller passes
+template <int NA, int NB>
+__device__ __forceinline__ void cr_load_slab(const float2 *Mt, int ct, float sg, const float2 *gj, const float2 *xb,
+                                             int l0, int tid, int R0, int s0, int m, int K, int nx, float2 (&ra)[NA],
+                                             float2 (&rb)[NB]) {
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {   // A[R0 + rr][l0 + kk], coalesced over rows
+    const int e = tid + 256 * u, rr = e % CRM_R, l = l0 + e / CRM_R;
+    const int j = min(R0 + rr, m - 1);
+    const float2 v = Mt[(size_t)min(l, m - 1) * m + j];
+    ra[u] = (R0 + rr < m && l < m) ? v : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {   // B[l0 + kk][s0 + sidx], coalesced over k
+    const int e = tid + 256 * u, l = l0 + e % CRM_K, sidx = s0 + e / CRM_K;
+    const int lc = min(l, m - 1), k = min(sidx, K - 1);
+    const float2 v = ct < 0 ? gj[(size_t)k * m + lc] : xb[((size_t)k * nx + ct) * m + lc];
+    rb[u] = (l < m && sidx < K) ? make_float2(sg * v.x, sg * v.y) : make_float2(0.f, 0.f);
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
+  using C = float2;
+  constexpr int SLAB = CRM_K * (CRM_R + 2) + CRM_K * (CRM_S + 2), TILE = CRM_S * (CRM_R + 1);
+  __shared__ C lds[SLAB > TILE ? SLAB : TILE];
+  C(*As)[CRM_R + 2] = (C(*)[CRM_R + 2])lds;
+  C(*Bs)[CRM_S + 2] = (C(*)[CRM_S + 2])(lds + CRM_K * (CRM_R + 2));
+  C(*Out)[CRM_R + 1] = (C(*)[CRM_R + 1])lds;
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const Grid &g = pp.g;
+  const int m = g.nz, K = pp.K, n = pp.P - 1, lv = bt.level;
+  const int stiles = (K + CRM_S - 1) / CRM_S, rtiles = (m + CRM_R - 1) / CRM_R;
+  const int st = local % stiles, rest = local / stiles;
+  const int rt = rest % rtiles, t = rest / rtiles;
+  const size_t mm = (size_t)m * m;
+  const C *T = (const C *)pp.T, *V = (const C *)pp.V, *W = (const C *)pp.W, *CR = (const C *)pp.CR;
+  const C *gs = (const C *)pp.gsep;
+  // up to three terms stacked along k: block, source column of x (-1: separator jg's
+  // staged copy) and sign; named slots, so that nothing is indexed at run time
+  const C *M0, *M1 = nullptr, *M2 = nullptr;
+  int c0, c1 = 0, c2 = 0, jg = 0, nterm, out;
+  float g0 = -1.f;
+  bool keep;
+  if (KIND == 0) {   // g_k -= ML_k g_{k - 2^l} + MU_k g_{k + 2^l}
+    const int s2 = 1 << lv, k = (t + 1) * 2 * s2;
+    out = separator(pp.part, k);
+    keep = true;
+    M0 = CR + ((size_t)(k - 1) * CR_LV + lv) * 2 * mm;
+    c0 = separator(pp.part, k - s2);
+    const bool right = k + s2 <= n;
+    if (right) { M1 = M0 + mm; c1 = separator(pp.part, k + s2); }
+    nterm = 1 + right;
+  } else {           // x_j = Binv_j g_j (- F_j x_{j - 2^l} - G_j x_{j + 2^l})
+    const int s2 = 1 << lv;
+    const int j = KIND == 1 ? 1 << cr_top(n) : (2 * t + 1) * s2;
+    out = separator(pp.part, j);
+    keep = false;
+    jg = j;
+    M0 = T + (size_t)out * mm;
+    c0 = -1;
+    g0 = 1.f;
+    const bool hf = KIND == 2 && j - s2 >= 1, hg = KIND == 2 && j + s2 <= n;
+    const C *Fj = V + (size_t)out * mm, *Gj = W + (size_t)out * mm;
+    const int cf = hf ? separator(pp.part, j - s2) : 0, cgc = hg ? separator(pp.part, j + s2) : 0;
+    M1 = hf ? Fj : (hg ? Gj : nullptr);
+    c1 = hf ? cf : cgc;
+    M2 = hf && hg ? Gj : nullptr;
+    c2 = cgc;
+    nterm = 1 + hf + hg;
+  }
+  const int R0 = rt * CRM_R, s0 = st * CRM_S, nx = g.nx;
+  C *const xb = (C *)pp.x;   // column i of source k at xb + (k nx + i) m
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NA = CRM_K * CRM_R / 256, NB = CRM_K * CRM_S / 256;
+  // each term's k range padded to a multiple of 4 (one MFMA k-step), cut into slabs
+  const int mp = (m + 3) / 4 * 4, spt = (mp + CRM_K - 1) / CRM_K, nsl = nterm * spt;
+  const C *gj = gs + (size_t)(jg > 0 ? jg - 1 : 0) * K * m;
+  auto load_slab = [&](int sl, C (&ra)[NA], C (&rb)[NB]) {
+    const int tau = sl / spt, l0 = (sl - tau * spt) * CRM_K;   // uniform
+    if (tau == 0) cr_load_slab(M0, c0, g0, gj, xb, l0, tid, R0, s0, m, K, nx, ra, rb);
+    else if (tau == 1) cr_load_slab(M1, c1, -1.f, gj, xb, l0, tid, R0, s0, m, K, nx, ra, rb);
+    else cr_load_slab(M2, c2, -1.f, gj, xb, l0, tid, R0, s0, m, K, nx, ra, rb);
+  };
+  floatx4 p1[CRM_ST], p2[CRM_ST], p3[CRM_ST];
+#pragma unroll
+  for (int y = 0; y < CRM_ST; ++y) p1[y] = p2[y] = p3[y] = floatx4{0.f, 0.f, 0.f, 0.f};
+  C ra[NA], rb[NB];
+  load_slab(0, ra, rb);
+  for (int sl = 0; sl < nsl; ++sl) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + 256 * u;
+      As[e / CRM_R][e % CRM_R] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e % CRM_K][e / CRM_K] = rb[u];
+    }
+    __syncthreads();
+    if (sl + 1 < nsl) load_slab(sl + 1, ra, rb);   // in flight during the products
+    const int nkq = min(CRM_K, mp - (sl % spt) * CRM_K) / 4;   // k-steps of this slab
+#pragma unroll
+    for (int kq = 0; kq < CRM_K / 4; ++kq) {
+      if (kq < nkq) {
+        const int kk = 4 * kq + (lane >> 4);
+        const C a = As[kk][wave * 16 + (lane & 15)];
+        C b[CRM_ST];
+#pragma unroll
+        for (int y = 0; y < CRM_ST; ++y) b[y] = Bs[kk][16 * y + (lane & 15)];
+        const float as = a.x + a.y;
+#pragma unroll
+        for (int y = 0; y < CRM_ST; ++y) {
+          p1[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[y].x, p1[y], 0, 0, 0);
+          p2[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[y].y, p2[y], 0, 0, 0);
+          p3[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b[y].x + b[y].y, p3[y], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // tile to LDS as [source][row], then column-contiguous updates
+#pragma unroll
+  for (int y = 0; y < CRM_ST; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Out[16 * y + (lane & 15)][wave * 16 + 4 * (lane >> 4) + r] =
+          make_float2(p1[y][r] - p2[y][r], p3[y][r] - p1[y][r] - p2[y][r]);
+  __syncthreads();
+  constexpr int NE = CRM_S * CRM_R / 256;
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + 256 * u;
+    const int sidx = e / CRM_R, rr = e - sidx * CRM_R;
+    const int row = R0 + rr, k = s0 + sidx;
+    if (row < m && k < K) {
+      C *d = xb + ((size_t)k * nx + out) * m + row;
+      const C o = Out[sidx][rr];
+      *d = keep ? make_float2(d->x + o.x, d->y + o.y) : o;
+    }
+  }
+}
+
 // Chunk sweeps of complex64 solves on the matrix cores (columns up to 144 TPW rows).
 // Item (chunk, side, tile of SW_S = 16 sources).  Each step is the product of the m x m
 // block T_i with an m x 16 right-hand side, as v_mfma_f32_16x16x4f32 tiles: wave w owns
@@ -1585,15 +1776,16 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     HIP_TRY(kf_malloc((void **)&p->W32, sizeof(float2) * n));
   }
   // the separators' reduction blocks, sized by the separator count
-  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32})
+  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32, (void *)p->sep32})
     if (q) HIP_TRY(hipFree(q));
   p->CRL64 = p->CR64 = nullptr;
-  p->CR32 = nullptr;
+  p->CR32 = p->sep32 = nullptr;
   if (chunks > 1) {
     const size_t nsep = chunks - 1;
     HIP_TRY(kf_malloc((void **)&p->CRL64, sizeof(double2) * nsep * 4 * mm));
     HIP_TRY(kf_malloc((void **)&p->CR64, sizeof(double2) * nsep * CR_LV * 2 * mm));
     HIP_TRY(kf_malloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
+    HIP_TRY(kf_malloc((void **)&p->sep32, sizeof(float2) * nsep * p->K * m));
   }
   p->part = part;
   p->P = chunks;
@@ -1618,7 +1810,7 @@ kf_status gj_invert(const GjJob *dj, int cnt, int m_max, hipStream_t s) {
     LAUNCH_CHECK();
   }
   const int t32 = (m_max + 31) / 32;
-  hipLaunchKernelGGL(k_gj_store, dim3(t32 * t32, cnt), dim3(256), 0, s, dj);
+  hipLaunchKernelGGL((k_gj_store<GJ_NB>), dim3(t32 * t32, cnt), dim3(256), 0, s, dj);
   LAUNCH_CHECK();
   return KF_OK;
 }
@@ -1905,7 +2097,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                            fp32 ? (const void *)p->V32 : (const void *)p->V64,
                            fp32 ? (const void *)p->W32 : (const void *)p->W64,
                            fp32 ? (const void *)p->CR32 : (const void *)p->CR64,
-                           fp32 ? (void *)p->sol32 : (void *)p->sol64};
+                           fp32 ? (void *)p->sol32 : (void *)p->sol64, (void *)p->sep32};
   }
   const dim3 blk = sweep_block(m_max, SolveThreads<R, NS>::N);
   const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
@@ -1932,10 +2124,11 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   std::vector<std::pair<int, int>> seq;   // (phase, level); phase 4: 0 fwd, 1 root, 2 bwd in .second / 16
   for (int ph = 0; ph < 4; ++ph) seq.push_back({ph, 0});
   for (int lv = 0; lv < top_max; ++lv) seq.push_back({4, lv});
+  if (fp32 && top_max >= 0) seq.push_back({6, 0});   // stage g at the separators (matrix-core levels)
   if (top_max >= 0) seq.push_back({4, 16});
   for (int lv = top_max - 1; lv >= 0; --lv) seq.push_back({4, 32 + lv});
   seq.push_back({5, 0});
-  static const int ids[6] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT};
+  static const int ids[7] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT, PROF_CHAIN};
   // complex64 chunk sweeps and middles on the matrix cores where the columns fit the
   // kernel (one row tile per wave up to 144 rows, two up to 288); in a batch each problem
   // takes its own kind: sweep group 0 (one tile), 1 (two tiles), 2 (vector units)
@@ -1969,7 +2162,10 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         const double m = p->nz, L = (double)p->nx / p->P;
         // a matrix-core sweep step costs its fixed 144 TPW-row tile whatever m is
         const double mt = ph <= 2 && sg < 2 ? 144.0 * (sg + 1) : m;
-        cost[q] = ph == 0 || ph == 2 ? mt * mt * 0.5 * L : ph == 5 ? m : mt * mt;
+        cost[q] = ph == 0 || ph == 2 ? mt * mt * 0.5 * L : ph == 5 || ph == 6 ? m : mt * mt;
+        // matrix-core reduction levels: (separator, row tile, source tile) items
+        const int CT = ((p->nz + CRM_R - 1) / CRM_R) * ((p->K + CRM_S - 1) / CRM_S);
+        const int GL = fp32 ? CT : G;
         bt.first[q] = tot;
         int items = 0;
         if (ph <= 2 && sweep_group(p) != sg) items = 0;
@@ -1979,10 +2175,14 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         else if (ph == 4) {
           if (n >= 1) {
             const int top = cr_top(n);
-            if (kind == 0 && lv < top) items = (n >> (lv + 1)) * G;
-            else if (kind == 1) items = top == 0 ? G : 0;   // else taken by the last forward level
-            else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * G;
+            if (kind == 0 && lv < top) items = (n >> (lv + 1)) * GL;
+            // the root: its own launch on the matrix cores, else taken by the last
+            // forward level where there is one
+            else if (kind == 1) items = (fp32 || top == 0) ? GL : 0;
+            else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * GL;
           }
+        } else if (ph == 6) {
+          items = n * p->K;
         } else if (p->P > 1) {
           items = p->P * (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
                                : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S));
@@ -2002,7 +2202,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         const double m = prof->nz, esz = 2.0 * sizeof(R);
         int cnt = 0, terms = 0;
         if (kind == 0 && lv < top) { cnt = n >> (lv + 1); terms = 2 * cnt; }
-        else if (kind == 1 && top == 0) { cnt = 1; terms = 1; }
+        else if (kind == 1 && (top == 0 || fp32)) { cnt = 1; terms = 1; }
         else if (kind == 2 && lv < top) { cnt = ((n >> lv) + 1) / 2; terms = 3 * cnt; }
         work = esz * (terms * m * m + (double)(terms + cnt) * prof->K * m);
       }
@@ -2029,10 +2229,15 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
           break;
         case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
         case 4:
-          if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
+          if (fp32) {
+            if (kind == 0) hipLaunchKernelGGL(k_cr_mfma<0>, dim3(grid), dim3(256), 0, s, bt);
+            else if (kind == 1) hipLaunchKernelGGL(k_cr_mfma<1>, dim3(grid), dim3(256), 0, s, bt);
+            else hipLaunchKernelGGL(k_cr_mfma<2>, dim3(grid), dim3(256), 0, s, bt);
+          } else if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
           else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
           else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);
           break;
+        case 6: hipLaunchKernelGGL(k_cr_stage, dim3(1, tot), dim3(256), 0, s, bt); break;
         default:
           if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
           else hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);

@@ -97,6 +97,8 @@ struct SweepProblem {
   const void *T, *V, *W;   // factors and spikes (c128 or c64)
   const void *CR;      // separators' reduction blocks ML, MU: [n][levels][2][m][m]
   void *x;             // right-hand sides in, solutions out: column-major [K][nx][nz] (compute type)
+  void *gsep;          // the separators' reduced right-hand sides, staged before the
+                       // back-substitution: [n][K][m] (complex64 solves)
 };
 struct SweepBatch {
   int n, total, level;           // level: cyclic-reduction level of the launch
@@ -168,6 +170,7 @@ struct kf_problem {
   double2 *CRL64 = nullptr;                    // separators' L, U during the reduction [n][4][m][m]
   double2 *CR64 = nullptr;                     // separators' ML, MU [n][levels][2][m][m]
   float2 *CR32 = nullptr;
+  float2 *sep32 = nullptr;                     // separators' right-hand sides staged by a solve [n][K][m]
   void *fac_jobs = nullptr;                    // device job tables of the factorisation
   size_t fac_jobs_cap = 0;                     // bytes
   double2 *sol64 = nullptr;                    // [K][nx][nz] column-major solve copy (c128)
