@@ -384,110 +384,156 @@ __global__ __launch_bounds__(256) void k_schur(FactorBatch bt, const SchurJob *j
   }
 }
 
-// Spike of chunk ch for the right-hand-side columns s0 .. s0+NSP-1:
+// Spike of chunk ch for the right-hand-side columns s0 .. s0+SP_N-1:
 //   which 0: V = A_c^-1 E_a C_a     (unit coupling weights at column a)
 //   which 1: W = A_c^-1 E_b C_{b+1} (at column b)
 // by the chunk's twisted solve: forward from the loaded end to mid, the middle
 // column, then back-substitution on both sides (the unloaded side's forward values
 // are zero).  Out[i] holds the m x m block of column i, transposed like T.
-template <int NSP>
+// Each step is T_i times an m x SP_N block (SP_N = 16 columns of the spike): thread
+// (row pair, half) owns rows 2 rp, 2 rp + 1 and columns 8 h .. 8 h + 7, so every element
+// of T_i it reads feeds eight complex products and every LDS value two; a chunk's T_i
+// are read m / 16 times per spike (from L2).  The step's right-hand side sits in LDS as
+// [row][column]; the previous step's values are the thread's accumulators.
+constexpr int SP_N = 16, SP_H = 8, SP_U = 4;
+__host__ __device__ inline int spike_pairs_padded(int m) { return ((m + 1) / 2 + 63) / 64 * 64; }
+
+__device__ __forceinline__ void spike_matvec(const double2 *__restrict__ Tt, int m, const double2 *w, int r0, int r1,
+                                             int h, double2 (&acc)[2][SP_H]) {
+#pragma unroll
+  for (int s = 0; s < SP_H; ++s) acc[0][s] = acc[1][s] = make_double2(0.0, 0.0);
+  const int r0c = min(r0, m - 1), r1c = min(r1, m - 1);
+  for (int lb = 0; lb < m; lb += SP_U) {
+    double2 ta[SP_U], tb[SP_U];
+#pragma unroll
+    for (int u = 0; u < SP_U; ++u) {
+      const size_t row = (size_t)min(lb + u, m - 1) * m;
+      ta[u] = Tt[row + r0c];
+      tb[u] = Tt[row + r1c];
+    }
+#pragma unroll
+    for (int u = 0; u < SP_U; ++u)
+      if (lb + u < m) {
+        const double2 *wl = w + (size_t)(lb + u) * SP_N + SP_H * h;
+#pragma unroll
+        for (int s = 0; s < SP_H; ++s) {
+          const double2 wv = wl[s];
+          cfma(acc[0][s], ta[u], wv);
+          cfma(acc[1][s], tb[u], wv);
+        }
+      }
+  }
+}
+
 __device__ __forceinline__ void spike_body(const Grid &g, Chunk ch, int which, int s0, const double2 *__restrict__ T,
-                                           double2 *Out, unsigned char *smem) {
+                                           double2 *Out, double2 *w /* LDS [m][SP_N] */) {
   using C = double2;
   const int m = g.nz;
   const size_t mm = (size_t)m * m;
-  C *w = (C *)smem;          // [NSP][m]
-  C *part = w + NSP * m;     // [G-1][NSP][m]
-  const int j = threadIdx.x;
-  const bool owner = threadIdx.y == 0 && j < m;
+  // a batch launches the threads of its tallest grid: here threads past 2 RP (h > 1)
+  // only take part in the barriers (their rows are out of range)
+  const int RP = spike_pairs_padded(m);
+  const int hh = threadIdx.x / RP, h = min(hh, 1), rp = hh > 1 ? m : threadIdx.x - hh * RP;
+  const int rr[2] = {2 * rp, 2 * rp + 1};
   const int ecol = which == 0 ? ch.a : ch.b + 1;   // coupling column of the unit right-hand side
   const int rcol = which == 0 ? ch.a : ch.b;       // column it sits in
-  C rhs[NSP], cur[NSP], xm[NSP];
+  C cur[2][SP_H];
 #pragma unroll
-  for (int t = 0; t < NSP; ++t) {
-    rhs[t] = (owner && j == s0 + t) ? coupling_x(g, ecol, j) : make_double2(0.0, 0.0);
-    cur[t] = make_double2(0.0, 0.0);
-  }
-  auto store = [&](int i, int t, C v) {
-    if (owner && s0 + t < m) Out[(size_t)i * mm + (size_t)(s0 + t) * m + j] = v;
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < SP_H; ++t) cur[a][t] = make_double2(0.0, 0.0);
+  // column s = s0 + 8 h + t of the unit right-hand side: the coupling weight at row s
+  auto rhs = [&](int a, int t) {
+    const int col = s0 + SP_H * h + t;
+    return rr[a] == col && rr[a] < m ? coupling_x(g, ecol, rr[a]) : make_double2(0.0, 0.0);
+  };
+  auto put = [&](int a, int t, C v) { w[(size_t)rr[a] * SP_N + SP_H * h + t] = v; };
+  auto store = [&](int i, C (&v)[2][SP_H]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+      if (rr[a] < m)
+#pragma unroll
+        for (int t = 0; t < SP_H; ++t) {
+          const int col = s0 + SP_H * h + t;
+          if (col < m) Out[(size_t)i * mm + (size_t)col * m + rr[a]] = v[a][t];
+        }
+  };
+  auto load = [&](int i, C (&v)[2][SP_H]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int t = 0; t < SP_H; ++t) {
+        const int col = s0 + SP_H * h + t;
+        v[a][t] = rr[a] < m && col < m ? Out[(size_t)i * mm + (size_t)col * m + rr[a]] : make_double2(0.0, 0.0);
+      }
   };
   // forward sweep from the loaded end
   const int fcnt = which == 0 ? ch.mid - ch.a : ch.b - ch.mid;
   for (int step = 0; step < fcnt; ++step) {
     const int i = which == 0 ? ch.a + step : ch.b - step;
     const int cc = which == 0 ? i : i + 1;
-    if (owner) {
-      const C cj = coupling_x(g, cc, j);
 #pragma unroll
-      for (int t = 0; t < NSP; ++t) w[t * m + j] = step == 0 ? rhs[t] : csub(make_double2(0.0, 0.0), cmul(cj, cur[t]));
-    }
+    for (int a = 0; a < 2; ++a)
+      if (rr[a] < m) {
+        const C cj = coupling_x(g, cc, rr[a]);
+#pragma unroll
+        for (int t = 0; t < SP_H; ++t) put(a, t, step == 0 ? rhs(a, t) : csub(make_double2(0.0, 0.0), cmul(cj, cur[a][t])));
+      }
     __syncthreads();
-    C acc[NSP];
-    col_matvec<double, NSP, 16>(T + (size_t)i * mm, m, w, part, acc);
-#pragma unroll
-    for (int t = 0; t < NSP; ++t) {
-      cur[t] = acc[t];
-      store(i, t, acc[t]);
-    }
+    spike_matvec(T + (size_t)i * mm, m, w, rr[0], rr[1], h, cur);
+    store(i, cur);
     __syncthreads();
   }
   // middle column
-  if (owner) {
+  {
     const int cc = which == 0 ? ch.mid : ch.mid + 1;
-    const C cj = fcnt > 0 ? coupling_x(g, cc, j) : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int t = 0; t < NSP; ++t) {
-      C r = rcol == ch.mid ? rhs[t] : make_double2(0.0, 0.0);
-      if (fcnt > 0) r = csub(r, cmul(cj, cur[t]));
-      w[t * m + j] = r;
-    }
+    for (int a = 0; a < 2; ++a)
+      if (rr[a] < m) {
+        const C cj = fcnt > 0 ? coupling_x(g, cc, rr[a]) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < SP_H; ++t) {
+          C r = rcol == ch.mid ? rhs(a, t) : make_double2(0.0, 0.0);
+          if (fcnt > 0) r = csub(r, cmul(cj, cur[a][t]));
+          put(a, t, r);
+        }
+      }
   }
   __syncthreads();
-  {
-    C acc[NSP];
-    col_matvec<double, NSP, 16>(T + (size_t)ch.mid * mm, m, w, part, acc);
-#pragma unroll
-    for (int t = 0; t < NSP; ++t) {
-      xm[t] = acc[t];
-      store(ch.mid, t, acc[t]);
-    }
-  }
+  spike_matvec(T + (size_t)ch.mid * mm, m, w, rr[0], rr[1], h, cur);
+  store(ch.mid, cur);
   __syncthreads();
   // back-substitution outward: x_i = y_i - T_i C x_prev (y_i = 0 on the unloaded side)
   for (int side = 0; side < 2; ++side) {
     const bool loaded = (side == 0) == (which == 0);
     const int cnt = side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
-#pragma unroll
-    for (int t = 0; t < NSP; ++t) cur[t] = xm[t];
+    if (side == 1) load(ch.mid, cur);   // the middle values (written by this thread)
     for (int step = 0; step < cnt; ++step) {
       const int i = side == 0 ? ch.mid - 1 - step : ch.mid + 1 + step;
       const int cc = side == 0 ? i + 1 : i;
-      C y[NSP];
-      if (owner) {
-        const C cj = coupling_x(g, cc, j);
 #pragma unroll
-        for (int t = 0; t < NSP; ++t) {
-          w[t * m + j] = cmul(cj, cur[t]);
-          y[t] = (loaded && s0 + t < m) ? Out[(size_t)i * mm + (size_t)(s0 + t) * m + j] : make_double2(0.0, 0.0);
+      for (int a = 0; a < 2; ++a)
+        if (rr[a] < m) {
+          const C cj = coupling_x(g, cc, rr[a]);
+#pragma unroll
+          for (int t = 0; t < SP_H; ++t) put(a, t, cmul(cj, cur[a][t]));
         }
-      }
       __syncthreads();
-      C acc[NSP];
-      col_matvec<double, NSP, 16>(T + (size_t)i * mm, m, w, part, acc);
-      if (owner)
+      C y[2][SP_H];
+      if (loaded) load(i, y);
+      spike_matvec(T + (size_t)i * mm, m, w, rr[0], rr[1], h, cur);
 #pragma unroll
-        for (int t = 0; t < NSP; ++t) {
-          cur[t] = csub(y[t], acc[t]);
-          store(i, t, cur[t]);
-        }
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < SP_H; ++t) cur[a][t] = csub(loaded ? y[a][t] : make_double2(0.0, 0.0), cur[a][t]);
+      store(i, cur);
       __syncthreads();
     }
   }
 }
 
-// item = (spike job, column group); jobs 0..P-2: W of chunks 0..P-2, then V of
+// item = (spike job, tile of SP_N columns); jobs 0..P-2: W of chunks 0..P-2, then V of
 // chunks 1..P-1.
-template <int NSP>
 __global__ __launch_bounds__(512) void k_spikes(FactorBatch bt) {
   extern __shared__ unsigned char smem[];
   const int item = item_of_block(bt.xs);
@@ -495,11 +541,11 @@ __global__ __launch_bounds__(512) void k_spikes(FactorBatch bt) {
   const int q = find_problem(bt.first, bt.n, item);
   const FactorProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
-  const int gm = (pp.g.nz + NSP - 1) / NSP;
+  const int gm = (pp.g.nz + SP_N - 1) / SP_N;
   const int job = local / gm, grp = local - job * gm;
   const int which = job < pp.P - 1 ? 1 : 0;
   const int c = which == 1 ? job : job - (pp.P - 1) + 1;
-  spike_body<NSP>(pp.g, chunk_of(pp.part, c), which, grp * NSP, pp.T, which == 0 ? pp.V : pp.W, smem);
+  spike_body(pp.g, chunk_of(pp.part, c), which, grp * SP_N, pp.T, which == 0 ? pp.V : pp.W, (double2 *)smem);
 }
 
 // ---- the separators' system by block cyclic reduction ----
@@ -2000,23 +2046,20 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
     if (st != KF_OK) return st;
   }
   // 5. spikes
-  constexpr int NSP = 2;
   double cost[KF_BATCH_MAX];
-  int tot = 0, pmax = 1;
+  int tot = 0;
   for (int q = 0; q < bt.n; ++q) {
     const double m = ps[q]->nz, L = (double)ps[q]->nx / ps[q]->P;
     bt.first[q] = tot;
-    tot += 2 * (ps[q]->P - 1) * ((ps[q]->nz + NSP - 1) / NSP);
-    pmax = std::max(pmax, ps[q]->P);
+    tot += 2 * (ps[q]->P - 1) * ((ps[q]->nz + SP_N - 1) / SP_N);
     cost[q] = m * m * 1.5 * L;
   }
   bt.first[bt.n] = bt.total = tot;
   if (tot == 0) return KF_OK;   // one chunk: no separators
   const unsigned grid_sp = xcd_split(bt.first, bt.n, cost, bt.xs);
-  const dim3 blk = sweep_block(m_max);
-  const size_t smem_sp = (1 + (blk.y - 1)) * NSP * (size_t)m_max * sizeof(double2);
-  HIP_TRY(hipFuncSetAttribute((const void *)k_spikes<NSP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
-  hipLaunchKernelGGL((k_spikes<NSP>), dim3(grid_sp), blk, smem_sp, s, bt);
+  const size_t smem_sp = (size_t)m_max * SP_N * sizeof(double2);
+  HIP_TRY(hipFuncSetAttribute((const void *)k_spikes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
+  hipLaunchKernelGGL(k_spikes, dim3(grid_sp), dim3(2 * spike_pairs_padded(m_max)), smem_sp, s, bt);
   LAUNCH_CHECK();
   // 6. the separators' system by block cyclic reduction
   if (ntot == 0) return KF_OK;
