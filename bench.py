@@ -185,10 +185,12 @@ def roofline_for(name, p, launches, total_ms, lib_work=None):
     return out
 
 
-def measured_traffic(name, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None for a
-    workload the counters were not taken on, or once the kernel sources differ from
-    the build the counters were taken on."""
+def measured_traffic(name, workload, work_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (FETCH_SIZE and
+    WRITE_SIZE, scaled by what the same counters read for a 1 GiB copy): their ratio to
+    the algorithmic bytes of the same launches, times this run's algorithmic bytes per
+    launch.  None for a workload the counters were not taken on, or once the kernel
+    sources differ from the build the counters were taken on."""
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -201,9 +203,9 @@ def measured_traffic(name, workload):
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2204_06489_amd", "csrc", "*"))):
         h.update(open(f, "rb").read())
     k = tab.get("kernels", {}).get(name)
-    if k is None or h.hexdigest()[:16] != tab.get("source_sha"):
+    if k is None or h.hexdigest()[:16] != tab.get("source_sha") or not work_per_launch:
         return None
-    return k["fetch_bytes"] + k["write_bytes"]
+    return k["ratio"] * work_per_launch
 
 
 def observed_data(inp, torch, KKTProblem):
@@ -659,7 +661,7 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     workload = f"{args.config}/{inp['nx']}x{inp['nz']}/K{inp['K']}/{inp['freq']:g}Hz/{args.pc}/{args.fwd_prec}"
     roof = roofline_for(dominant, p, *dom, dom_work)
-    roof["traffic"] = measured_traffic(dominant, workload)
+    roof["traffic"] = measured_traffic(dominant, workload, roof.get("work_per_launch"))
     roof["events"] = "HIP events around this family's launches only, over the timed steps"
     per_kernel = None
     if warm:
