@@ -73,9 +73,23 @@ def parse():
                     help="CHUNKS,SOURCES_PER_GROUP: set the block solver's shape instead of autotuning "
                          "(profiling runs: keeps the tuner's factorisations out of the trace)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--log-jsonl", default=None, metavar="PATH",
+                    help="append one JSON line per Newton step (warm-up and timed): iterations, the FGMRES "
+                         "residual history, misfits, ||Im ds||/||ds|| and the time breakdown")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def log_steps(args, workload, phase, stats):
+    """The per-step metrics log (JSON lines)."""
+    if not args.log_jsonl:
+        return
+    with open(args.log_jsonl, "a") as f:
+        for k, st in enumerate(stats):
+            rec = {"workload": workload, "phase": phase, "step": k}
+            rec.update({key: (float(v) if isinstance(v, float) else v) for key, v in st.items()})
+            f.write(json.dumps(rec) + "\n")
 
 
 def log(args, *a):
@@ -124,7 +138,8 @@ def kernel_work(name, p):
             red += sum(2 + (k - 2 * st >= 1) + 2 * (k + st <= n) + (k + 2 * st <= n) for k in range(2 * st, n + 1, 2 * st))
             st *= 2
         return 8.0 * m ** 3 * (inv + spike + red), "flops", "f64"
-    dt = "f32" if name.endswith("c64") or name == "blu_correct" else "f64"
+    inner32 = getattr(p, "inner_fp32", False)   # the step's block solves run in complex64
+    dt = "f32" if name.endswith("c64") or (name == "blu_correct" and inner32) else "f64"
     if name.startswith("blu_fwd") or name.startswith("blu_bwd"):
         # a dense m x m complex matvec per column and source: every chunk column but the middle
         cols = sum(b - a for a, b, mid in part)
@@ -135,7 +150,7 @@ def kernel_work(name, p):
         return 8.0 * m * m * blocks * K, "flops", dt
     if name == "blu_mid":
         # the meeting column of every chunk: one m x m complex matvec per source
-        return 8.0 * m * m * P * K, "flops", "f32" if getattr(p, "inner_fp32", False) else "f64"
+        return 8.0 * m * m * P * K, "flops", "f32" if inner32 else "f64"
     raise KeyError(name)
 
 
@@ -151,7 +166,8 @@ FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stag
 KERNEL_NAMES = {
     "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial<8|16, true> (+ k_finish)",
     "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
-    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_mfma", "blu_chain": "k_cr_solve",
+    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_mfma (complex64) / k_correct<double>",
+    "blu_chain": "k_cr_mfma<*> (complex64) / k_cr_solve<double,*,*>",
     "blu_mid": "k_sweep_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
     "blu_fwd_c128": "k_solve<double,*,0>", "blu_bwd_c128": "k_solve<double,*,2>",
 }
@@ -176,8 +192,8 @@ def roofline_for(name, p, launches, total_ms, lib_work=None):
         # complex64 sweeps and the interior correction run on the matrix cores (dense
         # FP32 MFMA peak); the FP64 sweeps on the vector units (FP64 vector peak)
         # (the matrix-core sweeps take columns of up to 288 rows)
-        bound = ("mfma" if name == "blu_correct" or (name in MFMA_KERNELS + ("blu_mid",) and dt == "f32" and p.nz <= 288)
-                 else "alu")
+        bound = ("mfma" if (name == "blu_correct" and dt == "f32")
+                 or (name in MFMA_KERNELS + ("blu_mid",) and dt == "f32" and p.nz <= 288) else "alu")
         out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     out.update({"frac": achieved / peak, "traffic": None, "kernel": KERNEL_NAMES.get(name, name), "family": name,
                 "launches": launches, "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount,
@@ -625,11 +641,13 @@ def main():
     # total time.  The timed steps then record that family only, so the other families'
     # events (thousands per step) do not weigh on the timed region.
     warm = None
+    warm_stats = []
     for w in range(args.warmup):
         last = w == args.warmup - 1
         if last:
             p.profile_enable(True)
         _, _, st = p.newton_step(d, **opts)
+        warm_stats.append(st)
         if last:
             warm = {f: p.profile_read(f) for f in FAMILIES}
             warm_work = {f: p.profile_work(f) for f in LIB_COUNTED}
@@ -660,6 +678,8 @@ def main():
                   f"mv={st['t_matvec_ms']:.1f} orth={st['t_orth_ms']:.1f} misfit={st['misfit_before']:.4f}")
     ms_per_step = elapsed / args.steps * 1e3
     workload = f"{args.config}/{inp['nx']}x{inp['nz']}/K{inp['K']}/{inp['freq']:g}Hz/{args.pc}/{args.fwd_prec}"
+    log_steps(args, workload, "warmup", warm_stats)
+    log_steps(args, workload, "timed", stats)
     roof = roofline_for(dominant, p, *dom, dom_work)
     roof["traffic"] = measured_traffic(dominant, workload, roof.get("work_per_launch"))
     roof["events"] = "HIP events around this family's launches only, over the timed steps"
