@@ -147,6 +147,11 @@ def kernel_work(name, p):
     if name == "blu_correct":
         # V_i and / or W_i (m x m) times the separator values, every interior column and source
         blocks = sum((b - a + 1) * ((1 if c > 0 else 0) + (1 if c < P - 1 else 0)) for c, (a, b, mid) in enumerate(part))
+        if inner32:
+            # complex64 solves: the spikes as FP16 pairs (8 bytes per complex entry) read
+            # once, the interior values read and written (complex64): bound by HBM
+            rows = sum(b - a + 1 for a, b, mid in part) * m
+            return 8.0 * m * m * blocks + 16.0 * rows * K, "bytes", dt
         return 8.0 * m * m * blocks * K, "flops", dt
     if name == "blu_mid":
         # the meeting column of every chunk: one m x m complex matvec per source
@@ -166,7 +171,7 @@ FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stag
 KERNEL_NAMES = {
     "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial<8|16, true> (+ k_finish)",
     "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
-    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_mfma (complex64) / k_correct<double>",
+    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_h (complex64, FP16-pair MFMA) / k_correct<double>",
     "blu_chain": "k_cr_mfma<*> (complex64) / k_cr_solve<double,*,*>",
     "blu_mid": "k_sweep_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
     "blu_fwd_c128": "k_solve<double,*,0>", "blu_bwd_c128": "k_solve<double,*,2>",

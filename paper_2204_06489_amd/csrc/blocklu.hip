@@ -90,14 +90,21 @@ __device__ __forceinline__ bool gj_better(double ob, int oi, double best, int bi
 struct GjPanel {
   int r, m, k0, nw, lane, wave;
   bool row;
-  double2 *rowbuf;   // LDS [2][NB]: the pivot row, the old row k
-  double *cbest;     // LDS [8]: per-wavefront candidates
+  double2 *cand;     // LDS [2][8][NB]: each wavefront's candidate pivot row, by step parity
+  double2 *rowk;     // LDS [2][NB]: row k before the step
+  double *cbest;     // LDS [2][8]: each wavefront's candidate modulus and row
   int *cidx;
   int *lperm;        // LDS [m]: the panel's row permutation
 };
 
+// One barrier per step: every wavefront publishes its best row (and row k its values)
+// before it, so that afterwards each thread finds the pivot row in LDS by itself.
+// The LDS areas alternate with the step's parity: a thread still reading step Q's
+// areas cannot meet step Q + 1's writes, and step Q + 2's writes wait for the barrier
+// of step Q + 1, which every thread reaches only after its reads of step Q.
 template <int NB, int Q>
 __device__ __forceinline__ void gj_pivot(const GjPanel &P, double2 (&acc)[NB]) {
+  constexpr int PAR = Q & 1;
   const int k = P.k0 + Q;
   double best = -1.0;
   int bi = P.m;
@@ -111,40 +118,48 @@ __device__ __forceinline__ void gj_pivot(const GjPanel &P, double2 (&acc)[NB]) {
     const int oi = __shfl_xor(bi, o, 64);
     if (gj_better(ob, oi, best, bi)) { best = ob; bi = oi; }
   }
-  if (P.lane == 0) { P.cbest[P.wave] = best; P.cidx[P.wave] = bi; }
+  double2 *cand = P.cand + PAR * 8 * NB, *rowk = P.rowk + PAR * NB;
+  if (P.lane == 0) { P.cbest[PAR * 8 + P.wave] = best; P.cidx[PAR * 8 + P.wave] = bi; }
+  if (P.row && P.r == bi)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) cand[P.wave * NB + c] = acc[c];
+  if (P.r == k)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) rowk[c] = acc[c];
   __syncthreads();
-  best = P.cbest[0];
-  bi = P.cidx[0];
-  for (int w = 1; w < P.nw; ++w)
-    if (gj_better(P.cbest[w], P.cidx[w], best, bi)) { best = P.cbest[w]; bi = P.cidx[w]; }
+  double cb[8];
+  int ci[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w)
+    if (w < P.nw) { cb[w] = P.cbest[PAR * 8 + w]; ci[w] = P.cidx[PAR * 8 + w]; }
+  int win = 0;
+  best = cb[0];
+  bi = ci[0];
+#pragma unroll
+  for (int w = 1; w < 8; ++w)
+    if (w < P.nw && gj_better(cb[w], ci[w], best, bi)) { best = cb[w]; bi = ci[w]; win = w; }
   // a column with no finite entry leaves bi = m: no interchange, every index stays in
   // range (the factors then carry the NaNs and the solves report them)
   const int pr = bi < P.m ? bi : k;
-  if (P.r == pr)
-#pragma unroll
-    for (int c = 0; c < NB; ++c) P.rowbuf[c] = acc[c];
-  if (P.r == k)
-#pragma unroll
-    for (int c = 0; c < NB; ++c) P.rowbuf[NB + c] = acc[c];
+  const double2 *prow = bi < P.m ? cand + win * NB : rowk;
   if (P.r == 0) {
     const int tmp = P.lperm[k];
     P.lperm[k] = P.lperm[pr];
     P.lperm[pr] = tmp;
   }
-  __syncthreads();
   // the new row k is the old row pr, scaled; the pivot entry becomes 1 / pivot
-  const double2 d = cdiv(make_double2(1.0, 0.0), P.rowbuf[Q]);
+  const double2 d = cdiv(make_double2(1.0, 0.0), prow[Q]);
   if (P.r == k) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) acc[c] = (c == Q) ? d : cmul(P.rowbuf[c], d);
+    for (int c = 0; c < NB; ++c) acc[c] = (c == Q) ? d : cmul(prow[c], d);
   } else if (P.row) {
     if (P.r == pr)   // the old row k moves to pr, then is eliminated like every other row
 #pragma unroll
-      for (int c = 0; c < NB; ++c) acc[c] = P.rowbuf[NB + c];
+      for (int c = 0; c < NB; ++c) acc[c] = rowk[c];
     const double2 f = acc[Q];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      const double2 pc = (c == Q) ? d : cmul(P.rowbuf[c], d);
+      const double2 pc = (c == Q) ? d : cmul(prow[c], d);
       acc[c] = csub(c == Q ? make_double2(0.0, 0.0) : acc[c], cmul(f, pc));
     }
   }
@@ -172,9 +187,9 @@ __global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
   const bool fac = b == t;               // this block is the next panel
   if (b >= npan || !(fac || (pp >= 0 && pp < npan && b != pp))) return;   // uniform
   __shared__ double2 x1[NB][NB];
-  __shared__ double2 rowbuf[2][NB];
-  __shared__ double cbest[8];
-  __shared__ int cidx[8];
+  __shared__ double2 cand[2][8][NB], rowk[2][NB];
+  __shared__ double cbest[2][8];
+  __shared__ int cidx[2][8];
   __shared__ int lperm[512];
   int *perm = (int *)(J.S + (size_t)m * m), *sig = perm + 2 * m;
   const int r = threadIdx.x, nt = blockDim.x;
@@ -219,7 +234,8 @@ __global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
   }
   // elimination of panel t (this block)
   for (int e = r; e < m; e += nt) lperm[e] = e;
-  const GjPanel P{r, m, cb0, (nt + 63) >> 6, r & 63, r >> 6, row, &rowbuf[0][0], cbest, cidx, lperm};
+  const GjPanel P{r, m, cb0, (nt + 63) >> 6, r & 63, r >> 6, row, &cand[0][0][0], &rowk[0][0], &cbest[0][0], &cidx[0][0],
+                  lperm};
   GjPivots<NB, 0>::run(P, ncol, acc);
   __syncthreads();   // lperm complete
   if (row)
@@ -1099,130 +1115,258 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
   }
 }
 
-// The same product on the matrix cores (complex64 solves): a workgroup computes a
-// 128 x 48 tile (rows x sources), each of its four wavefronts a 32 x 48 block as 2 x 3
-// tiles of v_mfma_f32_16x16x4f32, a complex product being three real ones (Gauss:
-// P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); Re = P1 - P2, Im = P3 - P1 - P2).  Operand lanes: A[i][k] in lane
-// i + 16 k, B[k][j] in lane j + 16 k; result D[i][j] in lane j + 16 (i / 4), element
-// i mod 4.  Up to 48 sources share one pass over V and W; k in slabs of 16 through
-// LDS with the next slab prefetched into registers; the tile goes back through LDS
-// so the updates of the column-major copy are coalesced.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-constexpr int CM_R = 128, CM_S = 48, CM_K = 16;
-__global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
+
+// The interior correction of complex64 solves with FP16 operands on the matrix cores.
+// Each FP32 operand value v is scaled by a power of two and held as two FP16 numbers,
+// hi = fp16(v') and lo = fp16(v' - hi), which carry 22 significant bits; a product is
+// hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo lo term is below 2^-22 of it), three
+// v_mfma_f32_16x16x32_f16 with FP32 accumulation, each eight times the k-depth of the
+// FP32 instruction at half its cycles.  So the product keeps FP32-class accuracy
+// while the matrix cores do a quarter of the work of the FP32 form, and the kernel is
+// bound by reading the spikes (as many bytes as their complex64 copy).
+// Scales: the spikes of interior column i (V_i and W_i together) by 2^e_i, the
+// separator values of chunk c and source k (both separators together) by 2^f_ck, each
+// bringing the largest modulus into [2^14, 2^15) so that hi stays finite and lo normal
+// for all but the smallest entries; the result is scaled back by 2^-(e_i + f_ck).
+// Planes (uint16 storage of FP16): [hi re, hi im, lo re, lo im][column][row j][k], k
+// running over V_i's columns (0..m-1) then W_i's (mk..mk+m-1), zero-padded to mk =
+// m rounded up to 32.
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+constexpr int CH_R = 128, CH_S = 48, CH_K = 32;
+
+__device__ __forceinline__ int scale_exponent(float mx) {
+  return mx > 0.f && mx <= 3.0e38f ? 14 - ilogbf(mx) : 0;
+}
+
+// chunk of column i (-1 for separator columns) and whether it has a left / right separator
+__device__ __forceinline__ int interior_chunk(const int *part, int P, int i, bool &hl, bool &hr) {
+  for (int c = 0; c < P; ++c)
+    if (i >= part[3 * c] && i <= part[3 * c + 1]) {
+      hl = c > 0;
+      hr = c < P - 1;
+      return c;
+    }
+  return -1;
+}
+
+// e_i for every column (block i): the largest |re|, |im| over V_i (with a left
+// separator) and W_i (with a right one)
+__global__ __launch_bounds__(256) void k_spike_exponents(Grid g, int P, const int *part, const float2 *V,
+                                                         const float2 *W, int *vwe) {
+  const int i = blockIdx.x, m = g.nz;
+  const size_t mm = (size_t)m * m;
+  bool hl = false, hr = false;
+  const int c = interior_chunk(part, P, i, hl, hr);
+  float mx = 0.f;
+  if (c >= 0)
+    for (size_t e = threadIdx.x; e < mm; e += 256) {
+      if (hl) { const float2 v = V[(size_t)i * mm + e]; mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y))); }
+      if (hr) { const float2 v = W[(size_t)i * mm + e]; mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y))); }
+    }
+  __shared__ float red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) vwe[i] = c >= 0 ? scale_exponent(red[0]) : 0;
+}
+
+// the planes of interior column blockIdx.y, a 32 x 32 tile (rows j, k) per workgroup
+__global__ __launch_bounds__(256) void k_spike_split(Grid g, int P, const int *part, const float2 *V, const float2 *W,
+                                                     const int *vwe, int k2, uint16_t *vwh) {
+  const int i = blockIdx.y, m = g.nz, mk = k2 / 2;
+  const size_t mm = (size_t)m * m;
+  bool hl = false, hr = false;
+  if (interior_chunk(part, P, i, hl, hr) < 0) return;
+  const int jt = (m + 31) / 32;
+  const int j0 = (blockIdx.x % jt) * 32, k0 = (blockIdx.x / jt) * 32;
+  __shared__ float2 tile[32][33];
+  const int lo = threadIdx.x & 31, hi = threadIdx.x >> 5;
+  const int e = vwe[i];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {   // read with lanes along j (column-major blocks)
+    const int k = k0 + hi + 8 * p, j = j0 + lo;
+    float2 v = make_float2(0.f, 0.f);
+    if (j < m) {
+      if (k < mk) { if (hl && k < m) v = V[(size_t)i * mm + (size_t)k * m + j]; }
+      else if (hr && k - mk < m) v = W[(size_t)i * mm + (size_t)(k - mk) * m + j];
+    }
+    tile[hi + 8 * p][lo] = make_float2(ldexpf(v.x, e), ldexpf(v.y, e));
+  }
+  __syncthreads();
+  const size_t plane = (size_t)g.nx * m * k2;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {   // write with lanes along k
+    const int j = j0 + hi + 8 * p, k = k0 + lo;
+    if (j >= m || k >= k2) continue;
+    const float2 v = tile[lo][hi + 8 * p];
+    const _Float16 hr_ = (_Float16)v.x, hi_ = (_Float16)v.y;
+    const _Float16 lr = (_Float16)(v.x - (float)hr_), li = (_Float16)(v.y - (float)hi_);
+    const size_t o = ((size_t)i * m + j) * k2 + k;
+    vwh[o] = __builtin_bit_cast(uint16_t, hr_);
+    vwh[plane + o] = __builtin_bit_cast(uint16_t, hi_);
+    vwh[2 * plane + o] = __builtin_bit_cast(uint16_t, lr);
+    vwh[3 * plane + o] = __builtin_bit_cast(uint16_t, li);
+  }
+}
+
+// f_ck for every chunk c and source k of a solve: grid (K, P) of one batch problem
+__global__ __launch_bounds__(256) void k_corr_exponents(SweepBatch bt) {
+  const int q = find_problem(bt.first, bt.n, blockIdx.y);
+  const SweepProblem &pp = bt.p[q];
+  const int c = blockIdx.y - bt.first[q], k = blockIdx.x;
+  if (k >= pp.K || pp.P < 2) return;
+  const Chunk ch = chunk_of(pp.part, c);
+  const int m = pp.g.nz;
+  float mx = 0.f;
+  for (int l = threadIdx.x; l < m; l += 256) {
+    if (c > 0) { const float2 v = colp<float>(pp.x, pp.g, k, ch.a - 1)[l]; mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y))); }
+    if (c < pp.P - 1) { const float2 v = colp<float>(pp.x, pp.g, k, ch.b + 1)[l]; mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y))); }
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pp.corr_e[c * pp.K + k] = scale_exponent(red[0]);
+}
+
+// X_I -= [V | W] [x_{s_left}; x_{s_right}] per chunk: a 128 x 48 tile (rows x sources)
+// per workgroup, each wavefront 32 rows (two 16-row tiles) x 3 source tiles; k in steps
+// of 32: the separator values split into FP16 planes in LDS ([plane][source][k]), the
+// spike planes read by each lane straight from memory (eight consecutive k of its row).
+// Operand layout of v_mfma_f32_16x16x32_f16: A[i][k] in lane i + 16 (k / 8), element
+// k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D[i][j] in lane j + 16 (i / 4),
+// element i % 4.  Products: re re and im im into their own sums (Re = rr - ii), the
+// two cross products into a third (Im).  item = (chunk, row tile, source tile).
+__global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
   using C = float2;
-  // the operand slabs and the output tile share one LDS buffer (the tile is written
-  // after the last slab is consumed)
-  constexpr int SLAB = CM_K * (CM_R + 2) + CM_K * (CM_S + 2), TILE = CM_S * (CM_R + 1);
-  __shared__ C lds[SLAB > TILE ? SLAB : TILE];
-  C(*As)[CM_R + 2] = (C(*)[CM_R + 2])lds;
-  C(*Bs)[CM_S + 2] = (C(*)[CM_S + 2])(lds + CM_K * (CM_R + 2));
-  C(*Out)[CM_R + 1] = (C(*)[CM_R + 1])lds;
+  constexpr int BK = CH_K + 8;   // LDS row of one source's k values (16-byte aligned)
+  constexpr int BSZ = 4 * CH_S * BK * 2, OSZ = CH_S * (CH_R + 1) * 8;
+  __shared__ __align__(16) unsigned char lds[BSZ > OSZ ? BSZ : OSZ];
+  _Float16 *Bs = (_Float16 *)lds;                    // [4][CH_S][BK]
+  C(*Out)[CH_R + 1] = (C(*)[CH_R + 1])lds;
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
   const SweepProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
-  const int stiles = (pp.K + CM_S - 1) / CM_S;
-  const int rtiles = (pp.lmax * pp.g.nz + CM_R - 1) / CM_R;
+  const int K = pp.K, m = pp.g.nz, nx = pp.g.nx, k2 = pp.k2, mk = k2 / 2;
+  const int stiles = (K + CH_S - 1) / CH_S;
+  const int rtiles = (pp.lmax * m + CH_R - 1) / CH_R;
   const int st = local % stiles, rest = local / stiles;
   const int c = rest / rtiles, rt = rest % rtiles;
   const Chunk ch = chunk_of(pp.part, c);
-  const Grid &g = pp.g;
-  const int m = g.nz, K = pp.K;
   const int rows = (ch.b - ch.a + 1) * m;
-  const int R0 = rt * CM_R;
+  const int R0 = rt * CH_R;
   if (R0 >= rows) return;   // uniform over the workgroup
-  const size_t mm = (size_t)m * m;
   const bool hl = c > 0, hr = c < pp.P - 1;
-  const int lk0 = hl ? 0 : m, lk1 = hr ? 2 * m : m;
-  const C *V = (const C *)pp.V, *W = (const C *)pp.W;
-  const int s0 = st * CM_S;
+  const int kbeg = hl ? 0 : mk, kend = hr ? k2 : mk;
+  const int s0 = st * CH_S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NA = CM_K * CM_R / 256, NB = CM_K * CM_S / 256;   // A, B elements per thread and slab
-  // load slots: A element (row R0 + (e % CM_R), k e / CM_R), B element (k e % CM_K, source e / CM_K)
-  int a_col[NA], a_j[NA], a_kk[NA];
-  bool a_ok[NA];
+  const C *xb = (const C *)pp.x;
+  const int *ce = pp.corr_e + c * K;
+  const size_t plane = (size_t)nx * m * k2;
+  const _Float16 *H = (const _Float16 *)pp.vwh;
+  // this lane's A rows (two tiles): column-stacked row R -> (column a + R / m, row R % m)
+  const _Float16 *arow[2];
 #pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    const int e = tid + 256 * u, rr = e % CM_R;
-    const int row = min(R0 + rr, rows - 1);
-    a_kk[u] = e / CM_R;
-    a_ok[u] = R0 + rr < rows;
-    a_col[u] = ch.a + row / m;
-    a_j[u] = row % m;
+  for (int x = 0; x < 2; ++x) {
+    const int R = min(R0 + wave * 32 + 16 * x + (lane & 15), rows - 1);
+    arow[x] = H + ((size_t)(ch.a + R / m) * m + R % m) * k2 + 8 * (lane >> 4);
   }
-  auto load_slab = [&](int kb, C (&ra)[NA], C (&rb)[NB]) {
+  floatx4 rr[2][3], ii[2][3], im[2][3];
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int l = kb + a_kk[u], lc = min(l, lk1 - 1);
-      const size_t base = (size_t)a_col[u] * mm + (size_t)(lc < m ? lc : lc - m) * m + a_j[u];
-      const C v = lc < m ? V[base] : W[base];
-      ra[u] = (a_ok[u] && l < lk1) ? v : make_float2(0.f, 0.f);
-    }
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int e = tid + 256 * u, l = kb + e % CM_K, sidx = s0 + e / CM_K;
-      const int lc = min(l, lk1 - 1), k = min(sidx, K - 1);
-      const C v = colp<float>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
-      rb[u] = (l < lk1 && sidx < K) ? v : make_float2(0.f, 0.f);
-    }
+    for (int y = 0; y < 3; ++y) rr[x][y] = ii[x][y] = im[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // B staging: thread t < 4 CH_S converts eight consecutive k of source s0 + t / 4
+  const int bsl = tid >> 2, bkg = (tid & 3) * 8, bsrc = s0 + bsl;
+  const bool bact = tid < 4 * CH_S && bsrc < K;
+  const int bf = bact ? ce[bsrc] : 0;
+  // the next k-step's operands, loaded while the current one is multiplied
+  halfx8 an[2][4];
+  C bn[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) an[x][p] = *(const halfx8 *)(arow[x] + p * plane + k0);
+    const int part = k0 < mk ? 0 : 1, l0 = k0 - part * mk + bkg;
+    const C *src = xb + ((size_t)(bact ? bsrc : 0) * nx + (part == 0 ? ch.a - 1 : ch.b + 1)) * m;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bn[u] = (bact && l0 + u < m) ? src[l0 + u] : make_float2(0.f, 0.f);
   };
-  constexpr int RT = CM_R / 64;   // row tiles of 16 per wavefront
-  floatx4 p1[RT][3], p2[RT][3], p3[RT][3];
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += CH_K) {
+    halfx8 a[2][4];
 #pragma unroll
-  for (int x = 0; x < RT; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 3; ++y) p1[x][y] = p2[x][y] = p3[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-  C ra[NA], rb[NB];
-  load_slab(lk0, ra, rb);
-  for (int kb = lk0; kb < lk1; kb += CM_K) {
+      for (int p = 0; p < 4; ++p) a[x][p] = an[x][p];
+    if (tid < 4 * CH_S) {   // separator values of this k-step, scaled and split
+      halfx8 h[4];
 #pragma unroll
-    for (int u = 0; u < NA; ++u) As[a_kk[u]][(tid + 256 * u) % CM_R] = ra[u];
+      for (int u = 0; u < 8; ++u) {
+        const float vr = ldexpf(bn[u].x, bf), vi = ldexpf(bn[u].y, bf);
+        const _Float16 hr_ = (_Float16)vr, hi_ = (_Float16)vi;
+        h[0][u] = hr_;
+        h[1][u] = hi_;
+        h[2][u] = (_Float16)(vr - (float)hr_);
+        h[3][u] = (_Float16)(vi - (float)hi_);
+      }
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int e = tid + 256 * u;
-      Bs[e % CM_K][e / CM_K] = rb[u];
+      for (int p = 0; p < 4; ++p) *(halfx8 *)(Bs + (p * CH_S + bsl) * BK + bkg) = h[p];
     }
     __syncthreads();
-    if (kb + CM_K < lk1) load_slab(kb + CM_K, ra, rb);   // in flight during the products
+    if (k0 + CH_K < kend) fetch(k0 + CH_K);
 #pragma unroll
-    for (int kq = 0; kq < CM_K / 4; ++kq) {
-      const int kk = 4 * kq + (lane >> 4);
-      C a[RT], b[3];
+    for (int y = 0; y < 3; ++y) {
+      halfx8 b[4];
 #pragma unroll
-      for (int x = 0; x < RT; ++x) a[x] = As[kk][wave * 16 * RT + 16 * x + (lane & 15)];
+      for (int p = 0; p < 4; ++p) b[p] = *(const halfx8 *)(Bs + (p * CH_S + 16 * y + (lane & 15)) * BK + 8 * (lane >> 4));
 #pragma unroll
-      for (int y = 0; y < 3; ++y) b[y] = Bs[kk][16 * y + (lane & 15)];
-      float as[RT], bs[3];
-#pragma unroll
-      for (int x = 0; x < RT; ++x) as[x] = a[x].x + a[x].y;
-#pragma unroll
-      for (int y = 0; y < 3; ++y) bs[y] = b[y].x + b[y].y;
-#pragma unroll
-      for (int x = 0; x < RT; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y) {
-          p1[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].x, b[y].x, p1[x][y], 0, 0, 0);
-          p2[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x].y, b[y].y, p2[x][y], 0, 0, 0);
-          p3[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[x], bs[y], p3[x][y], 0, 0, 0);
-        }
+      for (int x = 0; x < 2; ++x) {
+        rr[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][0], b[0], rr[x][y], 0, 0, 0);
+        rr[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][0], b[2], rr[x][y], 0, 0, 0);
+        rr[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][2], b[0], rr[x][y], 0, 0, 0);
+        ii[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][1], b[1], ii[x][y], 0, 0, 0);
+        ii[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][1], b[3], ii[x][y], 0, 0, 0);
+        ii[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][3], b[1], ii[x][y], 0, 0, 0);
+        im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][0], b[1], im[x][y], 0, 0, 0);
+        im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][0], b[3], im[x][y], 0, 0, 0);
+        im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][2], b[1], im[x][y], 0, 0, 0);
+        im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][1], b[0], im[x][y], 0, 0, 0);
+        im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][1], b[2], im[x][y], 0, 0, 0);
+        im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][3], b[0], im[x][y], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  // tile to LDS as [source][row], then column-contiguous updates
+  // tile to LDS as [source][row], scaled back, then column-contiguous updates
 #pragma unroll
-  for (int x = 0; x < RT; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 3; ++y)
+    for (int r = 0; r < 4; ++r) {
+      const int rr_ = wave * 32 + 16 * x + 4 * (lane >> 4) + r;
+      const int R = min(R0 + rr_, rows - 1);
+      const int ei = pp.vwe[ch.a + R / m];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        Out[16 * y + (lane & 15)][wave * 16 * RT + 16 * x + 4 * (lane >> 4) + r] =
-            make_float2(p1[x][y][r] - p2[x][y][r], p3[x][y][r] - p1[x][y][r] - p2[x][y][r]);
+      for (int y = 0; y < 3; ++y) {
+        const int sidx = min(s0 + 16 * y + (lane & 15), K - 1);
+        const int sc = -(ei + ce[sidx]);
+        Out[16 * y + (lane & 15)][rr_] = make_float2(ldexpf(rr[x][y][r] - ii[x][y][r], sc), ldexpf(im[x][y][r], sc));
+      }
+    }
   __syncthreads();
-  // eight updates at a time: their loads go out together (one latency per eight)
-  constexpr int NE = CM_S * CM_R / 256, EU = NE % 8 == 0 ? 8 : 4;
+  constexpr int NE = CH_S * CH_R / 256, EU = 8;
   static_assert(NE % EU == 0, "epilogue batches");
+  C *xw = (C *)pp.x;
 #pragma unroll 1
   for (int e0 = 0; e0 < NE; e0 += EU) {
     C *d[EU];
@@ -1231,18 +1375,18 @@ __global__ __launch_bounds__(256) void k_correct_mfma(SweepBatch bt) {
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
       const int e = tid + 256 * (e0 + u);
-      const int sidx = e / CM_R, rr = e - sidx * CM_R;
-      const int row = R0 + rr, k = s0 + sidx;
+      const int sidx = e / CH_R, rr_ = e - sidx * CH_R;
+      const int row = R0 + rr_, k = s0 + sidx;
       ok[u] = row < rows && k < K;
       const int rc = min(row, rows - 1);
-      d[u] = colp<float>(pp.x, g, min(k, K - 1), ch.a + rc / m) + (rc % m);
+      d[u] = xw + ((size_t)min(k, K - 1) * nx + ch.a + rc / m) * m + (rc % m);
       old[u] = *d[u];
     }
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
       const int e = tid + 256 * (e0 + u);
-      const int sidx = e / CM_R, rr = e - sidx * CM_R;
-      const C o = Out[sidx][rr];
+      const int sidx = e / CH_R, rr_ = e - sidx * CH_R;
+      const C o = Out[sidx][rr_];
       if (ok[u]) *d[u] = make_float2(old[u].x - o.x, old[u].y - o.y);
     }
   }
@@ -1822,16 +1966,23 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     HIP_TRY(kf_malloc((void **)&p->W32, sizeof(float2) * n));
   }
   // the separators' reduction blocks, sized by the separator count
-  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32, (void *)p->sep32})
+  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32, (void *)p->sep32, (void *)p->corr_e})
     if (q) HIP_TRY(hipFree(q));
   p->CRL64 = p->CR64 = nullptr;
   p->CR32 = p->sep32 = nullptr;
+  p->corr_e = nullptr;
   if (chunks > 1) {
     const size_t nsep = chunks - 1;
     HIP_TRY(kf_malloc((void **)&p->CRL64, sizeof(double2) * nsep * 4 * mm));
     HIP_TRY(kf_malloc((void **)&p->CR64, sizeof(double2) * nsep * CR_LV * 2 * mm));
     HIP_TRY(kf_malloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
     HIP_TRY(kf_malloc((void **)&p->sep32, sizeof(float2) * nsep * p->K * m));
+    HIP_TRY(kf_malloc((void **)&p->corr_e, sizeof(int) * chunks * p->K));
+    if (!p->vwh) {   // independent of the partition
+      p->vw_k2 = 2 * ((m + 31) / 32 * 32);
+      HIP_TRY(kf_malloc((void **)&p->vwh, sizeof(uint16_t) * 4 * (size_t)p->nx * m * p->vw_k2));
+      HIP_TRY(kf_malloc((void **)&p->vwe, sizeof(int) * p->nx));
+    }
   }
   p->part = part;
   p->P = chunks;
@@ -2101,6 +2252,15 @@ kf_status blu_factor_batch(const std::vector<kf_problem *> &all, int which, hipS
         kf_status st = launch_copy_c128_to_c64(p, n, p->T64, p->T32);
         if (st == KF_OK && p->P > 1) st = launch_copy_c128_to_c64(p, n, p->V64, p->V32);
         if (st == KF_OK && p->P > 1) st = launch_copy_c128_to_c64(p, n, p->W64, p->W32);
+        if (st == KF_OK && p->P > 1) {   // the spikes as scaled FP16 pairs for the interior correction
+          hipLaunchKernelGGL(k_spike_exponents, dim3(p->nx), dim3(256), 0, p->stream, p->grid(), p->P, p->d_part,
+                             p->V32, p->W32, p->vwe);
+          LAUNCH_CHECK();
+          const int jt = (p->nz + 31) / 32, kt = p->vw_k2 / 32;
+          hipLaunchKernelGGL(k_spike_split, dim3(jt * kt, p->nx), dim3(256), 0, p->stream, p->grid(), p->P,
+                             p->d_part, p->V32, p->W32, p->vwe, p->vw_k2, p->vwh);
+          LAUNCH_CHECK();
+        }
         if (st == KF_OK && p->P > 1)
           st = launch_copy_c128_to_c64(p, (int64_t)(p->P - 1) * CR_LV * 2 * p->nz * p->nz, p->CR64, p->CR32);
         if (st != KF_OK) return st;
@@ -2140,7 +2300,8 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                            fp32 ? (const void *)p->V32 : (const void *)p->V64,
                            fp32 ? (const void *)p->W32 : (const void *)p->W64,
                            fp32 ? (const void *)p->CR32 : (const void *)p->CR64,
-                           fp32 ? (void *)p->sol32 : (void *)p->sol64, (void *)p->sep32};
+                           fp32 ? (void *)p->sol32 : (void *)p->sol64, (void *)p->sep32, p->vwh, p->vwe,
+                           p->corr_e, p->vw_k2};
   }
   const dim3 blk = sweep_block(m_max, SolveThreads<R, NS>::N);
   const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
@@ -2227,7 +2388,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         } else if (ph == 6) {
           items = n * p->K;
         } else if (p->P > 1) {
-          items = p->P * (fp32 ? ((p->lmax * p->nz + CM_R - 1) / CM_R) * ((p->K + CM_S - 1) / CM_S)
+          items = p->P * (fp32 ? ((p->lmax * p->nz + CH_R - 1) / CH_R) * ((p->K + CH_S - 1) / CH_S)
                                : ((p->lmax * p->nz + CG_R - 1) / CG_R) * ((p->K + CG_S - 1) / CG_S));
         }
         tot += items;
@@ -2282,8 +2443,24 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
           break;
         case 6: hipLaunchKernelGGL(k_cr_stage, dim3(1, tot), dim3(256), 0, s, bt); break;
         default:
-          if (fp32) hipLaunchKernelGGL(k_correct_mfma, dim3(grid), dim3(256), 0, s, bt);
-          else hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
+          if (fp32) {
+            // the separators' scale exponents (item = chunk), then the FP16-split correction
+            // (a batch member with one chunk has no separators, no correction and no
+            // exponent buffer: it gets no items)
+            SweepBatch be = bt;
+            int tc = 0, kmax = 1;
+            for (int q2 = 0; q2 < bt.n; ++q2) {
+              be.first[q2] = tc;
+              if (ps[q2]->P > 1) tc += ps[q2]->P;
+              kmax = std::max(kmax, ps[q2]->K);
+            }
+            be.first[bt.n] = be.total = tc;
+            hipLaunchKernelGGL(k_corr_exponents, dim3(kmax, tc), dim3(256), 0, s, be);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_correct_h, dim3(grid), dim3(256), 0, s, bt);
+          } else {
+            hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
+          }
       }
       LAUNCH_CHECK();
     }

@@ -99,6 +99,10 @@ struct SweepProblem {
   void *x;             // right-hand sides in, solutions out: column-major [K][nx][nz] (compute type)
   void *gsep;          // the separators' reduced right-hand sides, staged before the
                        // back-substitution: [n][K][m] (complex64 solves)
+  const uint16_t *vwh; // the spikes of the interior columns as scaled FP16 pairs (see
+  const int *vwe;      //   blocklu.hip, the correction of complex64 solves): planes,
+  int *corr_e;         //   per-column exponents, per-(chunk, source) exponents
+  int k2;              // row length of the FP16 planes (2 x m rounded up to 32)
 };
 struct SweepBatch {
   int n, total, level;           // level: cyclic-reduction level of the launch
@@ -171,6 +175,10 @@ struct kf_problem {
   double2 *CR64 = nullptr;                     // separators' ML, MU [n][levels][2][m][m]
   float2 *CR32 = nullptr;
   float2 *sep32 = nullptr;                     // separators' right-hand sides staged by a solve [n][K][m]
+  uint16_t *vwh = nullptr;                     // spikes as scaled FP16 (hi, lo) pairs [4][nx][m][k2]
+  int *vwe = nullptr;                          // their per-column scale exponents [nx]
+  int *corr_e = nullptr;                       // per-(chunk, source) exponents of a solve's separators [P][K]
+  int vw_k2 = 0;
   void *fac_jobs = nullptr;                    // device job tables of the factorisation
   size_t fac_jobs_cap = 0;                     // bytes
   double2 *sol64 = nullptr;                    // [K][nx][nz] column-major solve copy (c128)
