@@ -1571,35 +1571,43 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
 
 // Chunk sweeps of complex64 solves on the matrix cores (columns up to 144 TPW rows).
 // Item (chunk, side, tile of SW_S = 16 sources).  Each step is the product of the m x m
-// block T_i with an m x 16 right-hand side, as v_mfma_f32_16x16x4f32 tiles: wave w owns
-// the row tiles w + 9 x (x < TPW).  With one tile per wave the wave holds its A operand
-// (T_i's rows, all columns) in registers, fetched for the next column while the current
-// one is multiplied (the blocks do not depend on the chain); with two, a ring of SW_D
-// k-steps per tile runs SW_D k-steps ahead, into the next column at the end of a step.
+// block T_i with an m x 16 right-hand side, as v_mfma_f32_16x16x4f32 tiles.  The 9 TPW
+// row tiles go to NW = 3 TPW wavefronts, SW_TW = 3 each (wave w: tiles w + NW x), and
+// the launch bounds keep the registers within three waves per SIMD: two workgroups
+// share a compute unit with three waves on every SIMD, where nine waves of one tile
+// pair each would leave one workgroup per unit and three waves on one SIMD against
+// two on the others.  Each tile keeps a ring of SW_D k-steps of T_i in registers, SW_D
+// k-steps ahead of the products and into the next column at the end of a step (the
+// blocks do not depend on the chain).
 // A complex product is three real ones (Gauss):
 //   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi);  Re = P1 - P2,  Im = P3 - P1 - P2.
 // Operand layout of the 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
 // j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
-// Per step: (a) all threads, coalesced over rows: store the previous column's result
-// from LDS, form the right-hand side in LDS (forward: b_i - C y_prev; back-substitution:
-// C x_prev, with y_i staged beside it; a chunk's middle, one step:
-// b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}); (b) each wave: its 16 x 16 tiles of T_i
-// times the right-hand side, the result (forward and middle: the product;
-// back-substitution: y_i - product) to LDS.
-constexpr int SW_S = 16, SW_T = 576, SW_D = 8;   // sources, threads, ring depth
+// Per step: (a) thread r < 144 TPW, row r of all sixteen sources (coalesced over rows):
+// store the previous column's result from LDS, form the right-hand side in LDS
+// (forward: b_i - C y_prev; back-substitution: C x_prev, with y_i taking the place of
+// the result it read; a chunk's middle, one step: b_mid - C_mid y_{mid-1} -
+// C_{mid+1} y_{mid+1}); (b) each wave: its 16 x 16 tiles of T_i times the right-hand
+// side, the result (forward and middle: the product; back-substitution: y_i - product)
+// to LDS.
+constexpr int SW_S = 16, SW_TW = 3;   // sources, row tiles per wave
 template <int TPW> struct SweepShape {
-  static constexpr int M = 144 * TPW, KS = M / 4, NA = M * SW_S / SW_T;   // rows, k-steps, slots per thread
+  // rows, k-steps, waves, threads, ring depth (a divisor of KS: the ring's slot of a
+  // k-step is then the same in every column)
+  static constexpr int M = 144 * TPW, KS = M / 4, NW = 3 * TPW, NT = 64 * NW, D = TPW == 1 ? 9 : 8;
+  static_assert(KS % D == 0, "ring depth divides the k-steps");
 };
 template <int PH, int TPW>   // PH 0: forward sweep, 1: chunk middles, 2: back-substitution
-size_t sweep_mfma_lds() { return (size_t)(PH == 2 ? 3 : 2) * SweepShape<TPW>::M * (SW_S + 1) * sizeof(float2); }
+size_t sweep_mfma_lds() { return (size_t)2 * SweepShape<TPW>::M * (SW_S + 1) * sizeof(float2); }
 template <int PH, int TPW>
-__global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
+__global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_sweep_mfma(SweepBatch bt) {
   using C = float2;
-  constexpr int SWM = SweepShape<TPW>::M, KS = SweepShape<TPW>::KS, NA = SweepShape<TPW>::NA;
+  constexpr int SWM = SweepShape<TPW>::M, KS = SweepShape<TPW>::KS, NW = SweepShape<TPW>::NW;
+  constexpr int SW_D = SweepShape<TPW>::D;
+  static_assert(NW * SW_TW * 16 == SWM && SweepShape<TPW>::NT >= SWM, "tiles and phase (a) rows");
   extern __shared__ unsigned char smem_raw[];
   C(*Bv)[SW_S + 1] = (C(*)[SW_S + 1])smem_raw;   // right-hand side of the step (B operand)
   C(*Pv)[SW_S + 1] = Bv + SWM;                    // the previous column's result
-  C(*Yv)[SW_S + 1] = Pv + SWM;                    // y_i (back-substitution only)
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
@@ -1623,90 +1631,97 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   };
   auto cc_of = [&](int i) { return PH == 0 ? (side == 0 ? i : i + 1) : (side == 0 ? i + 1 : i); };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // phase (a) slots: e = tid + SW_T u -> (row e % SWM, source e / SWM); per slot the
-  // offset of (source, row) in the column-major copy (column 0), and the row's coupling
-  // factor zn[row] (-1 / h^2); the column's factor ixh[i] is uniform
-  size_t aoff[NA];
-  C zf[NA];
-  bool aok[NA];
+  // phase (a) slots: the threads form four groups of SWM / 3, group q taking sources
+  // 4 q .. 4 q + 3 and thread l of a group the rows l, l + SWM / 3, l + 2 SWM / 3
+  // (coalesced over rows; rows from m on are zero in the right-hand side): slot u is
+  // row block u / 4 and source 4 q + u % 4.  Per row block the coupling factor zn[row]
+  // (-1 / h^2); the column's ixh[i] is uniform.
+  constexpr int RB = SWM / 3, SA = 12;
+  static_assert(4 * RB == SweepShape<TPW>::NT, "four source groups of SWM / 3 threads");
+  const int sq = tid / RB, rb = tid % RB;
   const double ih2 = -1.0 / (g.h * g.h);
+  int srow[3];
+  C zf[3];
 #pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    const int e = tid + SW_T * u, r = e % SWM, j = e / SWM;
-    aok[u] = r < m && s0 + j < K;
-    aoff[u] = (size_t)min(s0 + j, K - 1) * g.nx * m + min(r, m - 1);
-    const double2 z = g.zn[min(r, m - 1)];
-    zf[u] = make_float2((float)(z.x * ih2), (float)(z.y * ih2));
+  for (int c = 0; c < 3; ++c) {
+    srow[c] = rb + RB * c;
+    const double2 z = g.zn[min(srow[c], m - 1)];
+    zf[c] = make_float2((float)(z.x * ih2), (float)(z.y * ih2));
   }
   C *const Xb = (C *)pp.x;
-  auto xaddr = [&](int u, int i) { return Xb + aoff[u] + (size_t)i * m; };
-  auto slot_r = [&](int u) { return (tid + SW_T * u) % SWM; };
-  auto slot_j = [&](int u) { return (tid + SW_T * u) / SWM; };
+  const size_t sstride = (size_t)g.nx * m;   // one source to the next
+  auto slot_row = [&](int u) { return srow[u >> 2]; };
+  auto slot_src = [&](int u) { return 4 * sq + (u & 3); };
+  auto slot_ok = [&](int u) { return slot_row(u) < m && s0 + slot_src(u) < K; };
+  // the column's address is uniform (scalar registers), the row the lane's offset
+  auto xaddr = [&](int u, int i) {
+    return (Xb + (size_t)min(s0 + slot_src(u), K - 1) * sstride + (size_t)i * m) + min(slot_row(u), m - 1);
+  };
   // A operand of column i, tile x: lane (i', k') = (lane % 16, lane / 16) of k-step ks
-  // holds T_i[16 (wave + 9 x) + i'][4 ks + k'] (column-major block: rows contiguous).
+  // holds T_i[16 (wave + NW x) + i'][4 ks + k'] (column-major block: rows contiguous).
   // Every wave runs all KS k-steps (rows past m are clamped to row m - 1, k-steps past
   // the last one repeat it: the right-hand side is zero there), so the loads are
   // unconditional and the wait counts stay exact across the loop.  The last k-step reads
   // up to three columns beyond the block: the next block, or the zero padding after the
   // last one.
   const int akq = lane >> 4;
-  int arw[TPW];
+  int arw[SW_TW];
 #pragma unroll
-  for (int x = 0; x < TPW; ++x) arw[x] = min(16 * (wave + 9 * x) + (lane & 15), m - 1);
+  for (int x = 0; x < SW_TW; ++x) arw[x] = min(16 * (wave + NW * x) + (lane & 15), m - 1);
   const int ksl = (m - 1) / 4;
-  const size_t kstride = 4 * (size_t)m;
-  auto a_base = [&](int i, int x) { return T + (size_t)i * mm + (size_t)akq * m + arw[x]; };
-  constexpr int NREG = TPW == 1 ? KS : SW_D;   // k-steps held per tile
-  C areg[NREG][TPW];
-  // right-hand-side values of the next step, held in registers
-  C bnext[NA];
-  if (PH == 2) {   // x_mid into Pv
-    const int im = ch.mid;
+  // the loads as buffer loads: the block's descriptor in scalar registers (its range,
+  // the block and the three columns after it, lies inside T's allocation), the lane's
+  // offset in a vector register, the k-step's offset in a scalar one
+  const int nrec = (int)((mm + 4 * (size_t)m) * sizeof(C)), kso = 4 * m * (int)sizeof(C);
+  auto rsrc_of = [&](int i) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(T + (size_t)i * mm), (short)0, nrec, 0x00020000);
+  };
+  int avo[SW_TW];
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const C v = *xaddr(u, im);
-      Pv[slot_r(u)][slot_j(u)] = aok[u] ? v : make_float2(0.f, 0.f);
-    }
+  for (int x = 0; x < SW_TW; ++x) avo[x] = (akq * m + arw[x]) * (int)sizeof(C);
+  auto aload = [&](__amdgpu_buffer_rsrc_t rs, int x, int ks) {
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(rs, avo[x], min(ks, ksl) * kso, 0));
+  };
+  C areg[SW_D][SW_TW];
+  // right-hand-side values of the next step, held in registers
+  C bnext[SA];
+  if (PH == 2) {   // x_mid into Pv
+#pragma unroll
+    for (int u = 0; u < SA; ++u) Pv[slot_row(u)][slot_src(u)] = slot_ok(u) ? *xaddr(u, ch.mid) : make_float2(0.f, 0.f);
     __syncthreads();
   }
   // in the loop's order: right-hand side, coupling factor, then the block
   {
     const int i0 = col_of(0);
 #pragma unroll
-    for (int u = 0; u < NA; ++u) bnext[u] = *xaddr(u, i0);
+    for (int u = 0; u < SA; ++u) bnext[u] = *xaddr(u, i0);
   }
   // coupling to the previous column: C_cc = zn[row] ixh[cc] (-1 / h^2); the column
   // factor of the next step is fetched with the next right-hand side, ahead of the
   // block's loads
   double2 xh = g.ixh[PH == 2 ? cc_of(col_of(0)) : col_of(0)];
-  // the middle's neighbours y_{mid-1}, y_{mid+1} (PH 1; zero where the chunk has none)
-  C ym[PH == 1 ? NA : 1], yp[PH == 1 ? NA : 1];
-  double2 xh2 = make_double2(0.0, 0.0);
-  if (PH == 1) {
-    const bool hl = ch.mid > ch.a, hr = ch.mid < ch.b;
+  // the middle's neighbours y_{mid-1}, y_{mid+1} (PH 1; zero where the chunk has none),
+  // read where the right-hand side is formed (the middle is a single step)
+  const bool hl = PH == 1 && ch.mid > ch.a, hr = PH == 1 && ch.mid < ch.b;
+  const double2 xh2 = PH == 1 ? g.ixh[ch.mid + 1] : make_double2(0.0, 0.0);
+  {
+    const __amdgpu_buffer_rsrc_t r0 = rsrc_of(col_of(0));
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      ym[u] = hl ? *xaddr(u, ch.mid - 1) : make_float2(0.f, 0.f);
-      yp[u] = hr ? *xaddr(u, ch.mid + 1) : make_float2(0.f, 0.f);
-    }
-    xh2 = g.ixh[ch.mid + 1];
-  }
+    for (int x = 0; x < SW_TW; ++x)
 #pragma unroll
-  for (int x = 0; x < TPW; ++x) {
-    const C *ap = a_base(col_of(0), x);
-#pragma unroll
-    for (int ks = 0; ks < NREG; ++ks) areg[ks][x] = ap[min(ks, ksl) * kstride];
+      for (int ks = 0; ks < SW_D; ++ks) areg[ks][x] = aload(r0, x, ks);
   }
   for (int t = 0; t < cnt; ++t) {
     const int i = col_of(t);
     const C xf = make_float2((float)xh.x, (float)xh.y);
     // (a) store the previous result, form this step's right-hand side
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int r = slot_r(u), j = slot_j(u);
+    for (int u = 0; u < SA; ++u) {
+      const int r = slot_row(u), j = slot_src(u);
+      const C z = zf[u >> 2];
+      const C cj = make_float2(z.x * xf.x - z.y * xf.y, z.x * xf.y + z.y * xf.x);
       const C pv = Pv[r][j];
-      if (t > 0 && aok[u]) *xaddr(u, col_of(t - 1)) = pv;
-      const C cj = make_float2(zf[u].x * xf.x - zf[u].y * xf.y, zf[u].x * xf.y + zf[u].y * xf.x);
+      if (t > 0 && slot_ok(u)) *xaddr(u, col_of(t - 1)) = pv;
       const C cp = make_float2(cj.x * pv.x - cj.y * pv.y, cj.x * pv.y + cj.y * pv.x);
       const C bv = bnext[u];
       C rhs;
@@ -1714,21 +1729,22 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
       else if (PH == 1) {
         // b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}
         const C xf2 = make_float2((float)xh2.x, (float)xh2.y);
-        const C cl = cj;
-        const C cr = make_float2(zf[u].x * xf2.x - zf[u].y * xf2.y, zf[u].x * xf2.y + zf[u].y * xf2.x);
-        const C tl = make_float2(cl.x * ym[u].x - cl.y * ym[u].y, cl.x * ym[u].y + cl.y * ym[u].x);
-        const C tr = make_float2(cr.x * yp[u].x - cr.y * yp[u].y, cr.x * yp[u].y + cr.y * yp[u].x);
+        const C cr = make_float2(z.x * xf2.x - z.y * xf2.y, z.x * xf2.y + z.y * xf2.x);
+        const C ym = hl ? *xaddr(u, ch.mid - 1) : make_float2(0.f, 0.f);
+        const C yp = hr ? *xaddr(u, ch.mid + 1) : make_float2(0.f, 0.f);
+        const C tl = make_float2(cj.x * ym.x - cj.y * ym.y, cj.x * ym.y + cj.y * ym.x);
+        const C tr = make_float2(cr.x * yp.x - cr.y * yp.y, cr.x * yp.y + cr.y * yp.x);
         rhs = make_float2(bv.x - tl.x - tr.x, bv.y - tl.y - tr.y);
       } else {
         rhs = cp;
-        Yv[r][j] = aok[u] ? bv : make_float2(0.f, 0.f);
+        Pv[r][j] = bv;   // y_i, read back by the lane that forms x_i after the barrier
       }
-      Bv[r][j] = aok[u] ? rhs : make_float2(0.f, 0.f);
+      Bv[r][j] = slot_ok(u) ? rhs : make_float2(0.f, 0.f);
     }
     if (t + 1 < cnt) {
       const int in = col_of(t + 1);
 #pragma unroll
-      for (int u = 0; u < NA; ++u) bnext[u] = *xaddr(u, in);
+      for (int u = 0; u < SA; ++u) bnext[u] = *xaddr(u, in);
       xh = g.ixh[cc_of(in)];
     }
     __syncthreads();
@@ -1736,53 +1752,38 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
     //     copies of row m - 1, which nothing reads), the blocks fetched ahead as they
     //     are consumed (the last step fetches its own block again)
     {
-      floatx4 p1[TPW], p2[TPW], p3[TPW];
+      floatx4 p1[SW_TW], p2[SW_TW], p3[SW_TW];
 #pragma unroll
-      for (int x = 0; x < TPW; ++x) p1[x] = p2[x] = p3[x] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const int inext = t + 1 < cnt ? col_of(t + 1) : i;
-      const C *ac[TPW], *an[TPW];
+      for (int x = 0; x < SW_TW; ++x) p1[x] = p2[x] = p3[x] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const __amdgpu_buffer_rsrc_t rc = rsrc_of(i), rn = rsrc_of(t + 1 < cnt ? col_of(t + 1) : i);
 #pragma unroll
-      for (int x = 0; x < TPW; ++x) { ac[x] = a_base(i, x); an[x] = a_base(inext, x); }
-      if constexpr (TPW == 1) {
+      for (int ks = 0; ks < KS; ++ks) {
+        const C b = Bv[4 * ks + akq][lane & 15];
+        const float bs = b.x + b.y;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const C a = areg[ks][0];
-          const C b = Bv[4 * ks + akq][lane & 15];
-          p1[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1[0], 0, 0, 0);
-          p2[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2[0], 0, 0, 0);
-          p3[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, p3[0], 0, 0, 0);
-          areg[ks][0] = an[0][min(ks, ksl) * kstride];   // the next column's k-step
-          // keep each k-step's work in place: a sum of a later step's operands moved up
-          // would wait for that step's load
-          __builtin_amdgcn_sched_barrier(0);
+        for (int x = 0; x < SW_TW; ++x) {
+          const C a = areg[ks % SW_D][x];
+          const float as = a.x + a.y;
+          p1[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1[x], 0, 0, 0);
+          p2[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2[x], 0, 0, 0);
+          p3[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs, p3[x], 0, 0, 0);
+          // refill: k-step ks + SW_D of this column, else of the next one
+          const int kn = ks + SW_D;
+          areg[ks % SW_D][x] = kn < KS ? aload(rc, x, kn) : aload(rn, x, kn - KS);
         }
-      } else {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const C b = Bv[4 * ks + akq][lane & 15];
-          const float bs = b.x + b.y;
-#pragma unroll
-          for (int x = 0; x < TPW; ++x) {
-            const C a = areg[ks % NREG][x];
-            p1[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, p1[x], 0, 0, 0);
-            p2[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, p2[x], 0, 0, 0);
-            p3[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, bs, p3[x], 0, 0, 0);
-            // refill: k-step ks + NREG of this column, else of the next one
-            const int kn = ks + NREG;
-            areg[ks % NREG][x] = kn < KS ? ac[x][min(kn, ksl) * kstride] : an[x][min(kn - KS, ksl) * kstride];
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        // keep each k-step's work in place: a sum of a later step's operands moved up
+        // would wait for that step's load
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int x = 0; x < TPW; ++x)
+      for (int x = 0; x < SW_TW; ++x)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 16 * (wave + 9 * x) + 4 * (lane >> 4) + r, j = lane & 15;   // row < SWM
+          const int row = 16 * (wave + NW * x) + 4 * (lane >> 4) + r, j = lane & 15;   // row < SWM
           const C o = make_float2(p1[x][r] - p2[x][r], p3[x][r] - p1[x][r] - p2[x][r]);
           if (PH != 2) Pv[row][j] = o;
-          else {
-            const C y = Yv[row][j];
+          else {   // x_i = y_i - T_i C x_prev
+            const C y = Pv[row][j];
             Pv[row][j] = make_float2(y.x - o.x, y.y - o.y);
           }
         }
@@ -1792,8 +1793,8 @@ __global__ __launch_bounds__(SW_T) void k_sweep_mfma(SweepBatch bt) {
   // the last column's result
   const int il = col_of(cnt - 1);
 #pragma unroll
-  for (int u = 0; u < NA; ++u)
-    if (aok[u]) *xaddr(u, il) = Pv[slot_r(u)][slot_j(u)];
+  for (int u = 0; u < SA; ++u)
+    if (slot_ok(u)) *xaddr(u, il) = Pv[slot_row(u)][slot_src(u)];
 }
 
 template <typename R, int NS, int PH>
@@ -2414,21 +2415,21 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                    work);
       switch (ph) {
         case 0:
-          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 2>()), s, bt);
+          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<0, 2>()), s, bt);
           else if (sg == 0)
-            hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<0, 1>()), s, bt);
+            hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<0, 1>()), s, bt);
           else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
           break;
         case 1:
-          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<1, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 2>()), s, bt);
+          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<1, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<1, 2>()), s, bt);
           else if (sg == 0)
-            hipLaunchKernelGGL((k_sweep_mfma<1, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<1, 1>()), s, bt);
+            hipLaunchKernelGGL((k_sweep_mfma<1, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<1, 1>()), s, bt);
           else hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
           break;
         case 2:
-          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 2>()), s, bt);
+          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<2, 2>()), s, bt);
           else if (sg == 0)
-            hipLaunchKernelGGL((k_sweep_mfma<2, 1>), dim3(grid), dim3(SW_T), (sweep_mfma_lds<2, 1>()), s, bt);
+            hipLaunchKernelGGL((k_sweep_mfma<2, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<2, 1>()), s, bt);
           else hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
           break;
         case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
