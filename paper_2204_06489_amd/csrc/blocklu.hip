@@ -1797,6 +1797,181 @@ __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_sweep_mfma(SweepBatc
     if (slot_ok(u)) *xaddr(u, il) = Pv[slot_row(u)][slot_src(u)];
 }
 
+// Spikes on the matrix cores (columns up to 144 TPW rows): the chain of k_spikes (the
+// chunk's twisted solve for SP_N = 16 unit right-hand-side columns per item) with each
+// step T_i (m x m) times the m x 16 block as v_mfma_f64_16x16x4f64 tiles, four real
+// products per complex one.  Operand layout: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k as for the f32 16x16x4 instruction, but D[i][j] in lane j + 16 (i % 4),
+// element i / 4 (unlike the f32 form's lane j + 16 (i / 4), element i % 4).  The row tiles are those of the complex64 sweeps (three per wave, 3 TPW waves).
+// The coupling to the next column is diagonal in the rows, so the lanes that hold a
+// step's result also form the next step's right-hand side: the B operand is the only
+// LDS, and a step is (barrier, products, barrier, result and next right-hand side).
+// The blocks come in through buffer loads, a ring of SPM_D k-steps ahead, whose range is
+// the block: columns past m - 1 (the last k-steps, where the right-hand side is zero)
+// read as zero, so no read leaves the block.  The lane's offset runs in a vector
+// register, the range check covering all of it.
+constexpr int SPM_D = 4;
+template <int TPW>
+size_t spikes_mfma_lds() { return (size_t)SweepShape<TPW>::M * (SP_N + 1) * sizeof(double2); }
+template <int TPW>
+__global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_spikes_mfma(FactorBatch bt) {
+  using C = double2;
+  typedef double doublex4 __attribute__((ext_vector_type(4)));
+  constexpr int SWM = SweepShape<TPW>::M, KS = SweepShape<TPW>::KS, NW = SweepShape<TPW>::NW;
+  static_assert(KS % SPM_D == 0 && NW * SW_TW * 16 == SWM, "ring slots and row tiles");
+  extern __shared__ unsigned char smem_raw[];
+  C(*Bv)[SP_N + 1] = (C(*)[SP_N + 1])smem_raw;
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const FactorProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const Grid &g = pp.g;
+  const int m = g.nz;
+  const size_t mm = (size_t)m * m;
+  const int gm = (m + SP_N - 1) / SP_N;
+  const int job = local / gm, grp = local - job * gm;
+  const int which = job < pp.P - 1 ? 1 : 0;   // 1: W of chunk job, 0: V of chunk job - (P - 1) + 1
+  const Chunk ch = chunk_of(pp.part, which == 1 ? job : job - (pp.P - 1) + 1);
+  C *const Out = which == 0 ? pp.V : pp.W;
+  const C *T = pp.T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, akq = lane >> 4, jc = lane & 15;
+  const int col = grp * SP_N + jc;                 // the spike column of this lane's results
+  const int ecol = which == 0 ? ch.a : ch.b + 1;   // coupling column of the unit right-hand side
+  const int rcol = which == 0 ? ch.a : ch.b;       // column it sits in
+  // the chain: the forward sweep from the loaded end (fcnt steps), the middle column, then
+  // the back-substitution towards a (cnt0 steps) and towards b (cnt1 steps)
+  const int fcnt = which == 0 ? ch.mid - ch.a : ch.b - ch.mid, cnt0 = ch.mid - ch.a, cnt1 = ch.b - ch.mid;
+  const int nsteps = fcnt + 1 + cnt0 + cnt1;
+  auto col_at = [&](int t) {
+    if (t < fcnt) return which == 0 ? ch.a + t : ch.b - t;
+    if (t == fcnt) return ch.mid;
+    if (t <= fcnt + cnt0) return ch.mid - (t - fcnt);
+    return ch.mid + (t - fcnt - cnt0);
+  };
+  // the lane's result rows: 16 (wave + NW x) + 4 r + akq = r0 + (16 NW x + 4 r);
+  // addresses as a uniform base, the lane's offset and a constant (no clamping: only rows
+  // below m are read or written)
+  const int r0 = 16 * wave + akq, lo = col * m + r0;
+  auto row_of = [&](int x, int r) { return r0 + 16 * NW * x + 4 * r; };
+  const double ih2 = -1.0 / (g.h * g.h);
+  auto zrow = [&](int x, int r) {   // zn[row] (-1 / h^2), the row factor of the coupling
+    const int row = row_of(x, r);
+    const C z = row < m ? g.zn[r0 + 16 * NW * x + 4 * r] : make_double2(0.0, 0.0);
+    return cscale(z, ih2);
+  };
+  auto unit = [&](int x, int r) {
+    const int row = row_of(x, r);
+    return row == col && row < m ? cmul(zrow(x, r), g.ixh[ecol]) : make_double2(0.0, 0.0);
+  };
+  // A operand: lane (i', k') of k-step ks reads T_i[16 (wave + NW x) + i'][4 ks + k']
+  int avo[SW_TW];
+#pragma unroll
+  for (int x = 0; x < SW_TW; ++x) avo[x] = (akq * m + min(16 * (wave + NW * x) + jc, m - 1)) * (int)sizeof(C);
+  const int nrec = (int)(mm * sizeof(C)), kso = 4 * m * (int)sizeof(C);
+  auto rsrc_of = [&](int i) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(T + (size_t)i * mm), (short)0, nrec, 0x00020000);
+  };
+  auto aload = [&](__amdgpu_buffer_rsrc_t rs, int off) {
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  };
+  // right-hand side of the first step: the unit columns (forward), or the middle's
+  auto put = [&](int x, int r, C v) {
+    const int row = row_of(x, r);
+    Bv[row][jc] = row < m ? v : make_double2(0.0, 0.0);
+  };
+#pragma unroll
+  for (int x = 0; x < SW_TW; ++x)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put(x, r, (fcnt > 0 || rcol == ch.mid) ? unit(x, r) : make_double2(0.0, 0.0));
+  C areg[SPM_D][SW_TW];
+  int loff[SW_TW];   // offset of the next k-step to load, per tile
+  {
+    const __amdgpu_buffer_rsrc_t r0 = rsrc_of(col_at(0));
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x) {
+      loff[x] = avo[x];
+#pragma unroll
+      for (int ks = 0; ks < SPM_D; ++ks) {
+        areg[ks][x] = aload(r0, loff[x]);
+        loff[x] += kso;
+      }
+    }
+  }
+  for (int t = 0; t < nsteps; ++t) {
+    const int i = col_at(t);
+    __syncthreads();   // the right-hand side is in Bv
+    doublex4 re[SW_TW], im[SW_TW];
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x) re[x] = im[x] = doublex4{0.0, 0.0, 0.0, 0.0};
+    {
+      const __amdgpu_buffer_rsrc_t rc = rsrc_of(i), rn = rsrc_of(t + 1 < nsteps ? col_at(t + 1) : i);
+      // the offsets stay a running sum: without this the compiler keeps one register
+      // per k-step and tile for the whole kernel
+#pragma unroll
+      for (int x = 0; x < SW_TW; ++x) asm volatile("" : "+v"(loff[x]));
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const C b = Bv[4 * ks + akq][jc];
+#pragma unroll
+        for (int x = 0; x < SW_TW; ++x) {
+          const C a = areg[ks % SPM_D][x];
+          re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[x], 0, 0, 0);
+          re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[x], 0, 0, 0);
+          im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[x], 0, 0, 0);
+          im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im[x], 0, 0, 0);
+          if (ks + SPM_D == KS) loff[x] = avo[x];   // the next column's first k-step
+          areg[ks % SPM_D][x] = aload(ks + SPM_D < KS ? rc : rn, loff[x]);
+          loff[x] += kso;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    __syncthreads();   // every wave is done with Bv
+    // this step's result (back-substitution: y_i - product, y_i = 0 on the unloaded
+    // side), stored; then the next step's right-hand side from it
+    const bool back = t > fcnt, side0 = t <= fcnt + cnt0;
+    const bool loaded = back && (side0 == (which == 0));
+    const int tn = t + 1;
+    const bool has_next = tn < nsteps;
+    // coupling column of the next step and its kind: 0 forward, 1 middle, 2 back
+    int cn = 0, kn = 0;
+    if (has_next) {
+      const int in = col_at(tn);
+      if (tn < fcnt) { kn = 0; cn = which == 0 ? in : in + 1; }
+      else if (tn == fcnt) { kn = 1; cn = which == 0 ? ch.mid : ch.mid + 1; }
+      else if (tn <= fcnt + cnt0) { kn = 2; cn = in + 1; }
+      else { kn = 2; cn = in; }
+    }
+    const bool restart = has_next && tn == fcnt + cnt0 + 1;   // side b starts again from x_mid
+    C *const Oi = Out + (size_t)i * mm;
+    const C *const Om = Out + (size_t)ch.mid * mm;
+    const C xc = has_next ? g.ixh[cn] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(x, r), e = lo + 16 * NW * x + 4 * r;
+        const bool ok = row < m && col < m;
+        C v = make_double2(re[x][r], im[x][r]);
+        if (back) {
+          const C y = loaded && ok ? Oi[e] : make_double2(0.0, 0.0);
+          v = csub(y, v);
+        }
+        if (ok) Oi[e] = v;
+        if (has_next) {
+          if (restart) v = ok ? Om[e] : make_double2(0.0, 0.0);
+          const C cj = cmul(zrow(x, r), xc);
+          C rhs;
+          if (kn == 0) rhs = csub(make_double2(0.0, 0.0), cmul(cj, v));
+          else if (kn == 1) rhs = csub(rcol == ch.mid ? unit(x, r) : make_double2(0.0, 0.0), cmul(cj, v));
+          else rhs = cmul(cj, v);
+          put(x, r, rhs);
+        }
+      }
+  }
+}
+
 template <typename R, int NS, int PH>
 __global__ __launch_bounds__((SolveThreads<R, NS>::N)) void k_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
@@ -2209,9 +2384,20 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
   bt.first[bt.n] = bt.total = tot;
   if (tot == 0) return KF_OK;   // one chunk: no separators
   const unsigned grid_sp = xcd_split(bt.first, bt.n, cost, bt.xs);
-  const size_t smem_sp = (size_t)m_max * SP_N * sizeof(double2);
-  HIP_TRY(hipFuncSetAttribute((const void *)k_spikes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
-  hipLaunchKernelGGL(k_spikes, dim3(grid_sp), dim3(2 * spike_pairs_padded(m_max)), smem_sp, s, bt);
+  // columns up to 288 rows on the matrix cores, taller ones on the vector units
+  if (m_max <= SweepShape<1>::M) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_spikes_mfma<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)spikes_mfma_lds<1>()));
+    hipLaunchKernelGGL(k_spikes_mfma<1>, dim3(grid_sp), dim3(SweepShape<1>::NT), spikes_mfma_lds<1>(), s, bt);
+  } else if (m_max <= SweepShape<2>::M) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_spikes_mfma<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)spikes_mfma_lds<2>()));
+    hipLaunchKernelGGL(k_spikes_mfma<2>, dim3(grid_sp), dim3(SweepShape<2>::NT), spikes_mfma_lds<2>(), s, bt);
+  } else {
+    const size_t smem_sp = (size_t)m_max * SP_N * sizeof(double2);
+    HIP_TRY(hipFuncSetAttribute((const void *)k_spikes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
+    hipLaunchKernelGGL(k_spikes, dim3(grid_sp), dim3(2 * spike_pairs_padded(m_max)), smem_sp, s, bt);
+  }
   LAUNCH_CHECK();
   // 6. the separators' system by block cyclic reduction
   if (ntot == 0) return KF_OK;
