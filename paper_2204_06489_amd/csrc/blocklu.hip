@@ -43,6 +43,7 @@
 #include "common.h"
 
 #include <cstring>
+#include <type_traits>
 #include <map>
 #include <utility>
 #include <vector>
@@ -1811,14 +1812,81 @@ __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_sweep_mfma(SweepBatc
 // read as zero, so no read leaves the block.  The lane's offset runs in a vector
 // register, the range check covering all of it.
 constexpr int SPM_D = 4;
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+template <int TPW> struct F64Chain {
+  using C = double2;
+  static constexpr int KS = SweepShape<TPW>::KS, NW = SweepShape<TPW>::NW;
+  static_assert(KS % SPM_D == 0 && NW * SW_TW * 16 == SweepShape<TPW>::M, "ring slots and row tiles");
+  const C *T;
+  size_t mm;
+  int nrec, kso, akq, jc;
+  int avo[SW_TW], loff[SW_TW];   // the lane's offset in a block; the next k-step's, per tile
+  C areg[SPM_D][SW_TW];
+  // lane (i', k') of k-step ks reads T_i[16 (wave + NW x) + i'][4 ks + k']
+  __device__ __forceinline__ void init(const C *T_, int m, int lane, int wave) {
+    T = T_;
+    mm = (size_t)m * m;
+    nrec = (int)(mm * sizeof(C));
+    kso = 4 * m * (int)sizeof(C);
+    akq = lane >> 4;
+    jc = lane & 15;
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x) avo[x] = (akq * m + min(16 * (wave + NW * x) + jc, m - 1)) * (int)sizeof(C);
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int i) const {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(T + (size_t)i * mm), (short)0, nrec, 0x00020000);
+  }
+  __device__ __forceinline__ C aload(__amdgpu_buffer_rsrc_t rs, int off) const {
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  }
+  // the first SPM_D k-steps of column i0
+  __device__ __forceinline__ void prime(int i0) {
+    const __amdgpu_buffer_rsrc_t r0 = rsrc(i0);
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x) {
+      loff[x] = avo[x];
+#pragma unroll
+      for (int ks = 0; ks < SPM_D; ++ks) {
+        areg[ks][x] = aload(r0, loff[x]);
+        loff[x] += kso;
+      }
+    }
+  }
+  // re + i im = T_i B for this wave's row tiles (B[k][j] = Bv[k][j]); the ring runs on
+  // into column inext
+  __device__ __forceinline__ void product(const C (*Bv)[SP_N + 1], int i, int inext, doublex4 (&re)[SW_TW],
+                                          doublex4 (&im)[SW_TW]) {
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x) re[x] = im[x] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const __amdgpu_buffer_rsrc_t rc = rsrc(i), rn = rsrc(inext);
+    // the offsets stay a running sum: without this the compiler keeps one register per
+    // k-step and tile for the whole kernel
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x) asm volatile("" : "+v"(loff[x]));
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const C b = Bv[4 * ks + akq][jc];
+#pragma unroll
+      for (int x = 0; x < SW_TW; ++x) {
+        const C a = areg[ks % SPM_D][x];
+        re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[x], 0, 0, 0);
+        re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[x], 0, 0, 0);
+        im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[x], 0, 0, 0);
+        im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im[x], 0, 0, 0);
+        if (ks + SPM_D == KS) loff[x] = avo[x];   // the next column's first k-step
+        areg[ks % SPM_D][x] = aload(ks + SPM_D < KS ? rc : rn, loff[x]);
+        loff[x] += kso;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+};
 template <int TPW>
-size_t spikes_mfma_lds() { return (size_t)SweepShape<TPW>::M * (SP_N + 1) * sizeof(double2); }
+size_t f64_chain_lds() { return (size_t)SweepShape<TPW>::M * (SP_N + 1) * sizeof(double2); }
 template <int TPW>
 __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_spikes_mfma(FactorBatch bt) {
   using C = double2;
-  typedef double doublex4 __attribute__((ext_vector_type(4)));
-  constexpr int SWM = SweepShape<TPW>::M, KS = SweepShape<TPW>::KS, NW = SweepShape<TPW>::NW;
-  static_assert(KS % SPM_D == 0 && NW * SW_TW * 16 == SWM, "ring slots and row tiles");
+  constexpr int NW = SweepShape<TPW>::NW;
   extern __shared__ unsigned char smem_raw[];
   C(*Bv)[SP_N + 1] = (C(*)[SP_N + 1])smem_raw;
   const int item = item_of_block(bt.xs);
@@ -1834,7 +1902,6 @@ __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_spikes_mfma(FactorBa
   const int which = job < pp.P - 1 ? 1 : 0;   // 1: W of chunk job, 0: V of chunk job - (P - 1) + 1
   const Chunk ch = chunk_of(pp.part, which == 1 ? job : job - (pp.P - 1) + 1);
   C *const Out = which == 0 ? pp.V : pp.W;
-  const C *T = pp.T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, akq = lane >> 4, jc = lane & 15;
   const int col = grp * SP_N + jc;                 // the spike column of this lane's results
   const int ecol = which == 0 ? ch.a : ch.b + 1;   // coupling column of the unit right-hand side
@@ -1864,17 +1931,6 @@ __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_spikes_mfma(FactorBa
     const int row = row_of(x, r);
     return row == col && row < m ? cmul(zrow(x, r), g.ixh[ecol]) : make_double2(0.0, 0.0);
   };
-  // A operand: lane (i', k') of k-step ks reads T_i[16 (wave + NW x) + i'][4 ks + k']
-  int avo[SW_TW];
-#pragma unroll
-  for (int x = 0; x < SW_TW; ++x) avo[x] = (akq * m + min(16 * (wave + NW * x) + jc, m - 1)) * (int)sizeof(C);
-  const int nrec = (int)(mm * sizeof(C)), kso = 4 * m * (int)sizeof(C);
-  auto rsrc_of = [&](int i) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)(T + (size_t)i * mm), (short)0, nrec, 0x00020000);
-  };
-  auto aload = [&](__amdgpu_buffer_rsrc_t rs, int off) {
-    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-  };
   // right-hand side of the first step: the unit columns (forward), or the middle's
   auto put = [&](int x, int r, C v) {
     const int row = row_of(x, r);
@@ -1884,49 +1940,14 @@ __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_spikes_mfma(FactorBa
   for (int x = 0; x < SW_TW; ++x)
 #pragma unroll
     for (int r = 0; r < 4; ++r) put(x, r, (fcnt > 0 || rcol == ch.mid) ? unit(x, r) : make_double2(0.0, 0.0));
-  C areg[SPM_D][SW_TW];
-  int loff[SW_TW];   // offset of the next k-step to load, per tile
-  {
-    const __amdgpu_buffer_rsrc_t r0 = rsrc_of(col_at(0));
-#pragma unroll
-    for (int x = 0; x < SW_TW; ++x) {
-      loff[x] = avo[x];
-#pragma unroll
-      for (int ks = 0; ks < SPM_D; ++ks) {
-        areg[ks][x] = aload(r0, loff[x]);
-        loff[x] += kso;
-      }
-    }
-  }
+  F64Chain<TPW> A;
+  A.init(pp.T, m, lane, wave);
+  A.prime(col_at(0));
   for (int t = 0; t < nsteps; ++t) {
     const int i = col_at(t);
     __syncthreads();   // the right-hand side is in Bv
     doublex4 re[SW_TW], im[SW_TW];
-#pragma unroll
-    for (int x = 0; x < SW_TW; ++x) re[x] = im[x] = doublex4{0.0, 0.0, 0.0, 0.0};
-    {
-      const __amdgpu_buffer_rsrc_t rc = rsrc_of(i), rn = rsrc_of(t + 1 < nsteps ? col_at(t + 1) : i);
-      // the offsets stay a running sum: without this the compiler keeps one register
-      // per k-step and tile for the whole kernel
-#pragma unroll
-      for (int x = 0; x < SW_TW; ++x) asm volatile("" : "+v"(loff[x]));
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const C b = Bv[4 * ks + akq][jc];
-#pragma unroll
-        for (int x = 0; x < SW_TW; ++x) {
-          const C a = areg[ks % SPM_D][x];
-          re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[x], 0, 0, 0);
-          re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[x], 0, 0, 0);
-          im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[x], 0, 0, 0);
-          im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im[x], 0, 0, 0);
-          if (ks + SPM_D == KS) loff[x] = avo[x];   // the next column's first k-step
-          areg[ks % SPM_D][x] = aload(ks + SPM_D < KS ? rc : rn, loff[x]);
-          loff[x] += kso;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
+    A.product(Bv, i, t + 1 < nsteps ? col_at(t + 1) : i, re, im);
     __syncthreads();   // every wave is done with Bv
     // this step's result (back-substitution: y_i - product, y_i = 0 on the unloaded
     // side), stored; then the next step's right-hand side from it
@@ -1967,6 +1988,102 @@ __global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_spikes_mfma(FactorBa
           else if (kn == 1) rhs = csub(rcol == ch.mid ? unit(x, r) : make_double2(0.0, 0.0), cmul(cj, v));
           else rhs = cmul(cj, v);
           put(x, r, rhs);
+        }
+      }
+  }
+}
+
+// FP64 chunk sweeps on the matrix cores (columns up to 144 TPW rows): the steps of
+// k_sweep_mfma (item = chunk, side, 16 sources; PH 0 forward, 1 middles, 2
+// back-substitution) with the FP64 column product of the spikes (F64Chain, four real
+// MFMAs per complex product).  The lanes that hold a step's result also form the next
+// step's right-hand side (the coupling is diagonal in the rows), reading b_i or y_i for
+// their own entries, so the B operand is the only LDS.
+template <int PH, int TPW>
+__global__ __launch_bounds__(SweepShape<TPW>::NT, 3) void k_sweep64_mfma(SweepBatch bt) {
+  using C = double2;
+  constexpr int NW = SweepShape<TPW>::NW;
+  extern __shared__ unsigned char smem_raw[];
+  C(*Bv)[SP_N + 1] = (C(*)[SP_N + 1])smem_raw;
+  const int item = item_of_block(bt.xs);
+  if (item < 0) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int local = item - bt.first[q];
+  const int ST = (pp.K + SP_N - 1) / SP_N;
+  const int st = local % ST, rest = local / ST;
+  const Chunk ch = chunk_of(pp.part, PH == 1 ? rest : rest >> 1);
+  const int side = PH == 1 ? 0 : rest & 1;
+  const Grid &g = pp.g;
+  const int m = g.nz, K = pp.K, s0 = st * SP_N;
+  const int cnt = PH == 1 ? 1 : side == 0 ? ch.mid - ch.a : ch.b - ch.mid;
+  if (cnt <= 0) return;   // uniform over the workgroup
+  auto col_of = [&](int t) {
+    return PH == 1 ? ch.mid
+                   : PH == 0 ? (side == 0 ? ch.a + t : ch.b - t) : (side == 0 ? ch.mid - 1 - t : ch.mid + 1 + t);
+  };
+  auto cc_of = [&](int i) { return PH == 0 ? (side == 0 ? i : i + 1) : (side == 0 ? i + 1 : i); };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, akq = lane >> 4, jc = lane & 15;
+  const bool sok = s0 + jc < K;
+  // the lane's entries: rows 16 (wave + NW x) + 4 r + akq (the f64 D layout) of source
+  // s0 + jc, addressed as the lane's base plus a constant
+  const int r0 = 16 * wave + akq;
+  auto row_of = [&](int x, int r) { return r0 + 16 * NW * x + 4 * r; };
+  C *const Xl = (C *)pp.x + (size_t)min(s0 + jc, K - 1) * g.nx * m + r0;
+  auto xel = [&](int i, int x, int r) { return Xl + (size_t)i * m + (16 * NW * x + 4 * r); };
+  auto ok = [&](int x, int r) { return sok && row_of(x, r) < m; };
+  const double ih2 = -1.0 / (g.h * g.h);
+  auto zrow = [&](int x, int r) {   // zn[row] (-1 / h^2), the row factor of the coupling
+    const C z = row_of(x, r) < m ? g.zn[r0 + 16 * NW * x + 4 * r] : make_double2(0.0, 0.0);
+    return cscale(z, ih2);
+  };
+  auto put = [&](int x, int r, C v) {
+    Bv[row_of(x, r)][jc] = ok(x, r) ? v : make_double2(0.0, 0.0);
+  };
+  auto ld = [&](bool p, const C *a) { return p ? *a : make_double2(0.0, 0.0); };
+  // the first step's right-hand side
+  {
+    const int i0 = col_of(0);
+    const C xa = g.ixh[PH == 1 ? ch.mid : cc_of(i0)], xb2 = g.ixh[PH == 1 ? ch.mid + 1 : cc_of(i0)];
+    const bool hl = ch.mid > ch.a, hr = ch.mid < ch.b;
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool o = ok(x, r);
+        C rhs;
+        if (PH == 0) rhs = ld(o, xel(i0, x, r));   // b at the chunk's end: no coupling inside
+        else if (PH == 1) {                        // b_mid - C_mid y_{mid-1} - C_{mid+1} y_{mid+1}
+          const C z = zrow(x, r);
+          rhs = csub(csub(ld(o, xel(ch.mid, x, r)), cmul(cmul(z, xa), ld(o && hl, xel(ch.mid - 1, x, r)))),
+                     cmul(cmul(z, xb2), ld(o && hr, xel(ch.mid + 1, x, r))));
+        } else rhs = cmul(cmul(zrow(x, r), xa), ld(o, xel(ch.mid, x, r)));   // C x_mid
+        put(x, r, rhs);
+      }
+  }
+  F64Chain<TPW> A;
+  A.init((const C *)pp.T, m, lane, wave);
+  A.prime(col_of(0));
+  for (int t = 0; t < cnt; ++t) {
+    const int i = col_of(t);
+    __syncthreads();   // the right-hand side is in Bv
+    doublex4 re[SW_TW], im[SW_TW];
+    A.product(Bv, i, t + 1 < cnt ? col_of(t + 1) : i, re, im);
+    __syncthreads();   // every wave is done with Bv
+    const bool more = t + 1 < cnt;
+    const int in = more ? col_of(t + 1) : i;
+    const C xc = g.ixh[cc_of(in)];
+#pragma unroll
+    for (int x = 0; x < SW_TW; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool o = ok(x, r);
+        C v = make_double2(re[x][r], im[x][r]);
+        if (PH == 2) v = csub(ld(o, xel(i, x, r)), v);   // x_i = y_i - T_i C x_prev
+        if (o) *xel(i, x, r) = v;
+        if (more) {
+          const C cj = cmul(zrow(x, r), xc);
+          put(x, r, PH == 0 ? csub(ld(o, xel(in, x, r)), cmul(cj, v)) : cmul(cj, v));
         }
       }
   }
@@ -2387,12 +2504,12 @@ kf_status factor64_launch(const std::vector<kf_problem *> &ps, hipStream_t s, in
   // columns up to 288 rows on the matrix cores, taller ones on the vector units
   if (m_max <= SweepShape<1>::M) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_spikes_mfma<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)spikes_mfma_lds<1>()));
-    hipLaunchKernelGGL(k_spikes_mfma<1>, dim3(grid_sp), dim3(SweepShape<1>::NT), spikes_mfma_lds<1>(), s, bt);
+                                (int)f64_chain_lds<1>()));
+    hipLaunchKernelGGL(k_spikes_mfma<1>, dim3(grid_sp), dim3(SweepShape<1>::NT), f64_chain_lds<1>(), s, bt);
   } else if (m_max <= SweepShape<2>::M) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_spikes_mfma<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)spikes_mfma_lds<2>()));
-    hipLaunchKernelGGL(k_spikes_mfma<2>, dim3(grid_sp), dim3(SweepShape<2>::NT), spikes_mfma_lds<2>(), s, bt);
+                                (int)f64_chain_lds<2>()));
+    hipLaunchKernelGGL(k_spikes_mfma<2>, dim3(grid_sp), dim3(SweepShape<2>::NT), f64_chain_lds<2>(), s, bt);
   } else {
     const size_t smem_sp = (size_t)m_max * SP_N * sizeof(double2);
     HIP_TRY(hipFuncSetAttribute((const void *)k_spikes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_sp));
@@ -2520,11 +2637,11 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
   for (int lv = top_max - 1; lv >= 0; --lv) seq.push_back({4, 32 + lv});
   seq.push_back({5, 0});
   static const int ids[7] = {-1, PROF_MID, -1, PROF_REDRHS, PROF_CHAIN, PROF_CORRECT, PROF_CHAIN};
-  // complex64 chunk sweeps and middles on the matrix cores where the columns fit the
-  // kernel (one row tile per wave up to 144 rows, two up to 288); in a batch each problem
-  // takes its own kind: sweep group 0 (one tile), 1 (two tiles), 2 (vector units)
+  // chunk sweeps and middles on the matrix cores (FP32 or FP64) where the columns fit the
+  // kernels (up to 144 rows: 3 waves, up to 288: 6 waves of three row tiles); in a batch
+  // each problem takes its own kind: sweep group 0 (144), 1 (288), 2 (vector units)
   auto sweep_group = [&](const kf_problem *p) {
-    return !fp32 ? 2 : p->nz <= SweepShape<1>::M ? 0 : p->nz <= SweepShape<2>::M ? 1 : 2;
+    return p->nz <= SweepShape<1>::M ? 0 : p->nz <= SweepShape<2>::M ? 1 : 2;
   };
   if (fp32) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<0, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2539,7 +2656,25 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                                 (int)sweep_mfma_lds<1, 1>()));
     HIP_TRY(hipFuncSetAttribute((const void *)k_sweep_mfma<1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sweep_mfma_lds<1, 2>()));
+  } else {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep64_mfma<0, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)f64_chain_lds<2>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep64_mfma<1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)f64_chain_lds<2>()));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_sweep64_mfma<2, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)f64_chain_lds<2>()));
   }
+  // a matrix-core sweep phase for sweep group sg < 2
+  auto mfma_sweep = [&](auto phc, int sg, unsigned grid) {
+    constexpr int PH = decltype(phc)::value;
+    if (fp32) {
+      if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<PH, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<PH, 2>()), s, bt);
+      else hipLaunchKernelGGL((k_sweep_mfma<PH, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<PH, 1>()), s, bt);
+    } else {
+      if (sg == 1) hipLaunchKernelGGL((k_sweep64_mfma<PH, 2>), dim3(grid), dim3(SweepShape<2>::NT), f64_chain_lds<2>(), s, bt);
+      else hipLaunchKernelGGL((k_sweep64_mfma<PH, 1>), dim3(grid), dim3(SweepShape<1>::NT), f64_chain_lds<1>(), s, bt);
+    }
+  };
   for (const auto &e : seq) {
     const int ph = e.first, kind = e.second >> 4, lv = e.second & 15;
     // phases 0-2 run once per sweep group (problems of other groups get no items)
@@ -2601,21 +2736,15 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                    work);
       switch (ph) {
         case 0:
-          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<0, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<0, 2>()), s, bt);
-          else if (sg == 0)
-            hipLaunchKernelGGL((k_sweep_mfma<0, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<0, 1>()), s, bt);
+          if (sg < 2) mfma_sweep(std::integral_constant<int, 0>(), sg, grid);
           else hipLaunchKernelGGL((k_solve<R, NS, 0>), dim3(grid), blk, smem, s, bt);
           break;
         case 1:
-          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<1, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<1, 2>()), s, bt);
-          else if (sg == 0)
-            hipLaunchKernelGGL((k_sweep_mfma<1, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<1, 1>()), s, bt);
+          if (sg < 2) mfma_sweep(std::integral_constant<int, 1>(), sg, grid);
           else hipLaunchKernelGGL((k_solve<R, NS, 1>), dim3(grid), blk, smem, s, bt);
           break;
         case 2:
-          if (sg == 1) hipLaunchKernelGGL((k_sweep_mfma<2, 2>), dim3(grid), dim3(SweepShape<2>::NT), (sweep_mfma_lds<2, 2>()), s, bt);
-          else if (sg == 0)
-            hipLaunchKernelGGL((k_sweep_mfma<2, 1>), dim3(grid), dim3(SweepShape<1>::NT), (sweep_mfma_lds<2, 1>()), s, bt);
+          if (sg < 2) mfma_sweep(std::integral_constant<int, 2>(), sg, grid);
           else hipLaunchKernelGGL((k_solve<R, NS, 2>), dim3(grid), blk, smem, s, bt);
           break;
         case 3: hipLaunchKernelGGL((k_solve<R, NS, 3>), dim3(grid), blk, smem, s, bt); break;
