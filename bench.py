@@ -171,10 +171,10 @@ FAMILIES = SINGLE + ("blu_reduced_rhs", "blu_factor", "blu_sweep", "precond_stag
 KERNEL_NAMES = {
     "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial<8|16, true> (+ k_finish)",
     "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
-    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_h (complex64, FP16-pair MFMA) / k_correct<double>",
+    "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_h (complex64, FP16-pair MFMA) / k_correct64_mfma",
     "blu_chain": "k_cr_mfma<*> (complex64) / k_cr_solve<double,*,*>",
-    "blu_mid": "k_sweep_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
-    "blu_fwd_c128": "k_solve<double,*,0>", "blu_bwd_c128": "k_solve<double,*,2>",
+    "blu_mid": "k_sweep_mfma<1,*> / k_sweep64_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
+    "blu_fwd_c128": "k_sweep64_mfma<0,*> / k_solve<double,*,0>", "blu_bwd_c128": "k_sweep64_mfma<2,*> / k_solve<double,*,2>",
 }
 
 
@@ -194,11 +194,11 @@ def roofline_for(name, p, launches, total_ms, lib_work=None):
     else:
         achieved = amount / avg_s / 1e12
         peak = FP32_PEAK_TFLOPS if dt == "f32" else FP64_PEAK_TFLOPS
-        # complex64 sweeps and the interior correction run on the matrix cores (dense
-        # FP32 MFMA peak); the FP64 sweeps on the vector units (FP64 vector peak)
-        # (the matrix-core sweeps take columns of up to 288 rows)
-        bound = ("mfma" if (name == "blu_correct" and dt == "f32")
-                 or (name in MFMA_KERNELS + ("blu_mid",) and dt == "f32" and p.nz <= 288) else "alu")
+        # the sweeps (columns of up to 288 rows) and the interior correction run on the
+        # matrix cores: the dense FP32 MFMA peak for complex64, the FP64 one (equal to
+        # the FP64 vector rate) for FP64; taller columns sweep on the vector units
+        bound = ("mfma" if name == "blu_correct"
+                 or (name in MFMA_KERNELS + ("blu_mid", "blu_fwd_c128", "blu_bwd_c128") and p.nz <= 288) else "alu")
         out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     out.update({"frac": achieved / peak, "traffic": None, "kernel": KERNEL_NAMES.get(name, name), "family": name,
                 "launches": launches, "avg_launch_us": total_ms / launches * 1e3, "work_per_launch": amount,

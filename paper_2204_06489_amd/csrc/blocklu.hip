@@ -998,24 +998,29 @@ __global__ __launch_bounds__((SolveThreadsCR<R, NS>::N)) void k_cr_solve(SweepBa
   }
 }
 
-// 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}.  A workgroup
-//    takes one interior column and a tile of KT sources: the two separator vectors of
-//    the tile are staged in LDS, and thread (lane, group) accumulates rows lane + 64 u
-//    for KT / 4 sources, so each element of V_i and W_i is read once per tile and every
-//    LDS value feeds several rows.  item = (chunk, column of the chunk, source tile).
+// 5: interior correction x_i = z_i - V_i x_{s_left} - W_i x_{s_right}.  Per chunk it is
+// one dense product: with the interior columns of the chunk stacked (row R = (i - a) m
+// + j), X_I -= [V_stack | W_stack] [x_{s_left}; x_{s_right}], an (L m) x 2m by 2m x K
+// product, cut into CG_R x CG_S tiles (rows x sources).
+constexpr int CG_R = 64, CG_S = 32;
 
-// Per chunk the correction is one dense product: with the interior columns of the chunk
-// stacked (row R = (i - a) m + j), X_I -= [V_stack | W_stack] [x_{s_left}; x_{s_right}],
-// an (L m) x 2m by 2m x K product.  A workgroup computes a 64 x 32 tile (rows x
-// sources), k in slabs of 16 staged in LDS; the next slab is loaded into registers
-// while the current one is multiplied.  Thread (tr, ts) owns rows tr + 16 a and sources
-// ts + 16 b.  item = (chunk, row tile, source tile).
-constexpr int CG_R = 64, CG_S = 32, CG_K = 16;
-template <typename R>
-__global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
-  using C = cplx<R>;
-  __shared__ C As[CG_K][CG_R + 1];
-  __shared__ C Bs[CG_K][CG_S + 1];
+// The interior correction of FP64 solves on the matrix cores: 64 x 32 tiles (rows of
+// the chunk's stacked interior columns x sources, item = (chunk, row tile, source
+// tile)), each wavefront 16 rows x 32 sources as two 16 x 16 tiles of
+// v_mfma_f64_16x16x4f64 (four real products per complex one), k in slabs of CM_K
+// through LDS with the next slab loaded while the current one is multiplied.  The
+// f64 result layout (D[i][j] in lane j + 16 (i % 4), element i / 4) puts one lane's
+// entries in four sources' columns, so the tile goes through LDS once more for
+// row-contiguous updates.
+constexpr int CM_K = 32;
+__global__ __launch_bounds__(256) void k_correct64_mfma(SweepBatch bt) {
+  using C = double2;
+  typedef double dx4 __attribute__((ext_vector_type(4)));
+  constexpr int SL = CM_K * (CG_R + 1) + CM_K * (CG_S + 1), TL = CG_S * (CG_R + 1);
+  __shared__ C lds[SL > TL ? SL : TL];
+  C(*As)[CG_R + 1] = (C(*)[CG_R + 1])lds;
+  C(*Bs)[CG_S + 1] = (C(*)[CG_S + 1])(lds + CM_K * (CG_R + 1));
+  C(*Out)[CG_R + 1] = (C(*)[CG_R + 1])lds;
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
@@ -1036,83 +1041,77 @@ __global__ __launch_bounds__(256) void k_correct(SweepBatch bt) {
   const int lk0 = hl ? 0 : m, lk1 = hr ? 2 * m : m;
   const C *V = (const C *)pp.V, *W = (const C *)pp.W;
   const int s0 = st * CG_S;
-  const int tid = threadIdx.x, tr = tid & 15, ts = tid >> 4;
-  // this thread's load slots: A element (row R0 + (e & 63), k e >> 6), B element
-  // (k e & 15, source e >> 4); rows past the chunk load a clamped address and are zeroed
-  int a_col[4], a_j[4], a_ll[4];
-  bool a_ok[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NA = CM_K * CG_R / 256, NB = CM_K * CG_S / 256;
+  // load slots: A element (row R0 + e % 64, k e / 64), B element (k e % CM_K, source
+  // e / CM_K); rows past the chunk load a clamped address and are zeroed
+  auto load_slab = [&](int kb, C (&ra)[NA], C (&rb)[NB]) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = tid + 256 * u, rr = e & 63;
-    const int row = min(R0 + rr, rows - 1);
-    a_ll[u] = e >> 6;
-    a_ok[u] = R0 + rr < rows;
-    a_col[u] = ch.a + row / m;   // grid column of the row
-    a_j[u] = row % m;
-  }
-  int b_ll[2], b_ss[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + 256 * u;
-    b_ll[u] = e & 15;
-    b_ss[u] = e >> 4;
-  }
-  auto load_slab = [&](int kb, C (&ra)[4], C (&rb)[2]) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int l = kb + a_ll[u], lc = min(l, lk1 - 1);
-      const size_t base = (size_t)a_col[u] * mm + (size_t)(lc < m ? lc : lc - m) * m + a_j[u];
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + 256 * u, rr = e % CG_R, l = kb + e / CG_R;
+      const int row = min(R0 + rr, rows - 1), lc = min(l, lk1 - 1);
+      const size_t base = (size_t)(ch.a + row / m) * mm + (size_t)(lc < m ? lc : lc - m) * m + row % m;
       const C v = lc < m ? V[base] : W[base];
-      ra[u] = (a_ok[u] && l < lk1) ? v : mk<R>(0, 0);
+      ra[u] = (R0 + rr < rows && l < lk1) ? v : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int l = kb + b_ll[u], lc = min(l, lk1 - 1), sidx = s0 + b_ss[u];
-      const int k = min(sidx, K - 1);
-      const C v = colp<R>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
-      rb[u] = (l < lk1 && sidx < K) ? v : mk<R>(0, 0);
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + 256 * u, l = kb + e % CM_K, sidx = s0 + e / CM_K;
+      const int lc = min(l, lk1 - 1), k = min(sidx, K - 1);
+      const C v = colp<double>(pp.x, g, k, lc < m ? ch.a - 1 : ch.b + 1)[lc < m ? lc : lc - m];
+      rb[u] = (l < lk1 && sidx < K) ? v : make_double2(0.0, 0.0);
     }
   };
-  C acc[4][2];
+  dx4 re[2], im[2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = mk<R>(0, 0);
-  C ra[4], rb[2];
+  for (int y = 0; y < 2; ++y) re[y] = im[y] = dx4{0.0, 0.0, 0.0, 0.0};
+  C ra[NA], rb[NB];
   load_slab(lk0, ra, rb);
-  for (int kb = lk0; kb < lk1; kb += CG_K) {
+  for (int kb = lk0; kb < lk1; kb += CM_K) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) As[a_ll[u]][(tid + 256 * u) & 63] = ra[u];
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + 256 * u;
+      As[e / CG_R][e % CG_R] = ra[u];
+    }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) Bs[b_ll[u]][b_ss[u]] = rb[u];
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e % CM_K][e / CM_K] = rb[u];
+    }
     __syncthreads();
-    if (kb + CG_K < lk1) load_slab(kb + CG_K, ra, rb);   // in flight during the products
+    if (kb + CM_K < lk1) load_slab(kb + CM_K, ra, rb);   // in flight during the products
 #pragma unroll
-    for (int kk = 0; kk < CG_K; ++kk) {
-      C av[4], bv[2];
+    for (int kq = 0; kq < CM_K / 4; ++kq) {
+      const int kk = 4 * kq + (lane >> 4);
+      const C a = As[kk][16 * wave + (lane & 15)];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) av[x] = As[kk][tr + 16 * x];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = Bs[kk][ts + 16 * y];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) cfma(acc[x][y], av[x], bv[y]);
+      for (int y = 0; y < 2; ++y) {
+        const C b = Bs[kk][16 * y + (lane & 15)];
+        re[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[y], 0, 0, 0);
+        re[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[y], 0, 0, 0);
+        im[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[y], 0, 0, 0);
+        im[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im[y], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
+  // the tile to LDS as [source][row], then row-contiguous updates
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int row = R0 + tr + 16 * x;
-    if (row < rows)
+  for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const int k = s0 + ts + 16 * y;
-        if (k < K) {
-          C *d = colp<R>(pp.x, g, k, ch.a + row / m) + (row % m);
-          *d = csub(*d, acc[x][y]);
-        }
-      }
+    for (int r = 0; r < 4; ++r)
+      Out[16 * y + (lane & 15)][16 * wave + 4 * r + (lane >> 4)] = make_double2(re[y][r], im[y][r]);
+  __syncthreads();
+  constexpr int NE = CG_S * CG_R / 256;
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + 256 * u;
+    const int sidx = e / CG_R, rr = e - sidx * CG_R;
+    const int row = R0 + rr, k = s0 + sidx;
+    if (row < rows && k < K) {
+      C *d = colp<double>(pp.x, g, k, ch.a + row / m) + (row % m);
+      *d = csub(*d, Out[sidx][rr]);
+    }
   }
 }
 
@@ -2775,7 +2774,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
             LAUNCH_CHECK();
             hipLaunchKernelGGL(k_correct_h, dim3(grid), dim3(256), 0, s, bt);
           } else {
-            hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(256), 0, s, bt);
+            hipLaunchKernelGGL(k_correct64_mfma, dim3(grid), dim3(256), 0, s, bt);
           }
       }
       LAUNCH_CHECK();
