@@ -54,7 +54,7 @@ __device__ inline unsigned xcd_contiguous(unsigned b, unsigned n) {
 // Logical workgroup L = chunk + chunks * group owns the KKT_WG consecutive nodes
 // [chunk * KKT_WG, ...) of the flattened grid, one per thread, and loops over the
 // sources of its group.  Each node reads lambda_k and du_k at itself and its four
-// neighbours (the x-neighbours share its cache lines, the z-neighbours are the rows
+// neighbours (the x-neighbours from the adjacent lanes, the z-neighbours from the rows
 // above and below, read by the workgroups of those rows too), u_k at itself, and
 // writes y_u,k = A^H lambda_k and y_lambda,k = A du_k - P_k ds.  Because each XCD
 // owns a contiguous run of chunks and all workgroups of a group walk the same sources
@@ -63,6 +63,27 @@ __device__ inline unsigned xcd_contiguous(unsigned b, unsigned n) {
 // y_s = eps ds - sum_k P_k^* lambda_k is written here; otherwise each group writes
 // its part of the sum over k into ys_part ([group][Ng]) and k_kkt_ys_finish adds the
 // groups in fixed order.
+// The value held by the previous (UP) or the next lane of the wavefront, by DPP wave
+// shifts (wave_shr:1 / wave_shl:1); the first (last) lane receives zero.  Consecutive
+// lanes hold consecutive nodes of the flattened grid, so a node's x-neighbours come
+// from the adjacent lanes instead of loads.
+template <bool UP> __device__ __forceinline__ int wave_shift(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, UP ? 0x138 : 0x130, 0xf, 0xf, false);
+}
+template <bool UP> __device__ __forceinline__ double wave_shift(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = wave_shift<UP>((int)b), hi = wave_shift<UP>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <bool UP> __device__ __forceinline__ float wave_shift(float v) {
+  return __builtin_bit_cast(float, wave_shift<UP>(__builtin_bit_cast(int, v)));
+}
+template <bool UP> __device__ __forceinline__ double2 wave_shift(double2 v) {
+  return make_double2(wave_shift<UP>(v.x), wave_shift<UP>(v.y));
+}
+template <bool UP> __device__ __forceinline__ float2 wave_shift(float2 v) {
+  return make_float2(wave_shift<UP>(v.x), wave_shift<UP>(v.y));
+}
 constexpr int KKT_WG = 256;
 __global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, int nxc, unsigned chunks,
                                                       double eps, const double2 *__restrict__ xi,
@@ -72,6 +93,7 @@ __global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, in
   const unsigned chunk = L % chunks, grp = L / chunks;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t p = (size_t)chunk * KKT_WG + threadIdx.x;
+  const int lane = threadIdx.x & 63;
   if (p >= Nu) return;
   const int j = (int)(p / g.nx), i = (int)(p - (size_t)j * g.nx);
   const int nzc = g.nz - 2 * g.npml;
@@ -96,8 +118,13 @@ __global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, in
     const double2 l0 = lam[o], d0 = du[o], u = un[o];
     double2 ah = cmulc(s.cc, l0);     // conj(weight) * lambda: A^H lambda
     double2 a = cmul(s.cc, d0);
-    if (hxm) { ah = cadd(ah, cmulc(s.cxm, lam[o - 1])); cfma(a, s.cxm, du[o - 1]); }
-    if (hxp) { ah = cadd(ah, cmulc(s.cxp, lam[o + 1])); cfma(a, s.cxp, du[o + 1]); }
+    // x-neighbours from the adjacent lanes, the wavefront's end lanes from memory (every
+    // lane runs the shifts: the branches below only pick the terms)
+    double2 lm = wave_shift<true>(l0), dm = wave_shift<true>(d0), lp = wave_shift<false>(l0), dp = wave_shift<false>(d0);
+    if (lane == 0 && hxm) { lm = lam[o - 1]; dm = du[o - 1]; }
+    if (lane == 63 && hxp) { lp = lam[o + 1]; dp = du[o + 1]; }
+    if (hxm) { ah = cadd(ah, cmulc(s.cxm, lm)); cfma(a, s.cxm, dm); }
+    if (hxp) { ah = cadd(ah, cmulc(s.cxp, lp)); cfma(a, s.cxp, dp); }
     if (hzm) { ah = cadd(ah, cmulc(s.czm, lam[o - g.nx])); cfma(a, s.czm, du[o - g.nx]); }
     if (hzp) { ah = cadd(ah, cmulc(s.czp, lam[o + g.nx])); cfma(a, s.czp, du[o + g.nx]); }
     store_stream(yu + o, ah);
@@ -121,7 +148,8 @@ __device__ inline void store_stream(float2 *q, float2 v) {
 // sources (eq. Au=f).  Laid out like k_kkt_apply: logical workgroup chunk + chunks *
 // group owns KKT_WG consecutive nodes of the flattened grid and the STEN_KPG sources
 // of its group, the XCDs each own a contiguous run of chunks (neighbour rows are L2
-// hits), the source loop is unrolled by two and the outputs are streamed.
+// hits, x-neighbours come from the adjacent lanes), the source loop is unrolled by two
+// and the outputs are streamed.
 constexpr int STEN_KPG = 8;
 template <typename R, bool ADJ>
 __global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chunks, const cplx<R> *__restrict__ x,
@@ -130,6 +158,7 @@ __global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chun
   const unsigned chunk = L % chunks, grp = L / chunks;
   const size_t Nu = (size_t)g.nx * g.nz;
   const size_t p = (size_t)chunk * KKT_WG + threadIdx.x;
+  const int lane = threadIdx.x & 63;
   if (p >= Nu) return;
   const int j = (int)(p / g.nx), i = (int)(p - (size_t)j * g.nx);
   Stencil5 s = stencil_at(g, i, j);
@@ -141,9 +170,13 @@ __global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chun
 #pragma unroll 2
   for (int k = k0; k < k1; ++k) {
     const cplx<R> *xk = x + (size_t)k * Nu;
-    cplx<R> acc = cmul(cc, xk[p]);
-    if (hxm) cfma(acc, cxm, xk[p - 1]);
-    if (hxp) cfma(acc, cxp, xk[p + 1]);
+    const cplx<R> xc = xk[p];
+    cplx<R> xm = wave_shift<true>(xc), xp = wave_shift<false>(xc);   // x-neighbours from the adjacent lanes
+    if (lane == 0 && hxm) xm = xk[p - 1];
+    if (lane == 63 && hxp) xp = xk[p + 1];
+    cplx<R> acc = cmul(cc, xc);
+    if (hxm) cfma(acc, cxm, xm);
+    if (hxp) cfma(acc, cxp, xp);
     if (hzm) cfma(acc, czm, xk[p - g.nx]);
     if (hzp) cfma(acc, czp, xk[p + g.nx]);
     store_stream(y + (size_t)k * Nu + p, acc);
