@@ -112,8 +112,7 @@ __global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, in
   const double2 w2ds = cscale(ds, w2);
   double2 acc = make_double2(0.0, 0.0);
   const int k0 = grp * kpg, k1 = min(K, k0 + kpg);
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k) {
+  auto source = [&](int k) {
     const size_t o = (size_t)k * Nu + p;
     const double2 l0 = lam[o], d0 = du[o], u = un[o];
     double2 ah = cmulc(s.cc, l0);     // conj(weight) * lambda: A^H lambda
@@ -130,7 +129,15 @@ __global__ __launch_bounds__(KKT_WG) void k_kkt_apply(Grid g, int K, int kpg, in
     store_stream(yu + o, ah);
     store_stream(yl + o, csub(a, cmul(u, w2ds)));
     acc = cadd(acc, cmulc(u, l0));
+  };
+  // two sources per pass (their loads in flight together; the trip count is uniform, so
+  // every lane runs the wave shifts of both)
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    source(k);
+    source(k + 1);
   }
+  if (k < k1) source(k);
   if (!core) return;
   if (gridDim.x == chunks)
     y[(size_t)K * Nu + c] = csub(cscale(ds, eps), cscale(acc, w2));
@@ -167,8 +174,7 @@ __global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chun
                 czm = ccast<R>(s.czm), czp = ccast<R>(s.czp);
   const bool hxm = i > 0, hxp = i + 1 < g.nx, hzm = j > 0, hzp = j + 1 < g.nz;
   const int k0 = grp * STEN_KPG, k1 = min(K, k0 + STEN_KPG);
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k) {
+  auto source = [&](int k) {
     const cplx<R> *xk = x + (size_t)k * Nu;
     const cplx<R> xc = xk[p];
     cplx<R> xm = wave_shift<true>(xc), xp = wave_shift<false>(xc);   // x-neighbours from the adjacent lanes
@@ -180,7 +186,13 @@ __global__ __launch_bounds__(KKT_WG) void k_stencil(Grid g, int K, unsigned chun
     if (hzm) cfma(acc, czm, xk[p - g.nx]);
     if (hzp) cfma(acc, czp, xk[p + g.nx]);
     store_stream(y + (size_t)k * Nu + p, acc);
+  };
+  int k = k0;   // two sources per pass, as in k_kkt_apply
+  for (; k + 1 < k1; k += 2) {
+    source(k);
+    source(k + 1);
   }
+  if (k < k1) source(k);
 }
 
 // y_s = eps ds - omega^2 sum over source groups (fixed order)
