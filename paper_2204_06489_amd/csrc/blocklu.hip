@@ -80,8 +80,16 @@ struct GjJob {
   double2 *Tt;   // destination: the inverse, transposed (T stored column-major)
 };
 
-__device__ __forceinline__ bool gj_better(double ob, int oi, double best, int bi) {
-  return ob > best || (ob == best && oi < bi);
+// The pivot search compares 32-bit keys: the upper 22 bits of the modulus squared as an
+// FP32 number (a non-negative float orders as its bit pattern; 13 mantissa bits are ample
+// for choosing a pivot), then 1023 - row, so that the largest key is the largest modulus
+// and, among equal ones, the lowest row.  NaN moduli, and rows already pivoted, get key
+// 0; a key of 0 at the end means no finite entry (no interchange then).  Rows are
+// below 512.
+__device__ __forceinline__ unsigned gj_key(double a2, int r) {
+  if (!(a2 == a2)) return 0u;
+  const float f = a2 > 3.0e38 ? __builtin_inff() : (float)a2;
+  return (__float_as_uint(f) & ~0x3FFu) | (unsigned)(1023 - r);
 }
 
 // One elimination step of a panel held one row per thread (acc: the row's NB panel
@@ -93,54 +101,44 @@ struct GjPanel {
   bool row;
   double2 *cand;     // LDS [2][8][NB]: each wavefront's candidate pivot row, by step parity
   double2 *rowk;     // LDS [2][NB]: row k before the step
-  double *cbest;     // LDS [2][8]: each wavefront's candidate modulus and row
-  int *cidx;
+  unsigned *ckey;    // LDS [2][8]: each wavefront's best key
   int *lperm;        // LDS [m]: the panel's row permutation
 };
 
-// One barrier per step: every wavefront publishes its best row (and row k its values)
-// before it, so that afterwards each thread finds the pivot row in LDS by itself.
-// The LDS areas alternate with the step's parity: a thread still reading step Q's
-// areas cannot meet step Q + 1's writes, and step Q + 2's writes wait for the barrier
-// of step Q + 1, which every thread reaches only after its reads of step Q.
+// One barrier per step: every wavefront publishes its best key (and its row's values,
+// and row k its values) before it, so that afterwards each thread finds the pivot row
+// in LDS by itself.  The LDS areas alternate with the step's parity: a thread still
+// reading step Q's areas cannot meet step Q + 1's writes, and step Q + 2's writes wait
+// for the barrier of step Q + 1, which every thread reaches only after its reads of
+// step Q.
 template <int NB, int Q>
 __device__ __forceinline__ void gj_pivot(const GjPanel &P, double2 (&acc)[NB]) {
   constexpr int PAR = Q & 1;
   const int k = P.k0 + Q;
-  double best = -1.0;
-  int bi = P.m;
-  if (P.row && P.r >= k) {
-    const double a = cabs2(acc[Q]);
-    if (a > best) { best = a; bi = P.r; }
-  }
+  const unsigned mine = (P.row && P.r >= k) ? gj_key(cabs2(acc[Q]), P.r) : 0u;
+  unsigned key = mine;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ob = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (gj_better(ob, oi, best, bi)) { best = ob; bi = oi; }
-  }
+  for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, o, 64));
   double2 *cand = P.cand + PAR * 8 * NB, *rowk = P.rowk + PAR * NB;
-  if (P.lane == 0) { P.cbest[PAR * 8 + P.wave] = best; P.cidx[PAR * 8 + P.wave] = bi; }
-  if (P.row && P.r == bi)
+  if (P.lane == 0) P.ckey[PAR * 8 + P.wave] = key;
+  if (key != 0u && mine == key)   // this wavefront's best row (keys are unique per row)
 #pragma unroll
     for (int c = 0; c < NB; ++c) cand[P.wave * NB + c] = acc[c];
   if (P.r == k)
 #pragma unroll
     for (int c = 0; c < NB; ++c) rowk[c] = acc[c];
   __syncthreads();
-  double cb[8];
-  int ci[8];
+  unsigned best = 0u;
+  int win = 0;
 #pragma unroll
   for (int w = 0; w < 8; ++w)
-    if (w < P.nw) { cb[w] = P.cbest[PAR * 8 + w]; ci[w] = P.cidx[PAR * 8 + w]; }
-  int win = 0;
-  best = cb[0];
-  bi = ci[0];
-#pragma unroll
-  for (int w = 1; w < 8; ++w)
-    if (w < P.nw && gj_better(cb[w], ci[w], best, bi)) { best = cb[w]; bi = ci[w]; win = w; }
-  // a column with no finite entry leaves bi = m: no interchange, every index stays in
+    if (w < P.nw) {
+      const unsigned kw = P.ckey[PAR * 8 + w];
+      if (kw > best) { best = kw; win = w; }
+    }
+  // a column with no finite entry leaves key 0: no interchange, every index stays in
   // range (the factors then carry the NaNs and the solves report them)
+  const int bi = best != 0u ? 1023 - (int)(best & 0x3FFu) : P.m;
   const int pr = bi < P.m ? bi : k;
   const double2 *prow = bi < P.m ? cand + win * NB : rowk;
   if (P.r == 0) {
@@ -157,12 +155,11 @@ __device__ __forceinline__ void gj_pivot(const GjPanel &P, double2 (&acc)[NB]) {
     if (P.r == pr)   // the old row k moves to pr, then is eliminated like every other row
 #pragma unroll
       for (int c = 0; c < NB; ++c) acc[c] = rowk[c];
-    const double2 f = acc[Q];
+    // row -= (its entry in column Q) x the new row k = g x (old pivot row, 1 in column Q)
+    const double2 g = cmul(acc[Q], d);
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double2 pc = (c == Q) ? d : cmul(prow[c], d);
-      acc[c] = csub(c == Q ? make_double2(0.0, 0.0) : acc[c], cmul(f, pc));
-    }
+    for (int c = 0; c < NB; ++c)
+      acc[c] = c == Q ? csub(make_double2(0.0, 0.0), g) : csub(acc[c], cmul(g, prow[c]));
   }
 }
 
@@ -189,8 +186,7 @@ __global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
   if (b >= npan || !(fac || (pp >= 0 && pp < npan && b != pp))) return;   // uniform
   __shared__ double2 x1[NB][NB];
   __shared__ double2 cand[2][8][NB], rowk[2][NB];
-  __shared__ double cbest[2][8];
-  __shared__ int cidx[2][8];
+  __shared__ unsigned ckey[2][8];
   __shared__ int lperm[512];
   int *perm = (int *)(J.S + (size_t)m * m), *sig = perm + 2 * m;
   const int r = threadIdx.x, nt = blockDim.x;
@@ -235,7 +231,7 @@ __global__ __launch_bounds__(512) void k_gj_step(const GjJob *jobs, int t) {
   }
   // elimination of panel t (this block)
   for (int e = r; e < m; e += nt) lperm[e] = e;
-  const GjPanel P{r, m, cb0, (nt + 63) >> 6, r & 63, r >> 6, row, &cand[0][0][0], &rowk[0][0], &cbest[0][0], &cidx[0][0],
+  const GjPanel P{r, m, cb0, (nt + 63) >> 6, r & 63, r >> 6, row, &cand[0][0][0], &rowk[0][0], &ckey[0][0],
                   lperm};
   GjPivots<NB, 0>::run(P, ncol, acc);
   __syncthreads();   // lperm complete
