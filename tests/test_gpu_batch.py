@@ -128,3 +128,27 @@ def test_batch_mixing_sweep_kernels_matches_single_problem_solves():
               f"|x| {float(x64.abs().max()):.2e}", flush=True)
         assert rel(to_np(x), to_np(s1)) <= 1e-5
         assert rel(to_np(x64), to_np(xref)) <= 1e-3
+
+
+def test_batch_mixing_fp64_sweep_kernels_matches_single_problem_solves():
+    """The same mixed batch in FP64: the members' columns take the FP64 matrix-core sweeps
+    with three or six wavefronts, or the vector units above 288 rows, with three chunks
+    each (spikes, reduction and interior correction in every member)."""
+    shapes = [dict(nx=21, nz=19, npml=4, K=3, freq=6.0), dict(nx=21, nz=150, npml=4, K=2, freq=6.0),
+              dict(nx=21, nz=300, npml=4, K=2, freq=6.0)]
+    gpus, rhs = [], []
+    for q, sh in enumerate(shapes):
+        print(f"[case] mixed-kernel FP64 batch member {q}: {sh}", flush=True)
+        g = KKTProblem.from_inputs(tiny_inputs(seed=q, **sh), eps=1.0)
+        g.set_solver_shape(3, 2)
+        gpus.append(g)
+        rhs.append(to_dev(complex_normal(g.field_shape, seed=50 + q)))
+    singles = [g.helmholtz_solve(r, prec="c128", rtol=1e-30)[0] for g, r in zip(gpus, rhs)]
+    batch = KKTBatch(gpus)
+    xs = batch.helmholtz_solve(rhs, prec="c128")
+    batch.close()
+    for g, x, s1, r in zip(gpus, xs, singles, rhs):
+        res = rel(to_np(g.stencil_apply(x)), to_np(r))
+        print(f"member nz={g.nz}: batch vs single {rel(to_np(x), to_np(s1)):.1e}, residual {res:.1e}", flush=True)
+        assert rel(to_np(x), to_np(s1)) <= 1e-12
+        assert res <= 1e-12
