@@ -143,7 +143,7 @@ static void free_all(kf_problem *p) {
   dfree(p->d_rptr); dfree(p->d_rlist); dfree(p->d_r); dfree(p->d_wr);
   dfree(p->u_n); dfree(p->ys_part); dfree(p->T64); dfree(p->T32); dfree(p->fac_work); dfree(p->d_part); dfree(p->sol64); dfree(p->sol32);
   dfree(p->CRL64); dfree(p->CR64); dfree(p->CR32); dfree(p->sep32); dfree(p->vwh); dfree(p->vwe);
-  dfree(p->corr_e);
+  dfree(p->corr_e); dfree(p->cr_part);
   if (p->fac_jobs) hipFree(p->fac_jobs);
   dfree(p->V64); dfree(p->W64); dfree(p->V32); dfree(p->W32);
   dfree(p->vec_a); dfree(p->vec_b); dfree(p->vec_c); dfree(p->vec_d); dfree(p->red); dfree(p->red_out);

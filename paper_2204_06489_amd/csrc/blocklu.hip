@@ -1125,9 +1125,10 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // separator values of chunk c and source k (both separators together) by 2^f_ck, each
 // bringing the largest modulus into [2^14, 2^15) so that hi stays finite and lo normal
 // for all but the smallest entries; the result is scaled back by 2^-(e_i + f_ck).
-// Planes (uint16 storage of FP16): [hi re, hi im, lo re, lo im][column][row j][k], k
-// running over V_i's columns (0..m-1) then W_i's (mk..mk+m-1), zero-padded to mk =
-// m rounded up to 32.
+// Split values (uint16 storage of FP16): [column][row j][k / 8][hi re, hi im, lo re,
+// lo im][k % 8], k running over V_i's columns (0..m-1) then W_i's (mk..mk+m-1),
+// zero-padded to mk = m rounded up to 32: the four parts of eight consecutive k sit in
+// 64 contiguous bytes, so a k-step of 32 reads whole 128-byte lines of each row.
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 constexpr int CH_R = 128, CH_S = 48, CH_K = 32;
 
@@ -1170,7 +1171,7 @@ __global__ __launch_bounds__(256) void k_spike_exponents(Grid g, int P, const in
   if (threadIdx.x == 0) vwe[i] = c >= 0 ? scale_exponent(red[0]) : 0;
 }
 
-// the planes of interior column blockIdx.y, a 32 x 32 tile (rows j, k) per workgroup
+// the split values of interior column blockIdx.y, a 32 x 32 tile (rows j, k) per workgroup
 __global__ __launch_bounds__(256) void k_spike_split(Grid g, int P, const int *part, const float2 *V, const float2 *W,
                                                      const int *vwe, int k2, uint16_t *vwh) {
   const int i = blockIdx.y, m = g.nz, mk = k2 / 2;
@@ -1193,7 +1194,6 @@ __global__ __launch_bounds__(256) void k_spike_split(Grid g, int P, const int *p
     tile[hi + 8 * p][lo] = make_float2(ldexpf(v.x, e), ldexpf(v.y, e));
   }
   __syncthreads();
-  const size_t plane = (size_t)g.nx * m * k2;
 #pragma unroll
   for (int p = 0; p < 4; ++p) {   // write with lanes along k
     const int j = j0 + hi + 8 * p, k = k0 + lo;
@@ -1201,11 +1201,11 @@ __global__ __launch_bounds__(256) void k_spike_split(Grid g, int P, const int *p
     const float2 v = tile[lo][hi + 8 * p];
     const _Float16 hr_ = (_Float16)v.x, hi_ = (_Float16)v.y;
     const _Float16 lr = (_Float16)(v.x - (float)hr_), li = (_Float16)(v.y - (float)hi_);
-    const size_t o = ((size_t)i * m + j) * k2 + k;
+    const size_t o = ((size_t)i * m + j) * k2 * 4 + (size_t)(k >> 3) * 32 + (k & 7);
     vwh[o] = __builtin_bit_cast(uint16_t, hr_);
-    vwh[plane + o] = __builtin_bit_cast(uint16_t, hi_);
-    vwh[2 * plane + o] = __builtin_bit_cast(uint16_t, lr);
-    vwh[3 * plane + o] = __builtin_bit_cast(uint16_t, li);
+    vwh[o + 8] = __builtin_bit_cast(uint16_t, hi_);
+    vwh[o + 16] = __builtin_bit_cast(uint16_t, lr);
+    vwh[o + 24] = __builtin_bit_cast(uint16_t, li);
   }
 }
 
@@ -1234,8 +1234,9 @@ __global__ __launch_bounds__(256) void k_corr_exponents(SweepBatch bt) {
 
 // X_I -= [V | W] [x_{s_left}; x_{s_right}] per chunk: a 128 x 48 tile (rows x sources)
 // per workgroup, each wavefront 32 rows (two 16-row tiles) x 3 source tiles; k in steps
-// of 32: the separator values split into FP16 planes in LDS ([plane][source][k]), the
-// spike planes read by each lane straight from memory (eight consecutive k of its row).
+// of 32: the separator values split into FP16 parts in LDS ([part][source][k], two
+// buffers alternating with the k-step), the spikes' parts read by each lane straight
+// from memory (eight consecutive k of its row: 64 contiguous bytes).
 // Operand layout of v_mfma_f32_16x16x32_f16: A[i][k] in lane i + 16 (k / 8), element
 // k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D[i][j] in lane j + 16 (i / 4),
 // element i % 4.  Products: re re and im im into their own sums (Re = rr - ii), the
@@ -1243,9 +1244,9 @@ __global__ __launch_bounds__(256) void k_corr_exponents(SweepBatch bt) {
 __global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
   using C = float2;
   constexpr int BK = CH_K + 8;   // LDS row of one source's k values (16-byte aligned)
-  constexpr int BSZ = 4 * CH_S * BK * 2, OSZ = CH_S * (CH_R + 1) * 8;
+  constexpr int BSZ = 2 * 4 * CH_S * BK * 2, OSZ = CH_S * (CH_R + 1) * 8;
   __shared__ __align__(16) unsigned char lds[BSZ > OSZ ? BSZ : OSZ];
-  _Float16 *Bs = (_Float16 *)lds;                    // [4][CH_S][BK]
+  _Float16 *Bs = (_Float16 *)lds;                    // [2][4][CH_S][BK]
   C(*Out)[CH_R + 1] = (C(*)[CH_R + 1])lds;
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
@@ -1267,14 +1268,13 @@ __global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const C *xb = (const C *)pp.x;
   const int *ce = pp.corr_e + c * K;
-  const size_t plane = (size_t)nx * m * k2;
   const _Float16 *H = (const _Float16 *)pp.vwh;
   // this lane's A rows (two tiles): column-stacked row R -> (column a + R / m, row R % m)
   const _Float16 *arow[2];
 #pragma unroll
   for (int x = 0; x < 2; ++x) {
     const int R = min(R0 + wave * 32 + 16 * x + (lane & 15), rows - 1);
-    arow[x] = H + ((size_t)(ch.a + R / m) * m + R % m) * k2 + 8 * (lane >> 4);
+    arow[x] = H + ((size_t)(ch.a + R / m) * m + R % m) * k2 * 4 + 32 * (lane >> 4);
   }
   floatx4 rr[2][3], ii[2][3], im[2][3];
 #pragma unroll
@@ -1292,24 +1292,31 @@ __global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) an[x][p] = *(const halfx8 *)(arow[x] + p * plane + k0);
+      for (int p = 0; p < 4; ++p) an[x][p] = *(const halfx8 *)(arow[x] + 4 * k0 + 8 * p);
     const int part = k0 < mk ? 0 : 1, l0 = k0 - part * mk + bkg;
     const C *src = xb + ((size_t)(bact ? bsrc : 0) * nx + (part == 0 ? ch.a - 1 : ch.b + 1)) * m;
 #pragma unroll
     for (int u = 0; u < 8; ++u) bn[u] = (bact && l0 + u < m) ? src[l0 + u] : make_float2(0.f, 0.f);
   };
   fetch(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += CH_K) {
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += CH_K, buf ^= 1) {
     halfx8 a[2][4];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int p = 0; p < 4; ++p) a[x][p] = an[x][p];
+    C bc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bc[u] = bn[u];
+    // the next k-step's loads go out before this step's staging and barrier
+    if (k0 + CH_K < kend) fetch(k0 + CH_K);
+    _Float16 *Bb = Bs + buf * (4 * CH_S * BK);
     if (tid < 4 * CH_S) {   // separator values of this k-step, scaled and split
       halfx8 h[4];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float vr = ldexpf(bn[u].x, bf), vi = ldexpf(bn[u].y, bf);
+        const float vr = ldexpf(bc[u].x, bf), vi = ldexpf(bc[u].y, bf);
         const _Float16 hr_ = (_Float16)vr, hi_ = (_Float16)vi;
         h[0][u] = hr_;
         h[1][u] = hi_;
@@ -1317,15 +1324,17 @@ __global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
         h[3][u] = (_Float16)(vi - (float)hi_);
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) *(halfx8 *)(Bs + (p * CH_S + bsl) * BK + bkg) = h[p];
+      for (int p = 0; p < 4; ++p) *(halfx8 *)(Bb + (p * CH_S + bsl) * BK + bkg) = h[p];
     }
+    // one barrier per k-step: the staging buffers alternate, so a wavefront that stages
+    // step k + 1 cannot overwrite what a slower one still reads for step k, and the
+    // buffer of step k + 2 is free once every wavefront has passed step k + 1's barrier
     __syncthreads();
-    if (k0 + CH_K < kend) fetch(k0 + CH_K);
 #pragma unroll
     for (int y = 0; y < 3; ++y) {
       halfx8 b[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) b[p] = *(const halfx8 *)(Bs + (p * CH_S + 16 * y + (lane & 15)) * BK + 8 * (lane >> 4));
+      for (int p = 0; p < 4; ++p) b[p] = *(const halfx8 *)(Bb + (p * CH_S + 16 * y + (lane & 15)) * BK + 8 * (lane >> 4));
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         rr[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][0], b[0], rr[x][y], 0, 0, 0);
@@ -1342,8 +1351,8 @@ __global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
         im[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x][3], b[0], im[x][y], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
+  __syncthreads();   // the output tile below reuses the staging buffers
   // tile to LDS as [source][row], scaled back, then column-contiguous updates
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -1401,8 +1410,14 @@ __global__ __launch_bounds__(256) void k_correct_h(SweepBatch bt) {
 // vector-unit levels, and all rows of a level's separators run in parallel.  Tiles split a separator's rows over
 // workgroups, so a back-substitution level (x_j = Binv_j g_j - F_j x_j1 - G_j x_j2,
 // written over g_j) and the root take g_j from the copy staged by k_cr_stage instead
-// of from the column they overwrite.  item = (separator, row tile, source tile).
+// of from the column they overwrite.
+// The terms of a tile are split over workgroups (two for a forward level, three for a
+// back-substitution level; the root has one), which shortens each chain of slabs to
+// one block's: each writes its partial tile, and k_cr_combine adds the partials in
+// term order and applies the update.  item = (separator, row tile, source tile, term).
 constexpr int CRM_R = 64, CRM_S = 16, CRM_K = 64, CRM_ST = CRM_S / 16;
+// workgroups per tile of a level of kind 0 (forward), 1 (root), 2 (back-substitution)
+__host__ __device__ constexpr int cr_split(int kind) { return kind == 0 ? 2 : kind == 2 ? 3 : 1; }
 
 // gsep[(j - 1) K + k][l] = the separator j column of source k, every separator
 __global__ __launch_bounds__(256) void k_cr_stage(SweepBatch bt) {
@@ -1446,6 +1461,7 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
   C(*As)[CRM_R + 2] = (C(*)[CRM_R + 2])lds;
   C(*Bs)[CRM_S + 2] = (C(*)[CRM_S + 2])(lds + CRM_K * (CRM_R + 2));
   C(*Out)[CRM_R + 1] = (C(*)[CRM_R + 1])lds;
+  constexpr int NTM = cr_split(KIND);
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
@@ -1454,7 +1470,8 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
   const Grid &g = pp.g;
   const int m = g.nz, K = pp.K, n = pp.P - 1, lv = bt.level;
   const int stiles = (K + CRM_S - 1) / CRM_S, rtiles = (m + CRM_R - 1) / CRM_R;
-  const int st = local % stiles, rest = local / stiles;
+  const int tau = local % NTM, tile = local / NTM;   // this workgroup's term, its tile
+  const int st = tile % stiles, rest = tile / stiles;
   const int rt = rest % rtiles, t = rest / rtiles;
   const size_t mm = (size_t)m * m;
   const C *T = (const C *)pp.T, *V = (const C *)pp.V, *W = (const C *)pp.W, *CR = (const C *)pp.CR;
@@ -1492,12 +1509,15 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
     c2 = cgc;
     nterm = 1 + hf + hg;
   }
+  if (tau >= nterm) return;   // uniform: an edge separator has a term less
   const int R0 = rt * CRM_R, s0 = st * CRM_S, nx = g.nx;
   C *const xb = (C *)pp.x;   // column i of source k at xb + (k nx + i) m
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NA = CRM_K * CRM_R / 256, NB = CRM_K * CRM_S / 256;
-  // each term's k range padded to a multiple of 4 (one MFMA k-step), cut into slabs
-  const int mp = (m + 3) / 4 * 4, spt = (mp + CRM_K - 1) / CRM_K, nsl = nterm * spt;
+  // each term's k range padded to a multiple of 4 (one MFMA k-step), cut into slabs;
+  // this workgroup's: those of its term (of every term when the tile is not split)
+  const int mp = (m + 3) / 4 * 4, spt = (mp + CRM_K - 1) / CRM_K;
+  const int sl0 = NTM == 1 ? 0 : tau * spt, sl1 = NTM == 1 ? nterm * spt : sl0 + spt;
   const C *gj = gs + (size_t)(jg > 0 ? jg - 1 : 0) * K * m;
   auto load_slab = [&](int sl, C (&ra)[NA], C (&rb)[NB]) {
     const int tau = sl / spt, l0 = (sl - tau * spt) * CRM_K;   // uniform
@@ -1509,8 +1529,8 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
 #pragma unroll
   for (int y = 0; y < CRM_ST; ++y) p1[y] = p2[y] = p3[y] = floatx4{0.f, 0.f, 0.f, 0.f};
   C ra[NA], rb[NB];
-  load_slab(0, ra, rb);
-  for (int sl = 0; sl < nsl; ++sl) {
+  load_slab(sl0, ra, rb);
+  for (int sl = sl0; sl < sl1; ++sl) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int e = tid + 256 * u;
@@ -1522,7 +1542,7 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
       Bs[e % CRM_K][e / CRM_K] = rb[u];
     }
     __syncthreads();
-    if (sl + 1 < nsl) load_slab(sl + 1, ra, rb);   // in flight during the products
+    if (sl + 1 < sl1) load_slab(sl + 1, ra, rb);   // in flight during the products
     const int nkq = min(CRM_K, mp - (sl % spt) * CRM_K) / 4;   // k-steps of this slab
 #pragma unroll
     for (int kq = 0; kq < CRM_K / 4; ++kq) {
@@ -1551,7 +1571,19 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
       Out[16 * y + (lane & 15)][wave * 16 + 4 * (lane >> 4) + r] =
           make_float2(p1[y][r] - p2[y][r], p3[y][r] - p1[y][r] - p2[y][r]);
   __syncthreads();
-  constexpr int NE = CRM_S * CRM_R / 256;
+  constexpr int NE = CRM_S * CRM_R / 256, TS = CRM_S * CRM_R;
+  C o[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + 256 * u;
+    o[u] = Out[e / CRM_R][e % CRM_R];
+  }
+  if (NTM > 1) {   // the partial of this term, for k_cr_combine
+    C *part = pp.crp + ((size_t)tile * 3 + tau) * TS;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) part[tid + 256 * u] = o[u];
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int e = tid + 256 * u;
@@ -1559,8 +1591,54 @@ __global__ __launch_bounds__(256) void k_cr_mfma(SweepBatch bt) {
     const int row = R0 + rr, k = s0 + sidx;
     if (row < m && k < K) {
       C *d = xb + ((size_t)k * nx + out) * m + row;
-      const C o = Out[sidx][rr];
-      *d = keep ? make_float2(d->x + o.x, d->y + o.y) : o;
+      *d = keep ? make_float2(d->x + o[u].x, d->y + o[u].y) : o[u];
+    }
+  }
+}
+
+// The tiles of a split level (kind 0 or 2): the partials of the separator's terms
+// added in term order and applied (forward: g_k += sum; back-substitution: x_j = sum).
+// item = (separator, row tile, source tile), one workgroup each, blockIdx.x.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_cr_combine(SweepBatch bt) {
+  using C = float2;
+  const int item = blockIdx.x;
+  if (item >= bt.total) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int tile = item - bt.first[q];
+  const int m = pp.g.nz, K = pp.K, n = pp.P - 1, lv = bt.level, nx = pp.g.nx;
+  const int stiles = (K + CRM_S - 1) / CRM_S, rtiles = (m + CRM_R - 1) / CRM_R;
+  const int st = tile % stiles, rest = tile / stiles;
+  const int rt = rest % rtiles, t = rest / rtiles;
+  const int s2 = 1 << lv;
+  int out, nterm;
+  if (KIND == 0) {
+    const int k = (t + 1) * 2 * s2;
+    out = separator(pp.part, k);
+    nterm = 1 + (k + s2 <= n);
+  } else {
+    const int j = (2 * t + 1) * s2;
+    out = separator(pp.part, j);
+    nterm = 1 + (j - s2 >= 1) + (j + s2 <= n);
+  }
+  constexpr int TS = CRM_S * CRM_R;
+  const C *part = pp.crp + (size_t)tile * 3 * TS;
+  C *const xb = (C *)pp.x;
+  const int R0 = rt * CRM_R, s0 = st * CRM_S;
+#pragma unroll
+  for (int u = 0; u < TS / 256; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int sidx = e / CRM_R, rr = e - sidx * CRM_R;
+    const int row = R0 + rr, k = s0 + sidx;
+    C s = part[e];
+    for (int w = 1; w < nterm; ++w) {
+      const C v = part[w * TS + e];
+      s = make_float2(s.x + v.x, s.y + v.y);
+    }
+    if (row < m && k < K) {
+      C *d = xb + ((size_t)k * nx + out) * m + row;
+      *d = KIND == 0 ? make_float2(d->x + s.x, d->y + s.y) : s;
     }
   }
 }
@@ -2254,11 +2332,13 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     HIP_TRY(kf_malloc((void **)&p->W32, sizeof(float2) * n));
   }
   // the separators' reduction blocks, sized by the separator count
-  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32, (void *)p->sep32, (void *)p->corr_e})
+  for (void *q : {(void *)p->CRL64, (void *)p->CR64, (void *)p->CR32, (void *)p->sep32, (void *)p->corr_e,
+                  (void *)p->cr_part})
     if (q) HIP_TRY(hipFree(q));
   p->CRL64 = p->CR64 = nullptr;
   p->CR32 = p->sep32 = nullptr;
   p->corr_e = nullptr;
+  p->cr_part = nullptr;
   if (chunks > 1) {
     const size_t nsep = chunks - 1;
     HIP_TRY(kf_malloc((void **)&p->CRL64, sizeof(double2) * nsep * 4 * mm));
@@ -2266,6 +2346,9 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     HIP_TRY(kf_malloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
     HIP_TRY(kf_malloc((void **)&p->sep32, sizeof(float2) * nsep * p->K * m));
     HIP_TRY(kf_malloc((void **)&p->corr_e, sizeof(int) * chunks * p->K));
+    // tiles of a complex64 reduction level: at most one per (separator, row tile, source tile)
+    const size_t crt = nsep * ((m + CRM_R - 1) / CRM_R) * ((p->K + CRM_S - 1) / CRM_S);
+    HIP_TRY(kf_malloc((void **)&p->cr_part, sizeof(float2) * crt * 3 * CRM_S * CRM_R));
     if (!p->vwh) {   // independent of the partition
       p->vw_k2 = 2 * ((m + 31) / 32 * 32);
       HIP_TRY(kf_malloc((void **)&p->vwh, sizeof(uint16_t) * 4 * (size_t)p->nx * m * p->vw_k2));
@@ -2600,7 +2683,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
                            fp32 ? (const void *)p->W32 : (const void *)p->W64,
                            fp32 ? (const void *)p->CR32 : (const void *)p->CR64,
                            fp32 ? (void *)p->sol32 : (void *)p->sol64, (void *)p->sep32, p->vwh, p->vwe,
-                           p->corr_e, p->vw_k2};
+                           p->corr_e, p->vw_k2, p->cr_part};
   }
   const dim3 blk = sweep_block(m_max, SolveThreads<R, NS>::N);
   const size_t smem = (2 + (blk.y - 1)) * NS * (size_t)m_max * sizeof(cplx<R>);
@@ -2684,9 +2767,9 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         // a matrix-core sweep step costs its fixed 144 TPW-row tile whatever m is
         const double mt = ph <= 2 && sg < 2 ? 144.0 * (sg + 1) : m;
         cost[q] = ph == 0 || ph == 2 ? mt * mt * 0.5 * L : ph == 5 || ph == 6 ? m : mt * mt;
-        // matrix-core reduction levels: (separator, row tile, source tile) items
+        // matrix-core reduction levels: (separator, row tile, source tile, term) items
         const int CT = ((p->nz + CRM_R - 1) / CRM_R) * ((p->K + CRM_S - 1) / CRM_S);
-        const int GL = fp32 ? CT : G;
+        const int GL = fp32 ? CT * cr_split(kind) : G;
         bt.first[q] = tot;
         int items = 0;
         if (ph <= 2 && sweep_group(p) != sg) items = 0;
@@ -2748,6 +2831,14 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
             if (kind == 0) hipLaunchKernelGGL(k_cr_mfma<0>, dim3(grid), dim3(256), 0, s, bt);
             else if (kind == 1) hipLaunchKernelGGL(k_cr_mfma<1>, dim3(grid), dim3(256), 0, s, bt);
             else hipLaunchKernelGGL(k_cr_mfma<2>, dim3(grid), dim3(256), 0, s, bt);
+            if (kind != 1) {   // the split levels' partials added and applied, one workgroup per tile
+              LAUNCH_CHECK();
+              SweepBatch bc = bt;
+              for (int q2 = 0; q2 <= bt.n; ++q2) bc.first[q2] = bt.first[q2] / cr_split(kind);
+              bc.total = bc.first[bt.n];
+              if (kind == 0) hipLaunchKernelGGL(k_cr_combine<0>, dim3(bc.total), dim3(256), 0, s, bc);
+              else hipLaunchKernelGGL(k_cr_combine<2>, dim3(bc.total), dim3(256), 0, s, bc);
+            }
           } else if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
           else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
           else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);

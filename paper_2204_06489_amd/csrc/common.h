@@ -100,9 +100,10 @@ struct SweepProblem {
   void *gsep;          // the separators' reduced right-hand sides, staged before the
                        // back-substitution: [n][K][m] (complex64 solves)
   const uint16_t *vwh; // the spikes of the interior columns as scaled FP16 pairs (see
-  const int *vwe;      //   blocklu.hip, the correction of complex64 solves): planes,
+  const int *vwe;      //   blocklu.hip, the correction of complex64 solves): values,
   int *corr_e;         //   per-column exponents, per-(chunk, source) exponents
-  int k2;              // row length of the FP16 planes (2 x m rounded up to 32)
+  int k2;              // k range of a row of the FP16 pairs (2 x m rounded up to 32)
+  float2 *crp;         // complex64 reduction levels: the terms' partial tiles [tiles][3][16][64]
 };
 struct SweepBatch {
   int n, total, level;           // level: cyclic-reduction level of the launch
@@ -175,9 +176,10 @@ struct kf_problem {
   double2 *CR64 = nullptr;                     // separators' ML, MU [n][levels][2][m][m]
   float2 *CR32 = nullptr;
   float2 *sep32 = nullptr;                     // separators' right-hand sides staged by a solve [n][K][m]
-  uint16_t *vwh = nullptr;                     // spikes as scaled FP16 (hi, lo) pairs [4][nx][m][k2]
+  uint16_t *vwh = nullptr;                     // spikes as scaled FP16 (hi, lo) pairs [nx][m][k2 / 8][4][8]
   int *vwe = nullptr;                          // their per-column scale exponents [nx]
   int *corr_e = nullptr;                       // per-(chunk, source) exponents of a solve's separators [P][K]
+  float2 *cr_part = nullptr;                   // complex64 reduction levels: partial tiles of the terms [n][tiles][3]
   int vw_k2 = 0;
   void *fac_jobs = nullptr;                    // device job tables of the factorisation
   size_t fac_jobs_cap = 0;                     // bytes
