@@ -858,9 +858,11 @@ __device__ __forceinline__ void red_rhs_body(const Grid &g, int K, int s_col, vo
 //    group walking a short range of every term's columns in blocks of 8 loads; the
 //    signed vectors of all terms are staged in one round, and the terms accumulate into
 //    one sum reduced once over the groups.
+// pdst (not NULL): the sum is written there as [NS][m] instead of applied to column out
 template <typename R, int NS>
 __device__ __forceinline__ void cr_terms(const Grid &g, int K, void *X, int group, const cplx<R> *const *M,
-                                         const int *col, int out, bool keep, unsigned char *smem) {
+                                         const int *col, int out, bool keep, unsigned char *smem,
+                                         cplx<R> *pdst = nullptr) {
   using C = cplx<R>;
   constexpr int MV_U = 8;
   const int m = g.nz, nt = blockDim.x, tid = threadIdx.x;
@@ -923,11 +925,13 @@ __device__ __forceinline__ void cr_terms(const Grid &g, int K, void *X, int grou
   }
   if (gy == 0)
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (k0 + s < K) {
+    for (int s = 0; s < NS; ++s) {
+      if (pdst) pdst[s * m + j] = acc[s];
+      else if (k0 + s < K) {
         C *d = colp<R>(X, g, k0 + s, out) + j;
         *d = keep ? cadd(*d, acc[s]) : acc[s];
       }
+    }
 }
 
 __host__ __device__ inline int cr_top(int n) {   // floor(log2 n), n >= 1
@@ -938,21 +942,27 @@ __host__ __device__ inline int cr_top(int n) {   // floor(log2 n), n >= 1
 
 // KIND 0: forward reduction at level bt.level (item k = (t + 1) 2^(l+1)):
 //           g_k -= ML_k g_{k-2^l} + MU_k g_{k+2^l};
-// KIND 1: root, x = Binv g at separator 2^top (only where there is no forward level:
-//         otherwise the last forward level's one item, the root, finishes with it);
+// KIND 1: root, x = Binv g at separator 2^top;
 // KIND 2: back-substitution at level bt.level (item j = (2t + 1) 2^l):
 //           x_j = Binv_j g_j - F_j x_{j-2^l} - G_j x_{j+2^l}.
+// The terms of kinds 0 and 2 go to workgroups of their own (a term slot each, so the
+// chain of loads of each is one block's), which write their products as partials;
+// k_cr_combine64 adds them in slot order and applies them.
+// item = (separator, source group, term slot of the kind's split).
+__host__ __device__ constexpr int cr_split64(int kind) { return kind == 0 ? 2 : kind == 2 ? 3 : 1; }
 template <typename R, int NS, int KIND>
 __global__ __launch_bounds__((SolveThreadsCR<R, NS>::N)) void k_cr_solve(SweepBatch bt) {
   extern __shared__ unsigned char smem[];
   using C = cplx<R>;
+  constexpr int NTM = cr_split64(KIND);
   const int item = item_of_block(bt.xs);
   if (item < 0) return;
   const int q = find_problem(bt.first, bt.n, item);
   const SweepProblem &pp = bt.p[q];
   const int local = item - bt.first[q];
   const int G = (pp.K + NS - 1) / NS;
-  const int grp = local % G, t = local / G;
+  const int tau = local % NTM, tile = local / NTM;
+  const int grp = tile % G, t = tile / G;
   const Grid &g = pp.g;
   const int m = g.nz, n = pp.P - 1, lv = bt.level;
   const size_t mm = (size_t)m * m;
@@ -983,14 +993,61 @@ __global__ __launch_bounds__((SolveThreadsCR<R, NS>::N)) void k_cr_solve(SweepBa
     if (j - st >= 1) { M[1] = V + (size_t)out * mm; col[1] = separator(pp.part, j - st); }
     if (j + st <= n) { M[2] = W + (size_t)out * mm; col[2] = separator(pp.part, j + st); }
   }
-  cr_terms<R, NS>(g, pp.K, pp.x, grp, M, col, out, keep, smem);
-  if (KIND == 0 && lv == cr_top(n) - 1) {
-    // the last forward level has one item, the root 2^top: its value is final here, so
-    // the same workgroup takes x_root = Binv g_root (no launch of its own)
-    __syncthreads();   // this workgroup's g_root is written
-    const C *Mr[3] = {T + (size_t)out * mm, nullptr, nullptr};
-    const int cr[3] = {out, 0, 0};
-    cr_terms<R, NS>(g, pp.K, pp.x, grp, Mr, cr, out, false, smem);
+  if (NTM == 1) {
+    cr_terms<R, NS>(g, pp.K, pp.x, grp, M, col, out, keep, smem);
+    return;
+  }
+  // this workgroup's term: slot tau of a back-substitution, slot tau + 1 of a forward level
+  const int slot = KIND == 0 ? tau + 1 : tau;
+  if (!M[slot]) return;   // uniform: an edge separator has a term less
+  const C *Ms[3] = {nullptr, nullptr, nullptr};
+  Ms[slot] = M[slot];
+  C *pdst = (C *)pp.crp + ((size_t)tile * 3 + slot) * NS * m;
+  cr_terms<R, NS>(g, pp.K, pp.x, grp, Ms, col, out, keep, smem, pdst);
+}
+
+// The tiles of a split FP64 level: the partials of the present term slots added in slot
+// order (the slots carry their signs) and applied: forward g_k += sum, back-substitution
+// x_j = sum.  item = (separator, source group), blockIdx.x.
+template <typename R, int NS, int KIND>
+__global__ __launch_bounds__(256) void k_cr_combine64(SweepBatch bt) {
+  using C = cplx<R>;
+  const int item = blockIdx.x;
+  if (item >= bt.total) return;
+  const int q = find_problem(bt.first, bt.n, item);
+  const SweepProblem &pp = bt.p[q];
+  const int tile = item - bt.first[q];
+  const Grid &g = pp.g;
+  const int m = g.nz, n = pp.P - 1, lv = bt.level, K = pp.K;
+  const int G = (K + NS - 1) / NS;
+  const int grp = tile % G, t = tile / G, st = 1 << lv;
+  int out;
+  bool has[3];
+  if (KIND == 0) {
+    const int k = (t + 1) * 2 * st;
+    out = separator(pp.part, k);
+    has[0] = false, has[1] = true, has[2] = k + st <= n;
+  } else {
+    const int j = (2 * t + 1) * st;
+    out = separator(pp.part, j);
+    has[0] = true, has[1] = j - st >= 1, has[2] = j + st <= n;
+  }
+  const C *part = (const C *)pp.crp + (size_t)tile * 3 * NS * m;
+  for (int e = threadIdx.x; e < NS * m; e += 256) {
+    const int s = e / m, j = e - s * m, k = grp * NS + s;
+    C acc = mk<R>(0, 0);
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (has[c]) {
+        const C v = part[c * NS * m + e];
+        acc = any ? cadd(acc, v) : v;
+        any = true;
+      }
+    if (k < K) {
+      C *d = colp<R>(pp.x, g, k, out) + j;
+      *d = KIND == 0 ? cadd(*d, acc) : acc;
+    }
   }
 }
 
@@ -2346,9 +2403,13 @@ kf_status blu_set_shape(kf_problem *p, int chunks, int ns) {
     HIP_TRY(kf_malloc((void **)&p->CR32, sizeof(float2) * nsep * CR_LV * 2 * mm));
     HIP_TRY(kf_malloc((void **)&p->sep32, sizeof(float2) * nsep * p->K * m));
     HIP_TRY(kf_malloc((void **)&p->corr_e, sizeof(int) * chunks * p->K));
-    // tiles of a complex64 reduction level: at most one per (separator, row tile, source tile)
+    // the terms' partials of a reduction level: complex64, at most one tile per
+    // (separator, row tile, source tile); FP64, one m-vector per (separator, source),
+    // source groups padded
     const size_t crt = nsep * ((m + CRM_R - 1) / CRM_R) * ((p->K + CRM_S - 1) / CRM_S);
-    HIP_TRY(kf_malloc((void **)&p->cr_part, sizeof(float2) * crt * 3 * CRM_S * CRM_R));
+    const size_t b32 = sizeof(float2) * crt * 3 * CRM_S * CRM_R;
+    const size_t b64 = sizeof(double2) * nsep * (p->K + 8) * 3 * (size_t)m;
+    HIP_TRY(kf_malloc((void **)&p->cr_part, std::max(b32, b64)));
     if (!p->vwh) {   // independent of the partition
       p->vw_k2 = 2 * ((m + 31) / 32 * 32);
       HIP_TRY(kf_malloc((void **)&p->vwh, sizeof(uint16_t) * 4 * (size_t)p->nx * m * p->vw_k2));
@@ -2769,7 +2830,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         cost[q] = ph == 0 || ph == 2 ? mt * mt * 0.5 * L : ph == 5 || ph == 6 ? m : mt * mt;
         // matrix-core reduction levels: (separator, row tile, source tile, term) items
         const int CT = ((p->nz + CRM_R - 1) / CRM_R) * ((p->K + CRM_S - 1) / CRM_S);
-        const int GL = fp32 ? CT * cr_split(kind) : G;
+        const int GL = fp32 ? CT * cr_split(kind) : G * cr_split64(kind);
         bt.first[q] = tot;
         int items = 0;
         if (ph <= 2 && sweep_group(p) != sg) items = 0;
@@ -2780,9 +2841,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
           if (n >= 1) {
             const int top = cr_top(n);
             if (kind == 0 && lv < top) items = (n >> (lv + 1)) * GL;
-            // the root: its own launch on the matrix cores, else taken by the last
-            // forward level where there is one
-            else if (kind == 1) items = (fp32 || top == 0) ? GL : 0;
+            else if (kind == 1) items = GL;   // the root, a launch of its own
             else if (kind == 2 && lv < top) items = (((n >> lv) + 1) / 2) * GL;
           }
         } else if (ph == 6) {
@@ -2806,7 +2865,7 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
         const double m = prof->nz, esz = 2.0 * sizeof(R);
         int cnt = 0, terms = 0;
         if (kind == 0 && lv < top) { cnt = n >> (lv + 1); terms = 2 * cnt; }
-        else if (kind == 1 && (top == 0 || fp32)) { cnt = 1; terms = 1; }
+        else if (kind == 1) { cnt = 1; terms = 1; }
         else if (kind == 2 && lv < top) { cnt = ((n >> lv) + 1) / 2; terms = 3 * cnt; }
         work = esz * (terms * m * m + (double)(terms + cnt) * prof->K * m);
       }
@@ -2839,9 +2898,19 @@ kf_status solve_phases(const std::vector<kf_problem *> &ps, hipStream_t s, kf_pr
               if (kind == 0) hipLaunchKernelGGL(k_cr_combine<0>, dim3(bc.total), dim3(256), 0, s, bc);
               else hipLaunchKernelGGL(k_cr_combine<2>, dim3(bc.total), dim3(256), 0, s, bc);
             }
-          } else if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
-          else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
-          else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);
+          } else {
+            if (kind == 0) hipLaunchKernelGGL((k_cr_solve<R, NSC, 0>), dim3(grid), blkc, smemc, s, bt);
+            else if (kind == 1) hipLaunchKernelGGL((k_cr_solve<R, NSC, 1>), dim3(grid), blkc, smemc, s, bt);
+            else hipLaunchKernelGGL((k_cr_solve<R, NSC, 2>), dim3(grid), blkc, smemc, s, bt);
+            if (cr_split64(kind) > 1) {   // the partials added and applied, one workgroup per tile
+              LAUNCH_CHECK();
+              SweepBatch bc = bt;
+              for (int q2 = 0; q2 <= bt.n; ++q2) bc.first[q2] = bt.first[q2] / cr_split64(kind);
+              bc.total = bc.first[bt.n];
+              if (kind == 0) hipLaunchKernelGGL((k_cr_combine64<R, NSC, 0>), dim3(bc.total), dim3(256), 0, s, bc);
+              else hipLaunchKernelGGL((k_cr_combine64<R, NSC, 2>), dim3(bc.total), dim3(256), 0, s, bc);
+            }
+          }
           break;
         case 6: hipLaunchKernelGGL(k_cr_stage, dim3(1, tot), dim3(256), 0, s, bt); break;
         default:

@@ -103,7 +103,8 @@ struct SweepProblem {
   const int *vwe;      //   blocklu.hip, the correction of complex64 solves): values,
   int *corr_e;         //   per-column exponents, per-(chunk, source) exponents
   int k2;              // k range of a row of the FP16 pairs (2 x m rounded up to 32)
-  float2 *crp;         // complex64 reduction levels: the terms' partial tiles [tiles][3][16][64]
+  float2 *crp;         // the terms' partials of a split reduction level (complex64 tiles
+                       //   [tiles][3][16][64], or FP64 vectors [tiles][3][NS][m])
 };
 struct SweepBatch {
   int n, total, level;           // level: cyclic-reduction level of the launch
@@ -179,7 +180,7 @@ struct kf_problem {
   uint16_t *vwh = nullptr;                     // spikes as scaled FP16 (hi, lo) pairs [nx][m][k2 / 8][4][8]
   int *vwe = nullptr;                          // their per-column scale exponents [nx]
   int *corr_e = nullptr;                       // per-(chunk, source) exponents of a solve's separators [P][K]
-  float2 *cr_part = nullptr;                   // complex64 reduction levels: partial tiles of the terms [n][tiles][3]
+  float2 *cr_part = nullptr;                   // the terms' partials of a split reduction level
   int vw_k2 = 0;
   void *fac_jobs = nullptr;                    // device job tables of the factorisation
   size_t fac_jobs_cap = 0;                     // bytes
