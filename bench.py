@@ -172,7 +172,7 @@ KERNEL_NAMES = {
     "kkt_apply": "k_kkt_apply (+ k_kkt_ys_finish)", "gs_dot": "k_multidot_partial<8|16, true> (+ k_finish)",
     "gs_update": "k_axpy_dot_partial<true> (+ k_finish)", "blu_fwd_c64": "k_sweep_mfma<0,*>",
     "blu_bwd_c64": "k_sweep_mfma<2,*>", "blu_correct": "k_correct_h (complex64, FP16-pair MFMA) / k_correct64_mfma",
-    "blu_chain": "k_cr_mfma<*> (complex64) / k_cr_solve<double,*,*>",
+    "blu_chain": "k_cr_mfma<*> + k_cr_combine<*> (complex64) / k_cr_solve<double,*,*> + k_cr_combine64<*>",
     "blu_mid": "k_sweep_mfma<1,*> / k_sweep64_mfma<1,*> / k_solve<*,*,1>", "blu_reduced_rhs": "k_solve<*,*,3>",
     "blu_fwd_c128": "k_sweep64_mfma<0,*> / k_solve<double,*,0>", "blu_bwd_c128": "k_sweep64_mfma<2,*> / k_solve<double,*,2>",
 }
