@@ -152,3 +152,30 @@ def test_batch_mixing_fp64_sweep_kernels_matches_single_problem_solves():
         print(f"member nz={g.nz}: batch vs single {rel(to_np(x), to_np(s1)):.1e}, residual {res:.1e}", flush=True)
         assert rel(to_np(x), to_np(s1)) <= 1e-12
         assert res <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batch_with_uneven_chunk_counts_matches_single_problem_solves(prec):
+    """Members cut into 1, 2, 5 and 8 chunks share one batch: no separators, a root
+    alone, and reduction levels whose separators have two or three terms, each term's
+    product in a workgroup of its own and the partials added per member."""
+    shapes = [(dict(nx=21, nz=15, npml=4, K=3, freq=4.0), 1), (dict(nx=25, nz=19, npml=4, K=2, freq=6.0), 2),
+              (dict(nx=41, nz=23, npml=4, K=5, freq=6.0), 5), (dict(nx=47, nz=17, npml=4, K=18, freq=8.0), 8)]
+    dt = torch.complex64 if prec == "c64" else torch.complex128
+    gpus, rhs = [], []
+    for q, (sh, chunks) in enumerate(shapes):
+        print(f"[case] uneven-chunk batch member {q}: {sh}, {chunks} chunks, {prec}", flush=True)
+        g = KKTProblem.from_inputs(tiny_inputs(seed=q, **sh), eps=1.0)
+        g.set_solver_shape(chunks, 2)
+        gpus.append(g)
+        rhs.append(to_dev(complex_normal(g.field_shape, seed=60 + q), dt))
+    singles = [g.helmholtz_solve(r, prec=prec)[0] for g, r in zip(gpus, rhs)]
+    batch = KKTBatch(gpus)
+    xs = batch.helmholtz_solve(rhs, prec=prec)
+    batch.close()
+    for g, x, s1, r in zip(gpus, xs, singles, rhs):
+        r64 = r.to(torch.complex128)
+        res = rel(to_np(g.stencil_apply(x.to(torch.complex128))), to_np(r64))
+        print(f"member nz={g.nz}: batch vs single {rel(to_np(x), to_np(s1)):.1e}, residual {res:.1e}", flush=True)
+        assert rel(to_np(x), to_np(s1)) <= (1e-12 if prec == "c128" else 1e-5)
+        assert res <= (1e-12 if prec == "c128" else 1e-4)
