@@ -402,6 +402,20 @@ def bench_c4(args, torch, KKTProblem):
               f"factor {[round(s['t_factor_ms']) for s in seq]} ms, total {[round(s['t_total_ms']) for s in seq]} ms, "
               f"precond {[round(s['t_precond_ms']) for s in seq]} ms, matvec {[round(s['t_matvec_ms']) for s in seq]} ms, "
               f"orth {[round(s['t_orth_ms']) for s in seq]} ms")
+    # the same problems at once (newton_step_concurrent: each on a stream and a host
+    # thread of its own), so that one problem's latency-bound launches overlap the others'
+    from paper_2204_06489_amd.solver import newton_step_concurrent
+    reset()
+    t0 = time.perf_counter()
+    conc = []
+    for k in range(args.steps):
+        _, _, st = newton_step_concurrent(probs, ds, rtol=args.rtol, restart=20, maxit=600, pc=args.pc,
+                                          fwd_prec="c128", update_in_place=True, want_xi=False)
+        conc.append(st)
+    torch.cuda.synchronize()
+    t_conc = (time.perf_counter() - t0) / args.steps
+    log(args, f"concurrent (a stream and a host thread per problem): {t_conc*1e3:.0f} ms per step, iters "
+              f"{[[s['outer_iters'] for s in st] for st in conc]}")
     # the two smallest grids alone, where neither fills the chip: batched against one at a time
     small = KKTBatch(probs[:2])
     small.newton_step(ds[:2], use_graph=True, **kw)
@@ -433,6 +447,7 @@ def bench_c4(args, torch, KKTProblem):
                                 "hipGraph replay of each FGMRES column, FGMRES(20) to " + f"{args.rtol:g}"),
                    "global_batch": 500, "parallelism": "single GPU"},
         "one_at_a_time_s": t_seq,
+        "concurrent_streams_s": t_conc,
         "batched_without_graphs_s": t_batch_nograph,
         "two_smallest_grids": {"grids": ["201x71", "401x141"], "batched_s": t_small_batch,
                                "one_at_a_time_s": t_small_seq},

@@ -263,6 +263,26 @@ kf_status newton_continuation(kf_problem *const *problems /*[host][n]*/, int32_t
                               const kf_newton_opts *opts /*[host]*/, double *gamma_out,
                               kf_newton_stats *st /*[host], may be NULL*/);
 
+/* One Newton step (newton_step with opts) on each of n independent problems (e.g. one
+ * per frequency on its own grid, Section 6's multi-frequency setting) at once: for the
+ * call every problem runs on a stream of its own, created here, driven by a host thread
+ * of its own, so that the launches of one problem's latency-bound phases (block-solve
+ * chains, reduction levels, host round trips of its Krylov iteration) overlap the
+ * other problems' work.  Each problem computes exactly what newton_step computes alone.
+ * problems: [host][n] distinct problems, 1 <= n <= 16; d_obs: [host][n], problem q's
+ * data ([K][nrec] c128 device); xi_out, gamma_next: [host][n] arrays of newton_step's
+ * outputs (the arrays or their entries may be NULL); st: [host][n] statistics or NULL.
+ * The call first waits for the work already queued on the problems' own streams and
+ * gives them their streams back before it returns; no other call may use these
+ * problems meanwhile.  Every problem is stepped whatever the others return.  Returns
+ * the first status other than KF_OK and KF_ENOCONV in problem order (kf_last_error
+ * names the problem), else KF_ENOCONV if a problem reached maxit, else KF_OK. */
+kf_status newton_step_concurrent(kf_problem *const *problems /*[host][n]*/, int32_t n,
+                                 const void *const *d_obs /*[host][n]*/, const kf_newton_opts *opts /*[host]*/,
+                                 void *const *xi_out /*[host][n] or NULL*/,
+                                 double *const *gamma_next /*[host][n] or NULL*/, int32_t update_in_place,
+                                 kf_newton_stats *st /*[host][n], may be NULL*/);
+
 /* ---- reduced-space Gauss-Newton by conjugate gradients (Section 3) ----
  * The step the paper compares the full-space method with (Table 1 "CG"): with
  * u_n = A(gamma_n)^-1 f and r_k = d_k - Q u_k, CG on the normal equations

@@ -99,6 +99,8 @@ _SIGNATURES = {
     "helmholtz_adjoint_gradient": (C.c_int, [P, C.c_int32, P, P, P]),
     "newton_continuation": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(P), C.POINTER(C.c_int32),
                                       C.POINTER(KfNewtonOpts), P, C.POINTER(KfNewtonStats)]),
+    "newton_step_concurrent": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(P), C.POINTER(KfNewtonOpts),
+                                         C.POINTER(P), C.POINTER(P), C.c_int32, C.POINTER(KfNewtonStats)]),
     "rsgn_cg_step": (C.c_int, [P, P, C.POINTER(KfCgOpts), P, P, C.c_int32, C.POINTER(KfCgStats)]),
     "kf_sources": (C.c_int, [P, P]),
     "kf_set_hblock": (C.c_int, [P, C.c_int32, C.c_int32]),

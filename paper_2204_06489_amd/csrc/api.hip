@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <tuple>
 
 // ---------------------------------------------------------------------------
@@ -1164,6 +1165,72 @@ extern "C" kf_status newton_step(kf_problem *p, const void *d_obs, const kf_newt
   if (st) *st = S;
   prof_collect(p);
   return fst;
+}
+
+// ---------------------------------------------------------------------------
+// independent problems stepped at once, each on a stream and a host thread of its own
+// ---------------------------------------------------------------------------
+constexpr int KF_CONCURRENT_MAX = 16;
+extern "C" kf_status newton_step_concurrent(kf_problem *const *problems, int32_t n, const void *const *d_obs,
+                                            const kf_newton_opts *opts, void *const *xi_out,
+                                            double *const *gamma_next, int32_t update_in_place,
+                                            kf_newton_stats *st) {
+  if (!problems || !d_obs || !opts) return fail(KF_EINVAL, "null pointer argument");
+  if (n < 1 || n > KF_CONCURRENT_MAX) return fail(KF_EINVAL, "need 1..16 problems");
+  for (int q = 0; q < n; ++q) {
+    if (!problems[q] || !d_obs[q]) return fail(KF_EINVAL, "problem or data " + std::to_string(q) + " is NULL");
+    for (int r = 0; r < q; ++r)
+      if (problems[r] == problems[q]) return fail(KF_EINVAL, "problem " + std::to_string(q) + " appears twice");
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::vector<hipStream_t> saved(n), own(n, nullptr);
+  for (int q = 0; q < n; ++q) {
+    saved[q] = problems[q]->stream;
+    HIP_TRY(hipStreamSynchronize(saved[q]));   // the caller's work on this problem is done
+  }
+  for (int q = 0; q < n; ++q) {
+    const hipError_t e = hipStreamCreateWithFlags(&own[q], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (int r = 0; r < q; ++r) hipStreamDestroy(own[r]);
+      return fail(KF_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+    }
+  }
+  for (int q = 0; q < n; ++q) problems[q]->stream = own[q];
+  std::vector<kf_status> rs(n, KF_OK);
+  std::vector<std::string> msg(n);
+  std::vector<kf_newton_stats> S(n);
+  {
+    std::vector<std::thread> workers;
+    workers.reserve(n);
+    for (int q = 0; q < n; ++q)
+      workers.emplace_back([&, q] {
+        // the device is per host thread; the error text of newton_step is this thread's
+        if (hipSetDevice(dev) != hipSuccess) {
+          rs[q] = KF_EHIP;
+          msg[q] = "hipSetDevice failed in a worker thread";
+          return;
+        }
+        rs[q] = newton_step(problems[q], d_obs[q], opts, xi_out ? xi_out[q] : nullptr,
+                            gamma_next ? gamma_next[q] : nullptr, update_in_place, &S[q]);
+        if (rs[q] != KF_OK) msg[q] = g_last_error;
+        hipStreamSynchronize(own[q]);
+      });
+    for (auto &w : workers) w.join();
+  }
+  for (int q = 0; q < n; ++q) {
+    problems[q]->stream = saved[q];
+    hipStreamDestroy(own[q]);
+  }
+  if (st)
+    for (int q = 0; q < n; ++q) st[q] = S[q];
+  int bad = -1;
+  for (int q = 0; q < n && bad < 0; ++q)
+    if (rs[q] != KF_OK && rs[q] != KF_ENOCONV) bad = q;
+  for (int q = 0; q < n && bad < 0; ++q)
+    if (rs[q] == KF_ENOCONV) bad = q;
+  if (bad < 0) return KF_OK;
+  return fail(rs[bad], "problem " + std::to_string(bad) + ": " + msg[bad]);
 }
 
 // ---------------------------------------------------------------------------

@@ -317,6 +317,40 @@ class KKTProblem:
         check(lib().kf_profile_only(self._h, (name or "").encode()))
 
 
+def newton_step_concurrent(problems, d_obs, rtol=1e-6, restart=30, maxit=200, pc="exact", fwd_prec="c128",
+                           fwd_rtol=1e-10, misfit_after=False, update_in_place=True, want_xi=True, reorth_eta=0.1,
+                           outer="fgmres"):
+    """One Newton step on each of several independent problems at once
+    (newton_step_concurrent: a stream and a host thread per problem).  Returns
+    (list of xi or None, list of gamma_{n+1}, list of stats dicts, each with "converged")."""
+    n = len(problems)
+    o = KfNewtonOpts()
+    o.rtol, o.restart, o.maxit, o.pc = float(rtol), int(restart), int(maxit), _PC[pc]
+    o.fwd_prec, o.fwd_rtol, o.misfit_after = _PREC[fwd_prec], float(fwd_rtol), int(bool(misfit_after))
+    o.reorth_eta = float(reorth_eta)
+    o.outer = _OUTER[outer]
+    xis = [q.empty_xi() if want_xi else None for q in problems]
+    gs = [torch.empty((q.nz, q.nx), dtype=torch.float64, device=q.device) for q in problems]
+    arr = (C.c_void_p * n)(*[q._h.value for q in problems])
+    dp = (C.c_void_p * n)(*[_ptr(d, torch.complex128, q.K * q.nrec, "d_obs").value for d, q in zip(d_obs, problems)])
+    xp = (C.c_void_p * n)(*[_ptr(x).value if x is not None else None for x in xis])
+    gp = (C.c_void_p * n)(*[_ptr(g).value for g in gs])
+    st = (KfNewtonStats * n)()
+    torch.cuda.current_stream().synchronize()   # the outputs' allocation is complete
+    s = check(lib().newton_step_concurrent(arr, n, dp, C.byref(o), xp, gp, int(bool(update_in_place)), st),
+              allow=(KF_ENOCONV,))
+    stats = []
+    for k in range(n):
+        d = {f: getattr(st[k], f) for f, _ in KfNewtonStats._fields_ if f != "rel_res_hist"}
+        d["rel_res_hist"] = list(st[k].rel_res_hist[:max(0, st[k].outer_iters)])
+        d["converged"] = s != KF_ENOCONV or st[k].rel_res <= rtol
+        stats.append(d)
+    if update_in_place:
+        for q in problems:
+            q.gamma_token = getattr(q, "gamma_token", 0) + 1
+    return xis, gs, stats
+
+
 def newton_continuation(problems, d_obs, steps, rtol=1e-6, restart=30, maxit=200, pc="exact", fwd_prec="c128",
                         fwd_rtol=1e-10, reorth_eta=0.1):
     """Frequency continuation (newton_continuation): steps[q] Newton steps on problems[q],

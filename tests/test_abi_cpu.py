@@ -105,3 +105,12 @@ def test_null_handles_and_batches_are_rejected():
     nine = (C.c_void_p * 9)(*([1] * 9))
     assert L.kf_batch_create(nine, 9, None, C.byref(out)) == _lib.KF_EINVAL
     assert "1..8" in L.kf_last_error().decode()
+    # concurrent Newton steps: validated before any HIP call (the handles are not read)
+    opts = _lib.KfNewtonOpts()
+    two = (C.c_void_p * 2)(1, 1)
+    data = (C.c_void_p * 2)(8, 8)
+    assert L.newton_step_concurrent(None, 1, data, C.byref(opts), None, None, 1, None) == _lib.KF_EINVAL
+    assert L.newton_step_concurrent(two, 0, data, C.byref(opts), None, None, 1, None) == _lib.KF_EINVAL
+    assert "1..16" in L.kf_last_error().decode()
+    assert L.newton_step_concurrent(two, 2, data, C.byref(opts), None, None, 1, None) == _lib.KF_EINVAL
+    assert "appears twice" in L.kf_last_error().decode()
