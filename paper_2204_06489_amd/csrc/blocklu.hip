@@ -1055,11 +1055,11 @@ __global__ __launch_bounds__(256) void k_cr_combine64(SweepBatch bt) {
 // one dense product: with the interior columns of the chunk stacked (row R = (i - a) m
 // + j), X_I -= [V_stack | W_stack] [x_{s_left}; x_{s_right}], an (L m) x 2m by 2m x K
 // product, cut into CG_R x CG_S tiles (rows x sources).
-constexpr int CG_R = 64, CG_S = 48;
+constexpr int CG_R = 64, CG_S = 32;
 
-// The interior correction of FP64 solves on the matrix cores: 64 x 48 tiles (rows of
+// The interior correction of FP64 solves on the matrix cores: 64 x 32 tiles (rows of
 // the chunk's stacked interior columns x sources, item = (chunk, row tile, source
-// tile)), each wavefront 16 rows x 48 sources as three 16 x 16 tiles of
+// tile)), each wavefront 16 rows x 32 sources as two 16 x 16 tiles of
 // v_mfma_f64_16x16x4f64 (four real products per complex one), k in slabs of CM_K
 // through LDS with the next slab loaded while the current one is multiplied.  The
 // f64 result layout (D[i][j] in lane j + 16 (i % 4), element i / 4) puts one lane's
@@ -1115,10 +1115,9 @@ __global__ __launch_bounds__(256) void k_correct64_mfma(SweepBatch bt) {
       rb[u] = (l < lk1 && sidx < K) ? v : make_double2(0.0, 0.0);
     }
   };
-  constexpr int CG_ST = CG_S / 16;   // source tiles of 16 per wavefront
-  dx4 re[CG_ST], im[CG_ST];
+  dx4 re[2], im[2];
 #pragma unroll
-  for (int y = 0; y < CG_ST; ++y) re[y] = im[y] = dx4{0.0, 0.0, 0.0, 0.0};
+  for (int y = 0; y < 2; ++y) re[y] = im[y] = dx4{0.0, 0.0, 0.0, 0.0};
   C ra[NA], rb[NB];
   load_slab(lk0, ra, rb);
   for (int kb = lk0; kb < lk1; kb += CM_K) {
@@ -1139,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_correct64_mfma(SweepBatch bt) {
       const int kk = 4 * kq + (lane >> 4);
       const C a = As[kk][16 * wave + (lane & 15)];
 #pragma unroll
-      for (int y = 0; y < CG_ST; ++y) {
+      for (int y = 0; y < 2; ++y) {
         const C b = Bs[kk][16 * y + (lane & 15)];
         re[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[y], 0, 0, 0);
         re[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[y], 0, 0, 0);
@@ -1151,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_correct64_mfma(SweepBatch bt) {
   }
   // the tile to LDS as [source][row], then row-contiguous updates
 #pragma unroll
-  for (int y = 0; y < CG_ST; ++y)
+  for (int y = 0; y < 2; ++y)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       Out[16 * y + (lane & 15)][16 * wave + 4 * r + (lane >> 4)] = make_double2(re[y][r], im[y][r]);
