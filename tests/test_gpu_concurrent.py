@@ -63,3 +63,16 @@ def test_concurrent_steps_report_maxit_and_give_the_streams_back():
     assert st["converged"]
     with pytest.raises(Exception, match="appears twice"):
         newton_step_concurrent([gpus[0], gpus[0]], [dd[0], dd[0]])
+
+
+def test_concurrent_steps_report_the_first_failing_problem():
+    ins, data, orcs, gpus = _problems("exact")
+    dd = [to_dev(d) for d in data]
+    print("[case] concurrent steps with an invalid restart length", flush=True)
+    with pytest.raises(Exception, match="problem 0: .*restart"):
+        newton_step_concurrent(gpus, dd, restart=0)
+    # nothing was changed: the problems still step normally, alone and together
+    _, gs, sts = newton_step_concurrent(gpus, dd, rtol=1e-10, restart=30, maxit=300, pc="exact",
+                                        update_in_place=False, want_xi=False)
+    assert all(s["converged"] for s in sts)
+    assert all(torch.isfinite(g).all() for g in gs)
