@@ -177,8 +177,8 @@ kf_status kf_set_stream(kf_problem *p, void *hip_stream);
  * (0 = 1; FP64 solves use at most 4).  Results do not depend on either beyond rounding. */
 kf_status kf_set_solver_shape(kf_problem *p, int32_t chunks, int32_t sources_per_group);
 kf_status kf_get_solver_shape(kf_problem *p, int32_t *chunks /*[host]*/, int32_t *sources_per_group /*[host]*/);
-/* Autotuner of the solver shape: for chunk counts around the automatic choice (and 1) it
- * builds the factorisation (FP64, plus the complex64 copy when prec = KF_C64), and for
+/* Autotuner of the solver shape: for chunk counts around the automatic choice (and 1),
+ * then for the counts within 2 of the best of those, it builds the factorisation (FP64, plus the complex64 copy when prec = KF_C64), and for
  * each sources_per_group it times forward and adjoint block solves of all K sources
  * (complex64 sweeps with c128 I/O when prec = KF_C64, as in the inexact preconditioner;
  * FP64 otherwise) with HIP events on the problem's stream.  The score of a shape is

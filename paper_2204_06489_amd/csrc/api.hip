@@ -456,7 +456,7 @@ extern "C" kf_status kf_autotune(kf_problem *p, int32_t prec, double solves_per_
   };
   int count = 0, best_c = 1, best_ns = 1;
   double best = INFINITY;
-  for (int c : cand) {
+  auto eval = [&](int c) -> kf_status {
     CHECK_ST(blu_set_shape(p, c, 1));
     double tf = 0.0;
     CHECK_ST(timed(p, [&]() { return blu_factor(p, which); }, &tf));
@@ -479,7 +479,18 @@ extern "C" kf_status kf_autotune(kf_problem *p, int32_t prec, double solves_per_
       ++count;
       if (score < best) { best = score; best_c = c; best_ns = ns; }
     }
-  }
+    return KF_OK;
+  };
+  for (int c : cand) CHECK_ST(eval(c));
+  // a finer look around the best chunk count of the grid above (whose steps are ~1.4x):
+  // the solve's phases change in steps of their own (e.g. where the sweeps' items pass
+  // the number of compute units)
+  const int c0 = best_c;
+  for (int c : {c0 - 2, c0 - 1, c0 + 1, c0 + 2})
+    if (c > 1 && c <= pmax && 2 * c - 1 <= p->nx && std::find(cand.begin(), cand.end(), c) == cand.end()) {
+      cand.push_back(c);
+      CHECK_ST(eval(c));
+    }
   CHECK_ST(blu_set_shape(p, best_c, best_ns));
   tune_cache()[TuneKey{p->nx, p->nz, p->K, prec}] = {best_c, best_ns};
   if (n_table) *n_table = count;
