@@ -352,8 +352,9 @@ def bench_c4(args, torch, KKTProblem):
         ds.append(observed_data(inp, torch, KKTProblem))
         probs.append(KKTProblem.from_inputs(inp, reg_on_update=True))
         if not args.no_autotune:
-            best = probs[-1].autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)[0]
-            log(args, f"  autotuned shape P={best['chunks']} ns={best['sources_per_group']}")
+            probs[-1].autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)
+            c, ns = probs[-1].solver_shape
+            log(args, f"  autotuned shape P={c} ns={ns}")
     g0 = [torch.as_tensor(inp["gamma0"]).cuda() for inp in inps]
 
     def reset():
@@ -649,9 +650,10 @@ def main():
     elif not args.no_autotune:
         # shape of the block solver for this grid (setup, outside the timed region)
         table = p.autotune(prec="c64" if args.pc == "inexact" else "c128", solves_per_factor=100.0)
-        log(args, "autotune: " + ", ".join(f"P={r['chunks']} ns={r['sources_per_group']}: "
-                                            f"{r['t_factor_ms']:.1f}+100x{r['t_solve_ms']:.3f} ms"
-                                            for r in table[:4]))
+        c, ns = p.solver_shape
+        log(args, f"autotune: chose P={c} ns={ns}; best scores " + ", ".join(
+            f"P={r['chunks']} ns={r['sources_per_group']}: {r['t_factor_ms']:.1f}+100x{r['t_solve_ms']:.3f} ms"
+            for r in table[:4]))
     if args.solver == "rsgn":
         return bench_rsgn(args, torch, p, d, inp)
     opts = dict(rtol=args.rtol, restart=args.restart, maxit=600, pc=args.pc, fwd_prec=args.fwd_prec,
