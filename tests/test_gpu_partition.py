@@ -63,16 +63,20 @@ def test_invalid_shapes_are_rejected():
     assert gpu.solver_shape == (11, 4)
 
 
-def test_autotune_picks_the_fastest_measured_shape_and_stays_exact():
+def test_autotune_picks_a_best_measured_shape_and_stays_exact():
+    """The chosen shape is the best measured one, or (when a count refined around the
+    coarse grid's best scored better by at most 2%) the coarse grid's best."""
     inp = tiny_inputs(seed=3, nx=133, nz=37, npml=6, K=9)
     orc, gpu = oracle_and_gpu(inp, eps=1.0)
     table = gpu.autotune(prec="c64", solves_per_factor=50.0)
-    print("autotune table (best first):", table[:4])
+    print("autotune table (best first):", table[:4], "chosen:", gpu.solver_shape)
     assert len(table) >= 4
     for r in table:
         assert r["t_factor_ms"] > 0 and r["t_solve_ms"] > 0
         assert abs(r["score_ms"] - (r["t_factor_ms"] + 50.0 * r["t_solve_ms"])) <= 1e-9 * r["score_ms"]
-    assert gpu.solver_shape == (table[0]["chunks"], table[0]["sources_per_group"])
+    chosen = [r for r in table if (r["chunks"], r["sources_per_group"]) == gpu.solver_shape]
+    assert len(chosen) == 1
+    assert chosen[0]["score_ms"] * 0.98 <= table[0]["score_ms"] * (1 + 1e-12)
     b = complex_normal(gpu.field_shape, seed=4)
     x, _ = gpu.helmholtz_solve(to_dev(b), prec="c128")
     assert rel(to_np(x), orc.lu.solve(b)) <= 1e-10
