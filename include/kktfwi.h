@@ -441,7 +441,9 @@ kf_status helmholtz_solve_batched(kf_batch *b, int32_t adjoint, int32_t prec, co
  * device pointers (xi_out, gamma_next entries may be NULL) and st is [host][n].  The
  * problems' FGMRES iterations advance in lockstep, each with its own scalars and its own
  * stopping test.  use_graph = 1 replays each Krylov column's preconditioner and matvec
- * for all problems from a captured hipGraph.  opts->fwd_prec must be KF_C128. */
+ * for all problems from a captured hipGraph.  opts->fwd_prec must be KF_C128.  Where
+ * each problem fills the chip on its own, each launch here lasts as long as its slowest
+ * problem's items; newton_step_concurrent (above) overlaps whole problems instead. */
 kf_status newton_step_batched(kf_batch *b, const void *const *d_obs, const kf_newton_opts *opts,
                               void *const *xi_out, double *const *gamma_next, int32_t update_in_place,
                               int32_t use_graph, kf_newton_stats *st);
